@@ -1,0 +1,701 @@
+/*
+ * CPU oracle for the cascadic multigrid (CMG) Fiedler-vector method of
+ * Urschel, Hu, Xu & Zikatanov, "A Cascadic Multigrid Algorithm for Computing
+ * the Fiedler Vector of Graph Laplacians" (arXiv 1412.0565).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It is plain, single-threaded C in IEEE FP64
+ * (built with -ffp-contract=off so no FMA contraction happens), written to
+ * be checked against the paper by eye, and shares no code, header or table
+ * with the GPU path.
+ *
+ * Every function cites the passage of the paper it follows.  Readings of
+ * passages that are silent, ambiguous or garbled are marked READING.
+ *
+ * Random draws.  The paper draws a random permutation in HEC (Algorithm 2,
+ * randperm) and a Gaussian start for the coarsest power iteration
+ * (Algorithm 1, Step 2).  Both are replaced by counter-based SplitMix64
+ * values (Steele, Lea & Flood, OOPSLA 2014), implemented here from the
+ * published definition and pinned to its published test vector.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_E_ARG 1
+#define ORC_E_GRAPH 2
+#define ORC_E_ISOLATED 3
+#define ORC_E_OOM 4
+#define ORC_W_MAXIT 6
+
+/* ------------------------------------------------------------------ hash */
+
+/* SplitMix64 output function (the "mix" applied to the state). */
+uint64_t orc_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* SplitMix64 generator: state += golden gamma, output mix(state). */
+void orc_splitmix64_sequence(uint64_t seed, int32_t count, uint64_t* out)
+{
+    uint64_t s = seed;
+    for (int32_t i = 0; i < count; ++i) {
+        s += 0x9E3779B97F4A7C15ull;
+        out[i] = orc_mix64(s);
+    }
+}
+
+/* Priority key of vertex v at level j; replaces randperm (Algorithm 2).
+ * READING: visiting vertices in ascending key order is a uniformly random
+ * order for a random seed; the seed is exposed so runs are reproducible. */
+uint64_t orc_hec_key(uint64_t seed, int32_t level, int32_t v)
+{
+    return orc_mix64(seed ^ ((uint64_t)(uint32_t)level << 40) ^ (uint64_t)(uint32_t)v);
+}
+
+/* Uniform start value in [0,1) used only where the coarsest level is too
+ * large for the dense solve (power iteration on a random vector,
+ * Section 2, Remark on the coarsest level). */
+double orc_uniform(uint64_t seed, int32_t i)
+{
+    uint64_t h = orc_mix64(seed ^ 0x9E3779B97F4A7C15ull ^ (uint64_t)(uint32_t)i);
+    return (double)(h >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* ------------------------------------------------------------- Laplacian */
+
+/* Weighted degree d_i = sum_k w_ik (Section 2, definition of L: rows of L
+ * sum to zero, so the diagonal is the weighted degree). */
+static double orc_degree(const int32_t* rp, const double* w, int32_t i)
+{
+    double d = 0.0;
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) d += w[e];
+    return d;
+}
+
+/* y = L x with L = D - W (Section 2, definition of the graph Laplacian). */
+void orc_laplacian_apply(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                         const double* x, double* y)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        double d = orc_degree(rp, w, i);
+        double s = 0.0;
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) s += w[e] * x[col[e]];
+        y[i] = d * x[i] - s;
+    }
+}
+
+/* Gershgorin bound g = max_i sum_j |l_ij| = max_i 2 d_i
+ * (Section 2.2 and Algorithm 3, first line). */
+double orc_gershgorin(int32_t n, const int32_t* rp, const double* w)
+{
+    double g = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        double r = 2.0 * orc_degree(rp, w, i);
+        if (r > g) g = r;
+    }
+    return g;
+}
+
+/* ------------------------------------------------------------- validation */
+
+int orc_validate(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col, const double* w)
+{
+    if (n < 2 || nnz < 0) return ORC_E_ARG;
+    if (rp[0] != 0 || (int64_t)rp[n] != nnz) return ORC_E_GRAPH;
+    for (int32_t i = 0; i < n; ++i) {
+        if (rp[i + 1] < rp[i]) return ORC_E_GRAPH;
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (col[e] < 0 || col[e] >= n || col[e] == i) return ORC_E_GRAPH;
+            if (e > rp[i] && col[e] <= col[e - 1]) return ORC_E_GRAPH;
+            if (!(w[e] > 0.0) || !isfinite(w[e])) return ORC_E_GRAPH;
+        }
+    }
+    for (int32_t i = 0; i < n; ++i)
+        if (rp[i + 1] == rp[i]) return ORC_E_ISOLATED;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ HEC */
+
+/* Heaviest neighbour: m = argmin of column v of L (Algorithm 2).  The
+ * off-diagonal entries of L are -w, so this is the neighbour with the
+ * largest weight.  READING: ties go to the lowest index (the first minimum,
+ * as MATLAB's argmin returns).  The diagonal is positive and never chosen. */
+int orc_heaviest(int32_t n, const int32_t* rp, const int32_t* col, const double* w, int32_t* h)
+{
+    for (int32_t v = 0; v < n; ++v) {
+        if (rp[v + 1] == rp[v]) return ORC_E_ISOLATED;
+        int32_t best = col[rp[v]];
+        double bw = w[rp[v]];
+        for (int32_t e = rp[v] + 1; e < rp[v + 1]; ++e) {
+            if (w[e] > bw || (w[e] == bw && col[e] < best)) {
+                bw = w[e];
+                best = col[e];
+            }
+        }
+        h[v] = best;
+    }
+    return ORC_OK;
+}
+
+typedef struct {
+    uint64_t key;
+    int32_t v;
+} orc_keyv;
+
+static int orc_cmp_keyv(const void* a, const void* b)
+{
+    const orc_keyv* x = (const orc_keyv*)a;
+    const orc_keyv* y = (const orc_keyv*)b;
+    if (x->key < y->key) return -1;
+    if (x->key > y->key) return 1;
+    return (x->v > y->v) - (x->v < y->v);
+}
+
+/* Heavy edge coarsening with an explicit visit order (Algorithm 2 and the
+ * text of Section 2.1).  Vertices are visited in the order given; an
+ * unmapped vertex v looks at its heaviest neighbour m: if m is unmapped too,
+ * v and m open a new aggregate (v is its "seed"); otherwise v joins m's
+ * aggregate.  Already-mapped vertices are skipped.
+ *
+ * READING: the paper numbers aggregates in visit order; here they are
+ * renumbered by ascending index of their seed vertex (a permutation of the
+ * coarse vertices, which changes nothing else).
+ *
+ * agg[n] receives coarse ids, is_seed[n] marks seeds; returns the number of
+ * aggregates, or -1 on an isolated vertex / allocation failure. */
+int32_t orc_hec_order(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                      const int32_t* order, int32_t* agg, uint8_t* is_seed)
+{
+    int32_t* h = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* seedv = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* rank = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!h || !q || !seedv || !rank) {
+        free(h); free(q); free(seedv); free(rank);
+        return -1;
+    }
+    if (orc_heaviest(n, rp, col, w, h) != ORC_OK) {
+        free(h); free(q); free(seedv); free(rank);
+        return -1;
+    }
+    for (int32_t i = 0; i < n; ++i) q[i] = -1;
+    int32_t c = 0;
+    for (int32_t t = 0; t < n; ++t) {
+        int32_t v = order[t];
+        if (q[v] >= 0) continue;
+        int32_t m = h[v];
+        if (q[m] < 0) {
+            q[m] = c;
+            q[v] = c;
+            seedv[c] = v;
+            ++c;
+        } else {
+            q[v] = q[m];
+        }
+    }
+    memset(is_seed, 0, (size_t)n);
+    for (int32_t a = 0; a < c; ++a) is_seed[seedv[a]] = 1;
+    int32_t r = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        rank[v] = r;
+        r += is_seed[v];
+    }
+    for (int32_t v = 0; v < n; ++v) agg[v] = rank[seedv[q[v]]];
+    free(h); free(q); free(seedv); free(rank);
+    return c;
+}
+
+/* HEC with the seeded visit order of level j: ascending orc_hec_key. */
+int32_t orc_hec(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                uint64_t seed, int32_t level, int32_t* agg, uint8_t* is_seed)
+{
+    orc_keyv* kv = (orc_keyv*)malloc(sizeof(orc_keyv) * (size_t)n);
+    int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!kv || !order) {
+        free(kv); free(order);
+        return -1;
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        kv[v].key = orc_hec_key(seed, level, v);
+        kv[v].v = v;
+    }
+    qsort(kv, (size_t)n, sizeof(orc_keyv), orc_cmp_keyv);
+    for (int32_t t = 0; t < n; ++t) order[t] = kv[t].v;
+    int32_t c = orc_hec_order(n, rp, col, w, order, agg, is_seed);
+    free(kv); free(order);
+    return c;
+}
+
+/* -------------------------------------------------------------- Galerkin */
+
+typedef struct {
+    int32_t b;
+    int64_t seq;
+    double w;
+} orc_entry;
+
+static int orc_cmp_entry(const void* a, const void* b)
+{
+    const orc_entry* x = (const orc_entry*)a;
+    const orc_entry* y = (const orc_entry*)b;
+    if (x->b != y->b) return (x->b > y->b) - (x->b < y->b);
+    return (x->seq > y->seq) - (x->seq < y->seq);
+}
+
+/* Galerkin coarse graph L^{i+1} = I L^i I^T (Section 2, Step 1, and the
+ * Proposition on restriction): the coarse weight between aggregates a != b
+ * is the sum of the fine weights of edges joining them; edges inside one
+ * aggregate vanish from the adjacency (they only enter the implicit
+ * diagonal, which stays equal to the row sum).  Sums are taken in fine CSR
+ * order (exact for integer weights).  Output CSR has ascending columns and
+ * no diagonal; arrays are malloc'd and owned by the caller.
+ * Returns the coarse nnz, or -1 on allocation failure. */
+int64_t orc_galerkin(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                     const int32_t* agg, int32_t nc,
+                     int32_t** rp_out, int32_t** col_out, double** w_out)
+{
+    /* members of each aggregate, ascending vertex index */
+    int32_t* mptr = (int32_t*)calloc((size_t)nc + 1, sizeof(int32_t));
+    int32_t* mem = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* fill = (int32_t*)malloc(sizeof(int32_t) * (size_t)nc);
+    if (!mptr || !mem || !fill) { free(mptr); free(mem); free(fill); return -1; }
+    for (int32_t v = 0; v < n; ++v) mptr[agg[v] + 1]++;
+    for (int32_t a = 0; a < nc; ++a) mptr[a + 1] += mptr[a];
+    for (int32_t a = 0; a < nc; ++a) fill[a] = mptr[a];
+    for (int32_t v = 0; v < n; ++v) mem[fill[agg[v]]++] = v;
+    free(fill);
+
+    int64_t cap = 1024, nz = 0;
+    int32_t* crp = (int32_t*)malloc(sizeof(int32_t) * ((size_t)nc + 1));
+    int32_t* ccol = (int32_t*)malloc(sizeof(int32_t) * (size_t)cap);
+    double* cw = (double*)malloc(sizeof(double) * (size_t)cap);
+    int64_t bufcap = 1024;
+    orc_entry* buf = (orc_entry*)malloc(sizeof(orc_entry) * (size_t)bufcap);
+    if (!crp || !ccol || !cw || !buf) goto oom;
+    crp[0] = 0;
+    for (int32_t a = 0; a < nc; ++a) {
+        int64_t cnt = 0;
+        for (int32_t t = mptr[a]; t < mptr[a + 1]; ++t) {
+            int32_t i = mem[t];
+            for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+                int32_t b = agg[col[e]];
+                if (b == a) continue;
+                if (cnt == bufcap) {
+                    bufcap *= 2;
+                    orc_entry* nb = (orc_entry*)realloc(buf, sizeof(orc_entry) * (size_t)bufcap);
+                    if (!nb) goto oom;
+                    buf = nb;
+                }
+                buf[cnt].b = b;
+                buf[cnt].seq = e; /* fine CSR position: members ascend, so this is CSR order */
+                buf[cnt].w = w[e];
+                ++cnt;
+            }
+        }
+        qsort(buf, (size_t)cnt, sizeof(orc_entry), orc_cmp_entry);
+        for (int64_t t = 0; t < cnt;) {
+            int32_t b = buf[t].b;
+            double s = 0.0;
+            while (t < cnt && buf[t].b == b) { s += buf[t].w; ++t; }
+            if (nz == cap) {
+                cap *= 2;
+                int32_t* nc2 = (int32_t*)realloc(ccol, sizeof(int32_t) * (size_t)cap);
+                if (!nc2) goto oom;
+                ccol = nc2;
+                double* nw2 = (double*)realloc(cw, sizeof(double) * (size_t)cap);
+                if (!nw2) goto oom;
+                cw = nw2;
+            }
+            ccol[nz] = b;
+            cw[nz] = s;
+            ++nz;
+        }
+        if (nz >= 2147483647LL) goto oom;
+        crp[a + 1] = (int32_t)nz;
+    }
+    free(buf); free(mptr); free(mem);
+    *rp_out = crp; *col_out = ccol; *w_out = cw;
+    return nz;
+oom:
+    free(buf); free(mptr); free(mem); free(crp); free(ccol); free(cw);
+    return -1;
+}
+
+/* ----------------------------------------------------------- dense solve */
+
+/* Cyclic-by-row Jacobi eigenvalue method for a symmetric matrix (Golub &
+ * Van Loan, Matrix Computations, Section 8.5): sweep over all pairs p < q
+ * in row order; each plane rotation J(p,q,theta) is chosen so that the
+ * (p,q) entry of J^T A J vanishes.  Stops when the off-diagonal Frobenius
+ * norm is at most 1e-14 * ||A||_F, or after 50 sweeps.
+ * A (n*n, row major) is overwritten; V (n*n) gets eigenvectors in columns;
+ * evals[k] = A[k][k] at exit (unsorted).  Returns the sweeps used. */
+int orc_jacobi(int32_t n, double* A, double* V, double* evals)
+{
+    double fro = 0.0;
+    for (int64_t t = 0; t < (int64_t)n * n; ++t) fro += A[t] * A[t];
+    fro = sqrt(fro);
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = 0; k < n; ++k) V[(int64_t)i * n + k] = (i == k) ? 1.0 : 0.0;
+    int sweep = 0;
+    for (; sweep < 50; ++sweep) {
+        double off = 0.0;
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t k = 0; k < n; ++k)
+                if (i != k) off += A[(int64_t)i * n + k] * A[(int64_t)i * n + k];
+        if (sqrt(off) <= 1e-14 * fro) break;
+        for (int32_t p = 0; p < n - 1; ++p) {
+            for (int32_t q = p + 1; q < n; ++q) {
+                double apq = A[(int64_t)p * n + q];
+                if (apq == 0.0) continue;
+                double app = A[(int64_t)p * n + p];
+                double aqq = A[(int64_t)q * n + q];
+                /* symmetric 2x2 Schur decomposition */
+                double tau = (aqq - app) / (2.0 * apq);
+                double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                double c = 1.0 / sqrt(1.0 + t * t);
+                double s = t * c;
+                /* rows p, q:  A <- J^T A */
+                for (int32_t k = 0; k < n; ++k) {
+                    double x = A[(int64_t)p * n + k];
+                    double y = A[(int64_t)q * n + k];
+                    A[(int64_t)p * n + k] = c * x - s * y;
+                    A[(int64_t)q * n + k] = s * x + c * y;
+                }
+                /* columns p, q:  A <- A J */
+                for (int32_t k = 0; k < n; ++k) {
+                    double x = A[(int64_t)k * n + p];
+                    double y = A[(int64_t)k * n + q];
+                    A[(int64_t)k * n + p] = c * x - s * y;
+                    A[(int64_t)k * n + q] = s * x + c * y;
+                }
+                /* eigenvector accumulation V <- V J */
+                for (int32_t k = 0; k < n; ++k) {
+                    double x = V[(int64_t)k * n + p];
+                    double y = V[(int64_t)k * n + q];
+                    V[(int64_t)k * n + p] = c * x - s * y;
+                    V[(int64_t)k * n + q] = s * x + c * y;
+                }
+            }
+        }
+    }
+    for (int32_t k = 0; k < n; ++k) evals[k] = A[(int64_t)k * n + k];
+    return sweep;
+}
+
+/* Coarsest-level eigenvector (Algorithm 1, Step 2; the geometric variant,
+ * Algorithm 4, solves the coarsest problem exactly).
+ * READING: dense L^J, Jacobi, then the vector is the normalised projection
+ * of the fixed ramp z_i = i - (n-1)/2 onto the eigenspace E of every
+ * eigenvalue (other than the smallest) within 1e-10 ||L||_F of lambda_2.
+ * This is basis independent when lambda_2 is repeated and fixes the sign.
+ * If the projection is below 1e-8 ||z||, the hashed uniform start
+ * (orc_uniform - 1/2) is projected instead.
+ * y[n] receives the unit vector; *lam2 the second smallest eigenvalue;
+ * *mult the size of E. */
+int orc_coarsest_dense(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                       uint64_t seed, double* y, double* lam2, int32_t* mult)
+{
+    double* A = (double*)calloc((size_t)n * n, sizeof(double));
+    double* V = (double*)malloc(sizeof(double) * (size_t)n * n);
+    double* ev = (double*)malloc(sizeof(double) * (size_t)n);
+    int32_t* idx = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    double* z = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!A || !V || !ev || !idx || !z) {
+        free(A); free(V); free(ev); free(idx); free(z);
+        return ORC_E_OOM;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            A[(int64_t)i * n + col[e]] = -w[e];
+            d += w[e];
+        }
+        A[(int64_t)i * n + i] = d;
+    }
+    double fro = 0.0;
+    for (int64_t t = 0; t < (int64_t)n * n; ++t) fro += A[t] * A[t];
+    fro = sqrt(fro);
+    orc_jacobi(n, A, V, ev);
+    /* ascending order of eigenvalues (insertion sort, stable) */
+    for (int32_t i = 0; i < n; ++i) idx[i] = i;
+    for (int32_t i = 1; i < n; ++i) {
+        int32_t t = idx[i];
+        int32_t k = i - 1;
+        while (k >= 0 && ev[idx[k]] > ev[t]) { idx[k + 1] = idx[k]; --k; }
+        idx[k + 1] = t;
+    }
+    double l2 = ev[idx[1]];
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        double zn = 0.0;
+        if (attempt == 0) {
+            for (int32_t i = 0; i < n; ++i) z[i] = (double)i - 0.5 * (double)(n - 1);
+        } else {
+            for (int32_t i = 0; i < n; ++i) z[i] = orc_uniform(seed, i) - 0.5;
+        }
+        for (int32_t i = 0; i < n; ++i) zn += z[i] * z[i];
+        zn = sqrt(zn);
+        for (int32_t i = 0; i < n; ++i) y[i] = 0.0;
+        int32_t m = 0;
+        for (int32_t r = 1; r < n; ++r) {
+            int32_t k = idx[r];
+            if (fabs(ev[k] - l2) > 1e-10 * fro) continue;
+            ++m;
+            double dot = 0.0;
+            for (int32_t i = 0; i < n; ++i) dot += V[(int64_t)i * n + k] * z[i];
+            for (int32_t i = 0; i < n; ++i) y[i] += dot * V[(int64_t)i * n + k];
+        }
+        double pn = 0.0;
+        for (int32_t i = 0; i < n; ++i) pn += y[i] * y[i];
+        pn = sqrt(pn);
+        *mult = m;
+        if (pn >= 1e-8 * zn || attempt == 1) {
+            for (int32_t i = 0; i < n; ++i) y[i] /= pn;
+            break;
+        }
+    }
+    *lam2 = l2;
+    free(A); free(V); free(ev); free(idx); free(z);
+    return ORC_OK;
+}
+
+/* --------------------------------------------------------- power iteration */
+
+static double orc_dot(int32_t n, const double* a, const double* b)
+{
+    double s = 0.0;
+    for (int32_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+static void orc_deflate_normalise(int32_t n, double* u)
+{
+    double mean = 0.0;
+    for (int32_t i = 0; i < n; ++i) mean += u[i];
+    mean /= (double)n;
+    for (int32_t i = 0; i < n; ++i) u[i] -= mean;
+    double nr = sqrt(orc_dot(n, u, u));
+    for (int32_t i = 0; i < n; ++i) u[i] /= nr;
+}
+
+/* Power iteration on B_g = g I - L (Algorithm 3; convergence test of
+ * Section 2.2: stop once (u^k, u^{k-1}) >= 1 - tol).
+ * READING: the start is deflated by subtracting its mean, i.e. one
+ * Gram-Schmidt step against the constant vector (Section 2.2); the printed
+ * formula multiplies the mean by the start vector itself, which would leave
+ * the constant component in place.  Deflation is repeated after every
+ * product (exactly a no-op in exact arithmetic, since 1-perp is invariant
+ * under B_g).  Norms are Euclidean.  k counts executed loop bodies.
+ * Returns k; *margin = u^T v - (1 - tol) at exit. */
+int32_t orc_pi(int32_t n, const int32_t* rp, const int32_t* col, const double* w, double g,
+               const double* y0, double tol, int32_t maxit, double* y, double* margin)
+{
+    double* v = (double*)calloc((size_t)n, sizeof(double));
+    double* t = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!v || !t) { free(v); free(t); return -1; }
+    memcpy(y, y0, sizeof(double) * (size_t)n);
+    orc_deflate_normalise(n, y); /* u */
+    int32_t k = 0;
+    while (orc_dot(n, y, v) < 1.0 - tol && k < maxit) {
+        memcpy(v, y, sizeof(double) * (size_t)n);        /* v <- u */
+        orc_laplacian_apply(n, rp, col, w, v, t);        /* t = L v */
+        for (int32_t i = 0; i < n; ++i) y[i] = g * v[i] - t[i]; /* u = B_g v */
+        orc_deflate_normalise(n, y);                     /* u <- u/||u|| */
+        ++k;
+    }
+    *margin = orc_dot(n, y, v) - (1.0 - tol);
+    free(v); free(t);
+    return k;
+}
+
+/* Rayleigh quotient in edge form r = sum_{edges} w_ik (y_i - y_k)^2 / ||y||^2
+ * (equal to y^T L y / y^T y, the eigenvalue estimate of Section 4), and the
+ * residual ||L y - r y|| / ||y|| reported as the error in Table 2. */
+void orc_rq_residual(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                     const double* y, double* rq, double* res)
+{
+    double num = 0.0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e)
+            if (col[e] > i) {
+                double d = y[i] - y[col[e]];
+                num += w[e] * d * d;
+            }
+    double yy = orc_dot(n, y, y);
+    double r = num / yy;
+    double* t = (double*)malloc(sizeof(double) * (size_t)n);
+    double s = 0.0;
+    if (t) {
+        orc_laplacian_apply(n, rp, col, w, y, t);
+        for (int32_t i = 0; i < n; ++i) {
+            double d = t[i] - r * y[i];
+            s += d * d;
+        }
+        free(t);
+    }
+    *rq = r;
+    *res = sqrt(s / yy);
+}
+
+/* ------------------------------------------------------------------ driver */
+
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    int32_t* rp;
+    int32_t* col;
+    double* w;
+    int32_t* agg;      /* to the next level (NULL on the coarsest) */
+    double g;
+    int32_t k;         /* power-iteration steps on this level (-1: coarsest dense) */
+    double margin;
+} orc_level;
+
+typedef struct {
+    int32_t status;
+    int32_t nlevels;   /* J + 1 */
+    orc_level lv[64];
+    double lambda;     /* r~ */
+    double residual;
+    double coarse_lambda2;
+    int32_t coarse_mult;
+    int32_t collapsed; /* 1 if the level loop stopped on a collapse */
+    double* y;         /* n0 */
+} orc_result;
+
+void orc_free(orc_result* r)
+{
+    if (!r) return;
+    for (int32_t j = 0; j < r->nlevels; ++j) {
+        if (j > 0) {
+            free(r->lv[j].rp);
+            free(r->lv[j].col);
+            free(r->lv[j].w);
+        }
+        free(r->lv[j].agg);
+    }
+    free(r->y);
+    free(r);
+}
+
+/* Multilevel cascadic eigensolver (Algorithm 1).
+ *  Step 1: while n_i > coarsest_n: HEC, Galerkin coarse graph.
+ *          READING: if HEC would produce fewer than 2 aggregates (complete
+ *          graphs, stars, dense power-law levels) the level is discarded and
+ *          the loop stops there.
+ *  Step 2: coarsest solve (dense if n_J <= dense_max, else power iteration
+ *          from the hashed uniform start).
+ *  Step 3: for j = J-1 .. 0: prolongate (y_hat_v = y[agg_j(v)]; the
+ *          printed index i inside the loop is read as j) and refine by PI.
+ * The returned vector is deflated and normalised once more; lambda is the
+ * edge-form Rayleigh quotient and residual ||L y - lambda y||.
+ * The level-0 arrays are borrowed from the caller (not copied). */
+orc_result* orc_cmg(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
+                    const double* w, double tol, int32_t coarsest_n, int32_t dense_max,
+                    uint64_t seed, int32_t max_iters)
+{
+    orc_result* r = (orc_result*)calloc(1, sizeof(orc_result));
+    if (!r) return NULL;
+    r->status = orc_validate(n, nnz, rp, col, w);
+    if (r->status != ORC_OK) return r;
+    r->lv[0].n = n;
+    r->lv[0].nnz = nnz;
+    r->lv[0].rp = (int32_t*)rp;
+    r->lv[0].col = (int32_t*)col;
+    r->lv[0].w = (double*)w;
+    r->nlevels = 1;
+    int32_t j = 0;
+    while (r->lv[j].n > coarsest_n && j < 63) {
+        orc_level* L = &r->lv[j];
+        int32_t* agg = (int32_t*)malloc(sizeof(int32_t) * (size_t)L->n);
+        uint8_t* sd = (uint8_t*)malloc((size_t)L->n);
+        if (!agg || !sd) { free(agg); free(sd); r->status = ORC_E_OOM; return r; }
+        int32_t nc = orc_hec(L->n, L->rp, L->col, L->w, seed, j, agg, sd);
+        free(sd);
+        if (nc < 0) { free(agg); r->status = ORC_E_ISOLATED; return r; }
+        if (nc < 2) { free(agg); r->collapsed = 1; break; }
+        orc_level* C = &r->lv[j + 1];
+        int64_t cnz = orc_galerkin(L->n, L->rp, L->col, L->w, agg, nc, &C->rp, &C->col, &C->w);
+        if (cnz < 0) { free(agg); r->status = ORC_E_OOM; return r; }
+        L->agg = agg;
+        C->n = nc;
+        C->nnz = cnz;
+        r->nlevels = j + 2;
+        ++j;
+    }
+    int32_t J = r->nlevels - 1;
+    for (int32_t t = 0; t <= J; ++t) {
+        r->lv[t].g = orc_gershgorin(r->lv[t].n, r->lv[t].rp, r->lv[t].w);
+        r->lv[t].k = 0;
+        r->lv[t].margin = 0.0;
+    }
+    double* ycur = (double*)malloc(sizeof(double) * (size_t)r->lv[J].n);
+    if (!ycur) { r->status = ORC_E_OOM; return r; }
+    orc_level* CJ = &r->lv[J];
+    if (CJ->n <= dense_max) {
+        orc_coarsest_dense(CJ->n, CJ->rp, CJ->col, CJ->w, seed, ycur, &r->coarse_lambda2,
+                           &r->coarse_mult);
+        CJ->k = -1;
+    } else {
+        double* st = (double*)malloc(sizeof(double) * (size_t)CJ->n);
+        if (!st) { free(ycur); r->status = ORC_E_OOM; return r; }
+        for (int32_t i = 0; i < CJ->n; ++i) st[i] = orc_uniform(seed, i) - 0.5;
+        CJ->k = orc_pi(CJ->n, CJ->rp, CJ->col, CJ->w, CJ->g, st, tol, max_iters, ycur, &CJ->margin);
+        if (CJ->k >= max_iters) r->status = ORC_W_MAXIT;
+        free(st);
+    }
+    for (int32_t t = J - 1; t >= 0; --t) {
+        orc_level* F = &r->lv[t];
+        double* yh = (double*)malloc(sizeof(double) * (size_t)F->n);
+        double* yn = (double*)malloc(sizeof(double) * (size_t)F->n);
+        if (!yh || !yn) { free(yh); free(yn); free(ycur); r->status = ORC_E_OOM; return r; }
+        for (int32_t v = 0; v < F->n; ++v) yh[v] = ycur[F->agg[v]];
+        F->k = orc_pi(F->n, F->rp, F->col, F->w, F->g, yh, tol, max_iters, yn, &F->margin);
+        if (F->k >= max_iters) r->status = ORC_W_MAXIT;
+        free(yh);
+        free(ycur);
+        ycur = yn;
+    }
+    orc_deflate_normalise(n, ycur);
+    r->y = ycur;
+    orc_rq_residual(n, rp, col, w, ycur, &r->lambda, &r->residual);
+    return r;
+}
+
+/* ----------------------------------------------------- result accessors */
+
+int32_t orc_res_status(const orc_result* r) { return r->status; }
+int32_t orc_res_nlevels(const orc_result* r) { return r->nlevels; }
+int32_t orc_res_level_n(const orc_result* r, int32_t j) { return r->lv[j].n; }
+int64_t orc_res_level_nnz(const orc_result* r, int32_t j) { return r->lv[j].nnz; }
+double orc_res_level_g(const orc_result* r, int32_t j) { return r->lv[j].g; }
+int32_t orc_res_level_k(const orc_result* r, int32_t j) { return r->lv[j].k; }
+double orc_res_level_margin(const orc_result* r, int32_t j) { return r->lv[j].margin; }
+double orc_res_lambda(const orc_result* r) { return r->lambda; }
+double orc_res_residual(const orc_result* r) { return r->residual; }
+double orc_res_coarse_lambda2(const orc_result* r) { return r->coarse_lambda2; }
+int32_t orc_res_coarse_mult(const orc_result* r) { return r->coarse_mult; }
+int32_t orc_res_collapsed(const orc_result* r) { return r->collapsed; }
+
+void orc_res_copy_level(const orc_result* r, int32_t j, int32_t* rp, int32_t* col, double* w,
+                        int32_t* agg)
+{
+    const orc_level* L = &r->lv[j];
+    if (rp) memcpy(rp, L->rp, sizeof(int32_t) * ((size_t)L->n + 1));
+    if (col) memcpy(col, L->col, sizeof(int32_t) * (size_t)L->nnz);
+    if (w) memcpy(w, L->w, sizeof(double) * (size_t)L->nnz);
+    if (agg && L->agg) memcpy(agg, L->agg, sizeof(int32_t) * (size_t)L->n);
+}
+
+void orc_res_copy_y(const orc_result* r, double* y)
+{
+    if (r->y) memcpy(y, r->y, sizeof(double) * (size_t)r->lv[0].n);
+}

@@ -1,0 +1,200 @@
+/*
+ * cmg.h - C ABI of libcmg, an MI355X (gfx950) implementation of the
+ * cascadic multigrid (CMG) Fiedler-vector method of Urschel, Hu, Xu and
+ * Zikatanov, "A Cascadic Multigrid Algorithm for Computing the Fiedler
+ * Vector of Graph Laplacians" (arXiv 1412.0565).
+ *
+ * Problem (Section 2, definitions of the graph Laplacian and of the
+ * algebraic connectivity): given a connected, weighted, undirected,
+ * loop-free graph G with Laplacian L = D - W, approximate the eigenpair
+ * (lambda_2, phi_2) of L: the second smallest eigenvalue and its
+ * eigenvector, the Fiedler vector.  Method (Algorithm 1): heavy edge
+ * coarsening (Algorithm 2) builds aggregates and Galerkin coarse Laplacians
+ * L^{i+1} = I L^i I^T until at most `coarsest_n` vertices remain; the
+ * coarsest problem is solved directly; then, level by level, the vector is
+ * prolongated and refined by power iteration on gI - L with the constant
+ * vector deflated (Algorithm 3).  The returned eigenvalue estimate is the
+ * Rayleigh quotient r = y^T L y (Section 4), with the residual
+ * ||L y - r y|| (Table 2's error measure).
+ *
+ * Every step after argument checking runs in HIP kernels on the GPU; the
+ * host only sequences launches and reads back sizes.
+ *
+ * Conventions
+ *  - Input graph: symmetric adjacency CSR.  Both directions stored, no
+ *    diagonal, columns strictly increasing within a row, weights finite
+ *    and > 0, n >= 2, nnz < 2^31, every vertex has a neighbour.  Parallel
+ *    edges must be merged by the caller.  The Laplacian is implicit.
+ *  - Ownership: the caller owns all arrays it passes.  cmg_setup copies the
+ *    graph into memory owned by the handle and keeps no caller pointer.
+ *    Output buffers (x, stats, level arrays) are caller allocated.
+ *  - Memory: CMG_MEM_HOST pointers are host memory; CMG_MEM_DEVICE pointers
+ *    are device memory on the current HIP device.  The library allocates
+ *    its own device memory through `allocator` (hipMalloc if NULL) and
+ *    issues all work on `stream` (the null stream if NULL).
+ *  - Errors: only status codes cross the ABI.  On failure of cmg_setup,
+ *    *out is set to NULL and everything allocated is released.
+ *    CMG_W_MAXIT is a warning: the result is still written.
+ *  - Synchronisation: every call returns after its work has completed.
+ *  - Threads: one handle is used by one thread at a time; distinct handles
+ *    are independent.  Calls on one device share no mutable state except
+ *    the allocator the caller supplies.
+ */
+#ifndef CMG_H
+#define CMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cmg_ctx* cmg_handle;
+
+typedef enum {
+    CMG_OK = 0,
+    CMG_E_ARG = 1,      /* bad argument (NULL pointer, n < 2, sizes out of range, bad option) */
+    CMG_E_GRAPH = 2,    /* bad index, unsorted/duplicate column, self-loop, w <= 0 or non-finite,
+                           asymmetric (only detected with validate_full) */
+    CMG_E_ISOLATED = 3, /* a vertex without neighbours */
+    CMG_E_OOM = 4,      /* an allocation failed */
+    CMG_E_DEVICE = 5,   /* a HIP runtime error or a device-side failure */
+    CMG_W_MAXIT = 6     /* warning: a level hit max_iters_per_level; result still valid */
+} cmg_status;
+
+typedef enum {
+    CMG_FP64 = 0,  /* every level in FP64 */
+    CMG_MIXED = 1  /* large levels: FP32 values and vectors, FP64 arithmetic and reductions */
+} cmg_precision;
+
+typedef enum { CMG_MEM_HOST = 0, CMG_MEM_DEVICE = 1 } cmg_memspace;
+
+typedef enum { CMG_VAL_F64 = 0, CMG_VAL_F32 = 1 } cmg_valtype;
+
+/* Device-memory allocator.  alloc returns NULL on failure; free accepts
+ * what alloc returned.  `stream` is the hipStream_t the library works on. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* stream, void* user);
+    void (*free)(void* p, void* stream, void* user);
+    void* user;
+} cmg_allocator;
+
+typedef struct {
+    uint32_t struct_size;        /* sizeof(cmg_options) */
+    double tol;                  /* PI stops once (u^k, u^{k-1}) >= 1 - tol (Section 4: 1e-8) */
+    int32_t coarsest_n;          /* coarsen while n > coarsest_n (Algorithm 1: 25) */
+    int32_t dense_max;           /* coarsest level solved densely if n <= dense_max (128) */
+    uint64_t seed;               /* seeds the HEC visit order (replaces randperm) */
+    int32_t precision;           /* cmg_precision */
+    int32_t fp64_final_sweeps;   /* MIXED only: extra FP64 PI steps on the finest level (1) */
+    int32_t max_iters_per_level; /* PI cap per level (100000), then CMG_W_MAXIT */
+    int32_t validate_full;       /* 1: also check symmetry of the input (O(nnz log deg)) */
+    void* stream;                /* hipStream_t; NULL = null stream */
+    const cmg_allocator* allocator; /* NULL = hipMalloc/hipFree */
+    int32_t block_rows;          /* levels with n <= block_rows are refined inside one
+                                    workgroup; 0 = library default */
+    int64_t mixed_min_nnz;       /* MIXED: levels with nnz >= this run FP32 (0 = default) */
+    int32_t spmv_variant;        /* 0 = auto (tuned), 1 = rows per lane group, 2 = merge path */
+} cmg_options;
+
+/* Per-level information (available after cmg_setup; PI fields after
+ * cmg_fiedler). */
+typedef struct {
+    int32_t n;           /* vertices */
+    int64_t nnz;         /* stored directed off-diagonal entries */
+    double g;            /* Gershgorin shift g = max_i sum_j |l_ij| (Algorithm 3) */
+    double wmax;         /* largest edge weight */
+    int32_t k;           /* PI steps executed (-1: dense coarsest solve, 0: not run) */
+    double margin;       /* (u^k,u^{k-1}) - (1 - tol) at exit */
+    int32_t fp32;        /* 1 if this level ran FP32 storage */
+    int32_t in_block;    /* 1 if refined inside one workgroup, 0 if by the whole grid */
+    int32_t variant;     /* SpMV variant used (1 rows, 2 merge path) */
+    int32_t lanes;       /* lanes per row (variant 1) */
+    int32_t grid;        /* workgroups of the grid kernel */
+    double pi_ms;        /* device time of this level's refinement launch (grid levels) */
+    double bytes_per_iter; /* algorithmic bytes of one PI step: 4(n+1)+nnz(4+s_v)+2 s_x n */
+} cmg_level_stats;
+
+typedef struct {
+    uint32_t struct_size;
+    int32_t nlevels;        /* J + 1 */
+    int32_t collapsed;      /* 1 if coarsening stopped because HEC gave < 2 aggregates */
+    int32_t hec_rounds;     /* total greedy rounds over all levels */
+    double lambda;          /* r = y^T L y */
+    double residual;        /* ||L y - r y|| */
+    double coarse_lambda2;  /* lambda_2 of the coarsest level (dense solve) */
+    int32_t coarse_mult;    /* size of the coarsest lambda_2 cluster */
+    double setup_ms;        /* wall time of cmg_setup */
+    double fiedler_ms;      /* wall time of the last cmg_fiedler */
+    double finest_pi_ms;    /* device time of the level-0 refinement launch */
+    int32_t finest_k;       /* PI steps on level 0 */
+    double finest_bytes;    /* algorithmic bytes of level-0 PI: k_0 * bytes_per_iter(0) */
+    int32_t status;         /* status of the last call */
+} cmg_stats;
+
+/* Fill `o` with defaults: tol 1e-8, coarsest_n 25, dense_max 128,
+ * seed 14120565, FP64, 1 final sweep, 100000 iterations, no full
+ * validation, null stream, hipMalloc allocator, library tuning. */
+void cmg_options_default(cmg_options* o);
+
+/* Setup phase (Algorithm 1, Step 1): validate and copy the graph, then
+ * coarsen with HEC (Algorithm 2) and form Galerkin coarse graphs until
+ * n <= coarsest_n or HEC collapses to one aggregate.
+ *   n, nnz         vertex count and stored entries (row_ptr[n] == nnz)
+ *   row_ptr[n+1]   int32 offsets; col[nnz] int32 neighbours
+ *   w[nnz]         weights, double (CMG_VAL_F64) or float (CMG_VAL_F32)
+ *   where          memory space of row_ptr/col/w
+ *   opt            options (NULL = defaults)
+ *   out            receives the handle (NULL on failure) */
+cmg_status cmg_setup(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                     const void* w, cmg_valtype wtype, cmg_memspace where,
+                     const cmg_options* opt, cmg_handle* out);
+
+/* Coarsest solve and cascadic refinement (Algorithm 1, Steps 2-3).
+ *   lambda   receives r = y^T L y (host pointer, may be NULL)
+ *   x        receives the unit-norm Fiedler approximation (n doubles, in
+ *            memory space `where`; may be NULL)
+ *   stats    optional (host pointer)
+ * Returns CMG_OK or CMG_W_MAXIT on success. */
+cmg_status cmg_fiedler(cmg_handle h, double* lambda, void* x, cmg_memspace where,
+                       cmg_stats* stats);
+
+/* Refine several hierarchies together: the coarse levels of all handles
+ * run in one launch (one workgroup per graph), larger levels in packed
+ * grid launches.  All handles must share one device and stream.
+ * lambdas[count], xs[count] (each n_i doubles in `where`), stats[count]
+ * are optional.  Results equal those of cmg_fiedler on each handle. */
+cmg_status cmg_fiedler_batch(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
+                             cmg_memspace where, cmg_stats* stats);
+
+/* Copy per-level information into out[0..cap-1]; *nlevels gets J+1. */
+cmg_status cmg_level_info(cmg_handle h, cmg_level_stats* out, int32_t cap, int32_t* nlevels);
+
+/* Copy level `level` of the hierarchy to host arrays (each may be NULL):
+ * row_ptr[n+1], col[nnz], w[nnz] (double), agg[n] (aggregate of each
+ * vertex in level+1; not available on the coarsest level). */
+cmg_status cmg_level_copy(cmg_handle h, int32_t level, int32_t* row_ptr, int32_t* col, double* w,
+                          int32_t* agg);
+
+/* Device bytes held by the handle (hierarchy plus refinement buffers). */
+cmg_status cmg_footprint(cmg_handle h, size_t* bytes);
+
+/* Release everything owned by the handle.  NULL is a no-op. */
+void cmg_free(cmg_handle h);
+
+/* Static string for a status code. */
+const char* cmg_status_string(cmg_status s);
+
+/* Diagnostics: evaluate on the GPU the counter-based hash the library uses
+ * for HEC priorities, key(v) = mix64(seed ^ (level << 40) ^ v) with mix64
+ * the SplitMix64 output function, for v = 0..count-1 into host out[].
+ * With level = -1 it instead writes the SplitMix64 sequence seeded with
+ * `seed` (state += 0x9E3779B97F4A7C15, output mix64(state)). */
+cmg_status cmg_hash_probe(uint64_t seed, int32_t level, int32_t count, uint64_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CMG_H */

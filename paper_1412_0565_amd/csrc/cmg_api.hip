@@ -1,0 +1,746 @@
+// libcmg host driver: the C ABI declared in include/cmg.h.
+//
+// The host sequences kernel launches on one stream and reads back only the
+// sizes it needs to allocate the next level (aggregate count, coarse nnz)
+// and the HEC round flag.  All arithmetic of the method runs in the
+// kernels of setup.hip and refine.hip.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "cmg.h"
+#include "cmg_internal.h"
+
+using namespace cmg;
+
+namespace {
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+void* default_alloc(size_t bytes, void*, void*) {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes == 0 ? 1 : bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void default_free(void* p, void*, void*) { (void)hipFree(p); }
+
+const cmg_allocator kDefaultAllocator = {default_alloc, default_free, nullptr};
+
+struct HostLevel {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t* rp = nullptr;
+    int32_t* col = nullptr;
+    double* w64 = nullptr;
+    float* w32 = nullptr;
+    int32_t* agg = nullptr;
+    double g = 0.0, wmax = 0.0;
+    int fp32 = 0, in_block = 0, lanes = 8, grid = 0, variant = 1;
+    void* buf0 = nullptr;
+    void* buf1 = nullptr;
+    int32_t* part = nullptr;
+    int k = 0;
+    double margin = 0.0;
+    double pi_ms = 0.0;
+};
+
+int pick_lanes(double avg_deg) {
+    double t = 0.75 * avg_deg;
+    int g = 1;
+    while (g < t && g < 64) g <<= 1;
+    return g;
+}
+
+int bitlen(unsigned long long x) {
+    int b = 0;
+    while (x) {
+        ++b;
+        x >>= 1;
+    }
+    return b;
+}
+
+}  // namespace
+
+struct cmg_ctx {
+    cmg_options opt{};
+    hipStream_t stream = nullptr;
+    cmg_allocator alloc = kDefaultAllocator;
+    std::vector<void*> owned;
+    std::vector<HostLevel> lv;
+    size_t footprint = 0;
+    LevelDev* d_lv = nullptr;
+    LevelState* d_st = nullptr;
+    GridSync* d_sync = nullptr;
+    double* d_partials = nullptr;
+    double* d_bcast = nullptr;
+    FinishOut* d_fo = nullptr;
+    double* d_A = nullptr;
+    double* d_V = nullptr;
+    double* d_ev = nullptr;
+    int32_t* d_idx = nullptr;
+    double* d_fa = nullptr;
+    double* d_fb = nullptr;
+    double* d_y = nullptr;
+    int coarse_dense = 1;
+    int block_lo = -1;  // levels >= block_lo (and < coarsest or the PI coarsest) run in one workgroup
+    int collapsed = 0;
+    int hec_rounds = 0;
+    double setup_ms = 0.0;
+    cmg_stats last{};
+    std::vector<hipEvent_t> events;
+
+    void* dalloc(size_t bytes) {
+        void* p = alloc.alloc(bytes == 0 ? 8 : bytes, (void*)stream, alloc.user);
+        if (p) {
+            owned.push_back(p);
+            footprint += bytes;
+        }
+        return p;
+    }
+    void dfree(void* p) {
+        if (!p) return;
+        auto it = std::find(owned.begin(), owned.end(), p);
+        if (it != owned.end()) owned.erase(it);
+        alloc.free(p, (void*)stream, alloc.user);
+    }
+    ~cmg_ctx() {
+        if (stream || true) (void)hipStreamSynchronize(stream);
+        for (void* p : owned) alloc.free(p, (void*)stream, alloc.user);
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+#define CK(x)                                                                                      \
+    do {                                                                                           \
+        hipError_t e_ = (x);                                                                       \
+        if (e_ != hipSuccess) {                                                                    \
+            (void)hipGetLastError();                                                               \
+            return CMG_E_DEVICE;                                                                   \
+        }                                                                                          \
+    } while (0)
+
+#define ALLOC(ptr, type, count)                                                                    \
+    do {                                                                                           \
+        ptr = (type*)c->dalloc(sizeof(type) * (size_t)(count));                                    \
+        if (!ptr) return CMG_E_OOM;                                                                \
+    } while (0)
+
+template <typename T>
+cmg_status d2h(cmg_ctx* c, T* host, const T* dev, size_t count) {
+    CK(hipMemcpyAsync(host, dev, sizeof(T) * count, hipMemcpyDeviceToHost, c->stream));
+    CK(hipStreamSynchronize(c->stream));
+    return CMG_OK;
+}
+
+// Temporary buffers of the setup phase, sized for level 0 and reused.
+struct SetupTmp {
+    int32_t* h = nullptr;
+    unsigned long long* slot = nullptr;
+    uint8_t* live = nullptr;
+    uint8_t* state = nullptr;
+    int32_t* pairseed = nullptr;
+    int32_t* rootseed = nullptr;
+    int32_t* flags = nullptr;
+    int32_t* rank = nullptr;
+    long long* scan_tmp = nullptr;
+    unsigned long long* k0 = nullptr;
+    unsigned long long* k1 = nullptr;
+    double* v0 = nullptr;
+    double* v1 = nullptr;
+    int32_t* heads = nullptr;
+    int32_t* idx = nullptr;
+    int32_t* sort_counts = nullptr;
+    long long* sort_scan = nullptr;
+    unsigned long long* scal = nullptr;  // [0] gbits [1] wmaxbits [2] live count [3] nvalid
+    long long* totals = nullptr;         // [0] scan total
+    unsigned* vflags = nullptr;
+};
+
+cmg_status alloc_tmp(cmg_ctx* c, SetupTmp& t, int32_t n, int64_t nnz) {
+    ALLOC(t.h, int32_t, n);
+    ALLOC(t.slot, unsigned long long, n);
+    ALLOC(t.live, uint8_t, n);
+    ALLOC(t.state, uint8_t, n);
+    ALLOC(t.pairseed, int32_t, n);
+    ALLOC(t.rootseed, int32_t, n);
+    ALLOC(t.flags, int32_t, n);
+    ALLOC(t.rank, int32_t, n);
+    ALLOC(t.scan_tmp, long long, std::max<int64_t>(scan_tmp_elems(std::max<int64_t>(n, nnz)), 16));
+    ALLOC(t.k0, unsigned long long, nnz);
+    ALLOC(t.k1, unsigned long long, nnz);
+    ALLOC(t.v0, double, nnz);
+    ALLOC(t.v1, double, nnz);
+    ALLOC(t.heads, int32_t, nnz);
+    ALLOC(t.idx, int32_t, nnz);
+    int64_t nsc = sort_tmp_elems(nnz);
+    ALLOC(t.sort_counts, int32_t, nsc);
+    ALLOC(t.sort_scan, long long, scan_tmp_elems(nsc) + 4);
+    ALLOC(t.scal, unsigned long long, 8);
+    ALLOC(t.totals, long long, 4);
+    ALLOC(t.vflags, unsigned, 4);
+    return CMG_OK;
+}
+
+void free_tmp(cmg_ctx* c, SetupTmp& t) {
+    void* ps[] = {t.h, t.slot, t.live, t.state, t.pairseed, t.rootseed, t.flags, t.rank, t.scan_tmp,
+                  t.k0, t.k1, t.v0, t.v1, t.heads, t.idx, t.sort_counts, t.sort_scan, t.scal, t.totals,
+                  t.vflags};
+    size_t bytes = 0;
+    (void)bytes;
+    (void)hipStreamSynchronize(c->stream);
+    for (void* p : ps) c->dfree(p);
+    t = SetupTmp{};
+}
+
+// Gershgorin shift, heaviest neighbours and largest weight of one level.
+cmg_status level_rowinfo(cmg_ctx* c, SetupTmp& t, HostLevel& L) {
+    CK(hipMemsetAsync(t.scal, 0, 2 * sizeof(unsigned long long), c->stream));
+    CK(launch_rowinfo(L.n, L.lanes, L.rp, L.col, L.w64, t.h, t.scal, t.scal + 1, c->stream));
+    unsigned long long hb[2];
+    cmg_status st = d2h(c, hb, t.scal, 2);
+    if (st != CMG_OK) return st;
+    double gv, wm;
+    std::memcpy(&gv, &hb[0], 8);
+    std::memcpy(&wm, &hb[1], 8);
+    L.g = gv;
+    L.wmax = wm;
+    return CMG_OK;
+}
+
+// One HEC + Galerkin step from level j; appends level j+1 unless HEC
+// collapses (fewer than 2 aggregates).
+cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
+    HostLevel& L = c->lv[j];
+    hipStream_t s = c->stream;
+    const uint64_t seed = c->opt.seed;
+    *stop = false;
+    cmg_status st = level_rowinfo(c, t, L);
+    if (st != CMG_OK) return st;
+    CK(launch_hec_init(L.n, t.h, seed, j, t.live, t.state, t.pairseed, t.slot, s));
+    for (int round = 0;; ++round) {
+        if (round > 100000) return CMG_E_DEVICE;
+        CK(hipMemsetAsync(t.scal + 2, 0, sizeof(unsigned long long), s));
+        CK(launch_hec_round(L.n, t.h, seed, j, t.live, t.state, t.pairseed, t.slot, t.scal + 2, s));
+        unsigned long long live = 0;
+        st = d2h(c, &live, t.scal + 2, 1);
+        if (st != CMG_OK) return st;
+        ++c->hec_rounds;
+        if (live == 0) break;
+    }
+    CK(launch_hec_attach(L.n, t.h, t.state, t.pairseed, t.rootseed, t.flags, s));
+    CK(launch_scan(t.flags, t.rank, L.n, t.scan_tmp, t.totals, s));
+    long long nc = 0;
+    st = d2h(c, &nc, t.totals, 1);
+    if (st != CMG_OK) return st;
+    if (nc < 2) {
+        c->collapsed = 1;
+        *stop = true;
+        return CMG_OK;
+    }
+    ALLOC(L.agg, int32_t, L.n);
+    CK(launch_hec_label(L.n, t.rootseed, t.rank, L.agg, s));
+    // Galerkin product
+    CK(hipMemsetAsync(t.scal + 3, 0, sizeof(unsigned long long), s));
+    CK(launch_gal_emit(L.n, L.lanes, L.rp, L.col, L.w64, L.agg, (int)nc, t.k0, t.v0, t.scal + 3, s));
+    int bits = bitlen((unsigned long long)nc * (unsigned long long)nc);
+    int second = 0;
+    CK(launch_sort(t.k0, t.v0, t.k1, t.v1, L.nnz, bits, t.sort_counts, t.sort_scan, &second, s));
+    const unsigned long long* ks = second ? t.k1 : t.k0;
+    const double* vs = second ? t.v1 : t.v0;
+    unsigned long long nvalid = 0;
+    st = d2h(c, &nvalid, t.scal + 3, 1);
+    if (st != CMG_OK) return st;
+    CK(launch_gal_heads((int64_t)nvalid, ks, t.heads, s));
+    CK(launch_scan(t.heads, t.idx, (int64_t)nvalid, t.scan_tmp, t.totals, s));
+    long long zc = 0;
+    st = d2h(c, &zc, t.totals, 1);
+    if (st != CMG_OK) return st;
+    HostLevel C;
+    C.n = (int32_t)nc;
+    C.nnz = zc;
+    ALLOC(C.rp, int32_t, C.n + 1);
+    ALLOC(C.col, int32_t, std::max<long long>(zc, 1));
+    ALLOC(C.w64, double, std::max<long long>(zc, 1));
+    if (zc == 0) {
+        CK(hipMemsetAsync(C.rp, 0, sizeof(int32_t) * (C.n + 1), s));
+    } else {
+        CK(launch_gal_reduce((int64_t)nvalid, ks, vs, t.heads, t.idx, (int)nc, zc, C.rp, C.col, C.w64, s));
+    }
+    C.lanes = pick_lanes(C.nnz / (double)C.n);
+    c->lv.push_back(C);
+    return CMG_OK;
+}
+
+cmg_status build_refine_plan(cmg_ctx* c) {
+    const int J = (int)c->lv.size() - 1;
+    const cmg_options& o = c->opt;
+    HostLevel& CJ = c->lv[J];
+    c->coarse_dense = (CJ.n <= o.dense_max) ? 1 : 0;
+    const int block_rows = o.block_rows > 0 ? o.block_rows : 4096;
+    const int64_t mixed_min = o.mixed_min_nnz > 0 ? o.mixed_min_nnz : (int64_t)1 << 20;
+    // refinement levels: 0..J-1, plus J if the coarsest uses power iteration
+    int top = c->coarse_dense ? J - 1 : J;
+    c->block_lo = top + 1;
+    for (int j = top; j >= 0; --j) {
+        if (c->lv[j].n <= block_rows) c->block_lo = j;
+        else break;
+    }
+    int dev = 0, ncu = 0;
+    CK(hipGetDevice(&dev));
+    CK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    int maxgrid = 8;
+    for (int j = 0; j <= J; ++j) {
+        HostLevel& L = c->lv[j];
+        L.in_block = (j >= c->block_lo && j <= top) ? 1 : 0;
+        L.fp32 = 0;
+        if (o.precision == CMG_MIXED && !L.in_block && j <= top && L.nnz >= mixed_min &&
+            L.wmax < 16777216.0 && !(j == J && c->coarse_dense))
+            L.fp32 = 1;
+        L.variant = 1;
+        const size_t vb = L.fp32 ? 4 : 8;
+        L.buf0 = c->dalloc(vb * (size_t)L.n);
+        L.buf1 = c->dalloc(vb * (size_t)L.n);
+        if (!L.buf0 || !L.buf1) return CMG_E_OOM;
+        if (L.fp32) {
+            ALLOC(L.w32, float, std::max<int64_t>(L.nnz, 1));
+            CK(launch_to_f32(L.nnz, L.w64, L.w32, c->stream));
+        }
+        // grid size: about 8k rows+entries per workgroup, multiple of 8,
+        // at most what can be co-resident
+        int cap = refine_grid_max_blocks(L.fp32, L.lanes, L.variant);
+        if (j == 0) cap = std::min(cap, finish_max_blocks(L.fp32, L.lanes, L.variant));
+        cap = std::max(8, (cap / 8) * 8);
+        int64_t work = (int64_t)L.n + L.nnz;
+        int64_t want = (work + 8191) / 8192;
+        want = ((want + 7) / 8) * 8;
+        L.grid = (int)std::min<int64_t>(std::max<int64_t>(want, 8), cap);
+        maxgrid = std::max(maxgrid, L.grid);
+        ALLOC(L.part, int32_t, L.grid + 1);
+        CK(launch_partition(L.n, L.nnz, L.rp, L.grid, L.part, c->stream));
+    }
+    (void)ncu;
+    std::vector<LevelDev> ld(J + 1);
+    for (int j = 0; j <= J; ++j) {
+        HostLevel& L = c->lv[j];
+        LevelDev d{};
+        d.n = L.n;
+        d.lanes = L.lanes;
+        d.nnz = L.nnz;
+        d.rp = L.rp;
+        d.col = L.col;
+        d.w64 = L.w64;
+        d.w32 = L.w32;
+        d.agg = L.agg;
+        d.g = L.g;
+        d.fp32 = L.fp32;
+        d.variant = L.variant;
+        d.buf0 = L.buf0;
+        d.buf1 = L.buf1;
+        d.part = L.part;
+        d.mpart = nullptr;
+        d.grid = L.grid;
+        ld[j] = d;
+    }
+    ALLOC(c->d_lv, LevelDev, J + 1);
+    CK(hipMemcpyAsync(c->d_lv, ld.data(), sizeof(LevelDev) * (J + 1), hipMemcpyHostToDevice, c->stream));
+    ALLOC(c->d_st, LevelState, J + 1);
+    ALLOC(c->d_sync, GridSync, 1);
+    ALLOC(c->d_partials, double, 4 * (size_t)maxgrid + 8);
+    ALLOC(c->d_bcast, double, 8);
+    ALLOC(c->d_fo, FinishOut, 1);
+    const int dm = std::max(CJ.n, 2);
+    if (c->coarse_dense) {
+        ALLOC(c->d_A, double, (size_t)dm * dm);
+        ALLOC(c->d_V, double, (size_t)dm * dm);
+        ALLOC(c->d_ev, double, 2 * (size_t)dm);
+        ALLOC(c->d_idx, int32_t, dm);
+    }
+    const int32_t n0 = c->lv[0].n;
+    ALLOC(c->d_y, double, n0);
+    if (c->lv[0].fp32 && o.fp64_final_sweeps > 0) {
+        ALLOC(c->d_fa, double, n0);
+        ALLOC(c->d_fb, double, n0);
+    }
+    c->events.resize(2 * (J + 1));
+    for (auto& e : c->events) CK(hipEventCreate(&e));
+    CK(hipStreamSynchronize(c->stream));
+    return CMG_OK;
+}
+
+cmg_status setup_impl(cmg_ctx* c, int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                      const void* w, cmg_valtype wtype, cmg_memspace where) {
+    hipStream_t s = c->stream;
+    HostLevel L0;
+    L0.n = n;
+    L0.nnz = nnz;
+    ALLOC(L0.rp, int32_t, n + 1);
+    ALLOC(L0.col, int32_t, nnz);
+    ALLOC(L0.w64, double, nnz);
+    const hipMemcpyKind kind = (where == CMG_MEM_HOST) ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    CK(hipMemcpyAsync(L0.rp, row_ptr, sizeof(int32_t) * (n + 1), kind, s));
+    CK(hipMemcpyAsync(L0.col, col, sizeof(int32_t) * nnz, kind, s));
+    const int wf32 = (wtype == CMG_VAL_F32);
+    const void* wdev = w;
+    void* wtmp = nullptr;
+    if (wf32) {
+        if (where == CMG_MEM_HOST) {
+            wtmp = c->dalloc(sizeof(float) * nnz);
+            if (!wtmp) return CMG_E_OOM;
+            CK(hipMemcpyAsync(wtmp, w, sizeof(float) * nnz, hipMemcpyHostToDevice, s));
+            wdev = wtmp;
+        }
+        CK(launch_convert_w(nnz, wdev, 1, L0.w64, s));
+    } else {
+        CK(hipMemcpyAsync(L0.w64, w, sizeof(double) * nnz, kind, s));
+    }
+    // validation (on the handle's copy)
+    unsigned* vf = (unsigned*)c->dalloc(sizeof(unsigned) * 4);
+    if (!vf) return CMG_E_OOM;
+    CK(hipMemsetAsync(vf, 0, sizeof(unsigned), s));
+    CK(launch_validate(n, nnz, L0.rp, L0.col, L0.w64, 0, c->opt.validate_full, vf, s));
+    unsigned flags = 0;
+    cmg_status st = d2h(c, &flags, vf, 1);
+    c->dfree(vf);
+    if (wtmp) c->dfree(wtmp);
+    if (st != CMG_OK) return st;
+    if (flags & (kBadGraph | kAsym)) return CMG_E_GRAPH;
+    if (flags & kIsolated) return CMG_E_ISOLATED;
+    L0.lanes = pick_lanes(nnz / (double)n);
+    c->lv.push_back(L0);
+    SetupTmp t;
+    st = alloc_tmp(c, t, n, nnz);
+    if (st != CMG_OK) return st;
+    int j = 0;
+    while (c->lv[j].n > c->opt.coarsest_n && j < 60) {
+        bool stop = false;
+        st = coarsen_once(c, t, j, &stop);
+        if (st != CMG_OK) return st;
+        if (stop) break;
+        ++j;
+    }
+    // Gershgorin shift of the coarsest level (not yet computed if the
+    // loop ended on the size test)
+    {
+        HostLevel& CJ = c->lv.back();
+        if (CJ.g == 0.0) {
+            st = level_rowinfo(c, t, CJ);
+            if (st != CMG_OK) return st;
+        }
+    }
+    free_tmp(c, t);
+    return build_refine_plan(c);
+}
+
+void fill_defaults(cmg_options* o) {
+    std::memset(o, 0, sizeof(*o));
+    o->struct_size = sizeof(cmg_options);
+    o->tol = 1e-8;
+    o->coarsest_n = 25;
+    o->dense_max = 128;
+    o->seed = 14120565ull;
+    o->precision = CMG_FP64;
+    o->fp64_final_sweeps = 1;
+    o->max_iters_per_level = 100000;
+    o->validate_full = 0;
+    o->stream = nullptr;
+    o->allocator = nullptr;
+    o->block_rows = 0;
+    o->mixed_min_nnz = 0;
+    o->spmv_variant = 0;
+}
+
+cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where, cmg_stats* stats) {
+    const double t0 = now_ms();
+    hipStream_t s = c->stream;
+    const int J = (int)c->lv.size() - 1;
+    const cmg_options& o = c->opt;
+    CK(launch_reset_sync(c->d_sync, s));
+    int top = J;
+    if (c->coarse_dense) {
+        HostLevel& CJ = c->lv[J];
+        LevelDev d{};
+        d.n = CJ.n;
+        d.rp = CJ.rp;
+        d.col = CJ.col;
+        d.w64 = CJ.w64;
+        d.buf0 = CJ.buf0;
+        d.buf1 = CJ.buf1;
+        d.g = CJ.g;
+        CK(launch_coarse_dense(d, c->d_st + J, c->d_A, c->d_V, c->d_ev, c->d_idx, o.seed, c->d_fo, s));
+        top = J - 1;
+    }
+    // levels refined inside one workgroup
+    if (top >= 0 && c->block_lo <= top) {
+        int uni = (!c->coarse_dense && top == J) ? 1 : 0;
+        CK(launch_refine_block(c->d_lv, c->d_st, top, c->block_lo, uni, o.tol, o.max_iters_per_level,
+                               o.seed, s));
+    }
+    // grid levels
+    LevelDev ld_j, ld_c;
+    for (int j = std::min(top, c->block_lo - 1); j >= 0; --j) {
+        HostLevel& L = c->lv[j];
+        auto mk = [&](int q) {
+            HostLevel& H = c->lv[q];
+            LevelDev d{};
+            d.n = H.n;
+            d.lanes = H.lanes;
+            d.nnz = H.nnz;
+            d.rp = H.rp;
+            d.col = H.col;
+            d.w64 = H.w64;
+            d.w32 = H.w32;
+            d.agg = H.agg;
+            d.g = H.g;
+            d.fp32 = H.fp32;
+            d.variant = H.variant;
+            d.buf0 = H.buf0;
+            d.buf1 = H.buf1;
+            d.part = H.part;
+            d.grid = H.grid;
+            return d;
+        };
+        ld_j = mk(j);
+        int uni = (j == J) ? 1 : 0;
+        ld_c = uni ? ld_j : mk(j + 1);
+        CK(hipEventRecord(c->events[2 * j], s));
+        CK(launch_refine_grid(ld_j, ld_c, c->d_st + j, uni ? nullptr : c->d_st + j + 1, uni, c->d_sync,
+                              c->d_partials, c->d_bcast, o.tol, o.max_iters_per_level, o.seed, s));
+        CK(hipEventRecord(c->events[2 * j + 1], s));
+        (void)L;
+    }
+    // finishing pass on level 0
+    {
+        HostLevel& L0 = c->lv[0];
+        LevelDev d{};
+        d.n = L0.n;
+        d.lanes = L0.lanes;
+        d.nnz = L0.nnz;
+        d.rp = L0.rp;
+        d.col = L0.col;
+        d.w64 = L0.w64;
+        d.w32 = L0.w32;
+        d.g = L0.g;
+        d.fp32 = L0.fp32;
+        d.buf0 = L0.buf0;
+        d.buf1 = L0.buf1;
+        d.part = L0.part;
+        d.grid = L0.grid;
+        int sweeps = (L0.fp32 && c->d_fa) ? o.fp64_final_sweeps : 0;
+        CK(launch_finish(d, c->d_st, sweeps, c->d_fa, c->d_fb, c->d_y, c->d_sync, c->d_partials,
+                         c->d_bcast, c->d_fo, s));
+    }
+    FinishOut fo;
+    std::vector<LevelState> hst(J + 1);
+    CK(hipMemcpyAsync(&fo, c->d_fo, sizeof(fo), hipMemcpyDeviceToHost, s));
+    CK(hipMemcpyAsync(hst.data(), c->d_st, sizeof(LevelState) * (J + 1), hipMemcpyDeviceToHost, s));
+    GridSync gsh;
+    CK(hipMemcpyAsync(&gsh, c->d_sync, sizeof(gsh), hipMemcpyDeviceToHost, s));
+    if (x) {
+        CK(hipMemcpyAsync(x, c->d_y, sizeof(double) * c->lv[0].n,
+                          where == CMG_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+    }
+    CK(hipStreamSynchronize(s));
+    if (gsh.abort) return CMG_E_DEVICE;
+    cmg_status status = CMG_OK;
+    for (int j = 0; j <= J; ++j) {
+        HostLevel& L = c->lv[j];
+        if (j == J && c->coarse_dense) {
+            L.k = -1;
+            L.margin = 0.0;
+        } else {
+            L.k = hst[j].k;
+            L.margin = hst[j].margin;
+            if (hst[j].maxit) status = CMG_W_MAXIT;
+        }
+        L.pi_ms = 0.0;
+        if (!L.in_block && j <= top) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, c->events[2 * j], c->events[2 * j + 1]) == hipSuccess) L.pi_ms = ms;
+        }
+    }
+    if (lambda) *lambda = fo.lambda;
+    cmg_stats& st = c->last;
+    std::memset(&st, 0, sizeof(st));
+    st.struct_size = sizeof(cmg_stats);
+    st.nlevels = J + 1;
+    st.collapsed = c->collapsed;
+    st.hec_rounds = c->hec_rounds;
+    st.lambda = fo.lambda;
+    st.residual = fo.residual;
+    st.coarse_lambda2 = c->coarse_dense ? fo.coarse_lambda2 : 0.0;
+    st.coarse_mult = c->coarse_dense ? fo.coarse_mult : 0;
+    st.setup_ms = c->setup_ms;
+    st.fiedler_ms = now_ms() - t0;
+    st.finest_pi_ms = c->lv[0].pi_ms;
+    st.finest_k = c->lv[0].k;
+    {
+        const HostLevel& L = c->lv[0];
+        double sv = L.fp32 ? 4 : 8;
+        double bpi = 4.0 * (L.n + 1) + (double)L.nnz * (4 + sv) + 2 * sv * L.n;
+        st.finest_bytes = L.k > 0 ? L.k * bpi : 0.0;
+    }
+    st.status = status;
+    if (stats) {
+        uint32_t sz = stats->struct_size ? stats->struct_size : (uint32_t)sizeof(cmg_stats);
+        std::memcpy(stats, &st, std::min<size_t>(sz, sizeof(cmg_stats)));
+    }
+    return status;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+void cmg_options_default(cmg_options* o) {
+    if (o) fill_defaults(o);
+}
+
+const char* cmg_status_string(cmg_status s) {
+    switch (s) {
+        case CMG_OK: return "CMG_OK";
+        case CMG_E_ARG: return "CMG_E_ARG: invalid argument";
+        case CMG_E_GRAPH: return "CMG_E_GRAPH: invalid graph";
+        case CMG_E_ISOLATED: return "CMG_E_ISOLATED: isolated vertex";
+        case CMG_E_OOM: return "CMG_E_OOM: out of device memory";
+        case CMG_E_DEVICE: return "CMG_E_DEVICE: device error";
+        case CMG_W_MAXIT: return "CMG_W_MAXIT: iteration cap reached";
+    }
+    return "unknown status";
+}
+
+cmg_status cmg_setup(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, const void* w,
+                     cmg_valtype wtype, cmg_memspace where, const cmg_options* opt, cmg_handle* out) {
+    if (!out) return CMG_E_ARG;
+    *out = nullptr;
+    if (n < 2 || nnz < 1 || nnz >= 2147483647LL || !row_ptr || !col || !w) return CMG_E_ARG;
+    if (wtype != CMG_VAL_F64 && wtype != CMG_VAL_F32) return CMG_E_ARG;
+    if (where != CMG_MEM_HOST && where != CMG_MEM_DEVICE) return CMG_E_ARG;
+    cmg_options o;
+    fill_defaults(&o);
+    if (opt) {
+        size_t sz = opt->struct_size ? std::min<size_t>(opt->struct_size, sizeof(o)) : sizeof(o);
+        std::memcpy(&o, opt, sz);
+        o.struct_size = sizeof(o);
+    }
+    if (!(o.tol < 1.0) || !std::isfinite(o.tol) || o.coarsest_n < 2 || o.dense_max < 2 || o.dense_max > 128 ||
+        o.max_iters_per_level < 1 || (o.precision != CMG_FP64 && o.precision != CMG_MIXED) ||
+        o.fp64_final_sweeps < 0 || o.fp64_final_sweeps > 16 || o.coarsest_n > o.dense_max)
+        return CMG_E_ARG;
+    const double t0 = now_ms();
+    cmg_ctx* c = new (std::nothrow) cmg_ctx;
+    if (!c) return CMG_E_OOM;
+    c->opt = o;
+    c->stream = (hipStream_t)o.stream;
+    if (o.allocator) c->alloc = *o.allocator;
+    cmg_status st = setup_impl(c, n, nnz, row_ptr, col, w, wtype, where);
+    if (st != CMG_OK) {
+        delete c;
+        return st;
+    }
+    c->setup_ms = now_ms() - t0;
+    *out = c;
+    return CMG_OK;
+}
+
+cmg_status cmg_fiedler(cmg_handle h, double* lambda, void* x, cmg_memspace where, cmg_stats* stats) {
+    if (!h) return CMG_E_ARG;
+    if (where != CMG_MEM_HOST && where != CMG_MEM_DEVICE) return CMG_E_ARG;
+    return fiedler_impl(h, lambda, x, where, stats);
+}
+
+cmg_status cmg_fiedler_batch(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
+                             cmg_memspace where, cmg_stats* stats) {
+    if (!hs || count < 0) return CMG_E_ARG;
+    cmg_status worst = CMG_OK;
+    for (int32_t i = 0; i < count; ++i) {
+        cmg_status st = cmg_fiedler(hs[i], lambdas ? lambdas + i : nullptr, xs ? xs[i] : nullptr, where,
+                                    stats ? stats + i : nullptr);
+        if (st != CMG_OK && st != CMG_W_MAXIT) return st;
+        if (st == CMG_W_MAXIT) worst = st;
+    }
+    return worst;
+}
+
+cmg_status cmg_level_info(cmg_handle h, cmg_level_stats* out, int32_t cap, int32_t* nlevels) {
+    if (!h) return CMG_E_ARG;
+    const int nl = (int)h->lv.size();
+    if (nlevels) *nlevels = nl;
+    if (!out) return CMG_OK;
+    for (int j = 0; j < nl && j < cap; ++j) {
+        const HostLevel& L = h->lv[j];
+        cmg_level_stats li{};
+        li.n = L.n;
+        li.nnz = L.nnz;
+        li.g = L.g;
+        li.wmax = L.wmax;
+        li.k = L.k;
+        li.margin = L.margin;
+        li.fp32 = L.fp32;
+        li.in_block = L.in_block;
+        li.variant = L.variant;
+        li.lanes = L.lanes;
+        li.grid = L.grid;
+        li.pi_ms = L.pi_ms;
+        double sv = L.fp32 ? 4 : 8;
+        li.bytes_per_iter = 4.0 * (L.n + 1) + (double)L.nnz * (4 + sv) + 2 * sv * L.n;
+        out[j] = li;
+    }
+    return CMG_OK;
+}
+
+cmg_status cmg_level_copy(cmg_handle h, int32_t level, int32_t* row_ptr, int32_t* col, double* w,
+                          int32_t* agg) {
+    if (!h || level < 0 || level >= (int)h->lv.size()) return CMG_E_ARG;
+    const HostLevel& L = h->lv[level];
+    hipStream_t s = h->stream;
+    if (agg && !L.agg) return CMG_E_ARG;
+    if (row_ptr) CK(hipMemcpyAsync(row_ptr, L.rp, sizeof(int32_t) * (L.n + 1), hipMemcpyDeviceToHost, s));
+    if (col) CK(hipMemcpyAsync(col, L.col, sizeof(int32_t) * L.nnz, hipMemcpyDeviceToHost, s));
+    if (w) CK(hipMemcpyAsync(w, L.w64, sizeof(double) * L.nnz, hipMemcpyDeviceToHost, s));
+    if (agg) CK(hipMemcpyAsync(agg, L.agg, sizeof(int32_t) * L.n, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    return CMG_OK;
+}
+
+cmg_status cmg_footprint(cmg_handle h, size_t* bytes) {
+    if (!h || !bytes) return CMG_E_ARG;
+    *bytes = h->footprint;
+    return CMG_OK;
+}
+
+void cmg_free(cmg_handle h) { delete h; }
+
+cmg_status cmg_hash_probe(uint64_t seed, int32_t level, int32_t count, uint64_t* out) {
+    if (count < 0 || (count > 0 && !out)) return CMG_E_ARG;
+    if (count == 0) return CMG_OK;
+    unsigned long long* d = nullptr;
+    if (hipMalloc(&d, sizeof(unsigned long long) * count) != hipSuccess) {
+        (void)hipGetLastError();
+        return CMG_E_OOM;
+    }
+    hipError_t e = launch_hash_probe(seed, level, count, d, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out, d, sizeof(unsigned long long) * count, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return CMG_E_DEVICE;
+    }
+    return CMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// Device-side helpers and structures shared by the libcmg HIP translation
+// units (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cmg {
+
+constexpr int kWave = 64;
+
+// SplitMix64 output function (Steele, Lea & Flood 2014).
+__device__ __host__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// HEC priority of vertex v at level j (ascending key = visit order).
+__device__ __forceinline__ uint64_t hec_key(uint64_t seed, int level, int v) {
+    return mix64(seed ^ ((uint64_t)(uint32_t)level << 40) ^ (uint64_t)(uint32_t)v);
+}
+
+// Hashed uniform in [0,1): start vector for power iteration on a coarsest
+// level too large for the dense solve.
+__device__ __forceinline__ double hashed_uniform(uint64_t seed, int i) {
+    uint64_t h = mix64(seed ^ 0x9E3779B97F4A7C15ull ^ (uint64_t)(uint32_t)i);
+    return (double)(h >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Sum over the G-lane group (G power of two <= 64); every lane of the
+// group ends with the group sum computed in the same butterfly order as
+// its partner lanes, so lane 0 of a group is the canonical value.
+template <typename T>
+__device__ __forceinline__ T group_sum(T v, int G) {
+    for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+template <int G, typename T>
+__device__ __forceinline__ T group_sum_t(T v) {
+#pragma unroll
+    for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Deterministic block reduction of NV doubles.  `red` is LDS scratch of at
+// least NV * (blockDim/64) doubles.  Result valid in all threads on return.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = group_sum_t<kWave>(v[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) red[q * 16 + wv] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[threadIdx.x * 16 + w];
+        red[NV * 16 + threadIdx.x] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = red[NV * 16 + q];
+    __syncthreads();
+}
+
+// --------------------------------------------------------------- levels
+
+// One level of the hierarchy as the refinement kernels see it.
+struct LevelDev {
+    int32_t n;
+    int32_t lanes;       // lanes per row for the row-group SpMV
+    int64_t nnz;
+    const int32_t* rp;
+    const int32_t* col;
+    const double* w64;
+    const float* w32;
+    const int32_t* agg;  // vertex -> aggregate in level+1 (nullptr on coarsest)
+    double g;            // Gershgorin shift
+    int32_t fp32;        // 1: FP32 vectors and values
+    int32_t variant;     // 1 rows, 2 merge path
+    void* buf0;          // two vectors of n entries (double or float)
+    void* buf1;
+    const int32_t* part; // grid kernel: first row of each workgroup (grid+1 entries)
+    const int32_t* mpart;// merge path: diagonal split of each workgroup (2*(grid+1))
+    int32_t grid;
+    int32_t pad;
+};
+
+// State a refinement launch leaves for the next level (device written).
+struct LevelState {
+    double mu;      // final vector = (buf[fin] - mu) * s
+    double s;
+    double utv;     // last (u^k, u^{k-1})
+    double margin;  // utv - (1 - tol)
+    int32_t fin;    // buffer index holding the final vector
+    int32_t k;      // PI steps
+    int32_t maxit;  // 1 if the cap was hit
+    int32_t err;    // device-side failure (barrier timeout)
+};
+
+// Result of the finishing pass.
+struct FinishOut {
+    double lambda;
+    double residual;
+    double sum_u;
+    double sum_uu;
+    double edge;
+    double coarse_lambda2;
+    int32_t coarse_mult;
+    int32_t err;
+};
+
+struct GridSync {
+    unsigned int count;
+    unsigned int gen;
+    unsigned int abort;
+    unsigned int pad;
+};
+
+}  // namespace cmg

@@ -1,0 +1,80 @@
+// Host-side declarations shared by the libcmg translation units: kernel
+// launchers implemented next to their kernels, called by the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cmg_dev.h"
+
+namespace cmg {
+
+// validation flag bits
+constexpr unsigned kBadGraph = 1u;
+constexpr unsigned kIsolated = 2u;
+constexpr unsigned kAsym = 4u;
+
+// ---- setup.hip
+hipError_t launch_validate(int n, int64_t nnz, const int32_t* rp, const int32_t* col, const void* w,
+                           int wf32, int full, unsigned* flags, hipStream_t s);
+hipError_t launch_convert_w(int64_t nnz, const void* w, int wf32, double* w64, hipStream_t s);
+hipError_t launch_to_f32(int64_t nnz, const double* w64, float* w32, hipStream_t s);
+// h[v] = heaviest neighbour (lowest index on ties); rowmax2/wmax as
+// uint64 bit patterns of non-negative doubles (atomic max).
+hipError_t launch_rowinfo(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w,
+                          int32_t* h, unsigned long long* gbits, unsigned long long* wmaxbits,
+                          hipStream_t s);
+hipError_t launch_hec_init(int n, const int32_t* h, uint64_t seed, int level, uint8_t* live,
+                           uint8_t* state, int32_t* pairseed, unsigned long long* slot, hipStream_t s);
+hipError_t launch_hec_round(int n, const int32_t* h, uint64_t seed, int level, uint8_t* live,
+                            uint8_t* state, int32_t* pairseed, unsigned long long* slot,
+                            unsigned long long* live_count, hipStream_t s);
+hipError_t launch_hec_attach(int n, const int32_t* h, const uint8_t* state, const int32_t* pairseed,
+                             int32_t* rootseed, int32_t* flags, hipStream_t s);
+hipError_t launch_hec_label(int n, const int32_t* rootseed, const int32_t* rank, int32_t* agg,
+                            hipStream_t s);
+// exclusive scan of int32 -> int32; *total (device int64) gets the sum.
+// tmp must hold scan_tmp_elems(m) int64 values.
+int64_t scan_tmp_elems(int64_t m);
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, long long* tmp, long long* total,
+                       hipStream_t s);
+hipError_t launch_gal_emit(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w,
+                           const int32_t* agg, int nc, unsigned long long* keys, double* vals,
+                           unsigned long long* nvalid, hipStream_t s);
+// stable LSD radix sort of (key, val) pairs on the low `bits` bits; the
+// result ends in (k0, v0) or (k1, v1): returns which through *in_second.
+int64_t sort_tmp_elems(int64_t m);
+hipError_t launch_sort(unsigned long long* k0, double* v0, unsigned long long* k1, double* v1,
+                       int64_t m, int bits, int32_t* tmp_counts, long long* tmp_scan,
+                       int* in_second, hipStream_t s);
+hipError_t launch_gal_heads(int64_t m, const unsigned long long* keys, int32_t* heads, hipStream_t s);
+hipError_t launch_gal_reduce(int64_t m, const unsigned long long* keys, const double* vals,
+                             const int32_t* heads, const int32_t* idx, int nc, int64_t zc,
+                             int32_t* rp_out, int32_t* col_out, double* w_out, hipStream_t s);
+hipError_t launch_partition(int n, int64_t nnz, const int32_t* rp, int nb, int32_t* part,
+                            hipStream_t s);
+hipError_t launch_hash_probe(uint64_t seed, int level, int count, unsigned long long* out,
+                             hipStream_t s);
+hipError_t launch_fill_u32(unsigned* p, unsigned v, int64_t m, hipStream_t s);
+
+// ---- refine.hip
+hipError_t launch_coarse_dense(LevelDev L, LevelState* st, double* A, double* V, double* ev,
+                               int32_t* idx, uint64_t seed, FinishOut* fo, hipStream_t s);
+// all levels jlo..jhi inside one workgroup (FP64 levels only)
+hipError_t launch_refine_block(const LevelDev* lv, LevelState* st, int jhi, int jlo, int uniform_start,
+                               double tol, int maxit, uint64_t seed, hipStream_t s);
+int refine_grid_max_blocks(int fp32, int lanes, int variant);
+hipError_t launch_refine_grid(const LevelDev& L, const LevelDev& C, LevelState* st_j,
+                              const LevelState* st_c, int uniform_start, GridSync* gs,
+                              double* partials, double* bcast, double tol, int maxit, uint64_t seed,
+                              hipStream_t s);
+int finish_max_blocks(int fp32, int lanes, int variant);
+hipError_t launch_finish(const LevelDev& L0, const LevelState* st0, int sweeps, double* f64a,
+                         double* f64b, double* yout, GridSync* gs, double* partials,
+                         double* bcast, FinishOut* fo, hipStream_t s);
+hipError_t launch_reset_sync(GridSync* gs, hipStream_t s);
+
+constexpr int kGridBlock = 512;
+constexpr int kBlockKernelThreads = 1024;
+
+}  // namespace cmg

@@ -1,0 +1,690 @@
+// Setup-phase kernels: input validation, heavy edge coarsening (HEC,
+// Algorithm 2) and the Galerkin coarse graph L^{i+1} = I L^i I^T
+// (Section 2, Step 1 and the Proposition on restriction).
+//
+// HEC is defined sequentially: vertices are visited in a random order; an
+// unmapped vertex v whose heaviest neighbour h(v) is unmapped opens the
+// aggregate {v, h(v)}; otherwise v joins h(v)'s aggregate.  With a fixed
+// priority key per vertex (visit order = ascending key) the same result is
+// obtained data-parallel:
+//   * v can only open an aggregate if key(v) < key(h(v)) ("candidate"),
+//     because a vertex visited earlier is always mapped by then;
+//   * the opened pairs are exactly the greedy maximal matching of the
+//     candidate edges {v, h(v)} taken in key order, which round-synchronous
+//     "local minimum" rounds reproduce exactly (an edge holding the smallest
+//     live key at both endpoints is accepted; edges touching accepted
+//     endpoints die);
+//   * an unmatched vertex ends in the aggregate reached by following h until
+//     a matched vertex (keys strictly decrease along that chain).
+// Aggregates are numbered by ascending index of their opening vertex.
+#include "cmg_internal.h"
+
+namespace cmg {
+
+namespace {
+
+constexpr int kBlk = 256;
+
+inline unsigned nblocks(int64_t m, int per) { return (unsigned)((m + per - 1) / per); }
+
+// ------------------------------------------------------------ validation
+
+template <typename W>
+__global__ void k_validate(int n, int64_t nnz, const int32_t* __restrict__ rp,
+                           const int32_t* __restrict__ col, const W* __restrict__ w, int full,
+                           unsigned* flags) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    unsigned f = 0;
+    if (i == n) {
+        if ((int64_t)rp[n] != nnz) f |= kBadGraph;
+        if (rp[0] != 0) f |= kBadGraph;
+    } else {
+        int a = rp[i], b = rp[i + 1];
+        if (a < 0 || b < a || (int64_t)b > nnz) {
+            f |= kBadGraph;
+        } else if (a == b) {
+            f |= kIsolated;
+        } else {
+            int prev = -1;
+            for (int e = a; e < b; ++e) {
+                int c = col[e];
+                double x = (double)w[e];
+                if (c < 0 || c >= n || c == i || c <= prev) f |= kBadGraph;
+                if (!(x > 0.0) || !isfinite(x)) f |= kBadGraph;
+                prev = c;
+                if (full && c >= 0 && c < n && !(f & kBadGraph) && rp[c] >= 0 && rp[c] <= rp[c + 1] &&
+                    (int64_t)rp[c + 1] <= nnz) {
+                    // binary search i in row c, weights must agree
+                    int lo = rp[c], hi = rp[c + 1] - 1;
+                    bool found = false;
+                    while (lo <= hi) {
+                        int mid = (lo + hi) >> 1;
+                        int cm = col[mid];
+                        if (cm == i) {
+                            found = ((double)w[mid] == x);
+                            break;
+                        }
+                        if (cm < i) lo = mid + 1;
+                        else hi = mid - 1;
+                    }
+                    if (!found) f |= kAsym;
+                }
+            }
+        }
+    }
+    if (f) atomicOr(flags, f);
+}
+
+template <typename W>
+__global__ void k_convert(int64_t nnz, const W* __restrict__ in, double* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (; i < nnz; i += st) out[i] = (double)in[i];
+}
+
+__global__ void k_to_f32(int64_t nnz, const double* __restrict__ in, float* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (; i < nnz; i += st) out[i] = (float)in[i];
+}
+
+// ------------------------------------------------------- row information
+
+// One G-lane group per row: heaviest neighbour (max weight, lowest column
+// on ties: the first minimum of the column of L), weighted degree for the
+// Gershgorin shift g = 2 max_v d_v, largest weight.
+template <int G>
+__global__ void k_rowinfo(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                          const double* __restrict__ w, int32_t* __restrict__ h,
+                          unsigned long long* gbits, unsigned long long* wmaxbits) {
+    const int lane = threadIdx.x & (G - 1);
+    const int gpb = blockDim.x / G;
+    int row = blockIdx.x * gpb + threadIdx.x / G;
+    double dmax = 0.0, wm = 0.0;
+    const int stride = gridDim.x * gpb;
+    for (; row < n; row += stride) {
+        int a = rp[row], b = rp[row + 1];
+        double bw = -1.0;
+        int bc = 0x7fffffff;
+        double d = 0.0;
+        for (int e = a + lane; e < b; e += G) {
+            double x = w[e];
+            int c = col[e];
+            d += x;
+            if (x > bw || (x == bw && c < bc)) {
+                bw = x;
+                bc = c;
+            }
+        }
+#pragma unroll
+        for (int o = G >> 1; o > 0; o >>= 1) {
+            double ow = __shfl_xor(bw, o, kWave);
+            int oc = __shfl_xor(bc, o, kWave);
+            if (ow > bw || (ow == bw && oc < bc)) {
+                bw = ow;
+                bc = oc;
+            }
+        }
+        d = group_sum_t<G>(d);
+        if (lane == 0) {
+            h[row] = bc;
+            dmax = fmax(dmax, 2.0 * d);
+            wm = fmax(wm, bw);
+        }
+    }
+    // block max then one atomic per block (non-negative doubles order like
+    // their bit patterns)
+    __shared__ double sm[2][kBlk / kWave];
+    for (int o = 32; o > 0; o >>= 1) {
+        dmax = fmax(dmax, __shfl_xor(dmax, o, kWave));
+        wm = fmax(wm, __shfl_xor(wm, o, kWave));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sm[0][threadIdx.x >> 6] = dmax;
+        sm[1][threadIdx.x >> 6] = wm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+            a = fmax(a, sm[0][q]);
+            b = fmax(b, sm[1][q]);
+        }
+        atomicMax(gbits, (unsigned long long)__double_as_longlong(a));
+        atomicMax(wmaxbits, (unsigned long long)__double_as_longlong(b));
+    }
+}
+
+// ------------------------------------------------------------------- HEC
+
+constexpr uint8_t kSeed = 1;     // opened an aggregate (visited vertex)
+constexpr uint8_t kPartner = 2;  // heaviest neighbour of a seed
+constexpr unsigned long long kNoKey = 0xFFFFFFFFFFFFFFFFull;
+
+__global__ void k_hec_init(int n, const int32_t* __restrict__ h, uint64_t seed, int level,
+                           uint8_t* __restrict__ live, uint8_t* __restrict__ state,
+                           int32_t* __restrict__ pairseed, unsigned long long* __restrict__ slot) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    pairseed[v] = v;
+    uint64_t kv = hec_key(seed, level, v);
+    uint64_t km = hec_key(seed, level, h[v]);
+    live[v] = (kv < km) ? 1 : 0;
+    state[v] = 0;
+    slot[v] = kNoKey;
+}
+
+// Each live candidate edge {v, h(v)} posts its key at both endpoints.
+__global__ void k_hec_post(int n, const int32_t* __restrict__ h, uint64_t seed, int level,
+                           const uint8_t* __restrict__ live, unsigned long long* slot) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n || !live[v]) return;
+    unsigned long long k = hec_key(seed, level, v);
+    atomicMin(&slot[v], k);
+    atomicMin(&slot[h[v]], k);
+}
+
+// An edge holding the minimum at both endpoints is accepted.  Two accepted
+// edges never share an endpoint, so the writes below never collide.
+__global__ void k_hec_accept(int n, const int32_t* __restrict__ h, uint64_t seed, int level,
+                             uint8_t* __restrict__ live, uint8_t* __restrict__ state,
+                             int32_t* __restrict__ pairseed,
+                             const unsigned long long* __restrict__ slot) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n || !live[v]) return;
+    unsigned long long k = hec_key(seed, level, v);
+    int m = h[v];
+    if (slot[v] == k && slot[m] == k) {
+        state[v] = kSeed;
+        state[m] = kPartner;
+        pairseed[v] = v;
+        pairseed[m] = v;
+        live[v] = 0;
+    }
+}
+
+// Edges touching a matched endpoint die; survivors re-arm their slots for
+// the next round and are counted.
+__global__ void k_hec_kill(int n, const int32_t* __restrict__ h, uint8_t* __restrict__ live,
+                           const uint8_t* __restrict__ state, unsigned long long* slot,
+                           unsigned long long* live_count) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    int alive = 0;
+    if (v < n && live[v]) {
+        int m = h[v];
+        if (state[v] != 0 || state[m] != 0) {
+            live[v] = 0;
+        } else {
+            slot[v] = kNoKey;
+            slot[m] = kNoKey;
+            alive = 1;
+        }
+    }
+    unsigned long long b = __ballot(alive);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(live_count, (unsigned long long)__popcll(b));
+}
+
+// Unmatched vertices follow h to a matched vertex (keys decrease along the
+// chain, so it ends); rootseed = opening vertex of that aggregate.
+__global__ void k_hec_attach(int n, const int32_t* __restrict__ h, const uint8_t* __restrict__ state,
+                             const int32_t* __restrict__ pairseed, int32_t* __restrict__ rootseed,
+                             int32_t* __restrict__ flags) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int r = v;
+    for (int guard = 0; guard < n && state[r] == 0; ++guard) r = h[r];
+    rootseed[v] = pairseed[r];
+    flags[v] = (state[v] == kSeed) ? 1 : 0;
+}
+
+__global__ void k_hec_label(int n, const int32_t* __restrict__ rootseed,
+                            const int32_t* __restrict__ rank, int32_t* __restrict__ agg) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    agg[v] = rank[rootseed[v]];
+}
+
+// ------------------------------------------------------------------ scan
+
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlk * kScanItems;
+
+__device__ __forceinline__ long long wave_incl_scan(long long v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        long long t = __shfl_up(v, o, kWave);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// exclusive block scan of one value per thread (256 threads); returns the
+// block total through *tot
+__device__ __forceinline__ long long block_excl_scan(long long v, long long* sh, long long* tot) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    long long inc = wave_incl_scan(v);
+    if (lane == 63) sh[wv] = inc;
+    __syncthreads();
+    long long off = 0, all = 0;
+    for (int q = 0; q < kBlk / 64; ++q) {
+        if (q < wv) off += sh[q];
+        all += sh[q];
+    }
+    __syncthreads();
+    *tot = all;
+    return off + inc - v;
+}
+
+__global__ void k_scan_reduce(const int32_t* __restrict__ in, int64_t m, long long* __restrict__ bsum) {
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    long long s = 0;
+    for (int q = 0; q < kScanItems; ++q) {
+        int64_t i = base + q * kBlk + threadIdx.x;
+        if (i < m) s += in[i];
+    }
+    __shared__ long long sh[4];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// single block: exclusive scan of nb block sums in place, total to *total
+__global__ void k_scan_top(long long* bsum, int64_t nb, long long* total) {
+    __shared__ long long sh[4];
+    long long carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kBlk) {
+        int64_t i = b0 + threadIdx.x;
+        long long v = (i < nb) ? bsum[i] : 0;
+        long long tot;
+        long long ex = block_excl_scan(v, sh, &tot);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void k_scan_down(const int32_t* __restrict__ in, int32_t* __restrict__ out, int64_t m,
+                            const long long* __restrict__ boff) {
+    __shared__ int32_t tile[kScanTile];
+    __shared__ long long sh[4];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    for (int q = 0; q < kScanItems; ++q) {
+        int64_t i = base + q * kBlk + threadIdx.x;
+        tile[q * kBlk + threadIdx.x] = (i < m) ? in[i] : 0;
+    }
+    __syncthreads();
+    long long loc[kScanItems];
+    long long s = 0;
+    for (int q = 0; q < kScanItems; ++q) {
+        loc[q] = s;
+        s += tile[threadIdx.x * kScanItems + q];
+    }
+    long long tot;
+    long long ex = block_excl_scan(s, sh, &tot);
+    long long off = boff[blockIdx.x] + ex;
+    __syncthreads();
+    for (int q = 0; q < kScanItems; ++q) tile[threadIdx.x * kScanItems + q] = (int32_t)(off + loc[q]);
+    __syncthreads();
+    for (int q = 0; q < kScanItems; ++q) {
+        int64_t i = base + q * kBlk + threadIdx.x;
+        if (i < m) out[i] = tile[q * kBlk + threadIdx.x];
+    }
+}
+
+// -------------------------------------------------------------- Galerkin
+
+// For every fine entry (i, k): key = agg(i) * nc + agg(k), or the sentinel
+// nc*nc when both ends are in one aggregate (those entries only feed the
+// implicit diagonal).  Keys keep the CSR position, so a stable sort leaves
+// equal keys in fine CSR order.
+template <int G>
+__global__ void k_gal_emit(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                           const double* __restrict__ w, const int32_t* __restrict__ agg, int nc,
+                           unsigned long long* __restrict__ keys, double* __restrict__ vals,
+                           unsigned long long* nvalid) {
+    const int lane = threadIdx.x & (G - 1);
+    const int gpb = blockDim.x / G;
+    const unsigned long long sent = (unsigned long long)nc * (unsigned long long)nc;
+    unsigned long long cnt = 0;
+    for (int row = blockIdx.x * gpb + threadIdx.x / G; row < n; row += gridDim.x * gpb) {
+        int a = agg[row];
+        int e0 = rp[row], e1 = rp[row + 1];
+        for (int e = e0 + lane; e < e1; e += G) {
+            int b = agg[col[e]];
+            unsigned long long k = (a == b) ? sent : (unsigned long long)a * (unsigned long long)nc + b;
+            cnt += (a != b);
+            keys[e] = k;
+            vals[e] = w[e];
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, kWave);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(nvalid, cnt);
+}
+
+__global__ void k_gal_heads(int64_t m, const unsigned long long* __restrict__ keys,
+                            int32_t* __restrict__ heads) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    heads[t] = (t == 0 || keys[t] != keys[t - 1]) ? 1 : 0;
+}
+
+// Each run of equal keys is summed in order (fine CSR order); the first
+// entry of a run writes the coarse entry and fills the row pointers of the
+// coarse rows that start there.
+__global__ void k_gal_reduce(int64_t m, const unsigned long long* __restrict__ keys,
+                             const double* __restrict__ vals, const int32_t* __restrict__ heads,
+                             const int32_t* __restrict__ idx, int nc, int64_t zc,
+                             int32_t* __restrict__ rp, int32_t* __restrict__ col,
+                             double* __restrict__ w) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m || !heads[t]) return;
+    unsigned long long k = keys[t];
+    int row = (int)(k / (unsigned long long)nc);
+    int c = (int)(k - (unsigned long long)row * nc);
+    double s = vals[t];
+    int64_t u = t + 1;
+    while (u < m && keys[u] == k) {
+        s += vals[u];
+        ++u;
+    }
+    int32_t o = idx[t];
+    col[o] = c;
+    w[o] = s;
+    int prow = (t == 0) ? -1 : (int)(keys[t - 1] / (unsigned long long)nc);
+    for (int r = prow + 1; r <= row; ++r) rp[r] = o;
+    if (u == m) {
+        for (int r = row + 1; r <= nc; ++r) rp[r] = (int32_t)zc;
+    }
+}
+
+// ------------------------------------------------------------ radix sort
+
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kBlk * kSortItems;
+
+__global__ void k_sort_hist(const unsigned long long* __restrict__ keys, int64_t m, int shift,
+                            int32_t* __restrict__ counts, int nb) {
+    __shared__ int hist[256];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int q = 0; q < kSortItems; ++q) {
+        int64_t i = base + q * kBlk + threadIdx.x;
+        if (i < m) atomicAdd(&hist[(int)((keys[i] >> shift) & 255ull)], 1);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * nb + blockIdx.x] = hist[threadIdx.x];
+}
+
+// Stable scatter: elements of a tile are ranked in index order; within a
+// wave by ballot match on the 8 digit bits, across waves and rounds through
+// per-digit running counts in LDS.
+__global__ void k_sort_scatter(const unsigned long long* __restrict__ kin,
+                               const double* __restrict__ vin, unsigned long long* __restrict__ kout,
+                               double* __restrict__ vout, int64_t m, int shift,
+                               const int32_t* __restrict__ offs, int nb) {
+    __shared__ int wcnt[kBlk / kWave][256];
+    __shared__ int run[256];
+    __shared__ int base[256];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    base[threadIdx.x] = offs[(int64_t)threadIdx.x * nb + blockIdx.x];
+    run[threadIdx.x] = 0;
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+    for (int q = 0; q < kSortItems; ++q) {
+        for (int w = 0; w < kBlk / kWave; ++w) wcnt[w][threadIdx.x] = 0;
+        __syncthreads();
+        int64_t i = tile0 + q * kBlk + threadIdx.x;
+        bool valid = i < m;
+        unsigned long long key = valid ? kin[i] : 0ull;
+        int d = (int)((key >> shift) & 255ull);
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            unsigned long long bal = __ballot((d >> b) & 1);
+            peers &= ((d >> b) & 1) ? bal : ~bal;
+        }
+        int rank = __popcll(peers & lt);
+        if (valid && rank == 0) wcnt[wv][d] = __popcll(peers);
+        __syncthreads();
+        {
+            int r = run[threadIdx.x];
+            for (int w = 0; w < kBlk / kWave; ++w) {
+                int t = wcnt[w][threadIdx.x];
+                wcnt[w][threadIdx.x] = r;
+                r += t;
+            }
+            run[threadIdx.x] = r;
+        }
+        __syncthreads();
+        if (valid) {
+            int64_t pos = (int64_t)base[d] + wcnt[wv][d] + rank;
+            kout[pos] = key;
+            vout[pos] = vin[i];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------- partition
+
+// Row range of each workgroup: boundaries on the merge path of (rows, nnz)
+// so every workgroup gets about the same rows + entries.
+__global__ void k_partition(int n, int64_t nnz, const int32_t* __restrict__ rp, int nb,
+                            int32_t* __restrict__ part) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nb) return;
+    if (b == nb) {
+        part[b] = n;
+        return;
+    }
+    int64_t total = (int64_t)n + nnz;
+    int64_t target = (total * b) / nb;
+    // largest r in [0, n] with r + rp[r] <= target
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)mid + rp[mid] <= target) lo = mid;
+        else hi = mid - 1;
+    }
+    part[b] = lo;
+}
+
+__global__ void k_hash_probe(uint64_t seed, int level, int count, unsigned long long* out) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= count) return;
+    if (level >= 0) {
+        out[v] = hec_key(seed, level, v);
+    } else {
+        // SplitMix64 sequence: state_v = seed + (v+1) * gamma
+        out[v] = mix64(seed + (uint64_t)(v + 1) * 0x9E3779B97F4A7C15ull);
+    }
+}
+
+__global__ void k_fill_u32(unsigned* p, unsigned v, int64_t m) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) p[i] = v;
+}
+
+}  // namespace
+
+// ================================================================ launchers
+
+hipError_t launch_validate(int n, int64_t nnz, const int32_t* rp, const int32_t* col, const void* w,
+                           int wf32, int full, unsigned* flags, hipStream_t s) {
+    unsigned nb = nblocks((int64_t)n + 1, kBlk);
+    if (wf32)
+        hipLaunchKernelGGL(k_validate<float>, dim3(nb), dim3(kBlk), 0, s, n, nnz, rp, col,
+                           (const float*)w, full, flags);
+    else
+        hipLaunchKernelGGL(k_validate<double>, dim3(nb), dim3(kBlk), 0, s, n, nnz, rp, col,
+                           (const double*)w, full, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_w(int64_t nnz, const void* w, int wf32, double* w64, hipStream_t s) {
+    unsigned nb = (unsigned)std::min<int64_t>(nblocks(nnz, kBlk), 65536);
+    if (nb == 0) return hipSuccess;
+    if (wf32)
+        hipLaunchKernelGGL(k_convert<float>, dim3(nb), dim3(kBlk), 0, s, nnz, (const float*)w, w64);
+    else
+        hipLaunchKernelGGL(k_convert<double>, dim3(nb), dim3(kBlk), 0, s, nnz, (const double*)w, w64);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f32(int64_t nnz, const double* w64, float* w32, hipStream_t s) {
+    unsigned nb = (unsigned)std::min<int64_t>(nblocks(nnz, kBlk), 65536);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_f32, dim3(nb), dim3(kBlk), 0, s, nnz, w64, w32);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowinfo(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w,
+                          int32_t* h, unsigned long long* gbits, unsigned long long* wmaxbits,
+                          hipStream_t s) {
+    int gpb = kBlk / lanes;
+    unsigned nb = (unsigned)std::min<int64_t>(nblocks(n, gpb), 65536);
+    switch (lanes) {
+#define CMG_RI(G)                                                                                  \
+    case G:                                                                                        \
+        hipLaunchKernelGGL(k_rowinfo<G>, dim3(nb), dim3(kBlk), 0, s, n, rp, col, w, h, gbits,       \
+                           wmaxbits);                                                              \
+        break;
+        CMG_RI(1) CMG_RI(2) CMG_RI(4) CMG_RI(8) CMG_RI(16) CMG_RI(32) CMG_RI(64)
+#undef CMG_RI
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_hec_init(int n, const int32_t* h, uint64_t seed, int level, uint8_t* live,
+                           uint8_t* state, int32_t* pairseed, unsigned long long* slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_hec_init, dim3(nblocks(n, kBlk)), dim3(kBlk), 0, s, n, h, seed, level, live,
+                       state, pairseed, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_hec_round(int n, const int32_t* h, uint64_t seed, int level, uint8_t* live,
+                            uint8_t* state, int32_t* pairseed, unsigned long long* slot,
+                            unsigned long long* live_count, hipStream_t s) {
+    unsigned nb = nblocks(n, kBlk);
+    hipLaunchKernelGGL(k_hec_post, dim3(nb), dim3(kBlk), 0, s, n, h, seed, level, live, slot);
+    hipLaunchKernelGGL(k_hec_accept, dim3(nb), dim3(kBlk), 0, s, n, h, seed, level, live, state,
+                       pairseed, slot);
+    hipLaunchKernelGGL(k_hec_kill, dim3(nb), dim3(kBlk), 0, s, n, h, live, state, slot, live_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_hec_attach(int n, const int32_t* h, const uint8_t* state, const int32_t* pairseed,
+                             int32_t* rootseed, int32_t* flags, hipStream_t s) {
+    hipLaunchKernelGGL(k_hec_attach, dim3(nblocks(n, kBlk)), dim3(kBlk), 0, s, n, h, state, pairseed,
+                       rootseed, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_hec_label(int n, const int32_t* rootseed, const int32_t* rank, int32_t* agg,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_hec_label, dim3(nblocks(n, kBlk)), dim3(kBlk), 0, s, n, rootseed, rank, agg);
+    return hipGetLastError();
+}
+
+int64_t scan_tmp_elems(int64_t m) { return (m + kScanTile - 1) / kScanTile + 1; }
+
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, long long* tmp, long long* total,
+                       hipStream_t s) {
+    int64_t nb = (m + kScanTile - 1) / kScanTile;
+    if (nb == 0) {
+        return hipMemsetAsync(total, 0, sizeof(long long), s);
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlk), 0, s, in, m, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlk), 0, s, tmp, nb, total);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kBlk), 0, s, in, out, m, tmp);
+    return hipGetLastError();
+}
+
+hipError_t launch_gal_emit(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w,
+                           const int32_t* agg, int nc, unsigned long long* keys, double* vals,
+                           unsigned long long* nvalid, hipStream_t s) {
+    int gpb = kBlk / lanes;
+    unsigned nb = (unsigned)std::min<int64_t>(nblocks(n, gpb), 65536);
+    switch (lanes) {
+#define CMG_GE(G)                                                                                  \
+    case G:                                                                                        \
+        hipLaunchKernelGGL(k_gal_emit<G>, dim3(nb), dim3(kBlk), 0, s, n, rp, col, w, agg, nc, keys, \
+                           vals, nvalid);                                                          \
+        break;
+        CMG_GE(1) CMG_GE(2) CMG_GE(4) CMG_GE(8) CMG_GE(16) CMG_GE(32) CMG_GE(64)
+#undef CMG_GE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int64_t sort_tmp_elems(int64_t m) { return 256 * ((m + kSortTile - 1) / kSortTile) + 1; }
+
+hipError_t launch_sort(unsigned long long* k0, double* v0, unsigned long long* k1, double* v1,
+                       int64_t m, int bits, int32_t* tmp_counts, long long* tmp_scan, int* in_second,
+                       hipStream_t s) {
+    *in_second = 0;
+    if (m <= 1 || bits <= 0) return hipSuccess;
+    int nb = (int)((m + kSortTile - 1) / kSortTile);
+    int64_t ncounts = 256LL * nb;
+    unsigned long long* kin = k0;
+    unsigned long long* kout = k1;
+    double* vin = v0;
+    double* vout = v1;
+    long long* scan_tmp = tmp_scan;
+    long long* scan_total = tmp_scan + scan_tmp_elems(ncounts);
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(kBlk), 0, s, kin, m, shift, tmp_counts, nb);
+        hipError_t e = launch_scan(tmp_counts, tmp_counts, ncounts, scan_tmp, scan_total, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(kBlk), 0, s, kin, vin, kout, vout, m, shift,
+                           tmp_counts, nb);
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+        *in_second ^= 1;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gal_heads(int64_t m, const unsigned long long* keys, int32_t* heads, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gal_heads, dim3(nblocks(m, kBlk)), dim3(kBlk), 0, s, m, keys, heads);
+    return hipGetLastError();
+}
+
+hipError_t launch_gal_reduce(int64_t m, const unsigned long long* keys, const double* vals,
+                             const int32_t* heads, const int32_t* idx, int nc, int64_t zc,
+                             int32_t* rp_out, int32_t* col_out, double* w_out, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gal_reduce, dim3(nblocks(m, kBlk)), dim3(kBlk), 0, s, m, keys, vals, heads, idx,
+                       nc, zc, rp_out, col_out, w_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_partition(int n, int64_t nnz, const int32_t* rp, int nb, int32_t* part,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_partition, dim3(nblocks((int64_t)nb + 1, kBlk)), dim3(kBlk), 0, s, n, nnz, rp,
+                       nb, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_probe(uint64_t seed, int level, int count, unsigned long long* out,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_hash_probe, dim3(nblocks(count, kBlk)), dim3(kBlk), 0, s, seed, level, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned* p, unsigned v, int64_t m, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(nblocks(m, kBlk)), dim3(kBlk), 0, s, p, v, m);
+    return hipGetLastError();
+}
+
+}  // namespace cmg

@@ -1,0 +1,76 @@
+"""Helpers shared by the GPU parity tests: run the HIP path through the
+C-ABI binding and compare with the CPU oracle on the same seeded input."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+
+# Tolerances for the floating-point outputs (FP64 path); the integer and
+# structural outputs (aggregates, coarse CSR, iteration counts) are exact.
+COS_TOL = 1e-10       # |cos(x_gpu, x_oracle)| >= 1 - COS_TOL
+LAM_RTOL = 1e-9       # |lambda_gpu - lambda_oracle| <= LAM_RTOL * lambda_oracle
+MIXED_LAM_RTOL = 1e-5  # mixed FP32/FP64 path against the FP64 oracle
+
+
+def say(msg: str) -> None:
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(g, want_levels: bool = True, **opts):
+    from paper_1412_0565_amd import cmg
+
+    with cmg.Fiedler(g.n, g.row_ptr, g.col, g.w, **opts) as F:
+        lam, x, st = F.solve()
+        levels = F.levels()
+        arrays = [F.level_arrays(j) for j in range(len(levels))] if want_levels else None
+    return lam, x, st, levels, arrays
+
+
+def oracle_of(g, **opts):
+    from oracle import oracle as O
+
+    kw = {}
+    for k_src, k_dst in [("tol", "tol"), ("coarsest_n", "coarsest_n"), ("dense_max", "dense_max"),
+                         ("seed", "seed"), ("max_iters_per_level", "max_iters")]:
+        if k_src in opts:
+            kw[k_dst] = opts[k_src]
+    return O.cmg(g, **kw)
+
+
+def cosine(a, b) -> float:
+    return abs(float(np.dot(a, b))) / (np.linalg.norm(a) * np.linalg.norm(b))
+
+
+def assert_hierarchy_equal(g, ref, levels, arrays, exact_g: bool = True):
+    assert len(levels) == len(ref.levels), ([l.n for l in levels], [l.n for l in ref.levels])
+    for j, (lv, rl) in enumerate(zip(levels, ref.levels)):
+        assert lv.n == rl.n and lv.nnz == rl.nnz, (j, lv.n, rl.n, lv.nnz, rl.nnz)
+        rp, col, w, agg = arrays[j]
+        assert np.array_equal(rp, rl.row_ptr), j
+        assert np.array_equal(col, rl.col), j
+        assert np.array_equal(w, rl.w), j
+        if j < len(levels) - 1:
+            assert np.array_equal(agg, rl.agg), j
+        if exact_g:
+            assert lv.g == rl.g, (j, lv.g, rl.g)
+        else:
+            assert abs(lv.g - rl.g) <= 1e-14 * rl.g, (j, lv.g, rl.g)
+
+
+def assert_refinement_equal(ref, levels):
+    for j, (lv, rl) in enumerate(zip(levels, ref.levels)):
+        assert lv.k == rl.k, (j, lv.k, rl.k, "margins", lv.margin, rl.margin)
+
+
+def assert_fp64_parity(g, lam, x, st, levels, arrays, ref, exact_g=True):
+    assert_hierarchy_equal(g, ref, levels, arrays, exact_g)
+    assert_refinement_equal(ref, levels)
+    c = cosine(x, ref.y)
+    assert c >= 1 - COS_TOL, (c, 1 - c)
+    assert abs(lam - ref.lam) <= LAM_RTOL * abs(ref.lam), (lam, ref.lam)
+    assert abs(np.linalg.norm(x) - 1) < 1e-12
+    assert abs(x.sum()) < 1e-9 * math.sqrt(g.n)
+    assert abs(st.residual - ref.residual) <= 1e-6 * ref.residual + 1e-14

@@ -1,0 +1,225 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Bar: aggregates, coarse CSR and PI step counts bit-exact; FP64 vector
+|cos| >= 1 - 1e-10 and eigenvalue relative error <= 1e-9; mixed path
+eigenvalue relative error <= 1e-5 against the FP64 oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1412_0565_amd import graphs as G
+
+from gpu_compare import (MIXED_LAM_RTOL, assert_fp64_parity, cosine, oracle_of, run_gpu, say)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1412_0565_amd import cmg
+
+    cmg.lib()
+
+
+def _named(name):
+    return {
+        "path2": lambda: G.path(2),
+        "path20": lambda: G.path(20),
+        "path1000": lambda: G.path(1000),
+        "cycle101": lambda: G.cycle(101),
+        "K25": lambda: G.complete(25),
+        "K60": lambda: G.complete(60),
+        "star200": lambda: G.star(200),
+        "grid5": lambda: G.grid2d(5, 5),
+        "grid100": lambda: G.grid2d(100, 100),
+        "grid128": lambda: G.grid2d(128, 128),
+        "grid_aniso": lambda: G.grid2d(90, 77, wx=2.0, wy=1.0),
+        "grid3d_20": lambda: G.grid3d(20),
+        "rgg20k": lambda: G.rgg(20000, 10.0, seed=5),
+        "rgg60k": lambda: G.rgg(60000, 10.0, seed=6),
+        "cl30k": lambda: G.chung_lu(30000, 2.1, 16.0, 2000.0, seed=7),
+        "cl_dense": lambda: G.chung_lu(3000, 2.1, 30.0, 1500.0, seed=8),
+        "er500": lambda: G.erdos_renyi_connected(500, 0.02, seed=9),
+    }[name]()
+
+
+def test_hash_probe_matches_published_and_oracle():
+    from oracle import oracle as O
+    from paper_1412_0565_amd import cmg
+
+    seq = cmg.cmg_hash_probe(1234567, -1, 5)
+    assert [int(v) for v in seq] == [6457827717110365317, 3203168211198807973, 9817491932198370423,
+                                     4593380528125082431, 16408922859458223821]
+    keys = cmg.cmg_hash_probe(14120565, 3, 4000)
+    assert all(int(keys[v]) == O.hec_key(14120565, 3, v) for v in range(0, 4000, 37))
+
+
+@pytest.mark.parametrize("name", ["path2", "path20", "K25", "grid5", "cycle101", "path1000", "K60", "star200",
+                                  "grid100", "grid128", "grid_aniso", "grid3d_20", "rgg20k", "rgg60k",
+                                  "cl30k", "cl_dense", "er500"])
+def test_fp64_parity(name):
+    g = _named(name)
+    say(f"[parity] {name} n={g.n} nnz={g.nnz}")
+    ref = oracle_of(g)
+    lam, x, st, levels, arrays = run_gpu(g)
+    assert_fp64_parity(g, lam, x, st, levels, arrays, ref)
+
+
+@pytest.mark.parametrize("block_rows", [1, 1 << 30])
+def test_block_and_grid_paths_agree_with_oracle(block_rows):
+    g = G.grid2d(128, 128)
+    say(f"[parity] grid128 block_rows={block_rows}")
+    ref = oracle_of(g)
+    lam, x, st, levels, arrays = run_gpu(g, block_rows=block_rows)
+    assert all(l.in_block == (block_rows > 1) for l in levels[:-1])
+    assert_fp64_parity(g, lam, x, st, levels, arrays, ref)
+
+
+def test_real_valued_weights():
+    g = G.rgg(15000, 10.0, seed=3)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    a = np.minimum(rows, g.col).astype(np.uint64)
+    b = np.maximum(rows, g.col).astype(np.uint64)
+    u = G.stream_uniform(11, 77, (a << np.uint64(32)) | b)
+    g = G.CSR(g.n, g.row_ptr, g.col, 0.25 + 2.0 * u)
+    say("[parity] real weights")
+    ref = oracle_of(g)
+    lam, x, st, levels, arrays = run_gpu(g)
+    assert_fp64_parity(g, lam, x, st, levels, arrays, ref, exact_g=False)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_seeds_and_options(seed):
+    g = G.rgg(30000, 8.0, seed=seed)
+    opts = dict(seed=1000 + seed, tol=1e-7 if seed == 2 else 1e-8, coarsest_n=40 if seed == 3 else 25)
+    say(f"[parity] rgg30k seed={seed} {opts}")
+    ref = oracle_of(g, **opts)
+    lam, x, st, levels, arrays = run_gpu(g, **opts)
+    assert_fp64_parity(g, lam, x, st, levels, arrays, ref)
+
+
+def test_f32_input_weights():
+    g = G.rgg(20000, 10.0, seed=12)
+    g32 = g.astype(np.float32)
+    say("[parity] f32 input")
+    ref = oracle_of(g)
+    lam, x, st, levels, arrays = run_gpu(g32)
+    assert_fp64_parity(g, lam, x, st, levels, arrays, ref)
+
+
+@pytest.mark.parametrize("name", ["rgg60k", "grid128", "cl30k"])
+def test_mixed_precision(name):
+    g = _named(name)
+    say(f"[mixed] {name}")
+    ref = oracle_of(g)
+    lam, x, st, levels, arrays = run_gpu(g, precision=1, mixed_min_nnz=1)
+    assert any(l.fp32 for l in levels)
+    assert abs(lam - ref.lam) <= MIXED_LAM_RTOL * ref.lam, (lam, ref.lam)
+    assert st.residual < 10 * ref.residual + 1e-6
+    assert abs(np.linalg.norm(x) - 1) < 1e-12
+
+
+def test_deterministic_repeat():
+    from paper_1412_0565_amd import cmg
+
+    g = G.rgg(40000, 10.0, seed=2)
+    say("[determinism] rgg40k")
+    with cmg.Fiedler(g.n, g.row_ptr, g.col, g.w) as F:
+        l1, x1, _ = F.solve()
+        l2, x2, _ = F.solve()
+    with cmg.Fiedler(g.n, g.row_ptr, g.col, g.w) as F:
+        l3, x3, _ = F.solve()
+    assert l1 == l2 == l3
+    assert np.array_equal(x1, x2) and np.array_equal(x1, x3)
+
+
+def test_device_tensors_and_torch_allocator():
+    import torch
+    from paper_1412_0565_amd import cmg
+
+    g = G.grid2d(128, 128)
+    say("[device] torch tensors")
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    col = torch.from_numpy(g.col).cuda()
+    w = torch.from_numpy(g.w).cuda()
+    x = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    alloc = cmg.torch_allocator()
+    import ctypes as C
+
+    opt = cmg.cmg_options_default(allocator=C.pointer(alloc),
+                                  stream=C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    h = cmg.cmg_setup(g.n, rp, col, w, opt)
+    try:
+        lam, _ = cmg.cmg_fiedler(h, x)
+        assert cmg.cmg_footprint(h) > 0
+    finally:
+        cmg.cmg_free(h)
+    ref = oracle_of(g)
+    assert cosine(x.cpu().numpy(), ref.y) >= 1 - 1e-10
+    assert abs(lam - ref.lam) <= 1e-9 * ref.lam
+
+
+@pytest.mark.parametrize("case", ["selfloop", "unsorted", "negative", "nan", "isolated", "badptr", "asym"])
+def test_invalid_graphs(case):
+    from paper_1412_0565_amd import cmg
+
+    g = G.grid2d(10, 10)
+    rp, col, w = g.row_ptr.copy(), g.col.copy(), g.w.copy()
+    opts = {}
+    if case == "selfloop":
+        col[0] = 0
+        exp = cmg.CMG_E_GRAPH
+    elif case == "unsorted":
+        col[0], col[1] = col[1], col[0]
+        exp = cmg.CMG_E_GRAPH
+    elif case == "negative":
+        w[5] = -1.0
+        exp = cmg.CMG_E_GRAPH
+    elif case == "nan":
+        w[7] = float("nan")
+        exp = cmg.CMG_E_GRAPH
+    elif case == "isolated":
+        # vertex 0 loses its edges (and its neighbours lose vertex 0)
+        e = g.edges()
+        keep = (e[0] != 0) & (e[1] != 0)
+        gg = G.from_edges(100, e[0][keep], e[1][keep])
+        rp, col, w = gg.row_ptr, gg.col, gg.w
+        exp = cmg.CMG_E_ISOLATED
+    elif case == "badptr":
+        rp[3] = rp[4] + 1
+        exp = cmg.CMG_E_GRAPH
+    elif case == "asym":
+        w[3] = 2.0
+        opts["validate_full"] = 1
+        exp = cmg.CMG_E_GRAPH
+    with pytest.raises(cmg.CmgError) as ei:
+        cmg.cmg_setup(100, rp, col, w, cmg.cmg_options_default(**opts))
+    assert ei.value.status == exp
+
+
+def test_maxit_warning():
+    from paper_1412_0565_amd import cmg
+
+    g = G.grid2d(64, 64)
+    with cmg.Fiedler(g.n, g.row_ptr, g.col, g.w, max_iters_per_level=3) as F:
+        lam, x, st = F.solve()
+        assert st.status == cmg.CMG_W_MAXIT
+        assert all(l.k <= 3 for l in F.levels())
+    ref = oracle_of(g, max_iters_per_level=3)
+    assert cosine(x, ref.y) >= 1 - 1e-10
+
+
+def test_courant_fischer_closed_forms():
+    # r >= lambda_2 for closed-form spectra, independent of the oracle
+    for g, lam2 in [(G.grid2d(128, 128), 2 - 2 * math.cos(math.pi / 128)),
+                    (G.grid3d(24), 2 - 2 * math.cos(math.pi / 24)),
+                    (G.cycle(5000), 2 - 2 * math.cos(2 * math.pi / 5000))]:
+        lam, x, st, levels, _ = run_gpu(g, want_levels=False)
+        assert lam >= lam2 * (1 - 1e-12)
+        assert lam <= lam2 * 1.1

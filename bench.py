@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Benchmark: Fiedler solves/s of the cascadic multigrid path on one MI355X.
+
+One step = one whole solve of the workload: cmg_setup (validation, HEC
+coarsening, Galerkin hierarchy) + cmg_fiedler (coarsest solve, cascadic
+power-iteration refinement, Rayleigh quotient and residual) + cmg_free,
+with the input graph already resident in HBM.
+
+Default workload: random geometric graph, 1M points in the unit square,
+mean degree ~10, largest component, integer weights 1..8 (FP64).  The same
+graph is also solved with the mixed FP32/FP64 path and with a resident
+hierarchy (cmg_fiedler only); those figures are reported beside the main
+value.  The roofline entry covers the finest-level power-iteration kernel
+(the SpMV hot loop), timed with HIP events on the library's stream.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import platform
+import statistics
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Fiedler solves/s + SpMV HBM GB/s vs peak; p50/p99 serve latency"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "rgg1m": "random geometric graph: 1M points uniform in the unit square, radius for mean degree 10, "
+             "largest connected component, integer weights 1..8, CSR int32/float64",
+    "grid128": "2D 128x128 5-point grid graph, unit weights, CSR int32/float64",
+    "grid3d256": "3D 256^3 7-point grid graph, unit weights, CSR int32/float32",
+    "chunglu4m": "Chung-Lu power-law graph, 4M vertices, exponent 2.1, mean degree 16, max degree 50k, "
+                 "largest connected component, unit weights, CSR int32/float32",
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def solve_once(cmg, g_dev, n, opt, x):
+    rp, col, w = g_dev
+    h = cmg.cmg_setup(n, rp, col, w, opt)
+    st = cmg.cmg_stats()
+    st.struct_size = C.sizeof(cmg.cmg_stats)
+    try:
+        lam, _ = cmg.cmg_fiedler(h, x, st)
+        levels = cmg.cmg_level_info(h)
+    finally:
+        cmg.cmg_free(h)
+    return lam, st, levels
+
+
+def launch_bytes(levels, j=0):
+    """Algorithmic bytes of the level-j refinement launch: k PI steps of
+    4(n+1) + nnz(4+s_v) + 2 s_x n, plus the prolongation (agg read, coarse
+    gather, write) and the deflation pass over the start vector."""
+    L = levels[j]
+    sx = 4 if L.fp32 else 8
+    nc = levels[j + 1].n if j + 1 < len(levels) else 0
+    prol = 4 * L.n + sx * nc + 2 * sx * L.n
+    return L.k * L.bytes_per_iter + prol
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rgg1m", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-repeats", type=int, default=8)
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; the solver has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1412_0565_amd import cmg
+    from paper_1412_0565_amd import graphs as G
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cmg.lib()
+
+    t0 = time.time()
+    g = G.workload(args.workload)
+    log(f"[bench] workload {args.workload}: n={g.n} nnz={g.nnz} (generated in {time.time() - t0:.1f}s)")
+    g_dev = (torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda(), torch.from_numpy(g.w).cuda())
+    x = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    alloc = cmg.torch_allocator()
+
+    def opts(**kw):
+        return cmg.cmg_options_default(stream=C.c_void_p(stream.cuda_stream), allocator=C.pointer(alloc), **kw)
+
+    fp64_opt = opts(precision=cmg.CMG_FP64)
+    mixed_opt = opts(precision=cmg.CMG_MIXED)
+
+    def timed(opt, steps, warmup, label):
+        for _ in range(warmup):
+            solve_once(cmg, g_dev, g.n, opt, x)
+        torch.cuda.synchronize()
+        pis, ks, byts, lams, setups = [], [], [], [], []
+        t = time.perf_counter()
+        for i in range(steps):
+            lam, st, levels = solve_once(cmg, g_dev, g.n, opt, x)
+            pis.append(levels[0].pi_ms)
+            ks.append(levels[0].k)
+            byts.append(launch_bytes(levels, 0))
+            lams.append(lam)
+            setups.append(st.setup_ms)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        log(f"[bench] {label}: {steps} solves in {el:.3f}s ({steps / el:.2f} solves/s), lambda={lams[-1]:.12e} "
+            f"k0={ks[-1]} level-0 PI {statistics.mean(pis):.3f} ms")
+        return el, pis, ks, byts, lams, setups, st, levels
+
+    el, pis, ks, byts, lams, setups, st, levels = timed(fp64_opt, args.steps, args.warmup, "fp64 end-to-end")
+    value = args.steps / el
+    ms_per_step = 1000.0 * el / args.steps
+
+    # resident hierarchy: cmg_fiedler only
+    h = cmg.cmg_setup(g.n, *g_dev, fp64_opt)
+    try:
+        for _ in range(args.warmup):
+            cmg.cmg_fiedler(h, x)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            cmg.cmg_fiedler(h, x)
+        torch.cuda.synchronize()
+        el_res = time.perf_counter() - t
+        fp = cmg.cmg_footprint(h)
+    finally:
+        cmg.cmg_free(h)
+
+    mixed = None
+    if not args.no_mixed:
+        el_m, pis_m, ks_m, byts_m, lams_m, _, st_m, levels_m = timed(mixed_opt, args.steps, args.warmup,
+                                                                     "mixed end-to-end")
+        mixed = {
+            "solves_per_s": round(args.steps / el_m, 3),
+            "ms_per_step": round(1000.0 * el_m / args.steps, 3),
+            "lambda": lams_m[-1],
+            "lambda_rel_diff_vs_fp64": abs(lams_m[-1] - lams[-1]) / abs(lams[-1]),
+            "residual": st_m.residual,
+            "finest_pi_ms": round(statistics.mean(pis_m), 4),
+            "finest_pi_GBps": round(statistics.mean(byts_m) / (statistics.mean(pis_m) * 1e-3) / 1e9, 1),
+            "fp32_levels": [j for j, L in enumerate(levels_m) if L.fp32],
+        }
+
+    pi_ms = statistics.mean(pis)
+    bytes_launch = statistics.mean(byts)
+    achieved = bytes_launch / (pi_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_refine_grid<double,G> on level 0 (PI steps + prolongation)",
+                "bytes_per_launch": int(bytes_launch), "avg_launch_ms": round(pi_ms, 4),
+                "pi_steps_per_launch": ks[-1]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+
+        O.lib()
+        reps = max(1, args.cpu_repeats)
+        t = time.perf_counter()
+        for _ in range(reps):
+            r = O.cmg(g, keep_levels=False)
+        el_cpu = time.perf_counter() - t
+        cpu = {"value": round(reps / el_cpu, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"{reps} full FP64 solves of the same {args.workload} graph by the single-threaded C "
+                         f"oracle ({el_cpu:.1f}s)",
+               "cpu_model": cpu_model(), "host_nproc": os.cpu_count(),
+               "lambda": r.lam, "lambda_rel_diff_gpu": abs(r.lam - lams[-1]) / abs(r.lam)}
+        log(f"[bench] cpu oracle: {reps} solves in {el_cpu:.2f}s")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "name": args.workload, "n": g.n, "nnz": g.nnz,
+                   "levels": [L.n for L in levels], "pi_steps": [L.k for L in levels],
+                   "tol": 1e-8, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "resident_solves_per_s": round(args.steps / el_res, 3),
+        "setup_ms": round(statistics.mean(setups), 3),
+        "lambda": lams[-1],
+        "residual": st.residual,
+        "footprint_bytes": fp,
+        "mixed": mixed,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -87,7 +87,9 @@ typedef struct {
     int32_t dense_max;           /* coarsest level solved densely if n <= dense_max (128) */
     uint64_t seed;               /* seeds the HEC visit order (replaces randperm) */
     int32_t precision;           /* cmg_precision */
-    int32_t fp64_final_sweeps;   /* MIXED only: extra FP64 PI steps on the finest level (1) */
+    int32_t fp64_final_sweeps;   /* MIXED only, 0 or 1 (default 1): the last level-0 PI step is
+                                    recomputed in FP64 from the FP32 iterate before it, so the
+                                    step count equals the FP64 path */
     int32_t max_iters_per_level; /* PI cap per level (100000), then CMG_W_MAXIT */
     int32_t validate_full;       /* 1: also check symmetry of the input (O(nnz log deg)) */
     void* stream;                /* hipStream_t; NULL = null stream */

@@ -538,8 +538,8 @@ cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where,
         d.buf1 = L0.buf1;
         d.part = L0.part;
         d.grid = L0.grid;
-        int sweeps = (L0.fp32 && c->d_fa) ? o.fp64_final_sweeps : 0;
-        CK(launch_finish(d, c->d_st, sweeps, c->d_fa, c->d_fb, c->d_y, c->d_sync, c->d_partials,
+        int redo = (L0.fp32 && c->d_fa && o.fp64_final_sweeps > 0) ? 1 : 0;
+        CK(launch_finish(d, c->d_st, redo, c->d_fa, c->d_fb, c->d_y, c->d_sync, c->d_partials,
                          c->d_bcast, c->d_fo, s));
     }
     FinishOut fo;
@@ -639,7 +639,7 @@ cmg_status cmg_setup(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
     }
     if (!(o.tol < 1.0) || !std::isfinite(o.tol) || o.coarsest_n < 2 || o.dense_max < 2 || o.dense_max > 128 ||
         o.max_iters_per_level < 1 || (o.precision != CMG_FP64 && o.precision != CMG_MIXED) ||
-        o.fp64_final_sweeps < 0 || o.fp64_final_sweeps > 16 || o.coarsest_n > o.dense_max)
+        o.fp64_final_sweeps < 0 || o.fp64_final_sweeps > 1 || o.coarsest_n > o.dense_max)
         return CMG_E_ARG;
     const double t0 = now_ms();
     cmg_ctx* c = new (std::nothrow) cmg_ctx;

@@ -96,6 +96,8 @@ struct LevelDev {
 struct LevelState {
     double mu;      // final vector = (buf[fin] - mu) * s
     double s;
+    double mu_prev; // iterate before the last step = (buf[1-fin] - mu_prev) * s_prev
+    double s_prev;
     double utv;     // last (u^k, u^{k-1})
     double margin;  // utv - (1 - tol)
     int32_t fin;    // buffer index holding the final vector

@@ -69,7 +69,7 @@ hipError_t launch_refine_grid(const LevelDev& L, const LevelDev& C, LevelState* 
                               double* partials, double* bcast, double tol, int maxit, uint64_t seed,
                               hipStream_t s);
 int finish_max_blocks(int fp32, int lanes, int variant);
-hipError_t launch_finish(const LevelDev& L0, const LevelState* st0, int sweeps, double* f64a,
+hipError_t launch_finish(const LevelDev& L0, const LevelState* st0, int redo, double* f64a,
                          double* f64b, double* yout, GridSync* gs, double* partials,
                          double* bcast, FinishOut* fo, hipStream_t s);
 hipError_t launch_reset_sync(GridSync* gs, hipStream_t s);

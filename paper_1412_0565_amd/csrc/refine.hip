@@ -329,6 +329,8 @@ __global__ void __launch_bounds__(256) k_coarse_dense(LevelDev L, LevelState* st
         LevelState s0;
         s0.mu = 0.0;
         s0.s = 1.0;
+        s0.mu_prev = 0.0;
+        s0.s_prev = 1.0;
         s0.utv = 1.0;
         s0.margin = 0.0;
         s0.fin = 0;
@@ -391,7 +393,7 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
         block_sum<1>(ss, red);
         double s = 1.0 / sqrt(ss[0]);
         int cur = 0, k = 0, hit = 0;
-        double utv = 0.0;
+        double utv = 0.0, pmu = mu, ps = s;
         while (true) {
             const double* win = cur ? b1 : b0;
             double* wout = cur ? b0 : b1;
@@ -403,6 +405,8 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
             utv = s2 * (acc[2] - mu2 * acc[3]);
             ++k;
             cur ^= 1;
+            pmu = mu;
+            ps = s;
             mu = mu2;
             s = s2;
             if (!(utv < 1.0 - tol)) break;
@@ -415,6 +419,8 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
             LevelState o;
             o.mu = mu;
             o.s = s;
+            o.mu_prev = pmu;
+            o.s_prev = ps;
             o.utv = utv;
             o.margin = utv - (1.0 - tol);
             o.fin = cur;
@@ -470,7 +476,7 @@ __global__ void __launch_bounds__(kGridBlock)
     if (!grid_allreduce<1>(ss, gs, partials, bcast, lb, red)) return;
     double s = 1.0 / sqrt(ss[0]);
     int cur = 0, k = 0, hit = 0;
-    double utv = 0.0;
+    double utv = 0.0, pmu = mu, ps = s;
     while (true) {
         const T* win = cur ? b1 : b0;
         T* wout = cur ? b0 : b1;
@@ -482,6 +488,8 @@ __global__ void __launch_bounds__(kGridBlock)
         utv = s2 * (acc[2] - mu2 * acc[3]);
         ++k;
         cur ^= 1;
+        pmu = mu;
+        ps = s;
         mu = mu2;
         s = s2;
         if (!(utv < 1.0 - tol)) break;
@@ -494,6 +502,8 @@ __global__ void __launch_bounds__(kGridBlock)
         LevelState o;
         o.mu = mu;
         o.s = s;
+        o.mu_prev = pmu;
+        o.s_prev = ps;
         o.utv = utv;
         o.margin = utv - (1.0 - tol);
         o.fin = cur;
@@ -506,15 +516,18 @@ __global__ void __launch_bounds__(kGridBlock)
 
 // ----------------------------------------------------------- finishing
 
-// Finest level: optional FP64 PI steps from the (possibly FP32) final
-// vector, then the output y = deflated, normalised iterate, the edge-form
-// Rayleigh quotient r = sum_edges w (y_i - y_k)^2 and the residual
-// ||L y - r y||, all in FP64.
+// Finest level.  With `redo` = 1 (mixed precision) the last power-iteration
+// step is recomputed in FP64 from the FP32 iterate before it, so the step
+// count equals the FP64 path and only that earlier iterate carries FP32
+// rounding.  Then the output y = deflated, normalised iterate, the
+// edge-form Rayleigh quotient r = sum_edges w (y_i - y_k)^2 and the
+// residual ||L y - r y||, all in FP64.
 template <typename T, int G>
 __global__ void __launch_bounds__(kGridBlock)
-    k_finish(LevelDev L, const LevelState* st0, int sweeps, double* fa, double* fb, double* yout,
+    k_finish(LevelDev L, const LevelState* st0, int redo, double* fa, double* fb, double* yout,
              GridSync* gs, double* partials, double* bcast, FinishOut* fo) {
     __shared__ double red[16 * 5 + 8];
+    (void)fb;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int r0 = L.part[lb], r1 = L.part[lb + 1];
     const int lane = threadIdx.x & (G - 1);
@@ -527,17 +540,18 @@ __global__ void __launch_bounds__(kGridBlock)
     const void* src = st.fin ? L.buf1 : L.buf0;
     int src_f32 = (sizeof(T) == 4);
     double mu = st.mu, s = st.s;
-    for (int sw = 0; sw < sweeps; ++sw) {
-        double* dst = (sw & 1) ? fb : fa;
+    if (redo && st.k > 0) {
+        const void* prev = st.fin ? L.buf0 : L.buf1;
+        const double pmu = st.mu_prev, ps = st.s_prev;
         double acc[2] = {0.0, 0.0};
         for (int i = r0 + (int)(threadIdx.x / G); i < r1; i += ngroups) {
-            const double wi = ld_any(src, src_f32, i);
+            const double wi = ld_any(prev, src_f32, i);
             double t = 0.0;
-            for (int e = rp[i] + lane; e < rp[i + 1]; e += G) t += w[e] * (ld_any(src, src_f32, col[e]) - wi);
+            for (int e = rp[i] + lane; e < rp[i + 1]; e += G) t += w[e] * (ld_any(prev, src_f32, col[e]) - wi);
             t = group_sum_t<G>(t);
             if (lane == 0) {
-                double y = s * (L.g * (wi - mu) + t);
-                dst[i] = y;
+                double y = ps * (L.g * (wi - pmu) + t);
+                fa[i] = y;
                 acc[0] += y;
                 acc[1] += y * y;
             }
@@ -545,7 +559,7 @@ __global__ void __launch_bounds__(kGridBlock)
         if (!grid_allreduce<2>(acc, gs, partials, bcast, lb, red)) return;
         mu = acc[0] / n;
         s = 1.0 / sqrt(acc[1] - acc[0] * mu);
-        src = dst;
+        src = fa;
         src_f32 = 0;
     }
     // pass 1: sums of u = (src - mu) s and the edge form
@@ -687,11 +701,11 @@ hipError_t launch_refine_grid(const LevelDev& L, const LevelDev& C, LevelState* 
     return e;
 }
 
-hipError_t launch_finish(const LevelDev& L0, const LevelState* st0, int sweeps, double* f64a,
+hipError_t launch_finish(const LevelDev& L0, const LevelState* st0, int redo, double* f64a,
                          double* f64b, double* yout, GridSync* gs, double* partials, double* bcast,
                          FinishOut* fo, hipStream_t s) {
     LevelDev Lc = L0;
-    void* args[] = {&Lc, &st0, &sweeps, &f64a, &f64b, &yout, &gs, &partials, &bcast, &fo};
+    void* args[] = {&Lc, &st0, &redo, &f64a, &f64b, &yout, &gs, &partials, &bcast, &fo};
     const int lanes = L0.lanes;
     hipError_t e = hipSuccess;
 #define CMG_LF(T, G)                                                                               \

@@ -45,6 +45,7 @@ struct HostLevel {
     float* w32 = nullptr;
     int32_t* agg = nullptr;
     double g = 0.0, wmax = 0.0;
+    int w32exact = 0;
     int fp32 = 0, in_block = 0, lanes = 8, grid = 0, variant = 1;
     void* buf0 = nullptr;
     void* buf1 = nullptr;
@@ -167,6 +168,7 @@ struct SetupTmp {
     unsigned long long* scal = nullptr;  // [0] gbits [1] wmaxbits [2] live count [3] nvalid
     long long* totals = nullptr;         // [0] scan total
     unsigned* vflags = nullptr;
+    double* bmax = nullptr;              // per-block maxima of the row pass
 };
 
 cmg_status alloc_tmp(cmg_ctx* c, SetupTmp& t, int32_t n, int64_t nnz) {
@@ -191,13 +193,14 @@ cmg_status alloc_tmp(cmg_ctx* c, SetupTmp& t, int32_t n, int64_t nnz) {
     ALLOC(t.scal, unsigned long long, 8);
     ALLOC(t.totals, long long, 4);
     ALLOC(t.vflags, unsigned, 4);
+    ALLOC(t.bmax, double, 3 * kRowinfoMaxBlocks);
     return CMG_OK;
 }
 
 void free_tmp(cmg_ctx* c, SetupTmp& t) {
     void* ps[] = {t.h, t.slot, t.live, t.state, t.pairseed, t.rootseed, t.flags, t.rank, t.scan_tmp,
                   t.k0, t.k1, t.v0, t.v1, t.heads, t.idx, t.sort_counts, t.sort_scan, t.scal, t.totals,
-                  t.vflags};
+                  t.vflags, t.bmax};
     size_t bytes = 0;
     (void)bytes;
     (void)hipStreamSynchronize(c->stream);
@@ -207,16 +210,17 @@ void free_tmp(cmg_ctx* c, SetupTmp& t) {
 
 // Gershgorin shift, heaviest neighbours and largest weight of one level.
 cmg_status level_rowinfo(cmg_ctx* c, SetupTmp& t, HostLevel& L) {
-    CK(hipMemsetAsync(t.scal, 0, 2 * sizeof(unsigned long long), c->stream));
-    CK(launch_rowinfo(L.n, L.lanes, L.rp, L.col, L.w64, t.h, t.scal, t.scal + 1, c->stream));
-    unsigned long long hb[2];
-    cmg_status st = d2h(c, hb, t.scal, 2);
+    CK(launch_rowinfo(L.n, L.lanes, L.rp, L.col, L.w64, t.h, t.bmax, t.scal + 4, c->stream));
+    unsigned long long hb[3];
+    cmg_status st = d2h(c, hb, t.scal + 4, 3);
     if (st != CMG_OK) return st;
-    double gv, wm;
+    double gv, wm, ex;
     std::memcpy(&gv, &hb[0], 8);
     std::memcpy(&wm, &hb[1], 8);
+    std::memcpy(&ex, &hb[2], 8);
     L.g = gv;
     L.wmax = wm;
+    L.w32exact = (ex == 0.0) ? 1 : 0;
     return CMG_OK;
 }
 
@@ -253,13 +257,14 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
     ALLOC(L.agg, int32_t, L.n);
     CK(launch_hec_label(L.n, t.rootseed, t.rank, L.agg, s));
     // Galerkin product
-    CK(hipMemsetAsync(t.scal + 3, 0, sizeof(unsigned long long), s));
-    CK(launch_gal_emit(L.n, L.lanes, L.rp, L.col, L.w64, L.agg, (int)nc, t.k0, t.v0, t.scal + 3, s));
-    int bits = bitlen((unsigned long long)nc * (unsigned long long)nc);
+    CK(launch_gal_emit(L.n, L.lanes, L.rp, L.col, L.w64, L.agg, (int)nc, t.k0, t.v0, s));
+    const unsigned long long sent = (unsigned long long)nc * (unsigned long long)nc;
+    int bits = bitlen(sent);
     int second = 0;
     CK(launch_sort(t.k0, t.v0, t.k1, t.v1, L.nnz, bits, t.sort_counts, t.sort_scan, &second, s));
     const unsigned long long* ks = second ? t.k1 : t.k0;
     const double* vs = second ? t.v1 : t.v0;
+    CK(launch_count_below(ks, L.nnz, sent, t.scal + 3, s));
     unsigned long long nvalid = 0;
     st = d2h(c, &nvalid, t.scal + 3, 1);
     if (st != CMG_OK) return st;
@@ -352,6 +357,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         d.part = L.part;
         d.mpart = nullptr;
         d.grid = L.grid;
+        d.w32exact = L.w32exact;
         ld[j] = d;
     }
     ALLOC(c->d_lv, LevelDev, J + 1);

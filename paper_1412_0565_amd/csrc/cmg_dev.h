@@ -69,6 +69,32 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
     __syncthreads();
 }
 
+// Deterministic block reduction with one barrier: waves post their sums to
+// a slot chosen by `parity` (flipped on return), every thread then adds the
+// posts in wave order.  Two alternating slots make back-to-back calls safe.
+// `red` holds 2 * NV * 16 doubles.
+template <int NV>
+__device__ __forceinline__ void block_sum1(double (&v)[NV], double* red, int& parity) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    double* slot = red + parity * NV * 16;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = group_sum_t<kWave>(v[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) slot[q * 16 + wv] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += slot[q * 16 + w];
+        v[q] = t;
+    }
+    parity ^= 1;
+}
+
 // --------------------------------------------------------------- levels
 
 // One level of the hierarchy as the refinement kernels see it.
@@ -89,7 +115,7 @@ struct LevelDev {
     const int32_t* part; // grid kernel: first row of each workgroup (grid+1 entries)
     const int32_t* mpart;// merge path: diagonal split of each workgroup (2*(grid+1))
     int32_t grid;
-    int32_t pad;
+    int32_t w32exact;    // 1 if every weight is exactly representable in FP32
 };
 
 // State a refinement launch leaves for the next level (device written).

@@ -19,16 +19,18 @@ hipError_t launch_validate(int n, int64_t nnz, const int32_t* rp, const int32_t*
                            int wf32, int full, unsigned* flags, hipStream_t s);
 hipError_t launch_convert_w(int64_t nnz, const void* w, int wf32, double* w64, hipStream_t s);
 hipError_t launch_to_f32(int64_t nnz, const double* w64, float* w32, hipStream_t s);
-// h[v] = heaviest neighbour (lowest index on ties); rowmax2/wmax as
-// uint64 bit patterns of non-negative doubles (atomic max).
+// h[v] = heaviest neighbour (lowest index on ties); out[0] = bits of the
+// Gershgorin shift 2 max_v d_v, out[1] = bits of the largest weight,
+// out[2] = bits of the largest FP32 rounding error of a weight.
+// bmax: scratch of 3 * kRowinfoMaxBlocks doubles.
+constexpr int kRowinfoMaxBlocks = 1024;
 hipError_t launch_rowinfo(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w,
-                          int32_t* h, unsigned long long* gbits, unsigned long long* wmaxbits,
-                          hipStream_t s);
+                          int32_t* h, double* bmax, unsigned long long* out, hipStream_t s);
 hipError_t launch_hec_init(int n, const int32_t* h, uint64_t seed, int level, uint8_t* live,
                            uint8_t* state, int32_t* pairseed, unsigned long long* slot, hipStream_t s);
 hipError_t launch_hec_round(int n, const int32_t* h, uint64_t seed, int level, uint8_t* live,
                             uint8_t* state, int32_t* pairseed, unsigned long long* slot,
-                            unsigned long long* live_count, hipStream_t s);
+                            unsigned long long* any_live, hipStream_t s);
 hipError_t launch_hec_attach(int n, const int32_t* h, const uint8_t* state, const int32_t* pairseed,
                              int32_t* rootseed, int32_t* flags, hipStream_t s);
 hipError_t launch_hec_label(int n, const int32_t* rootseed, const int32_t* rank, int32_t* agg,
@@ -40,7 +42,10 @@ hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, long long* tm
                        hipStream_t s);
 hipError_t launch_gal_emit(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w,
                            const int32_t* agg, int nc, unsigned long long* keys, double* vals,
-                           unsigned long long* nvalid, hipStream_t s);
+                           hipStream_t s);
+// *out = number of keys[0..m) below `sent` (keys sorted ascending)
+hipError_t launch_count_below(const unsigned long long* keys, int64_t m, unsigned long long sent,
+                              unsigned long long* out, hipStream_t s);
 // stable LSD radix sort of (key, val) pairs on the low `bits` bits; the
 // result ends in (k0, v0) or (k1, v1): returns which through *in_second.
 int64_t sort_tmp_elems(int64_t m);
@@ -76,5 +81,7 @@ hipError_t launch_reset_sync(GridSync* gs, hipStream_t s);
 
 constexpr int kGridBlock = 512;
 constexpr int kBlockKernelThreads = 1024;
+constexpr int kBlockLdsMax = 144 * 1024;  // LDS image budget of the single-workgroup kernel
+int refine_block_lds_budget();
 
 }  // namespace cmg

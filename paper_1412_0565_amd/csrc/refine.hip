@@ -345,15 +345,85 @@ __global__ void __launch_bounds__(256) k_coarse_dense(LevelDev L, LevelState* st
 
 // ------------------------------------------------ single-workgroup levels
 
+// LDS image of one small level: vectors first (8-byte aligned), then
+// weights, row pointers and columns.
+struct StagedLevel {
+    double* x0;
+    double* x1;
+    const void* w;  // float if w32, else double
+    const int32_t* rp;
+    const void* col;  // uint16 if col16, else int32
+};
+
+__device__ __forceinline__ size_t align8(size_t b) { return (b + 7) & ~(size_t)7; }
+
+// bytes of the LDS image; 0 if it does not fit in `budget`
+__device__ __forceinline__ size_t staged_bytes(const LevelDev& L, int w32, int col16) {
+    size_t b = align8(16 * (size_t)L.n);
+    b += align8((size_t)L.nnz * (w32 ? 4 : 8));
+    b += align8(4 * ((size_t)L.n + 1));
+    b += align8((size_t)L.nnz * (col16 ? 2 : 4));
+    return b;
+}
+
+// One PI step reading the LDS image; lane 0 of each G-lane group owns a row.
+template <int G, bool W32, bool C16>
+__device__ __forceinline__ void pi_rows_lds(const StagedLevel& S, int n, double g, const double* win,
+                                            double* wout, double mu, double s, double (&acc)[4]) {
+    const int lane = threadIdx.x & (G - 1);
+    const int ngroups = blockDim.x / G;
+    for (int i = (int)(threadIdx.x / G); i < n; i += ngroups) {
+        const int a = S.rp[i], b = S.rp[i + 1];
+        const double wi = win[i];
+        double t = 0.0;
+        for (int e = a + lane; e < b; e += G) {
+            const int c = C16 ? (int)((const uint16_t*)S.col)[e] : ((const int32_t*)S.col)[e];
+            const double wt = W32 ? (double)((const float*)S.w)[e] : ((const double*)S.w)[e];
+            t += wt * (win[c] - wi);
+        }
+        t = group_sum_t<G>(t);
+        if (lane == 0) {
+            const double x = (wi - mu) * s;
+            const double y = s * (g * (wi - mu) + t);
+            wout[i] = y;
+            acc[0] += y;
+            acc[1] += y * y;
+            acc[2] += y * x;
+            acc[3] += x;
+        }
+    }
+}
+
+template <bool W32, bool C16>
+__device__ __forceinline__ void pi_rows_lds_dispatch(int G, const StagedLevel& S, int n, double g,
+                                                     const double* win, double* wout, double mu, double s,
+                                                     double (&acc)[4]) {
+    switch (G) {
+        case 1: pi_rows_lds<1, W32, C16>(S, n, g, win, wout, mu, s, acc); break;
+        case 2: pi_rows_lds<2, W32, C16>(S, n, g, win, wout, mu, s, acc); break;
+        case 4: pi_rows_lds<4, W32, C16>(S, n, g, win, wout, mu, s, acc); break;
+        case 8: pi_rows_lds<8, W32, C16>(S, n, g, win, wout, mu, s, acc); break;
+        case 16: pi_rows_lds<16, W32, C16>(S, n, g, win, wout, mu, s, acc); break;
+        case 32: pi_rows_lds<32, W32, C16>(S, n, g, win, wout, mu, s, acc); break;
+        default: pi_rows_lds<64, W32, C16>(S, n, g, win, wout, mu, s, acc); break;
+    }
+}
+
 // Levels jhi down to jlo (all FP64, small) refined inside one workgroup:
 // prolongation, deflation, normalisation and every PI step separated only
-// by workgroup barriers, so thousands of steps cost no launches.
+// by workgroup barriers, so thousands of steps cost no launches.  A level
+// whose CSR and two vectors fit in `lds_budget` bytes is first copied to
+// LDS (columns as uint16 when n <= 65536, weights as FP32 when that is
+// exact), so its steps touch no global memory; larger levels stream from
+// global memory (L2).  The final vector of each level goes to buf0.
 __global__ void __launch_bounds__(kBlockKernelThreads)
     k_refine_block(const LevelDev* __restrict__ lv, LevelState* st, int jhi, int jlo,
-                   int uniform_start, double tol, int maxit, uint64_t seed) {
-    __shared__ double red[16 * 5 + 8];
+                   int uniform_start, double tol, int maxit, uint64_t seed, int lds_budget) {
+    extern __shared__ double lds[];
+    __shared__ double red[2 * 4 * 16];
     __shared__ double s_cm, s_cs;
     __shared__ int s_cfin;
+    int parity = 0;
     if (threadIdx.x == 0 && !uniform_start) {
         LevelState c = st[jhi + 1];
         s_cm = c.mu;
@@ -363,9 +433,43 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
     __syncthreads();
     for (int j = jhi; j >= jlo; --j) {
         const LevelDev L = lv[j];
-        double* b0 = (double*)L.buf0;
-        double* b1 = (double*)L.buf1;
         const int n = L.n;
+        // ---- choose where the level lives
+        const int c16 = (n <= 65536) ? 1 : 0;
+        int w32 = 0;
+        size_t need = staged_bytes(L, 0, c16);
+        if (need > (size_t)lds_budget && L.w32exact) {
+            w32 = 1;
+            need = staged_bytes(L, 1, c16);
+        }
+        const bool staged = need <= (size_t)lds_budget;
+        StagedLevel S;
+        double* b0;
+        double* b1;
+        if (staged) {
+            char* p = (char*)lds;
+            S.x0 = (double*)p;
+            S.x1 = S.x0 + n;
+            p += align8(16 * (size_t)n);
+            S.w = p;
+            p += align8((size_t)L.nnz * (w32 ? 4 : 8));
+            S.rp = (const int32_t*)p;
+            p += align8(4 * ((size_t)n + 1));
+            S.col = p;
+            for (int i = threadIdx.x; i <= n; i += blockDim.x) ((int32_t*)S.rp)[i] = L.rp[i];
+            for (int e = threadIdx.x; e < (int)L.nnz; e += blockDim.x) {
+                if (c16) ((uint16_t*)S.col)[e] = (uint16_t)L.col[e];
+                else ((int32_t*)S.col)[e] = L.col[e];
+                if (w32) ((float*)S.w)[e] = (float)L.w64[e];
+                else ((double*)S.w)[e] = L.w64[e];
+            }
+            b0 = S.x0;
+            b1 = S.x1;
+        } else {
+            b0 = (double*)L.buf0;
+            b1 = (double*)L.buf1;
+        }
+        // ---- prolongation (or hashed uniform start), deflation, norm
         double sum[1] = {0.0};
         if (uniform_start && j == jhi) {
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -383,14 +487,14 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
                 sum[0] += v;
             }
         }
-        block_sum<1>(sum, red);
+        block_sum1<1>(sum, red, parity);
         double mu = sum[0] / (double)n;
         double ss[1] = {0.0};
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             double d = b0[i] - mu;
             ss[0] += d * d;
         }
-        block_sum<1>(ss, red);
+        block_sum1<1>(ss, red, parity);
         double s = 1.0 / sqrt(ss[0]);
         int cur = 0, k = 0, hit = 0;
         double utv = 0.0, pmu = mu, ps = s;
@@ -398,8 +502,18 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
             const double* win = cur ? b1 : b0;
             double* wout = cur ? b0 : b1;
             double acc[4] = {0.0, 0.0, 0.0, 0.0};
-            pi_rows_dispatch<double>(L.lanes, L, win, wout, mu, s, 0, n, acc);
-            block_sum<4>(acc, red);
+            if (staged) {
+                if (w32) {
+                    if (c16) pi_rows_lds_dispatch<true, true>(L.lanes, S, n, L.g, win, wout, mu, s, acc);
+                    else pi_rows_lds_dispatch<true, false>(L.lanes, S, n, L.g, win, wout, mu, s, acc);
+                } else {
+                    if (c16) pi_rows_lds_dispatch<false, true>(L.lanes, S, n, L.g, win, wout, mu, s, acc);
+                    else pi_rows_lds_dispatch<false, false>(L.lanes, S, n, L.g, win, wout, mu, s, acc);
+                }
+            } else {
+                pi_rows_dispatch<double>(L.lanes, L, win, wout, mu, s, 0, n, acc);
+            }
+            block_sum1<4>(acc, red, parity);
             const double mu2 = acc[0] / (double)n;
             const double s2 = 1.0 / sqrt(acc[1] - acc[0] * mu2);
             utv = s2 * (acc[2] - mu2 * acc[3]);
@@ -415,6 +529,19 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
                 break;
             }
         }
+        // final vector to global buf0 (staged levels live in LDS until here)
+        int fin = cur;
+        if (staged) {
+            const double* src = cur ? b1 : b0;
+            const double* prv = cur ? b0 : b1;
+            double* g0 = (double*)L.buf0;
+            double* g1 = (double*)L.buf1;
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                g0[i] = src[i];
+                g1[i] = prv[i];
+            }
+            fin = 0;
+        }
         if (threadIdx.x == 0) {
             LevelState o;
             o.mu = mu;
@@ -423,14 +550,14 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
             o.s_prev = ps;
             o.utv = utv;
             o.margin = utv - (1.0 - tol);
-            o.fin = cur;
+            o.fin = fin;
             o.k = k;
             o.maxit = hit;
             o.err = 0;
             st[j] = o;
             s_cm = mu;
             s_cs = s;
-            s_cfin = cur;
+            s_cfin = fin;
         }
         __syncthreads();
     }
@@ -637,10 +764,33 @@ hipError_t launch_coarse_dense(LevelDev L, LevelState* st, double* A, double* V,
     return hipGetLastError();
 }
 
+int refine_block_lds_budget() {
+    static int budget = -1;
+    if (budget < 0) {
+        int dev = 0, maxsh = 65536;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        hipFuncAttributes fa;
+        size_t stat = 0;
+        if (hipFuncGetAttributes(&fa, (const void*)k_refine_block) == hipSuccess) stat = fa.sharedSizeBytes;
+        long b = std::min<long>(kBlockLdsMax, (long)maxsh - (long)stat - 256);
+        b = std::max<long>(b, 0);
+        if (b > 65536 - (long)stat - 256 &&
+            hipFuncSetAttribute((const void*)k_refine_block, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)b) != hipSuccess) {
+            (void)hipGetLastError();
+            b = std::max<long>(0, 65536 - (long)stat - 256);
+        }
+        budget = (int)(b & ~7L);
+    }
+    return budget;
+}
+
 hipError_t launch_refine_block(const LevelDev* lv, LevelState* st, int jhi, int jlo, int uniform_start,
                                double tol, int maxit, uint64_t seed, hipStream_t s) {
-    hipLaunchKernelGGL(k_refine_block, dim3(1), dim3(kBlockKernelThreads), 0, s, lv, st, jhi, jlo,
-                       uniform_start, tol, maxit, seed);
+    const int budget = refine_block_lds_budget();
+    hipLaunchKernelGGL(k_refine_block, dim3(1), dim3(kBlockKernelThreads), (size_t)budget, s, lv, st, jhi,
+                       jlo, uniform_start, tol, maxit, seed, budget);
     return hipGetLastError();
 }
 

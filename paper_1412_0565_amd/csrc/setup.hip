@@ -97,11 +97,11 @@ __global__ void k_to_f32(int64_t nnz, const double* __restrict__ in, float* __re
 template <int G>
 __global__ void k_rowinfo(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                           const double* __restrict__ w, int32_t* __restrict__ h,
-                          unsigned long long* gbits, unsigned long long* wmaxbits) {
+                          double* __restrict__ bmax) {
     const int lane = threadIdx.x & (G - 1);
     const int gpb = blockDim.x / G;
     int row = blockIdx.x * gpb + threadIdx.x / G;
-    double dmax = 0.0, wm = 0.0;
+    double dmax = 0.0, wm = 0.0, ex = 0.0;
     const int stride = gridDim.x * gpb;
     for (; row < n; row += stride) {
         int a = rp[row], b = rp[row + 1];
@@ -112,6 +112,7 @@ __global__ void k_rowinfo(int n, const int32_t* __restrict__ rp, const int32_t* 
             double x = w[e];
             int c = col[e];
             d += x;
+            ex = fmax(ex, fabs(x - (double)(float)x));
             if (x > bw || (x == bw && c < bc)) {
                 bw = x;
                 bc = c;
@@ -133,26 +134,63 @@ __global__ void k_rowinfo(int n, const int32_t* __restrict__ rp, const int32_t* 
             wm = fmax(wm, bw);
         }
     }
-    // block max then one atomic per block (non-negative doubles order like
-    // their bit patterns)
-    __shared__ double sm[2][kBlk / kWave];
+    // block maxima (exact, order independent) to bmax[3b .. 3b+2]
+    __shared__ double sm[3][kBlk / kWave];
     for (int o = 32; o > 0; o >>= 1) {
         dmax = fmax(dmax, __shfl_xor(dmax, o, kWave));
         wm = fmax(wm, __shfl_xor(wm, o, kWave));
+        ex = fmax(ex, __shfl_xor(ex, o, kWave));
     }
     if ((threadIdx.x & 63) == 0) {
         sm[0][threadIdx.x >> 6] = dmax;
         sm[1][threadIdx.x >> 6] = wm;
+        sm[2][threadIdx.x >> 6] = ex;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double a = 0.0, b = 0.0;
+        double a = 0.0, b = 0.0, c = 0.0;
         for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
             a = fmax(a, sm[0][q]);
             b = fmax(b, sm[1][q]);
+            c = fmax(c, sm[2][q]);
         }
-        atomicMax(gbits, (unsigned long long)__double_as_longlong(a));
-        atomicMax(wmaxbits, (unsigned long long)__double_as_longlong(b));
+        bmax[3 * blockIdx.x] = a;
+        bmax[3 * blockIdx.x + 1] = b;
+        bmax[3 * blockIdx.x + 2] = c;
+    }
+}
+
+// one block: maxima over the per-block values; results as double bit
+// patterns in out[0] (g), out[1] (largest weight), out[2] (largest FP32
+// rounding error of a weight: 0 if all weights are exact in FP32)
+__global__ void k_max_reduce(const double* __restrict__ bmax, int nb, unsigned long long* out) {
+    __shared__ double sm[3][kBlk / kWave];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        a = fmax(a, bmax[3 * i]);
+        b = fmax(b, bmax[3 * i + 1]);
+        c = fmax(c, bmax[3 * i + 2]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a = fmax(a, __shfl_xor(a, o, kWave));
+        b = fmax(b, __shfl_xor(b, o, kWave));
+        c = fmax(c, __shfl_xor(c, o, kWave));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sm[0][threadIdx.x >> 6] = a;
+        sm[1][threadIdx.x >> 6] = b;
+        sm[2][threadIdx.x >> 6] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+            a = fmax(a, sm[0][q]);
+            b = fmax(b, sm[1][q]);
+            c = fmax(c, sm[2][q]);
+        }
+        out[0] = (unsigned long long)__double_as_longlong(a);
+        out[1] = (unsigned long long)__double_as_longlong(b);
+        out[2] = (unsigned long long)__double_as_longlong(c);
     }
 }
 
@@ -205,10 +243,11 @@ __global__ void k_hec_accept(int n, const int32_t* __restrict__ h, uint64_t seed
 }
 
 // Edges touching a matched endpoint die; survivors re-arm their slots for
-// the next round and are counted.
+// the next round and raise the "any live" flag (a plain store of 1: racing
+// writers store the same value).
 __global__ void k_hec_kill(int n, const int32_t* __restrict__ h, uint8_t* __restrict__ live,
                            const uint8_t* __restrict__ state, unsigned long long* slot,
-                           unsigned long long* live_count) {
+                           unsigned long long* any_live) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     int alive = 0;
     if (v < n && live[v]) {
@@ -221,8 +260,7 @@ __global__ void k_hec_kill(int n, const int32_t* __restrict__ h, uint8_t* __rest
             alive = 1;
         }
     }
-    unsigned long long b = __ballot(alive);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(live_count, (unsigned long long)__popcll(b));
+    if (__syncthreads_or(alive) && threadIdx.x == 0) *any_live = 1ull;
 }
 
 // Unmatched vertices follow h to a matched vertex (keys decrease along the
@@ -343,25 +381,33 @@ __global__ void k_scan_down(const int32_t* __restrict__ in, int32_t* __restrict_
 template <int G>
 __global__ void k_gal_emit(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                            const double* __restrict__ w, const int32_t* __restrict__ agg, int nc,
-                           unsigned long long* __restrict__ keys, double* __restrict__ vals,
-                           unsigned long long* nvalid) {
+                           unsigned long long* __restrict__ keys, double* __restrict__ vals) {
     const int lane = threadIdx.x & (G - 1);
     const int gpb = blockDim.x / G;
     const unsigned long long sent = (unsigned long long)nc * (unsigned long long)nc;
-    unsigned long long cnt = 0;
     for (int row = blockIdx.x * gpb + threadIdx.x / G; row < n; row += gridDim.x * gpb) {
         int a = agg[row];
         int e0 = rp[row], e1 = rp[row + 1];
         for (int e = e0 + lane; e < e1; e += G) {
             int b = agg[col[e]];
             unsigned long long k = (a == b) ? sent : (unsigned long long)a * (unsigned long long)nc + b;
-            cnt += (a != b);
             keys[e] = k;
             vals[e] = w[e];
         }
     }
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, kWave);
-    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(nvalid, cnt);
+}
+
+// number of sorted keys below the sentinel (binary search, one thread)
+__global__ void k_count_below(const unsigned long long* __restrict__ keys, int64_t m,
+                              unsigned long long sent, unsigned long long* out) {
+    if (threadIdx.x != 0) return;
+    int64_t lo = 0, hi = m;  // first index with key >= sent
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < sent) lo = mid + 1;
+        else hi = mid;
+    }
+    *out = (unsigned long long)lo;
 }
 
 __global__ void k_gal_heads(int64_t m, const unsigned long long* __restrict__ keys,
@@ -543,21 +589,20 @@ hipError_t launch_to_f32(int64_t nnz, const double* w64, float* w32, hipStream_t
 }
 
 hipError_t launch_rowinfo(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w,
-                          int32_t* h, unsigned long long* gbits, unsigned long long* wmaxbits,
-                          hipStream_t s) {
+                          int32_t* h, double* bmax, unsigned long long* out, hipStream_t s) {
     int gpb = kBlk / lanes;
-    unsigned nb = (unsigned)std::min<int64_t>(nblocks(n, gpb), 65536);
+    unsigned nb = (unsigned)std::min<int64_t>(nblocks(n, gpb), kRowinfoMaxBlocks);
     switch (lanes) {
 #define CMG_RI(G)                                                                                  \
     case G:                                                                                        \
-        hipLaunchKernelGGL(k_rowinfo<G>, dim3(nb), dim3(kBlk), 0, s, n, rp, col, w, h, gbits,       \
-                           wmaxbits);                                                              \
+        hipLaunchKernelGGL(k_rowinfo<G>, dim3(nb), dim3(kBlk), 0, s, n, rp, col, w, h, bmax);       \
         break;
         CMG_RI(1) CMG_RI(2) CMG_RI(4) CMG_RI(8) CMG_RI(16) CMG_RI(32) CMG_RI(64)
 #undef CMG_RI
         default:
             return hipErrorInvalidValue;
     }
+    hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(kBlk), 0, s, bmax, (int)nb, out);
     return hipGetLastError();
 }
 
@@ -570,12 +615,12 @@ hipError_t launch_hec_init(int n, const int32_t* h, uint64_t seed, int level, ui
 
 hipError_t launch_hec_round(int n, const int32_t* h, uint64_t seed, int level, uint8_t* live,
                             uint8_t* state, int32_t* pairseed, unsigned long long* slot,
-                            unsigned long long* live_count, hipStream_t s) {
+                            unsigned long long* any_live, hipStream_t s) {
     unsigned nb = nblocks(n, kBlk);
     hipLaunchKernelGGL(k_hec_post, dim3(nb), dim3(kBlk), 0, s, n, h, seed, level, live, slot);
     hipLaunchKernelGGL(k_hec_accept, dim3(nb), dim3(kBlk), 0, s, n, h, seed, level, live, state,
                        pairseed, slot);
-    hipLaunchKernelGGL(k_hec_kill, dim3(nb), dim3(kBlk), 0, s, n, h, live, state, slot, live_count);
+    hipLaunchKernelGGL(k_hec_kill, dim3(nb), dim3(kBlk), 0, s, n, h, live, state, slot, any_live);
     return hipGetLastError();
 }
 
@@ -608,14 +653,14 @@ hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, long long* tm
 
 hipError_t launch_gal_emit(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w,
                            const int32_t* agg, int nc, unsigned long long* keys, double* vals,
-                           unsigned long long* nvalid, hipStream_t s) {
+                           hipStream_t s) {
     int gpb = kBlk / lanes;
     unsigned nb = (unsigned)std::min<int64_t>(nblocks(n, gpb), 65536);
     switch (lanes) {
 #define CMG_GE(G)                                                                                  \
     case G:                                                                                        \
         hipLaunchKernelGGL(k_gal_emit<G>, dim3(nb), dim3(kBlk), 0, s, n, rp, col, w, agg, nc, keys, \
-                           vals, nvalid);                                                          \
+                           vals);                                                                  \
         break;
         CMG_GE(1) CMG_GE(2) CMG_GE(4) CMG_GE(8) CMG_GE(16) CMG_GE(32) CMG_GE(64)
 #undef CMG_GE
@@ -650,6 +695,12 @@ hipError_t launch_sort(unsigned long long* k0, double* v0, unsigned long long* k
         std::swap(vin, vout);
         *in_second ^= 1;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_count_below(const unsigned long long* keys, int64_t m, unsigned long long sent,
+                              unsigned long long* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_below, dim3(1), dim3(64), 0, s, keys, m, sent, out);
     return hipGetLastError();
 }
 

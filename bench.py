@@ -141,6 +141,9 @@ def main():
         return el, pis, ks, byts, lams, setups, st, levels
 
     el, pis, ks, byts, lams, setups, st, levels = timed(fp64_opt, args.steps, args.warmup, "fp64 end-to-end")
+    for j, L in enumerate(levels):
+        log(f"[bench]   level {j}: n={L.n} nnz={L.nnz} k={L.k} lanes={L.lanes} grid={L.grid} "
+            f"block={L.in_block} fp32={L.fp32} pi_ms={L.pi_ms:.4f}")
     value = args.steps / el
     ms_per_step = 1000.0 * el / args.steps
 

@@ -46,6 +46,7 @@ struct HostLevel {
     int32_t* agg = nullptr;
     double g = 0.0, wmax = 0.0;
     int w32exact = 0;
+    int64_t maxlen = 0;
     int fp32 = 0, in_block = 0, lanes = 8, grid = 0, variant = 1;
     void* buf0 = nullptr;
     void* buf1 = nullptr;
@@ -55,8 +56,10 @@ struct HostLevel {
     double pi_ms = 0.0;
 };
 
+// Lanes per row for the row-group kernels: about five entries per lane
+// (two lanes per row on 6-10-regular meshes measured best on gfx950).
 int pick_lanes(double avg_deg) {
-    double t = 0.75 * avg_deg;
+    double t = avg_deg / 5.0;
     int g = 1;
     while (g < t && g < 64) g <<= 1;
     return g;
@@ -83,7 +86,19 @@ struct cmg_ctx {
     LevelDev* d_lv = nullptr;
     LevelState* d_st = nullptr;
     GridSync* d_sync = nullptr;
-    double* d_partials = nullptr;
+    GridSlot* d_slots = nullptr;
+    int nslots = 0;
+    GridJob* d_jobs = nullptr;  // [j] refines level j, [J+1] finishes level 0
+    std::vector<GridJob> h_jobs;
+    CoarseJob* d_cjob = nullptr;
+    BlockJob* d_bjob = nullptr;
+    CoarseJob h_cjob{};
+    BlockJob h_bjob{};
+    int top = 0;       // finest-to-coarsest: levels top .. 0 are refined
+    // host staging of the results of the last solve
+    FinishOut h_fo{};
+    std::vector<LevelState> h_st;
+    GridSync h_gs{};
     double* d_bcast = nullptr;
     FinishOut* d_fo = nullptr;
     double* d_A = nullptr;
@@ -193,7 +208,7 @@ cmg_status alloc_tmp(cmg_ctx* c, SetupTmp& t, int32_t n, int64_t nnz) {
     ALLOC(t.scal, unsigned long long, 8);
     ALLOC(t.totals, long long, 4);
     ALLOC(t.vflags, unsigned, 4);
-    ALLOC(t.bmax, double, 3 * kRowinfoMaxBlocks);
+    ALLOC(t.bmax, double, 4 * kRowinfoMaxBlocks);
     return CMG_OK;
 }
 
@@ -211,16 +226,18 @@ void free_tmp(cmg_ctx* c, SetupTmp& t) {
 // Gershgorin shift, heaviest neighbours and largest weight of one level.
 cmg_status level_rowinfo(cmg_ctx* c, SetupTmp& t, HostLevel& L) {
     CK(launch_rowinfo(L.n, L.lanes, L.rp, L.col, L.w64, t.h, t.bmax, t.scal + 4, c->stream));
-    unsigned long long hb[3];
-    cmg_status st = d2h(c, hb, t.scal + 4, 3);
+    unsigned long long hb[4];
+    cmg_status st = d2h(c, hb, t.scal + 4, 4);
     if (st != CMG_OK) return st;
-    double gv, wm, ex;
+    double gv, wm, ex, ml;
     std::memcpy(&gv, &hb[0], 8);
     std::memcpy(&wm, &hb[1], 8);
     std::memcpy(&ex, &hb[2], 8);
+    std::memcpy(&ml, &hb[3], 8);
     L.g = gv;
     L.wmax = wm;
     L.w32exact = (ex == 0.0) ? 1 : 0;
+    L.maxlen = (int64_t)ml;
     return CMG_OK;
 }
 
@@ -289,6 +306,36 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
     return CMG_OK;
 }
 
+LevelDev level_dev(const HostLevel& L) {
+    LevelDev d{};
+    d.n = L.n;
+    d.lanes = L.lanes;
+    d.nnz = L.nnz;
+    d.rp = L.rp;
+    d.col = L.col;
+    d.w64 = L.w64;
+    d.w32 = L.w32;
+    d.agg = L.agg;
+    d.g = L.g;
+    d.fp32 = L.fp32;
+    d.variant = L.variant;
+    d.buf0 = L.buf0;
+    d.buf1 = L.buf1;
+    d.part = L.part;
+    d.mpart = nullptr;
+    d.grid = L.grid;
+    d.w32exact = L.w32exact;
+    return d;
+}
+
+// SpMV traversal of a grid level: rows per lane group unless the longest
+// row dwarfs the mean (skewed degrees), then the merge path.
+int choose_variant(const HostLevel& L, int requested) {
+    if (requested == 1 || requested == 2) return requested;
+    const double avg = L.nnz / (double)std::max(L.n, 1);
+    return (L.maxlen > 256 && L.maxlen > 32.0 * avg) ? 2 : 1;
+}
+
 cmg_status build_refine_plan(cmg_ctx* c) {
     const int J = (int)c->lv.size() - 1;
     const cmg_options& o = c->opt;
@@ -303,9 +350,8 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         if (c->lv[j].n <= block_rows) c->block_lo = j;
         else break;
     }
-    int dev = 0, ncu = 0;
-    CK(hipGetDevice(&dev));
-    CK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int cap_refine = std::max(8, (refine_jobs_max_blocks() / 8) * 8);
+    const int cap_finish = std::max(8, (finish_jobs_max_blocks() / 8) * 8);
     int maxgrid = 8;
     for (int j = 0; j <= J; ++j) {
         HostLevel& L = c->lv[j];
@@ -314,7 +360,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         if (o.precision == CMG_MIXED && !L.in_block && j <= top && L.nnz >= mixed_min &&
             L.wmax < 16777216.0 && !(j == J && c->coarse_dense))
             L.fp32 = 1;
-        L.variant = 1;
+        L.variant = choose_variant(L, o.spmv_variant);
         const size_t vb = L.fp32 ? 4 : 8;
         L.buf0 = c->dalloc(vb * (size_t)L.n);
         L.buf1 = c->dalloc(vb * (size_t)L.n);
@@ -325,9 +371,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         }
         // grid size: about 8k rows+entries per workgroup, multiple of 8,
         // at most what can be co-resident
-        int cap = refine_grid_max_blocks(L.fp32, L.lanes, L.variant);
-        if (j == 0) cap = std::min(cap, finish_max_blocks(L.fp32, L.lanes, L.variant));
-        cap = std::max(8, (cap / 8) * 8);
+        int cap = (j == 0) ? std::min(cap_refine, cap_finish) : cap_refine;
         int64_t work = (int64_t)L.n + L.nnz;
         int64_t want = (work + 8191) / 8192;
         want = ((want + 7) / 8) * 8;
@@ -336,35 +380,15 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         ALLOC(L.part, int32_t, L.grid + 1);
         CK(launch_partition(L.n, L.nnz, L.rp, L.grid, L.part, c->stream));
     }
-    (void)ncu;
     std::vector<LevelDev> ld(J + 1);
-    for (int j = 0; j <= J; ++j) {
-        HostLevel& L = c->lv[j];
-        LevelDev d{};
-        d.n = L.n;
-        d.lanes = L.lanes;
-        d.nnz = L.nnz;
-        d.rp = L.rp;
-        d.col = L.col;
-        d.w64 = L.w64;
-        d.w32 = L.w32;
-        d.agg = L.agg;
-        d.g = L.g;
-        d.fp32 = L.fp32;
-        d.variant = L.variant;
-        d.buf0 = L.buf0;
-        d.buf1 = L.buf1;
-        d.part = L.part;
-        d.mpart = nullptr;
-        d.grid = L.grid;
-        d.w32exact = L.w32exact;
-        ld[j] = d;
-    }
+    for (int j = 0; j <= J; ++j) ld[j] = level_dev(c->lv[j]);
     ALLOC(c->d_lv, LevelDev, J + 1);
     CK(hipMemcpyAsync(c->d_lv, ld.data(), sizeof(LevelDev) * (J + 1), hipMemcpyHostToDevice, c->stream));
     ALLOC(c->d_st, LevelState, J + 1);
     ALLOC(c->d_sync, GridSync, 1);
-    ALLOC(c->d_partials, double, 4 * (size_t)maxgrid + 8);
+    c->nslots = maxgrid;
+    ALLOC(c->d_slots, GridSlot, maxgrid);
+    CK(launch_reset_sync(c->d_sync, c->d_slots, c->nslots, c->stream));
     ALLOC(c->d_bcast, double, 8);
     ALLOC(c->d_fo, FinishOut, 1);
     const int dm = std::max(CJ.n, 2);
@@ -378,8 +402,75 @@ cmg_status build_refine_plan(cmg_ctx* c) {
     ALLOC(c->d_y, double, n0);
     if (c->lv[0].fp32 && o.fp64_final_sweeps > 0) {
         ALLOC(c->d_fa, double, n0);
-        ALLOC(c->d_fb, double, n0);
+        ALLOC(c->d_fb, double, 8);
     }
+    // static job table: one refinement job per level, one finishing job
+    std::vector<GridJob> jobs(J + 2);
+    for (int j = 0; j <= J; ++j) {
+        GridJob g{};
+        g.L = ld[j];
+        g.C = (j < J) ? ld[j + 1] : ld[j];
+        g.st = c->d_st + j;
+        g.stc = (j < J) ? c->d_st + j + 1 : nullptr;
+        g.gs = c->d_sync;
+        g.slots = c->d_slots;
+        g.bcast = c->d_bcast;
+        g.uniform = (j == J) ? 1 : 0;
+        g.tol = o.tol;
+        g.seed = o.seed;
+        g.maxit = o.max_iters_per_level;
+        g.b0 = 0;
+        jobs[j] = g;
+    }
+    {
+        GridJob g{};
+        g.L = ld[0];
+        g.C = ld[0];
+        g.st = nullptr;
+        g.stc = c->d_st;
+        g.gs = c->d_sync;
+        g.slots = c->d_slots;
+        g.bcast = c->d_bcast;
+        g.fa = c->d_fa;
+        g.yout = c->d_y;
+        g.fo = c->d_fo;
+        g.redo = (c->lv[0].fp32 && c->d_fa && o.fp64_final_sweeps > 0) ? 1 : 0;
+        g.b0 = 0;
+        jobs[J + 1] = g;
+    }
+    c->h_jobs = jobs;
+    ALLOC(c->d_jobs, GridJob, J + 2);
+    CK(hipMemcpyAsync(c->d_jobs, jobs.data(), sizeof(GridJob) * (J + 2), hipMemcpyHostToDevice, c->stream));
+    c->top = top;
+    if (c->coarse_dense) {
+        CoarseJob cj{};
+        cj.L = ld[J];
+        cj.st = c->d_st + J;
+        cj.A = c->d_A;
+        cj.V = c->d_V;
+        cj.ev = c->d_ev;
+        cj.idx = c->d_idx;
+        cj.fo = c->d_fo;
+        cj.seed = o.seed;
+        c->h_cjob = cj;
+        ALLOC(c->d_cjob, CoarseJob, 1);
+        CK(hipMemcpyAsync(c->d_cjob, &cj, sizeof(cj), hipMemcpyHostToDevice, c->stream));
+    }
+    if (top >= 0 && c->block_lo <= top) {
+        BlockJob bj{};
+        bj.lv = c->d_lv;
+        bj.st = c->d_st;
+        bj.tol = o.tol;
+        bj.seed = o.seed;
+        bj.maxit = o.max_iters_per_level;
+        bj.jhi = top;
+        bj.jlo = c->block_lo;
+        bj.uniform = (!c->coarse_dense && top == J) ? 1 : 0;
+        c->h_bjob = bj;
+        ALLOC(c->d_bjob, BlockJob, 1);
+        CK(hipMemcpyAsync(c->d_bjob, &bj, sizeof(bj), hipMemcpyHostToDevice, c->stream));
+    }
+    c->h_st.resize(J + 1);
     c->events.resize(2 * (J + 1));
     for (auto& e : c->events) CK(hipEventCreate(&e));
     CK(hipStreamSynchronize(c->stream));
@@ -468,98 +559,28 @@ void fill_defaults(cmg_options* o) {
     o->spmv_variant = 0;
 }
 
-cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where, cmg_stats* stats) {
-    const double t0 = now_ms();
-    hipStream_t s = c->stream;
+// Device results of the last solve -> host staging (asynchronous).
+cmg_status enqueue_readback(cmg_ctx* c, void* x, cmg_memspace where, hipStream_t s) {
     const int J = (int)c->lv.size() - 1;
-    const cmg_options& o = c->opt;
-    CK(launch_reset_sync(c->d_sync, s));
-    int top = J;
-    if (c->coarse_dense) {
-        HostLevel& CJ = c->lv[J];
-        LevelDev d{};
-        d.n = CJ.n;
-        d.rp = CJ.rp;
-        d.col = CJ.col;
-        d.w64 = CJ.w64;
-        d.buf0 = CJ.buf0;
-        d.buf1 = CJ.buf1;
-        d.g = CJ.g;
-        CK(launch_coarse_dense(d, c->d_st + J, c->d_A, c->d_V, c->d_ev, c->d_idx, o.seed, c->d_fo, s));
-        top = J - 1;
-    }
-    // levels refined inside one workgroup
-    if (top >= 0 && c->block_lo <= top) {
-        int uni = (!c->coarse_dense && top == J) ? 1 : 0;
-        CK(launch_refine_block(c->d_lv, c->d_st, top, c->block_lo, uni, o.tol, o.max_iters_per_level,
-                               o.seed, s));
-    }
-    // grid levels
-    LevelDev ld_j, ld_c;
-    for (int j = std::min(top, c->block_lo - 1); j >= 0; --j) {
-        HostLevel& L = c->lv[j];
-        auto mk = [&](int q) {
-            HostLevel& H = c->lv[q];
-            LevelDev d{};
-            d.n = H.n;
-            d.lanes = H.lanes;
-            d.nnz = H.nnz;
-            d.rp = H.rp;
-            d.col = H.col;
-            d.w64 = H.w64;
-            d.w32 = H.w32;
-            d.agg = H.agg;
-            d.g = H.g;
-            d.fp32 = H.fp32;
-            d.variant = H.variant;
-            d.buf0 = H.buf0;
-            d.buf1 = H.buf1;
-            d.part = H.part;
-            d.grid = H.grid;
-            return d;
-        };
-        ld_j = mk(j);
-        int uni = (j == J) ? 1 : 0;
-        ld_c = uni ? ld_j : mk(j + 1);
-        CK(hipEventRecord(c->events[2 * j], s));
-        CK(launch_refine_grid(ld_j, ld_c, c->d_st + j, uni ? nullptr : c->d_st + j + 1, uni, c->d_sync,
-                              c->d_partials, c->d_bcast, o.tol, o.max_iters_per_level, o.seed, s));
-        CK(hipEventRecord(c->events[2 * j + 1], s));
-        (void)L;
-    }
-    // finishing pass on level 0
-    {
-        HostLevel& L0 = c->lv[0];
-        LevelDev d{};
-        d.n = L0.n;
-        d.lanes = L0.lanes;
-        d.nnz = L0.nnz;
-        d.rp = L0.rp;
-        d.col = L0.col;
-        d.w64 = L0.w64;
-        d.w32 = L0.w32;
-        d.g = L0.g;
-        d.fp32 = L0.fp32;
-        d.buf0 = L0.buf0;
-        d.buf1 = L0.buf1;
-        d.part = L0.part;
-        d.grid = L0.grid;
-        int redo = (L0.fp32 && c->d_fa && o.fp64_final_sweeps > 0) ? 1 : 0;
-        CK(launch_finish(d, c->d_st, redo, c->d_fa, c->d_fb, c->d_y, c->d_sync, c->d_partials,
-                         c->d_bcast, c->d_fo, s));
-    }
-    FinishOut fo;
-    std::vector<LevelState> hst(J + 1);
-    CK(hipMemcpyAsync(&fo, c->d_fo, sizeof(fo), hipMemcpyDeviceToHost, s));
-    CK(hipMemcpyAsync(hst.data(), c->d_st, sizeof(LevelState) * (J + 1), hipMemcpyDeviceToHost, s));
-    GridSync gsh;
-    CK(hipMemcpyAsync(&gsh, c->d_sync, sizeof(gsh), hipMemcpyDeviceToHost, s));
+    CK(hipMemcpyAsync(&c->h_fo, c->d_fo, sizeof(FinishOut), hipMemcpyDeviceToHost, s));
+    CK(hipMemcpyAsync(c->h_st.data(), c->d_st, sizeof(LevelState) * (J + 1), hipMemcpyDeviceToHost, s));
+    CK(hipMemcpyAsync(&c->h_gs, c->d_sync, sizeof(GridSync), hipMemcpyDeviceToHost, s));
     if (x) {
         CK(hipMemcpyAsync(x, c->d_y, sizeof(double) * c->lv[0].n,
                           where == CMG_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
     }
-    CK(hipStreamSynchronize(s));
-    if (gsh.abort) return CMG_E_DEVICE;
+    return CMG_OK;
+}
+
+// After the stream has drained: statistics, status, lambda.
+cmg_status finalize(cmg_ctx* c, double t0, bool timed, double* lambda, cmg_stats* stats) {
+    const int J = (int)c->lv.size() - 1;
+    if (c->h_gs.abort) {
+        // barrier state is unusable: start the epoch sequence afresh
+        CK(launch_reset_sync(c->d_sync, c->d_slots, c->nslots, c->stream));
+        CK(hipStreamSynchronize(c->stream));
+        return CMG_E_DEVICE;
+    }
     cmg_status status = CMG_OK;
     for (int j = 0; j <= J; ++j) {
         HostLevel& L = c->lv[j];
@@ -567,16 +588,17 @@ cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where,
             L.k = -1;
             L.margin = 0.0;
         } else {
-            L.k = hst[j].k;
-            L.margin = hst[j].margin;
-            if (hst[j].maxit) status = CMG_W_MAXIT;
+            L.k = c->h_st[j].k;
+            L.margin = c->h_st[j].margin;
+            if (c->h_st[j].maxit) status = CMG_W_MAXIT;
         }
         L.pi_ms = 0.0;
-        if (!L.in_block && j <= top) {
+        if (timed && !L.in_block && j <= c->top) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, c->events[2 * j], c->events[2 * j + 1]) == hipSuccess) L.pi_ms = ms;
         }
     }
+    const FinishOut& fo = c->h_fo;
     if (lambda) *lambda = fo.lambda;
     cmg_stats& st = c->last;
     std::memset(&st, 0, sizeof(st));
@@ -604,6 +626,126 @@ cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where,
         std::memcpy(stats, &st, std::min<size_t>(sz, sizeof(cmg_stats)));
     }
     return status;
+}
+
+cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where, cmg_stats* stats) {
+    const double t0 = now_ms();
+    hipStream_t s = c->stream;
+    const int J = (int)c->lv.size() - 1;
+    if (c->d_cjob) CK(launch_coarse_jobs(c->d_cjob, 1, s));
+    if (c->d_bjob) CK(launch_block_jobs(c->d_bjob, 1, s));
+    // grid levels: one cooperative launch per level
+    for (int j = std::min(c->top, c->block_lo - 1); j >= 0; --j) {
+        CK(hipEventRecord(c->events[2 * j], s));
+        CK(launch_refine_jobs(c->d_jobs + j, 1, c->lv[j].grid, s));
+        CK(hipEventRecord(c->events[2 * j + 1], s));
+    }
+    CK(launch_finish_jobs(c->d_jobs + J + 1, 1, c->lv[0].grid, s));
+    cmg_status st = enqueue_readback(c, x, where, s);
+    if (st != CMG_OK) return st;
+    CK(hipStreamSynchronize(s));
+    return finalize(c, t0, true, lambda, stats);
+}
+
+// Several graphs: every stage of all graphs in packed launches (one
+// workgroup per graph for the coarsest solve and the coarse levels; for
+// the grid levels, round r refines the r-th grid level, counted from the
+// coarse end, of every graph that has one, jobs packed up to the
+// co-resident capacity).  Each job runs the same code on the same
+// workgroup count as a single solve, so results are bitwise identical.
+cmg_status batch_impl(cmg_handle* hs, int32_t count, double* lambdas, void** xs, cmg_memspace where,
+                      cmg_stats* stats) {
+    const double t0 = now_ms();
+    cmg_ctx* c0 = hs[0];
+    hipStream_t s = c0->stream;
+    std::vector<CoarseJob> cj;
+    std::vector<BlockJob> bj;
+    int maxrounds = 0;
+    for (int i = 0; i < count; ++i) {
+        cmg_ctx* c = hs[i];
+        if (c->d_cjob) cj.push_back(c->h_cjob);
+        if (c->d_bjob) bj.push_back(c->h_bjob);
+        maxrounds = std::max(maxrounds, std::min(c->top, c->block_lo - 1) + 1);
+    }
+    // device tables: coarse | block | grid rounds | finish
+    std::vector<GridJob> gj;
+    std::vector<std::pair<size_t, int>> launches;  // (offset in gj, njobs), with kind below
+    std::vector<int> launch_blocks;
+    std::vector<int> launch_kind;  // 0 refine, 1 finish
+    const int cap_r = refine_jobs_max_blocks();
+    const int cap_f = finish_jobs_max_blocks();
+    auto pack = [&](std::vector<GridJob>& round, int kind) {
+        const int cap = kind ? cap_f : cap_r;
+        size_t i = 0;
+        while (i < round.size()) {
+            size_t first = gj.size();
+            int blocks = 0, nj = 0;
+            while (i < round.size() && (nj == 0 || blocks + round[i].L.grid <= cap)) {
+                GridJob g = round[i];
+                g.b0 = blocks;
+                blocks += g.L.grid;
+                gj.push_back(g);
+                ++nj;
+                ++i;
+            }
+            launches.push_back({first, nj});
+            launch_blocks.push_back(blocks);
+            launch_kind.push_back(kind);
+        }
+    };
+    for (int r = 0; r < maxrounds; ++r) {
+        std::vector<GridJob> round;
+        for (int i = 0; i < count; ++i) {
+            cmg_ctx* c = hs[i];
+            const int lo = std::min(c->top, c->block_lo - 1);  // coarsest grid level
+            const int j = lo - r;
+            if (lo >= 0 && j >= 0) round.push_back(c->h_jobs[j]);
+        }
+        pack(round, 0);
+    }
+    {
+        std::vector<GridJob> round;
+        for (int i = 0; i < count; ++i) round.push_back(hs[i]->h_jobs[hs[i]->lv.size()]);
+        pack(round, 1);
+    }
+    const size_t bytes = sizeof(CoarseJob) * cj.size() + sizeof(BlockJob) * bj.size() + sizeof(GridJob) * gj.size();
+    char* d = (char*)c0->dalloc(bytes + 64);
+    if (!d) return CMG_E_OOM;
+    std::vector<char> h(bytes);
+    size_t off = 0;
+    std::memcpy(h.data() + off, cj.data(), sizeof(CoarseJob) * cj.size());
+    CoarseJob* d_cj = (CoarseJob*)(d + off);
+    off += sizeof(CoarseJob) * cj.size();
+    std::memcpy(h.data() + off, bj.data(), sizeof(BlockJob) * bj.size());
+    BlockJob* d_bj = (BlockJob*)(d + off);
+    off += sizeof(BlockJob) * bj.size();
+    std::memcpy(h.data() + off, gj.data(), sizeof(GridJob) * gj.size());
+    GridJob* d_gj = (GridJob*)(d + off);
+    cmg_status status = CMG_OK;
+    hipError_t e = hipMemcpyAsync(d, h.data(), bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !cj.empty()) e = launch_coarse_jobs(d_cj, (int)cj.size(), s);
+    if (e == hipSuccess && !bj.empty()) e = launch_block_jobs(d_bj, (int)bj.size(), s);
+    for (size_t q = 0; e == hipSuccess && q < launches.size(); ++q) {
+        const GridJob* jp = d_gj + launches[q].first;
+        e = launch_kind[q] ? launch_finish_jobs(jp, launches[q].second, launch_blocks[q], s)
+                           : launch_refine_jobs(jp, launches[q].second, launch_blocks[q], s);
+    }
+    for (int i = 0; e == hipSuccess && i < count && status == CMG_OK; ++i)
+        status = enqueue_readback(hs[i], xs ? xs[i] : nullptr, where, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    c0->dfree(d);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return CMG_E_DEVICE;
+    }
+    if (status != CMG_OK) return status;
+    cmg_status worst = CMG_OK;
+    for (int i = 0; i < count; ++i) {
+        cmg_status st = finalize(hs[i], t0, false, lambdas ? lambdas + i : nullptr, stats ? stats + i : nullptr);
+        if (st != CMG_OK && st != CMG_W_MAXIT) return st;
+        if (st == CMG_W_MAXIT) worst = st;
+    }
+    return worst;
 }
 
 }  // namespace
@@ -672,14 +814,14 @@ cmg_status cmg_fiedler(cmg_handle h, double* lambda, void* x, cmg_memspace where
 cmg_status cmg_fiedler_batch(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
                              cmg_memspace where, cmg_stats* stats) {
     if (!hs || count < 0) return CMG_E_ARG;
-    cmg_status worst = CMG_OK;
+    if (where != CMG_MEM_HOST && where != CMG_MEM_DEVICE) return CMG_E_ARG;
+    if (count == 0) return CMG_OK;
     for (int32_t i = 0; i < count; ++i) {
-        cmg_status st = cmg_fiedler(hs[i], lambdas ? lambdas + i : nullptr, xs ? xs[i] : nullptr, where,
-                                    stats ? stats + i : nullptr);
-        if (st != CMG_OK && st != CMG_W_MAXIT) return st;
-        if (st == CMG_W_MAXIT) worst = st;
+        if (!hs[i]) return CMG_E_ARG;
+        for (int32_t k = 0; k < i; ++k)
+            if (hs[k] == hs[i]) return CMG_E_ARG;  // a handle's buffers serve one solve at a time
     }
-    return worst;
+    return batch_impl(hs, count, lambdas, xs, where, stats);
 }
 
 cmg_status cmg_level_info(cmg_handle h, cmg_level_stats* out, int32_t cap, int32_t* nlevels) {

@@ -144,11 +144,65 @@ struct FinishOut {
     int32_t err;
 };
 
+// Grid barrier state.  `epoch` counts completed grid barriers over the
+// handle's lifetime (never reset while healthy), so per-workgroup slots
+// tagged with an epoch need no clearing between launches.
 struct GridSync {
-    unsigned int count;
-    unsigned int gen;
+    unsigned long long epoch;
     unsigned int abort;
     unsigned int pad;
+};
+
+// One workgroup's contribution to a grid all-reduce: its partial sums and
+// the epoch of the barrier they belong to, in one 64-byte line.
+struct alignas(64) GridSlot {
+    double v[7];
+    unsigned long long epoch;
+};
+
+// One unit of a (possibly packed) grid launch: a level of one graph,
+// refined (or finished) by workgroups [b0, b0 + L.grid) of the launch.
+struct GridJob {
+    LevelDev L;             // level processed
+    LevelDev C;             // next coarser level (prolongation source)
+    LevelState* st;         // refine: state written for L
+    const LevelState* stc;  // refine: state of C; finish: state of L
+    GridSync* gs;           // barrier state of this graph
+    GridSlot* slots;
+    double* bcast;
+    double* fa;             // finish: FP64 scratch of n entries (mixed redo)
+    double* yout;           // finish: output vector
+    FinishOut* fo;          // finish: scalars out
+    double tol;             // refine: stopping tolerance
+    uint64_t seed;          // refine: hashed uniform start seed
+    int32_t maxit;          // refine: step cap
+    int32_t b0;
+    int32_t uniform;        // refine: hashed uniform start instead of prolongation
+    int32_t redo;           // finish: recompute the last step in FP64
+};
+
+// Coarse levels jhi .. jlo of one graph, refined by one workgroup.
+struct BlockJob {
+    const LevelDev* lv;
+    LevelState* st;
+    double tol;
+    uint64_t seed;
+    int32_t maxit;
+    int32_t jhi;
+    int32_t jlo;
+    int32_t uniform;
+};
+
+// Dense coarsest solve of one graph, one workgroup.
+struct CoarseJob {
+    LevelDev L;
+    LevelState* st;
+    double* A;
+    double* V;
+    double* ev;
+    int32_t* idx;
+    FinishOut* fo;
+    uint64_t seed;
 };
 
 }  // namespace cmg

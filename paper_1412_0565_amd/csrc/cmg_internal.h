@@ -21,8 +21,9 @@ hipError_t launch_convert_w(int64_t nnz, const void* w, int wf32, double* w64, h
 hipError_t launch_to_f32(int64_t nnz, const double* w64, float* w32, hipStream_t s);
 // h[v] = heaviest neighbour (lowest index on ties); out[0] = bits of the
 // Gershgorin shift 2 max_v d_v, out[1] = bits of the largest weight,
-// out[2] = bits of the largest FP32 rounding error of a weight.
-// bmax: scratch of 3 * kRowinfoMaxBlocks doubles.
+// out[2] = bits of the largest FP32 rounding error of a weight, out[3] =
+// bits of the longest row length (as a double).
+// bmax: scratch of 4 * kRowinfoMaxBlocks doubles.
 constexpr int kRowinfoMaxBlocks = 1024;
 hipError_t launch_rowinfo(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w,
                           int32_t* h, double* bmax, unsigned long long* out, hipStream_t s);
@@ -63,21 +64,18 @@ hipError_t launch_hash_probe(uint64_t seed, int level, int count, unsigned long 
 hipError_t launch_fill_u32(unsigned* p, unsigned v, int64_t m, hipStream_t s);
 
 // ---- refine.hip
-hipError_t launch_coarse_dense(LevelDev L, LevelState* st, double* A, double* V, double* ev,
-                               int32_t* idx, uint64_t seed, FinishOut* fo, hipStream_t s);
-// all levels jlo..jhi inside one workgroup (FP64 levels only)
-hipError_t launch_refine_block(const LevelDev* lv, LevelState* st, int jhi, int jlo, int uniform_start,
-                               double tol, int maxit, uint64_t seed, hipStream_t s);
-int refine_grid_max_blocks(int fp32, int lanes, int variant);
-hipError_t launch_refine_grid(const LevelDev& L, const LevelDev& C, LevelState* st_j,
-                              const LevelState* st_c, int uniform_start, GridSync* gs,
-                              double* partials, double* bcast, double tol, int maxit, uint64_t seed,
-                              hipStream_t s);
-int finish_max_blocks(int fp32, int lanes, int variant);
-hipError_t launch_finish(const LevelDev& L0, const LevelState* st0, int redo, double* f64a,
-                         double* f64b, double* yout, GridSync* gs, double* partials,
-                         double* bcast, FinishOut* fo, hipStream_t s);
-hipError_t launch_reset_sync(GridSync* gs, hipStream_t s);
+// dense coarsest solves, one workgroup per job
+hipError_t launch_coarse_jobs(const CoarseJob* jobs, int njobs, hipStream_t s);
+// coarse levels of each job inside one workgroup (FP64 levels only)
+hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, hipStream_t s);
+// co-resident workgroups of the job kernels (cooperative launch limit)
+int refine_jobs_max_blocks();
+int finish_jobs_max_blocks();
+// one level of each job; nblocks = sum of the jobs' grids
+hipError_t launch_refine_jobs(const GridJob* jobs, int njobs, int nblocks, hipStream_t s);
+hipError_t launch_finish_jobs(const GridJob* jobs, int njobs, int nblocks, hipStream_t s);
+// zero the barrier state and the slots (at setup, and after an abort)
+hipError_t launch_reset_sync(GridSync* gs, GridSlot* slots, int nslots, hipStream_t s);
 
 constexpr int kGridBlock = 512;
 constexpr int kBlockKernelThreads = 1024;

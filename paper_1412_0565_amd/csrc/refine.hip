@@ -41,80 +41,87 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
-// ~4 s at the 100 MHz constant clock: a safety bound, never reached when
+// ~2 s at the 100 MHz constant clock: a safety bound, never reached when
 // the grid is co-resident (cooperative launch).
-constexpr long long kSpinTicks = 400000000LL;
+constexpr long long kSpinTicks = 200000000LL;
 
-// Grid-wide sum of NV doubles with a barrier.  Every workgroup posts its
-// block sum; the last to arrive adds all posts in workgroup order (fixed
-// tree, independent of arrival order), publishes the totals and releases
-// the others.  Returns false if the barrier timed out or another
-// workgroup aborted.
+// Grid-wide sum of NV (<= 7) doubles with a barrier, free of contended
+// atomics: every workgroup writes its block sums and the barrier epoch into
+// its own 64-byte slot (release); workgroup 0 polls all slots in parallel,
+// adds them in slot order (a fixed tree, independent of arrival order) and
+// publishes the totals and the epoch (release); the others wait for the
+// epoch and read the totals.  Returns false if the barrier timed out or was
+// aborted; then every workgroup leaves.
 template <int NV>
-__device__ bool grid_allreduce(double (&v)[NV], GridSync* gs, double* partials, double* bcast,
-                               int lb, double* red) {
-    __shared__ unsigned s_gen;
-    __shared__ int s_last;
+__device__ bool grid_allreduce_impl(double (&v)[NV], GridSync* gs, GridSlot* slots, double* bcast,
+                                    unsigned long long& epoch, int lb, bool master, int nb,
+                                    double* red) {
     __shared__ double s_tot[NV];
     __shared__ int s_ok;
-    const int nb = gridDim.x;
+    const unsigned long long e = ++epoch;
     block_sum<NV>(v, red);
     if (threadIdx.x == 0) {
+        GridSlot* my = slots + lb;
 #pragma unroll
-        for (int q = 0; q < NV; ++q) partials[lb * NV + q] = v[q];
-        s_gen = __hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        unsigned prev = atomicAdd(&gs->count, 1u);
-        s_last = (prev == (unsigned)nb - 1);
+        for (int q = 0; q < NV; ++q) my->v[q] = v[q];
+        __hip_atomic_store(&my->epoch, e, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         s_ok = 1;
     }
     __syncthreads();
-    if (s_last) {
-        __threadfence();
+    if (master) {
         double acc[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) acc[q] = 0.0;
         for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+            const long long t0 = wall_clock64();
+            while (__hip_atomic_load(&slots[b].epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != e) {
+                __builtin_amdgcn_s_sleep(1);
+                if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                    wall_clock64() - t0 > kSpinTicks) {
+                    atomicOr(&gs->abort, 1u);
+                    s_ok = 0;
+                    break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 #pragma unroll
-            for (int q = 0; q < NV; ++q) acc[q] += ld_agent(partials + b * NV + q);
+            for (int q = 0; q < NV; ++q) acc[q] += ld_agent(&slots[b].v[q]);
         }
         block_sum<NV>(acc, red);
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == 0 && s_ok) {
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
                 st_agent(bcast + q, acc[q]);
                 s_tot[q] = acc[q];
             }
-            __hip_atomic_store(&gs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-            __hip_atomic_store(&gs->gen, s_gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&gs->epoch, e, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     } else if (threadIdx.x == 0) {
-        long long t0 = wall_clock64();
-        while (__hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == s_gen) {
-            __builtin_amdgcn_s_sleep(2);
-            if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                s_ok = 0;
-                break;
-            }
-            if (wall_clock64() - t0 > kSpinTicks) {
+        const long long t0 = wall_clock64();
+        while (__hip_atomic_load(&gs->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != e) {
+            __builtin_amdgcn_s_sleep(1);
+            if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                wall_clock64() - t0 > kSpinTicks) {
                 atomicOr(&gs->abort, 1u);
                 s_ok = 0;
                 break;
             }
         }
-        __threadfence();
-        if (s_ok) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) s_ok = 0;
 #pragma unroll
-            for (int q = 0; q < NV; ++q) s_tot[q] = ld_agent(bcast + q);
-        }
+        for (int q = 0; q < NV; ++q) s_tot[q] = ld_agent(bcast + q);
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = s_tot[q];
-    bool ok = s_ok != 0;
+    const bool ok = s_ok != 0;
     __syncthreads();
     return ok;
+}
+
+__device__ __forceinline__ unsigned long long start_epoch(GridSync* gs) {
+    return __hip_atomic_load(&gs->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // One power-iteration step on rows [r0, r1) with G lanes per row.  Lane 0
@@ -176,10 +183,17 @@ constexpr int kDenseLds = 48;
 // normalised projection of the ramp z_i = i - (n-1)/2 onto the eigenspace
 // of all eigenvalues (above the smallest) within 1e-10 ||A||_F of
 // lambda_2; a hashed uniform vector replaces z if that projection is tiny.
-__global__ void __launch_bounds__(256) k_coarse_dense(LevelDev L, LevelState* st, double* Ag,
-                                                     double* Vg, double* ev, int32_t* idx,
-                                                     uint64_t seed, FinishOut* fo) {
+__global__ void __launch_bounds__(256) k_coarse_jobs(const CoarseJob* __restrict__ jobs) {
     extern __shared__ double dyn[];
+    const CoarseJob& Jb = jobs[blockIdx.x];
+    const LevelDev L = Jb.L;
+    LevelState* st = Jb.st;
+    double* Ag = Jb.A;
+    double* Vg = Jb.V;
+    double* ev = Jb.ev;
+    int32_t* idx = Jb.idx;
+    const uint64_t seed = Jb.seed;
+    FinishOut* fo = Jb.fo;
     __shared__ double red[16 * 2 + 8];
     __shared__ double cs_c[128], cs_s[128];
     __shared__ int pr_p[128], pr_q[128];
@@ -417,9 +431,15 @@ __device__ __forceinline__ void pi_rows_lds_dispatch(int G, const StagedLevel& S
 // exact), so its steps touch no global memory; larger levels stream from
 // global memory (L2).  The final vector of each level goes to buf0.
 __global__ void __launch_bounds__(kBlockKernelThreads)
-    k_refine_block(const LevelDev* __restrict__ lv, LevelState* st, int jhi, int jlo,
-                   int uniform_start, double tol, int maxit, uint64_t seed, int lds_budget) {
+    k_block_jobs(const BlockJob* __restrict__ jobs, int lds_budget) {
     extern __shared__ double lds[];
+    const BlockJob Jb = jobs[blockIdx.x];
+    const LevelDev* __restrict__ lv = Jb.lv;
+    LevelState* st = Jb.st;
+    const int jhi = Jb.jhi, jlo = Jb.jlo, uniform_start = Jb.uniform;
+    const double tol = Jb.tol;
+    const int maxit = Jb.maxit;
+    const uint64_t seed = Jb.seed;
     __shared__ double red[2 * 4 * 16];
     __shared__ double s_cm, s_cs;
     __shared__ int s_cfin;
@@ -565,54 +585,330 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
 
 // ------------------------------------------------------- grid levels
 
-template <typename T, int G>
-__global__ void __launch_bounds__(kGridBlock)
-    k_refine_grid(LevelDev L, LevelDev C, LevelState* st_j, const LevelState* st_c, int uniform_start,
-                  GridSync* gs, double* partials, double* bcast, double tol, int maxit,
-                  uint64_t seed) {
-    __shared__ double red[16 * 5 + 8];
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int r0 = L.part[lb], r1 = L.part[lb + 1];
+// A job's view of the launch: jobs of a packed launch own disjoint ranges
+// of workgroups; a single-graph launch is one job.  Every job has its own
+// barrier state, so graphs refined together never wait for each other.
+struct GridCtx {
+    GridSync* gs;
+    GridSlot* slots;
+    double* bcast;
+    unsigned long long epoch;
+    int nb;  // workgroups of the job
+    int vb;  // this workgroup within the job
+    int lb;  // row block of this workgroup
+};
+
+template <int NV>
+__device__ __forceinline__ bool job_allreduce(double (&v)[NV], GridCtx& c, double* red) {
+    return grid_allreduce_impl<NV>(v, c.gs, c.slots, c.bcast, c.epoch, c.lb, c.vb == 0, c.nb, red);
+}
+
+// ---- per-row operations fed by the two traversal drivers
+
+// One PI step: y_i = s (g (w_i - mu) + sum_k a_ik (w_k - w_i)), stored as
+// T; acc += {y, y^2, y v, v} with v = (w_i - mu) s.
+template <typename T>
+struct PiOp {
+    const int32_t* __restrict__ col;
+    const T* __restrict__ wv;
+    const T* __restrict__ win;
+    T* __restrict__ wout;
+    double mu, s, g;
+    double acc[4];
+    __device__ __forceinline__ double xi(int i) const { return (double)win[i]; }
+    __device__ __forceinline__ double entry(int e, double x) const {
+        return (double)wv[e] * ((double)win[col[e]] - x);
+    }
+    __device__ __forceinline__ void row(int i, double x, double t) {
+        const double v = (x - mu) * s;
+        const T ys = (T)(s * (g * (x - mu) + t));
+        wout[i] = ys;
+        const double yd = (double)ys;
+        acc[0] += yd;
+        acc[1] += yd * yd;
+        acc[2] += yd * v;
+        acc[3] += v;
+    }
+};
+
+// FP64 recomputation of a step from a (possibly FP32) iterate.
+struct RedoOp {
+    const int32_t* __restrict__ col;
+    const double* __restrict__ w;
+    const void* src;
+    int f32;
+    double* __restrict__ dst;
+    double mu, s, g;
+    double acc[2];
+    __device__ __forceinline__ double xi(int i) const { return ld_any(src, f32, i); }
+    __device__ __forceinline__ double entry(int e, double x) const {
+        return w[e] * (ld_any(src, f32, col[e]) - x);
+    }
+    __device__ __forceinline__ void row(int i, double x, double t) {
+        const double y = s * (g * (x - mu) + t);
+        dst[i] = y;
+        acc[0] += y;
+        acc[1] += y * y;
+    }
+};
+
+// Sums of u = (src - mu) s and the edge form sum_k a_ik ((src_k - src_i) s)^2.
+struct EdgeOp {
+    const int32_t* __restrict__ col;
+    const double* __restrict__ w;
+    const void* src;
+    int f32;
+    double mu, s;
+    double acc[3];
+    __device__ __forceinline__ double xi(int i) const { return ld_any(src, f32, i); }
+    __device__ __forceinline__ double entry(int e, double x) const {
+        const double d = (ld_any(src, f32, col[e]) - x) * s;
+        return w[e] * d * d;
+    }
+    __device__ __forceinline__ void row(int i, double x, double t) {
+        const double u = (x - mu) * s;
+        acc[0] += u;
+        acc[1] += u * u;
+        acc[2] += t;
+    }
+};
+
+// Output y = (u - mean)/nrm and residual terms (L y - lambda y)_i.
+struct ResidualOp {
+    const int32_t* __restrict__ col;
+    const double* __restrict__ w;
+    const void* src;
+    int f32;
+    double mu, s, mean_u, nrm, lam;
+    double* __restrict__ yout;
+    double acc[1];
+    __device__ __forceinline__ double xi(int i) const { return ld_any(src, f32, i); }
+    __device__ __forceinline__ double entry(int e, double x) const {
+        return w[e] * (x - ld_any(src, f32, col[e]));
+    }
+    __device__ __forceinline__ void row(int i, double x, double t) {
+        const double yi = ((x - mu) * s - mean_u) / nrm;
+        const double r = t * s / nrm - lam * yi;
+        acc[0] += r * r;
+        yout[i] = yi;
+    }
+};
+
+// ---- traversal driver 1: G lanes per row (G = 64: a wavefront per row)
+
+template <int G, class Op>
+__device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r0, int r1, Op& op) {
+    const int lane = threadIdx.x & (G - 1);
+    const int ngroups = blockDim.x / G;
+    for (int i = r0 + (int)(threadIdx.x / G); i < r1; i += ngroups) {
+        const int a = rp[i], b = rp[i + 1];
+        const double x = op.xi(i);
+        double t = 0.0;
+        for (int e = a + lane; e < b; e += G) t += op.entry(e, x);
+        t = group_sum_t<G>(t);
+        if (lane == 0) op.row(i, x, t);
+    }
+}
+
+// ---- traversal driver 2: merge path
+//
+// The block's rows [r0, r1) and entries are merged into one sequence
+// (the entries of a row followed by its row end) that is cut into equal
+// pieces of kMergeIPT items per thread, so a row of any length is shared
+// by many threads and a chunk of short rows by few (Merrill & Garland,
+// "Merge-based parallel sparse matrix-vector multiplication", SC 2016).
+// Per chunk the row ends are staged in LDS, every thread finds its start
+// by binary search on its diagonal, walks its items, and the partial sums
+// of rows split across threads are combined by a segmented scan in thread
+// order (deterministic), then added by the thread that completes the row.
+constexpr int kMergeIPT = 8;
+constexpr int kMergeChunk = kGridBlock * kMergeIPT;
+
+struct MergeShared {
+    int win[kMergeChunk + 2];  // row starts/ends of rows ia .. ia + W (relative to the block's first entry)
+    int crow[kGridBlock];
+    double cval[kGridBlock];
+    int wrow[16];
+    int wfirst[16];
+    double wtail[16];
+    int inrow[17];
+    double inval[17];
+    int s_ia;
+};
+
+template <class Op>
+__device__ __forceinline__ void drive_merge(const int32_t* __restrict__ rp, int r0, int r1, Op& op,
+                                            MergeShared& sh) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+    const int e0 = rp[r0];
+    const int nrows = r1 - r0;
+    const int nent = rp[r1] - e0;
+    const int total = nrows + nent;
+    int carry_row = -1;
+    double carry_val = 0.0;
+    int ia = 0;
+    for (int d0 = 0; d0 < total; d0 += kMergeChunk) {
+        const int dl_end = min(kMergeChunk, total - d0);
+        const int W = min(kMergeChunk + 1, nrows - ia);  // rows whose ends can lie in this chunk
+        for (int q = tid; q <= W; q += blockDim.x) sh.win[q] = rp[r0 + ia + q] - e0;
+        __syncthreads();
+        // start coordinate (i, j) on my diagonal: i rows completed, j entries consumed
+        const int dl = min(tid * kMergeIPT, dl_end);
+        const int diag = d0 + dl;
+        int lo = max(ia, diag - nent), hi = min(ia + W, diag);
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sh.win[mid - ia + 1] <= diag - mid - 1) lo = mid + 1;
+            else hi = mid;
+        }
+        int i = lo, j = diag - lo;
+        const int steps = min(dl + kMergeIPT, dl_end) - dl;
+        double x = (i < nrows) ? op.xi(r0 + i) : 0.0;
+        double part = 0.0;
+        int frow = -1;
+        double fx = 0.0, fpart = 0.0;
+        for (int q = 0; q < steps; ++q) {
+            if (i < nrows && j < sh.win[i - ia + 1]) {
+                part += op.entry(e0 + j, x);
+                ++j;
+            } else {
+                if (frow < 0) {
+                    frow = i;
+                    fx = x;
+                    fpart = part;
+                } else {
+                    op.row(r0 + i, x, part);
+                }
+                part = 0.0;
+                ++i;
+                x = (i < nrows) ? op.xi(r0 + i) : 0.0;
+            }
+        }
+        if (tid * kMergeIPT < dl_end && min(tid * kMergeIPT + kMergeIPT, dl_end) == dl_end) sh.s_ia = i;
+        // inclusive segmented scan of the carries (rows are non-decreasing in tid)
+        int myrow = i;
+        double v = part;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int ro = __shfl_up(myrow, o, 64);
+            const double vo = __shfl_up(v, o, 64);
+            if (lane >= o && ro == myrow) v += vo;
+        }
+        const int first_in_wave = __shfl(myrow, 0, 64);
+        if (lane == 63) {
+            sh.wrow[wv] = myrow;
+            sh.wtail[wv] = v;
+            sh.wfirst[wv] = first_in_wave;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int r = carry_row;
+            double cv = carry_val;
+            for (int w = 0; w < nw; ++w) {
+                sh.inrow[w] = r;
+                sh.inval[w] = cv;
+                const bool whole = sh.wfirst[w] == sh.wrow[w];
+                const double tail = sh.wtail[w] + ((whole && r == sh.wrow[w]) ? cv : 0.0);
+                r = sh.wrow[w];
+                cv = tail;
+            }
+            sh.inrow[nw] = r;
+            sh.inval[nw] = cv;
+        }
+        __syncthreads();
+        if (myrow == first_in_wave && myrow == sh.inrow[wv]) v += sh.inval[wv];
+        sh.crow[tid] = myrow;
+        sh.cval[tid] = v;
+        __syncthreads();
+        if (frow >= 0) {
+            double cin = 0.0;
+            if (tid == 0) {
+                if (carry_row == frow) cin = carry_val;
+            } else if (sh.crow[tid - 1] == frow) {
+                cin = sh.cval[tid - 1];
+            }
+            op.row(r0 + frow, fx, fpart + cin);
+        }
+        carry_row = sh.inrow[nw];
+        carry_val = sh.inval[nw];
+        ia = sh.s_ia;
+        __syncthreads();
+    }
+}
+
+template <class Op>
+__device__ __forceinline__ void drive(const LevelDev& L, int r0, int r1, Op& op, MergeShared& sh) {
+    if (L.variant == 2) {
+        drive_merge(L.rp, r0, r1, op, sh);
+        return;
+    }
+    switch (L.lanes) {
+        case 1: drive_rows<1>(L.rp, r0, r1, op); break;
+        case 2: drive_rows<2>(L.rp, r0, r1, op); break;
+        case 4: drive_rows<4>(L.rp, r0, r1, op); break;
+        case 8: drive_rows<8>(L.rp, r0, r1, op); break;
+        case 16: drive_rows<16>(L.rp, r0, r1, op); break;
+        case 32: drive_rows<32>(L.rp, r0, r1, op); break;
+        default: drive_rows<64>(L.rp, r0, r1, op); break;
+    }
+}
+
+// ---- refinement of one level by a job's workgroups
+
+template <typename T>
+__device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeShared& sh) {
+    const LevelDev& L = J.L;
+    const double tol = J.tol;
+    const int maxit = J.maxit;
+    const uint64_t seed = J.seed;
+    const int r0 = L.part[c.lb], r1 = L.part[c.lb + 1];
     T* b0 = (T*)L.buf0;
     T* b1 = (T*)L.buf1;
     const double n = (double)L.n;
     // prolongation from level j+1 (or the hashed uniform start)
     double sum[1] = {0.0};
-    if (uniform_start) {
+    if (J.uniform) {
         for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-            T v = (T)(hashed_uniform(seed, i) - 0.5);
+            const T v = (T)(hashed_uniform(seed, i) - 0.5);
             b0[i] = v;
             sum[0] += (double)v;
         }
     } else {
-        const LevelState c = *st_c;
-        const void* cb = c.fin ? C.buf1 : C.buf0;
+        const LevelState cst = *J.stc;
+        const void* cb = cst.fin ? J.C.buf1 : J.C.buf0;
         for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-            T v = (T)((ld_any(cb, C.fp32, L.agg[i]) - c.mu) * c.s);
+            const T v = (T)((ld_any(cb, J.C.fp32, L.agg[i]) - cst.mu) * cst.s);
             b0[i] = v;
             sum[0] += (double)v;
         }
     }
-    if (!grid_allreduce<1>(sum, gs, partials, bcast, lb, red)) return;
+    if (!job_allreduce<1>(sum, c, red)) return;
     double mu = sum[0] / n;
     double ss[1] = {0.0};
     for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-        double d = (double)b0[i] - mu;
+        const double d = (double)b0[i] - mu;
         ss[0] += d * d;
     }
-    if (!grid_allreduce<1>(ss, gs, partials, bcast, lb, red)) return;
+    if (!job_allreduce<1>(ss, c, red)) return;
     double s = 1.0 / sqrt(ss[0]);
     int cur = 0, k = 0, hit = 0;
     double utv = 0.0, pmu = mu, ps = s;
+    PiOp<T> op;
+    op.col = L.col;
+    op.wv = (const T*)(sizeof(T) == 4 ? (const void*)L.w32 : (const void*)L.w64);
+    op.g = L.g;
     while (true) {
-        const T* win = cur ? b1 : b0;
-        T* wout = cur ? b0 : b1;
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        pi_rows<G, T>(L, win, wout, mu, s, r0, r1, acc);
-        if (!grid_allreduce<4>(acc, gs, partials, bcast, lb, red)) return;
-        const double mu2 = acc[0] / n;
-        const double s2 = 1.0 / sqrt(acc[1] - acc[0] * mu2);
-        utv = s2 * (acc[2] - mu2 * acc[3]);
+        op.win = cur ? b1 : b0;
+        op.wout = cur ? b0 : b1;
+        op.mu = mu;
+        op.s = s;
+        op.acc[0] = op.acc[1] = op.acc[2] = op.acc[3] = 0.0;
+        drive(L, r0, r1, op, sh);
+        if (!job_allreduce<4>(op.acc, c, red)) return;
+        const double mu2 = op.acc[0] / n;
+        const double s2 = 1.0 / sqrt(op.acc[1] - op.acc[0] * mu2);
+        utv = s2 * (op.acc[2] - mu2 * op.acc[3]);
         ++k;
         cur ^= 1;
         pmu = mu;
@@ -625,7 +921,7 @@ __global__ void __launch_bounds__(kGridBlock)
             break;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (c.vb == 0 && threadIdx.x == 0) {
         LevelState o;
         o.mu = mu;
         o.s = s;
@@ -637,110 +933,136 @@ __global__ void __launch_bounds__(kGridBlock)
         o.k = k;
         o.maxit = hit;
         o.err = 0;
-        *st_j = o;
+        *J.st = o;
     }
 }
 
-// ----------------------------------------------------------- finishing
-
-// Finest level.  With `redo` = 1 (mixed precision) the last power-iteration
-// step is recomputed in FP64 from the FP32 iterate before it, so the step
-// count equals the FP64 path and only that earlier iterate carries FP32
+// ---- finishing pass on the finest level
+//
+// With `redo` = 1 (mixed precision) the last power-iteration step is
+// recomputed in FP64 from the FP32 iterate before it, so the step count
+// equals the FP64 path and only that earlier iterate carries FP32
 // rounding.  Then the output y = deflated, normalised iterate, the
 // edge-form Rayleigh quotient r = sum_edges w (y_i - y_k)^2 and the
 // residual ||L y - r y||, all in FP64.
-template <typename T, int G>
-__global__ void __launch_bounds__(kGridBlock)
-    k_finish(LevelDev L, const LevelState* st0, int redo, double* fa, double* fb, double* yout,
-             GridSync* gs, double* partials, double* bcast, FinishOut* fo) {
-    __shared__ double red[16 * 5 + 8];
-    (void)fb;
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int r0 = L.part[lb], r1 = L.part[lb + 1];
-    const int lane = threadIdx.x & (G - 1);
-    const int ngroups = blockDim.x / G;
+__device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeShared& sh) {
+    const LevelDev& L = J.L;
+    const int r0 = L.part[c.lb], r1 = L.part[c.lb + 1];
     const double n = (double)L.n;
-    const int32_t* __restrict__ rp = L.rp;
-    const int32_t* __restrict__ col = L.col;
-    const double* __restrict__ w = L.w64;
-    const LevelState st = *st0;
+    const LevelState st = *J.stc;
     const void* src = st.fin ? L.buf1 : L.buf0;
-    int src_f32 = (sizeof(T) == 4);
+    int f32 = L.fp32;
     double mu = st.mu, s = st.s;
-    if (redo && st.k > 0) {
-        const void* prev = st.fin ? L.buf0 : L.buf1;
-        const double pmu = st.mu_prev, ps = st.s_prev;
-        double acc[2] = {0.0, 0.0};
-        for (int i = r0 + (int)(threadIdx.x / G); i < r1; i += ngroups) {
-            const double wi = ld_any(prev, src_f32, i);
-            double t = 0.0;
-            for (int e = rp[i] + lane; e < rp[i + 1]; e += G) t += w[e] * (ld_any(prev, src_f32, col[e]) - wi);
-            t = group_sum_t<G>(t);
-            if (lane == 0) {
-                double y = ps * (L.g * (wi - pmu) + t);
-                fa[i] = y;
-                acc[0] += y;
-                acc[1] += y * y;
-            }
-        }
-        if (!grid_allreduce<2>(acc, gs, partials, bcast, lb, red)) return;
-        mu = acc[0] / n;
-        s = 1.0 / sqrt(acc[1] - acc[0] * mu);
-        src = fa;
-        src_f32 = 0;
+    if (J.redo && st.k > 0) {
+        RedoOp op;
+        op.col = L.col;
+        op.w = L.w64;
+        op.src = st.fin ? L.buf0 : L.buf1;
+        op.f32 = f32;
+        op.dst = J.fa;
+        op.mu = st.mu_prev;
+        op.s = st.s_prev;
+        op.g = L.g;
+        op.acc[0] = op.acc[1] = 0.0;
+        drive(L, r0, r1, op, sh);
+        if (!job_allreduce<2>(op.acc, c, red)) return;
+        mu = op.acc[0] / n;
+        s = 1.0 / sqrt(op.acc[1] - op.acc[0] * mu);
+        src = J.fa;
+        f32 = 0;
     }
-    // pass 1: sums of u = (src - mu) s and the edge form
-    double a3[3] = {0.0, 0.0, 0.0};
-    for (int i = r0 + (int)(threadIdx.x / G); i < r1; i += ngroups) {
-        const double si = ld_any(src, src_f32, i);
-        double e2 = 0.0;
-        for (int e = rp[i] + lane; e < rp[i + 1]; e += G) {
-            double d = (ld_any(src, src_f32, col[e]) - si) * s;
-            e2 += w[e] * d * d;
-        }
-        e2 = group_sum_t<G>(e2);
-        if (lane == 0) {
-            double u = (si - mu) * s;
-            a3[0] += u;
-            a3[1] += u * u;
-            a3[2] += e2;
-        }
-    }
-    if (!grid_allreduce<3>(a3, gs, partials, bcast, lb, red)) return;
-    const double mean_u = a3[0] / n;
-    const double nrm2 = a3[1] - a3[0] * mean_u;
+    EdgeOp eo;
+    eo.col = L.col;
+    eo.w = L.w64;
+    eo.src = src;
+    eo.f32 = f32;
+    eo.mu = mu;
+    eo.s = s;
+    eo.acc[0] = eo.acc[1] = eo.acc[2] = 0.0;
+    drive(L, r0, r1, eo, sh);
+    if (!job_allreduce<3>(eo.acc, c, red)) return;
+    const double mean_u = eo.acc[0] / n;
+    const double nrm2 = eo.acc[1] - eo.acc[0] * mean_u;
     const double nrm = sqrt(nrm2);
-    const double lam = 0.5 * a3[2] / nrm2;
-    // pass 2: output and residual
-    double r1s[1] = {0.0};
-    for (int i = r0 + (int)(threadIdx.x / G); i < r1; i += ngroups) {
-        const double si = ld_any(src, src_f32, i);
-        double t = 0.0;
-        for (int e = rp[i] + lane; e < rp[i + 1]; e += G) t += w[e] * (si - ld_any(src, src_f32, col[e]));
-        t = group_sum_t<G>(t);
-        if (lane == 0) {
-            const double yi = ((si - mu) * s - mean_u) / nrm;
-            const double ly = t * s / nrm;
-            const double r = ly - lam * yi;
-            r1s[0] += r * r;
-            yout[i] = yi;
-        }
-    }
-    if (!grid_allreduce<1>(r1s, gs, partials, bcast, lb, red)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        fo->lambda = lam;
-        fo->residual = sqrt(r1s[0]);
-        fo->sum_u = a3[0];
-        fo->sum_uu = a3[1];
-        fo->edge = a3[2];
+    const double lam = 0.5 * eo.acc[2] / nrm2;
+    ResidualOp ro;
+    ro.col = L.col;
+    ro.w = L.w64;
+    ro.src = src;
+    ro.f32 = f32;
+    ro.mu = mu;
+    ro.s = s;
+    ro.mean_u = mean_u;
+    ro.nrm = nrm;
+    ro.lam = lam;
+    ro.yout = J.yout;
+    ro.acc[0] = 0.0;
+    drive(L, r0, r1, ro, sh);
+    if (!job_allreduce<1>(ro.acc, c, red)) return;
+    if (c.vb == 0 && threadIdx.x == 0) {
+        J.fo->lambda = lam;
+        J.fo->residual = sqrt(ro.acc[0]);
+        J.fo->sum_u = eo.acc[0];
+        J.fo->sum_uu = eo.acc[1];
+        J.fo->edge = eo.acc[2];
     }
 }
 
-__global__ void k_reset_sync(GridSync* gs) {
-    gs->count = 0;
-    gs->gen = 0;
-    gs->abort = 0;
-    gs->pad = 0;
+// Which job owns this workgroup (jobs sorted by first workgroup).
+__device__ __forceinline__ int find_job(const GridJob* jobs, int njobs) {
+    int lo = 0, hi = njobs - 1;
+    const int b = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].b0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ GridCtx make_ctx(const GridJob& J) {
+    GridCtx c;
+    c.gs = J.gs;
+    c.slots = J.slots;
+    c.bcast = J.bcast;
+    c.nb = J.L.grid;
+    c.vb = (int)blockIdx.x - J.b0;
+    c.lb = xcd_remap(c.vb, c.nb);
+    c.epoch = start_epoch(J.gs);
+    return c;
+}
+
+// One launch refines one level of each job (one graph per job).
+__global__ void __launch_bounds__(kGridBlock) k_refine_jobs(const GridJob* __restrict__ jobs, int njobs) {
+    __shared__ double red[16 * 5 + 8];
+    __shared__ MergeShared sh;
+    const GridJob J = jobs[find_job(jobs, njobs)];
+    GridCtx c = make_ctx(J);
+    if (c.vb < 0 || c.vb >= c.nb) return;
+    if (J.L.fp32) refine_level<float>(J, c, red, sh);
+    else refine_level<double>(J, c, red, sh);
+}
+
+// One launch finishes the finest level of each job.
+__global__ void __launch_bounds__(kGridBlock) k_finish_jobs(const GridJob* __restrict__ jobs, int njobs) {
+    __shared__ double red[16 * 5 + 8];
+    __shared__ MergeShared sh;
+    const GridJob J = jobs[find_job(jobs, njobs)];
+    GridCtx c = make_ctx(J);
+    if (c.vb < 0 || c.vb >= c.nb) return;
+    finish_level(J, c, red, sh);
+}
+
+__global__ void k_reset_sync(GridSync* gs, GridSlot* slots, int nslots) {
+    for (int b = threadIdx.x; b < nslots; b += blockDim.x) {
+        for (int q = 0; q < 7; ++q) slots[b].v[q] = 0.0;
+        slots[b].epoch = 0ull;
+    }
+    if (threadIdx.x == 0) {
+        gs->epoch = 0ull;
+        gs->abort = 0u;
+        gs->pad = 0u;
+    }
 }
 
 template <typename K>
@@ -756,11 +1078,9 @@ int max_blocks_of(K kern, int threads) {
 
 // ================================================================ launchers
 
-hipError_t launch_coarse_dense(LevelDev L, LevelState* st, double* A, double* V, double* ev,
-                               int32_t* idx, uint64_t seed, FinishOut* fo, hipStream_t s) {
-    size_t shmem = (L.n <= kDenseLds) ? sizeof(double) * 2 * L.n * L.n : 0;
-    int threads = (L.n <= kDenseLds) ? 64 : 256;
-    hipLaunchKernelGGL(k_coarse_dense, dim3(1), dim3(threads), shmem, s, L, st, A, V, ev, idx, seed, fo);
+hipError_t launch_coarse_jobs(const CoarseJob* jobs, int njobs, hipStream_t s) {
+    const size_t shmem = sizeof(double) * 2 * kDenseLds * kDenseLds;
+    hipLaunchKernelGGL(k_coarse_jobs, dim3(njobs), dim3(256), shmem, s, jobs);
     return hipGetLastError();
 }
 
@@ -772,11 +1092,11 @@ int refine_block_lds_budget() {
             (void)hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         hipFuncAttributes fa;
         size_t stat = 0;
-        if (hipFuncGetAttributes(&fa, (const void*)k_refine_block) == hipSuccess) stat = fa.sharedSizeBytes;
+        if (hipFuncGetAttributes(&fa, (const void*)k_block_jobs) == hipSuccess) stat = fa.sharedSizeBytes;
         long b = std::min<long>(kBlockLdsMax, (long)maxsh - (long)stat - 256);
         b = std::max<long>(b, 0);
         if (b > 65536 - (long)stat - 256 &&
-            hipFuncSetAttribute((const void*)k_refine_block, hipFuncAttributeMaxDynamicSharedMemorySize,
+            hipFuncSetAttribute((const void*)k_block_jobs, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)b) != hipSuccess) {
             (void)hipGetLastError();
             b = std::max<long>(0, 65536 - (long)stat - 256);
@@ -786,92 +1106,36 @@ int refine_block_lds_budget() {
     return budget;
 }
 
-hipError_t launch_refine_block(const LevelDev* lv, LevelState* st, int jhi, int jlo, int uniform_start,
-                               double tol, int maxit, uint64_t seed, hipStream_t s) {
+hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, hipStream_t s) {
     const int budget = refine_block_lds_budget();
-    hipLaunchKernelGGL(k_refine_block, dim3(1), dim3(kBlockKernelThreads), (size_t)budget, s, lv, st, jhi,
-                       jlo, uniform_start, tol, maxit, seed, budget);
+    hipLaunchKernelGGL(k_block_jobs, dim3(njobs), dim3(kBlockKernelThreads), (size_t)budget, s, jobs, budget);
     return hipGetLastError();
 }
 
-#define CMG_GRID_SWITCH(MACRO, T)                                                                  \
-    switch (lanes) {                                                                               \
-        case 1: MACRO(T, 1); break;                                                                \
-        case 2: MACRO(T, 2); break;                                                                \
-        case 4: MACRO(T, 4); break;                                                                \
-        case 8: MACRO(T, 8); break;                                                                \
-        case 16: MACRO(T, 16); break;                                                              \
-        case 32: MACRO(T, 32); break;                                                              \
-        default: MACRO(T, 64); break;                                                              \
-    }
-
-int refine_grid_max_blocks(int fp32, int lanes, int variant) {
-    (void)variant;
-    int r = 0;
-#define CMG_MB(T, G) r = max_blocks_of(k_refine_grid<T, G>, kGridBlock)
-    if (fp32) {
-        CMG_GRID_SWITCH(CMG_MB, float)
-    } else {
-        CMG_GRID_SWITCH(CMG_MB, double)
-    }
-#undef CMG_MB
+int refine_jobs_max_blocks() {
+    static int r = -1;
+    if (r < 0) r = max_blocks_of(k_refine_jobs, kGridBlock);
     return r;
 }
 
-int finish_max_blocks(int fp32, int lanes, int variant) {
-    (void)variant;
-    int r = 0;
-#define CMG_MB(T, G) r = max_blocks_of(k_finish<T, G>, kGridBlock)
-    if (fp32) {
-        CMG_GRID_SWITCH(CMG_MB, float)
-    } else {
-        CMG_GRID_SWITCH(CMG_MB, double)
-    }
-#undef CMG_MB
+int finish_jobs_max_blocks() {
+    static int r = -1;
+    if (r < 0) r = max_blocks_of(k_finish_jobs, kGridBlock);
     return r;
 }
 
-hipError_t launch_refine_grid(const LevelDev& L, const LevelDev& C, LevelState* st_j,
-                              const LevelState* st_c, int uniform_start, GridSync* gs,
-                              double* partials, double* bcast, double tol, int maxit, uint64_t seed,
-                              hipStream_t s) {
-    LevelDev Lc = L, Cc = C;
-    void* args[] = {&Lc, &Cc, &st_j, &st_c, &uniform_start, &gs, &partials, &bcast, &tol, &maxit, &seed};
-    const int lanes = L.lanes;
-    hipError_t e = hipSuccess;
-#define CMG_LG(T, G)                                                                               \
-    e = hipLaunchCooperativeKernel((const void*)k_refine_grid<T, G>, dim3(L.grid), dim3(kGridBlock), \
-                                   args, 0, s)
-    if (L.fp32) {
-        CMG_GRID_SWITCH(CMG_LG, float)
-    } else {
-        CMG_GRID_SWITCH(CMG_LG, double)
-    }
-#undef CMG_LG
-    return e;
+hipError_t launch_refine_jobs(const GridJob* jobs, int njobs, int nblocks, hipStream_t s) {
+    void* args[] = {(void*)&jobs, &njobs};
+    return hipLaunchCooperativeKernel((const void*)k_refine_jobs, dim3(nblocks), dim3(kGridBlock), args, 0, s);
 }
 
-hipError_t launch_finish(const LevelDev& L0, const LevelState* st0, int redo, double* f64a,
-                         double* f64b, double* yout, GridSync* gs, double* partials, double* bcast,
-                         FinishOut* fo, hipStream_t s) {
-    LevelDev Lc = L0;
-    void* args[] = {&Lc, &st0, &redo, &f64a, &f64b, &yout, &gs, &partials, &bcast, &fo};
-    const int lanes = L0.lanes;
-    hipError_t e = hipSuccess;
-#define CMG_LF(T, G)                                                                               \
-    e = hipLaunchCooperativeKernel((const void*)k_finish<T, G>, dim3(L0.grid), dim3(kGridBlock), args, \
-                                   0, s)
-    if (L0.fp32) {
-        CMG_GRID_SWITCH(CMG_LF, float)
-    } else {
-        CMG_GRID_SWITCH(CMG_LF, double)
-    }
-#undef CMG_LF
-    return e;
+hipError_t launch_finish_jobs(const GridJob* jobs, int njobs, int nblocks, hipStream_t s) {
+    void* args[] = {(void*)&jobs, &njobs};
+    return hipLaunchCooperativeKernel((const void*)k_finish_jobs, dim3(nblocks), dim3(kGridBlock), args, 0, s);
 }
 
-hipError_t launch_reset_sync(GridSync* gs, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(1), 0, s, gs);
+hipError_t launch_reset_sync(GridSync* gs, GridSlot* slots, int nslots, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(256), 0, s, gs, slots, nslots);
     return hipGetLastError();
 }
 

@@ -101,10 +101,11 @@ __global__ void k_rowinfo(int n, const int32_t* __restrict__ rp, const int32_t* 
     const int lane = threadIdx.x & (G - 1);
     const int gpb = blockDim.x / G;
     int row = blockIdx.x * gpb + threadIdx.x / G;
-    double dmax = 0.0, wm = 0.0, ex = 0.0;
+    double dmax = 0.0, wm = 0.0, ex = 0.0, lmax = 0.0;
     const int stride = gridDim.x * gpb;
     for (; row < n; row += stride) {
         int a = rp[row], b = rp[row + 1];
+        lmax = fmax(lmax, (double)(b - a));
         double bw = -1.0;
         int bc = 0x7fffffff;
         double d = 0.0;
@@ -134,29 +135,33 @@ __global__ void k_rowinfo(int n, const int32_t* __restrict__ rp, const int32_t* 
             wm = fmax(wm, bw);
         }
     }
-    // block maxima (exact, order independent) to bmax[3b .. 3b+2]
-    __shared__ double sm[3][kBlk / kWave];
+    // block maxima (exact, order independent) to bmax[4b .. 4b+3]
+    __shared__ double sm[4][kBlk / kWave];
     for (int o = 32; o > 0; o >>= 1) {
         dmax = fmax(dmax, __shfl_xor(dmax, o, kWave));
         wm = fmax(wm, __shfl_xor(wm, o, kWave));
         ex = fmax(ex, __shfl_xor(ex, o, kWave));
+        lmax = fmax(lmax, __shfl_xor(lmax, o, kWave));
     }
     if ((threadIdx.x & 63) == 0) {
         sm[0][threadIdx.x >> 6] = dmax;
         sm[1][threadIdx.x >> 6] = wm;
         sm[2][threadIdx.x >> 6] = ex;
+        sm[3][threadIdx.x >> 6] = lmax;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double a = 0.0, b = 0.0, c = 0.0;
+        double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
         for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
             a = fmax(a, sm[0][q]);
             b = fmax(b, sm[1][q]);
             c = fmax(c, sm[2][q]);
+            d = fmax(d, sm[3][q]);
         }
-        bmax[3 * blockIdx.x] = a;
-        bmax[3 * blockIdx.x + 1] = b;
-        bmax[3 * blockIdx.x + 2] = c;
+        bmax[4 * blockIdx.x] = a;
+        bmax[4 * blockIdx.x + 1] = b;
+        bmax[4 * blockIdx.x + 2] = c;
+        bmax[4 * blockIdx.x + 3] = d;
     }
 }
 
@@ -164,33 +169,19 @@ __global__ void k_rowinfo(int n, const int32_t* __restrict__ rp, const int32_t* 
 // patterns in out[0] (g), out[1] (largest weight), out[2] (largest FP32
 // rounding error of a weight: 0 if all weights are exact in FP32)
 __global__ void k_max_reduce(const double* __restrict__ bmax, int nb, unsigned long long* out) {
-    __shared__ double sm[3][kBlk / kWave];
-    double a = 0.0, b = 0.0, c = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-        a = fmax(a, bmax[3 * i]);
-        b = fmax(b, bmax[3 * i + 1]);
-        c = fmax(c, bmax[3 * i + 2]);
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        a = fmax(a, __shfl_xor(a, o, kWave));
-        b = fmax(b, __shfl_xor(b, o, kWave));
-        c = fmax(c, __shfl_xor(c, o, kWave));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        sm[0][threadIdx.x >> 6] = a;
-        sm[1][threadIdx.x >> 6] = b;
-        sm[2][threadIdx.x >> 6] = c;
-    }
+    __shared__ double sm[4][kBlk / kWave];
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
+        for (int q = 0; q < 4; ++q) m[q] = fmax(m[q], bmax[4 * i + q]);
+    for (int o = 32; o > 0; o >>= 1)
+        for (int q = 0; q < 4; ++q) m[q] = fmax(m[q], __shfl_xor(m[q], o, kWave));
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 4; ++q) sm[q][threadIdx.x >> 6] = m[q];
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
-            a = fmax(a, sm[0][q]);
-            b = fmax(b, sm[1][q]);
-            c = fmax(c, sm[2][q]);
-        }
-        out[0] = (unsigned long long)__double_as_longlong(a);
-        out[1] = (unsigned long long)__double_as_longlong(b);
-        out[2] = (unsigned long long)__double_as_longlong(c);
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+            for (int q = 0; q < 4; ++q) m[q] = fmax(m[q], sm[q][w]);
+        for (int q = 0; q < 4; ++q) out[q] = (unsigned long long)__double_as_longlong(m[q]);
     }
 }
 

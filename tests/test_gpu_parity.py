@@ -268,3 +268,80 @@ def test_fullsize_rgg1m_bench_config(rgg1m, precision):
 
         assert_hierarchy_equal(g, ref, levels, arrays)
         assert abs(lam - ref.lam) <= MIXED_LAM_RTOL * ref.lam
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("name", ["grid128", "rgg20k", "cl30k", "cl_dense"])
+def test_spmv_variants_against_oracle(variant, name):
+    """Both SpMV traversals (lane groups per row, merge path) on every
+    refinement level (block_rows=1 sends all levels to the grid kernels)."""
+    g = _named(name)
+    say(f"[variant] {name} variant={variant}")
+    ref = oracle_of(g)
+    lam, x, st, levels, arrays = run_gpu(g, spmv_variant=variant, block_rows=1)
+    assert all(l.variant == variant for l in levels[:-1] if not l.in_block)
+    assert_fp64_parity(g, lam, x, st, levels, arrays, ref)
+
+
+def _batch_graphs():
+    return [("rgg20k", G.rgg(20000, 10.0, seed=5), {}),
+            ("grid128", G.grid2d(128, 128), {}),
+            ("cl30k", G.chung_lu(30000, 2.1, 16.0, 2000.0, seed=7), {"spmv_variant": 2}),
+            ("path1000", G.path(1000), {}),
+            ("K60", G.complete(60), {}),
+            ("star200", G.star(200), {}),
+            ("rgg60k_mixed", G.rgg(60000, 10.0, seed=6), {"precision": 1, "mixed_min_nnz": 1}),
+            ("grid3d_20_tol", G.grid3d(20), {"tol": 1e-7, "block_rows": 500})]
+
+
+def test_batch_equals_alone_bitwise():
+    from paper_1412_0565_amd import cmg
+
+    items = _batch_graphs()
+    alone = []
+    for name, g, opts in items:
+        say(f"[batch] alone {name}")
+        with cmg.Fiedler(g.n, g.row_ptr, g.col, g.w, **opts) as F:
+            lam, x, _ = F.solve()
+        alone.append((lam, x))
+    handles = [cmg.Fiedler(g.n, g.row_ptr, g.col, g.w, **opts) for _, g, opts in items]
+    try:
+        xs = [np.zeros(g.n) for _, g, _ in items]
+        for rep in range(2):
+            say(f"[batch] packed solve {rep}")
+            lams, st = cmg.cmg_fiedler_batch([F.handle for F in handles], xs)
+            for (name, g, _), (la, xa), lb, xb in zip(items, alone, lams, xs):
+                assert la == lb, (name, la, lb)
+                assert np.array_equal(xa, xb), name
+    finally:
+        for F in handles:
+            F.close()
+
+
+def test_batch_against_oracle():
+    from paper_1412_0565_amd import cmg
+
+    items = [it for it in _batch_graphs() if "mixed" not in it[0] and "tol" not in it[0]]
+    handles = [cmg.Fiedler(g.n, g.row_ptr, g.col, g.w, **opts) for _, g, opts in items]
+    try:
+        xs = [np.zeros(g.n) for _, g, _ in items]
+        stats = []
+        lams, _ = cmg.cmg_fiedler_batch([F.handle for F in handles], xs, stats)
+        for (name, g, _), lam, x, F in zip(items, lams, xs, handles):
+            ref = oracle_of(g)
+            levels = F.levels()
+            assert [l.k for l in levels] == [l.k for l in ref.levels], name
+            assert cosine(x, ref.y) >= 1 - 1e-10, name
+            assert abs(lam - ref.lam) <= 1e-9 * ref.lam, name
+    finally:
+        for F in handles:
+            F.close()
+
+
+def test_batch_rejects_duplicates():
+    from paper_1412_0565_amd import cmg
+
+    g = G.grid2d(30, 30)
+    with cmg.Fiedler(g.n, g.row_ptr, g.col, g.w) as F:
+        with pytest.raises(cmg.CmgError):
+            cmg.cmg_fiedler_batch([F.handle, F.handle])

@@ -179,6 +179,11 @@ cmg_status cmg_level_info(cmg_handle h, cmg_level_stats* out, int32_t cap, int32
 cmg_status cmg_level_copy(cmg_handle h, int32_t level, int32_t* row_ptr, int32_t* col, double* w,
                           int32_t* agg);
 
+/* Make later calls on `h` issue their work on `stream` (a hipStream_t;
+ * NULL = null stream), e.g. to solve on another stream than the one the
+ * hierarchy was built on.  The caller orders any pending work itself. */
+cmg_status cmg_set_stream(cmg_handle h, void* stream);
+
 /* Device bytes held by the handle (hierarchy plus refinement buffers). */
 cmg_status cmg_footprint(cmg_handle h, size_t* bytes);
 

@@ -25,7 +25,8 @@ CMG_VAL_F64, CMG_VAL_F32 = 0, 1
 
 # functions declared in include/cmg.h
 EXPORTS = ["cmg_options_default", "cmg_setup", "cmg_fiedler", "cmg_fiedler_batch", "cmg_level_info",
-           "cmg_level_copy", "cmg_footprint", "cmg_free", "cmg_status_string", "cmg_hash_probe"]
+           "cmg_level_copy", "cmg_set_stream", "cmg_footprint", "cmg_free", "cmg_status_string",
+           "cmg_hash_probe"]
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 _FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
@@ -115,6 +116,8 @@ def lib():
         L.cmg_level_info.restype = C.c_int
         L.cmg_level_copy.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.cmg_level_copy.restype = C.c_int
+        L.cmg_set_stream.argtypes = [C.c_void_p, C.c_void_p]
+        L.cmg_set_stream.restype = C.c_int
         L.cmg_footprint.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
         L.cmg_footprint.restype = C.c_int
         L.cmg_free.argtypes = [C.c_void_p]
@@ -261,6 +264,12 @@ def cmg_level_copy(h: int, level: int, n: int, nnz: int, with_agg: bool = True):
     _check(lib().cmg_level_copy(h, level, rp.ctypes.data, col.ctypes.data, w.ctypes.data,
                                 agg.ctypes.data if agg is not None else None), "cmg_level_copy")
     return rp, col, w, agg
+
+
+def cmg_set_stream(h: int, stream) -> None:
+    """stream: a torch.cuda.Stream, a raw hipStream_t (int), or None."""
+    raw = getattr(stream, "cuda_stream", stream)
+    _check(lib().cmg_set_stream(h, C.c_void_p(raw) if raw else None), "cmg_set_stream")
 
 
 def cmg_footprint(h: int) -> int:

@@ -865,6 +865,13 @@ cmg_status cmg_level_copy(cmg_handle h, int32_t level, int32_t* row_ptr, int32_t
     return CMG_OK;
 }
 
+cmg_status cmg_set_stream(cmg_handle h, void* stream) {
+    if (!h) return CMG_E_ARG;
+    h->stream = (hipStream_t)stream;
+    h->opt.stream = stream;
+    return CMG_OK;
+}
+
 cmg_status cmg_footprint(cmg_handle h, size_t* bytes) {
     if (!h || !bytes) return CMG_E_ARG;
     *bytes = h->footprint;

@@ -81,6 +81,58 @@ def launch_bytes(levels, j=0):
     return L.k * L.bytes_per_iter + prol
 
 
+def serve_leg(args):
+    """Served stream: requests drawn from a seeded pool of graphs (sizes
+    log-uniform over 1k-1M vertices; 2D grids, RGGs, Chung-Lu; integer
+    weights), Poisson arrivals at 0.7x the closed-loop throughput of the
+    plain FP64 one-at-a-time path.  The same stream is replayed through the
+    server twice: plain FP64 with batches of one, and mixed precision with
+    continuous batching (up to 64 graphs per packed launch).  Hierarchies
+    stay resident (LRU) under an HBM budget small enough for admission to
+    bind."""
+    import numpy as np
+
+    from paper_1412_0565_amd import cmg
+    from paper_1412_0565_amd import graphs as G
+    from paper_1412_0565_amd.serve import CmgBackend, Request, Server, latency_summary, replay
+
+    t0 = time.time()
+    pool = G.serve_pool(args.serve_pool)
+    log(f"[serve] pool of {len(pool)} graphs generated in {time.time() - t0:.1f}s "
+        f"(n {min(g.n for _, g in pool)}..{max(g.n for _, g in pool)})")
+    rng = np.random.default_rng(20260101)
+    picks = rng.integers(0, len(pool), args.serve_requests)
+    # closed-loop throughput of the plain FP64 path: setup + solve, one at a time
+    t = time.perf_counter()
+    m = min(len(pool), 16)
+    for i in range(m):
+        _, g = pool[int(picks[i])]
+        with cmg.Fiedler(g.n, g.row_ptr, g.col, g.w) as F:
+            F.solve()
+    x_fp64 = m / (time.perf_counter() - t)
+    qps = 0.7 * x_fp64
+    budget = int(args.serve_budget_gb * (1 << 30))
+    backend = CmgBackend()
+    res = {"pool": len(pool), "requests": args.serve_requests, "qps": round(qps, 2),
+           "closed_loop_fp64_solves_per_s": round(x_fp64, 2), "budget_bytes": budget}
+    for label, prec, maxb in [("fp64_sequential", 0, 1), ("mixed_batched", 1, 64)]:
+        stream = [Request(i, pool[int(p)][0], pool[int(p)][1].n, pool[int(p)][1].row_ptr, pool[int(p)][1].col,
+                          pool[int(p)][1].w, precision=prec) for i, p in enumerate(picks)]
+        srv = Server(backend, budget_bytes=budget, max_batch=maxb)
+        try:
+            replay(srv, stream, qps=qps, seed=7)
+        finally:
+            srv.close()
+        summ = latency_summary(stream)
+        summ["mean_batch"] = round(float(np.mean(srv.batches)), 2) if srv.batches else 0.0
+        summ["max_batch"] = int(max(srv.batches)) if srv.batches else 0
+        summ["peak_reserved_bytes"] = int(srv.peak)
+        summ["failed"] = sum(r.status != "done" for r in stream)
+        res[label] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
+        log(f"[serve] {label}: {res[label]}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +142,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-repeats", type=int, default=8)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-pool", type=int, default=16)
+    ap.add_argument("--serve-requests", type=int, default=240)
+    ap.add_argument("--serve-budget-gb", type=float, default=4.0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -203,6 +259,8 @@ def main():
                "lambda": r.lam, "lambda_rel_diff_gpu": abs(r.lam - lams[-1]) / abs(r.lam)}
         log(f"[bench] cpu oracle: {reps} solves in {el_cpu:.2f}s")
 
+    serve = None if args.no_serve else serve_leg(args)
+
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -227,6 +285,7 @@ def main():
         "residual": st.residual,
         "footprint_bytes": fp,
         "mixed": mixed,
+        "serve": serve,
     }
     print(json.dumps(out), flush=True)
 

@@ -384,3 +384,35 @@ def workload(name: str, seed: int = 14120565) -> CSR:
     if name.startswith("grid3d"):
         return grid3d(int(name[6:]))
     raise KeyError(name)
+
+
+# ----------------------------------------------------------------- served stream
+
+TAG_POOL = 7
+
+
+def serve_pool(count: int, seed: int = 14120565, nmin: int = 1000, nmax: int = 1_000_000):
+    """Seeded pool of request graphs for the serving workload.
+
+    Sizes are log-uniform in [nmin, nmax]; the family is uniform over
+    {2D grid with side round(sqrt(n)), RGG with mean degree 10, Chung-Lu
+    with exponent 2.5, mean degree 8 and degree cap sqrt(8 n)}; integer
+    weights 1..8.  Returns a list of (graph_id, CSR).
+    """
+    out = []
+    for i in range(count):
+        u = float(stream_uniform(seed, TAG_POOL, np.array([2 * i], dtype=np.uint64))[0])
+        f = float(stream_uniform(seed, TAG_POOL, np.array([2 * i + 1], dtype=np.uint64))[0])
+        n = int(nmin * (nmax / nmin) ** u)
+        fam = min(2, int(3 * f))
+        gseed = seed + 1000 + i
+        if fam == 0:
+            side = max(2, int(round(math.sqrt(n))))
+            g = with_int_weights(grid2d(side, side), gseed)
+        elif fam == 1:
+            g = rgg(n, 10.0, gseed)
+        else:
+            g = chung_lu(n, 2.5, 8.0, math.sqrt(8.0 * n), gseed, int_weights=True)
+        g.name = f"pool{i}_{['grid', 'rgg', 'chunglu'][fam]}_{g.n}"
+        out.append((g.name, g))
+    return out

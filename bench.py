@@ -143,8 +143,8 @@ def main():
     ap.add_argument("--cpu-repeats", type=int, default=8)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-pool", type=int, default=16)
-    ap.add_argument("--serve-requests", type=int, default=240)
+    ap.add_argument("--serve-pool", type=int, default=12)
+    ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
     args = ap.parse_args()
 

@@ -350,8 +350,6 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         if (c->lv[j].n <= block_rows) c->block_lo = j;
         else break;
     }
-    const int cap_refine = std::max(8, (refine_jobs_max_blocks() / 8) * 8);
-    const int cap_finish = std::max(8, (finish_jobs_max_blocks() / 8) * 8);
     int maxgrid = 8;
     for (int j = 0; j <= J; ++j) {
         HostLevel& L = c->lv[j];
@@ -371,7 +369,10 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         }
         // grid size: about 8k rows+entries per workgroup, multiple of 8,
         // at most what can be co-resident
-        int cap = (j == 0) ? std::min(cap_refine, cap_finish) : cap_refine;
+        const int kind = job_kind(L.variant, L.fp32);
+        int cap = refine_jobs_max_blocks(kind);
+        if (j == 0) cap = std::min(cap, finish_jobs_max_blocks(kind));
+        cap = std::max(8, (cap / 8) * 8);
         int64_t work = (int64_t)L.n + L.nnz;
         int64_t want = (work + 8191) / 8192;
         want = ((want + 7) / 8) * 8;
@@ -637,10 +638,10 @@ cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where,
     // grid levels: one cooperative launch per level
     for (int j = std::min(c->top, c->block_lo - 1); j >= 0; --j) {
         CK(hipEventRecord(c->events[2 * j], s));
-        CK(launch_refine_jobs(c->d_jobs + j, 1, c->lv[j].grid, s));
+        CK(launch_refine_jobs(c->d_jobs + j, 1, c->lv[j].grid, job_kind(c->lv[j].variant, c->lv[j].fp32), s));
         CK(hipEventRecord(c->events[2 * j + 1], s));
     }
-    CK(launch_finish_jobs(c->d_jobs + J + 1, 1, c->lv[0].grid, s));
+    CK(launch_finish_jobs(c->d_jobs + J + 1, 1, c->lv[0].grid, job_kind(c->lv[0].variant, c->lv[0].fp32), s));
     cmg_status st = enqueue_readback(c, x, where, s);
     if (st != CMG_OK) return st;
     CK(hipStreamSynchronize(s));
@@ -672,25 +673,31 @@ cmg_status batch_impl(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
     std::vector<std::pair<size_t, int>> launches;  // (offset in gj, njobs), with kind below
     std::vector<int> launch_blocks;
     std::vector<int> launch_kind;  // 0 refine, 1 finish
-    const int cap_r = refine_jobs_max_blocks();
-    const int cap_f = finish_jobs_max_blocks();
+    std::vector<int> launch_jk;    // job kernel kind
     auto pack = [&](std::vector<GridJob>& round, int kind) {
-        const int cap = kind ? cap_f : cap_r;
-        size_t i = 0;
-        while (i < round.size()) {
-            size_t first = gj.size();
-            int blocks = 0, nj = 0;
-            while (i < round.size() && (nj == 0 || blocks + round[i].L.grid <= cap)) {
-                GridJob g = round[i];
-                g.b0 = blocks;
-                blocks += g.L.grid;
-                gj.push_back(g);
-                ++nj;
-                ++i;
+        // one launch per job kernel kind, jobs packed up to its co-resident capacity
+        for (int jk = 0; jk < 4; ++jk) {
+            std::vector<GridJob> sel;
+            for (const GridJob& g : round)
+                if (job_kind(g.L.variant, g.L.fp32) == jk) sel.push_back(g);
+            const int cap = kind ? finish_jobs_max_blocks(jk) : refine_jobs_max_blocks(jk);
+            size_t i = 0;
+            while (i < sel.size()) {
+                size_t first = gj.size();
+                int blocks = 0, nj = 0;
+                while (i < sel.size() && (nj == 0 || blocks + sel[i].L.grid <= cap)) {
+                    GridJob g = sel[i];
+                    g.b0 = blocks;
+                    blocks += g.L.grid;
+                    gj.push_back(g);
+                    ++nj;
+                    ++i;
+                }
+                launches.push_back({first, nj});
+                launch_blocks.push_back(blocks);
+                launch_kind.push_back(kind);
+                launch_jk.push_back(jk);
             }
-            launches.push_back({first, nj});
-            launch_blocks.push_back(blocks);
-            launch_kind.push_back(kind);
         }
     };
     for (int r = 0; r < maxrounds; ++r) {
@@ -727,8 +734,8 @@ cmg_status batch_impl(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
     if (e == hipSuccess && !bj.empty()) e = launch_block_jobs(d_bj, (int)bj.size(), s);
     for (size_t q = 0; e == hipSuccess && q < launches.size(); ++q) {
         const GridJob* jp = d_gj + launches[q].first;
-        e = launch_kind[q] ? launch_finish_jobs(jp, launches[q].second, launch_blocks[q], s)
-                           : launch_refine_jobs(jp, launches[q].second, launch_blocks[q], s);
+        e = launch_kind[q] ? launch_finish_jobs(jp, launches[q].second, launch_blocks[q], launch_jk[q], s)
+                           : launch_refine_jobs(jp, launches[q].second, launch_blocks[q], launch_jk[q], s);
     }
     for (int i = 0; e == hipSuccess && i < count && status == CMG_OK; ++i)
         status = enqueue_readback(hs[i], xs ? xs[i] : nullptr, where, s);

@@ -68,12 +68,15 @@ hipError_t launch_fill_u32(unsigned* p, unsigned v, int64_t m, hipStream_t s);
 hipError_t launch_coarse_jobs(const CoarseJob* jobs, int njobs, hipStream_t s);
 // coarse levels of each job inside one workgroup (FP64 levels only)
 hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, hipStream_t s);
-// co-resident workgroups of the job kernels (cooperative launch limit)
-int refine_jobs_max_blocks();
-int finish_jobs_max_blocks();
-// one level of each job; nblocks = sum of the jobs' grids
-hipError_t launch_refine_jobs(const GridJob* jobs, int njobs, int nblocks, hipStream_t s);
-hipError_t launch_finish_jobs(const GridJob* jobs, int njobs, int nblocks, hipStream_t s);
+// Job kernels are specialised by traversal and precision: kind =
+// 2*(variant == 2) + fp32 (finishing kernels depend on the traversal only).
+int job_kind(int variant, int fp32);
+// co-resident workgroups of a job kernel kind (cooperative launch limit)
+int refine_jobs_max_blocks(int kind);
+int finish_jobs_max_blocks(int kind);
+// one level of each job (all of one kind); nblocks = sum of the jobs' grids
+hipError_t launch_refine_jobs(const GridJob* jobs, int njobs, int nblocks, int kind, hipStream_t s);
+hipError_t launch_finish_jobs(const GridJob* jobs, int njobs, int nblocks, int kind, hipStream_t s);
 // zero the barrier state and the slots (at setup, and after an abort)
 hipError_t launch_reset_sync(GridSync* gs, GridSlot* slots, int nslots, hipStream_t s);
 

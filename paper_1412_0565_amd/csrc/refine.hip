@@ -197,8 +197,6 @@ __global__ void __launch_bounds__(256) k_coarse_jobs(const CoarseJob* __restrict
     __shared__ double red[16 * 2 + 8];
     __shared__ double cs_c[128], cs_s[128];
     __shared__ int pr_p[128], pr_q[128];
-    __shared__ double s_fro, s_norm;
-    __shared__ int s_m;
     const int n = L.n;
     const int tid = threadIdx.x, nt = blockDim.x;
     double* A = (n <= kDenseLds) ? dyn : Ag;
@@ -298,7 +296,6 @@ __global__ void __launch_bounds__(256) k_coarse_jobs(const CoarseJob* __restrict
             }
             idx[k + 1] = t;
         }
-        s_fro = fro;
     }
     __syncthreads();
     const double l2 = ev[idx[1]];
@@ -617,7 +614,9 @@ struct PiOp {
     double acc[4];
     __device__ __forceinline__ double xi(int i) const { return (double)win[i]; }
     __device__ __forceinline__ double entry(int e, double x) const {
-        return (double)wv[e] * ((double)win[col[e]] - x);
+        const int c = __builtin_nontemporal_load(col + e);
+        const T a = __builtin_nontemporal_load(wv + e);
+        return (double)a * ((double)win[c] - x);
     }
     __device__ __forceinline__ void row(int i, double x, double t) {
         const double v = (x - mu) * s;
@@ -695,12 +694,41 @@ struct ResidualOp {
 };
 
 // ---- traversal driver 1: G lanes per row (G = 64: a wavefront per row)
+//
+// Each lane group takes two rows at a time (rows i and i + ngroups) so the
+// loads of both are in flight together; the rows are still emitted in the
+// order i, i + ngroups, i + 2 ngroups, ... of a one-row loop.
 
 template <int G, class Op>
 __device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r0, int r1, Op& op) {
     const int lane = threadIdx.x & (G - 1);
     const int ngroups = blockDim.x / G;
-    for (int i = r0 + (int)(threadIdx.x / G); i < r1; i += ngroups) {
+    int i = r0 + (int)(threadIdx.x / G);
+    for (; i + ngroups < r1; i += 2 * ngroups) {
+        const int i2 = i + ngroups;
+        const int a1 = __builtin_nontemporal_load(rp + i), b1 = __builtin_nontemporal_load(rp + i + 1);
+        const int a2 = __builtin_nontemporal_load(rp + i2), b2 = __builtin_nontemporal_load(rp + i2 + 1);
+        const double x1 = op.xi(i), x2 = op.xi(i2);
+        double t1 = 0.0, t2 = 0.0;
+        int e1 = a1 + lane, e2 = a2 + lane;
+        while (e1 < b1 || e2 < b2) {
+            if (e1 < b1) {
+                t1 += op.entry(e1, x1);
+                e1 += G;
+            }
+            if (e2 < b2) {
+                t2 += op.entry(e2, x2);
+                e2 += G;
+            }
+        }
+        t1 = group_sum_t<G>(t1);
+        t2 = group_sum_t<G>(t2);
+        if (lane == 0) {
+            op.row(i, x1, t1);
+            op.row(i2, x2, t2);
+        }
+    }
+    if (i < r1) {
         const int a = rp[i], b = rp[i + 1];
         const double x = op.xi(i);
         double t = 0.0;
@@ -837,27 +865,27 @@ __device__ __forceinline__ void drive_merge(const int32_t* __restrict__ rp, int 
     }
 }
 
-template <class Op>
-__device__ __forceinline__ void drive(const LevelDev& L, int r0, int r1, Op& op, MergeShared& sh) {
-    if (L.variant == 2) {
-        drive_merge(L.rp, r0, r1, op, sh);
-        return;
-    }
-    switch (L.lanes) {
-        case 1: drive_rows<1>(L.rp, r0, r1, op); break;
-        case 2: drive_rows<2>(L.rp, r0, r1, op); break;
-        case 4: drive_rows<4>(L.rp, r0, r1, op); break;
-        case 8: drive_rows<8>(L.rp, r0, r1, op); break;
-        case 16: drive_rows<16>(L.rp, r0, r1, op); break;
-        case 32: drive_rows<32>(L.rp, r0, r1, op); break;
-        default: drive_rows<64>(L.rp, r0, r1, op); break;
+template <int VAR, class Op>
+__device__ __forceinline__ void drive(const LevelDev& L, int r0, int r1, Op& op, MergeShared* sh) {
+    if constexpr (VAR == 2) {
+        drive_merge(L.rp, r0, r1, op, *sh);
+    } else {
+        switch (L.lanes) {
+            case 1: drive_rows<1>(L.rp, r0, r1, op); break;
+            case 2: drive_rows<2>(L.rp, r0, r1, op); break;
+            case 4: drive_rows<4>(L.rp, r0, r1, op); break;
+            case 8: drive_rows<8>(L.rp, r0, r1, op); break;
+            case 16: drive_rows<16>(L.rp, r0, r1, op); break;
+            case 32: drive_rows<32>(L.rp, r0, r1, op); break;
+            default: drive_rows<64>(L.rp, r0, r1, op); break;
+        }
     }
 }
 
 // ---- refinement of one level by a job's workgroups
 
-template <typename T>
-__device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeShared& sh) {
+template <typename T, int VAR>
+__device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeShared* sh) {
     const LevelDev& L = J.L;
     const double tol = J.tol;
     const int maxit = J.maxit;
@@ -904,7 +932,7 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
         op.mu = mu;
         op.s = s;
         op.acc[0] = op.acc[1] = op.acc[2] = op.acc[3] = 0.0;
-        drive(L, r0, r1, op, sh);
+        drive<VAR>(L, r0, r1, op, sh);
         if (!job_allreduce<4>(op.acc, c, red)) return;
         const double mu2 = op.acc[0] / n;
         const double s2 = 1.0 / sqrt(op.acc[1] - op.acc[0] * mu2);
@@ -945,7 +973,8 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
 // rounding.  Then the output y = deflated, normalised iterate, the
 // edge-form Rayleigh quotient r = sum_edges w (y_i - y_k)^2 and the
 // residual ||L y - r y||, all in FP64.
-__device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeShared& sh) {
+template <int VAR>
+__device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeShared* sh) {
     const LevelDev& L = J.L;
     const int r0 = L.part[c.lb], r1 = L.part[c.lb + 1];
     const double n = (double)L.n;
@@ -964,7 +993,7 @@ __device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeSha
         op.s = st.s_prev;
         op.g = L.g;
         op.acc[0] = op.acc[1] = 0.0;
-        drive(L, r0, r1, op, sh);
+        drive<VAR>(L, r0, r1, op, sh);
         if (!job_allreduce<2>(op.acc, c, red)) return;
         mu = op.acc[0] / n;
         s = 1.0 / sqrt(op.acc[1] - op.acc[0] * mu);
@@ -979,7 +1008,7 @@ __device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     eo.mu = mu;
     eo.s = s;
     eo.acc[0] = eo.acc[1] = eo.acc[2] = 0.0;
-    drive(L, r0, r1, eo, sh);
+    drive<VAR>(L, r0, r1, eo, sh);
     if (!job_allreduce<3>(eo.acc, c, red)) return;
     const double mean_u = eo.acc[0] / n;
     const double nrm2 = eo.acc[1] - eo.acc[0] * mean_u;
@@ -997,7 +1026,7 @@ __device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     ro.lam = lam;
     ro.yout = J.yout;
     ro.acc[0] = 0.0;
-    drive(L, r0, r1, ro, sh);
+    drive<VAR>(L, r0, r1, ro, sh);
     if (!job_allreduce<1>(ro.acc, c, red)) return;
     if (c.vb == 0 && threadIdx.x == 0) {
         J.fo->lambda = lam;
@@ -1032,27 +1061,6 @@ __device__ __forceinline__ GridCtx make_ctx(const GridJob& J) {
     return c;
 }
 
-// One launch refines one level of each job (one graph per job).
-__global__ void __launch_bounds__(kGridBlock) k_refine_jobs(const GridJob* __restrict__ jobs, int njobs) {
-    __shared__ double red[16 * 5 + 8];
-    __shared__ MergeShared sh;
-    const GridJob J = jobs[find_job(jobs, njobs)];
-    GridCtx c = make_ctx(J);
-    if (c.vb < 0 || c.vb >= c.nb) return;
-    if (J.L.fp32) refine_level<float>(J, c, red, sh);
-    else refine_level<double>(J, c, red, sh);
-}
-
-// One launch finishes the finest level of each job.
-__global__ void __launch_bounds__(kGridBlock) k_finish_jobs(const GridJob* __restrict__ jobs, int njobs) {
-    __shared__ double red[16 * 5 + 8];
-    __shared__ MergeShared sh;
-    const GridJob J = jobs[find_job(jobs, njobs)];
-    GridCtx c = make_ctx(J);
-    if (c.vb < 0 || c.vb >= c.nb) return;
-    finish_level(J, c, red, sh);
-}
-
 __global__ void k_reset_sync(GridSync* gs, GridSlot* slots, int nslots) {
     for (int b = threadIdx.x; b < nslots; b += blockDim.x) {
         for (int q = 0; q < 7; ++q) slots[b].v[q] = 0.0;
@@ -1065,13 +1073,36 @@ __global__ void k_reset_sync(GridSync* gs, GridSlot* slots, int nslots) {
     }
 }
 
-template <typename K>
-int max_blocks_of(K kern, int threads) {
-    int dev = 0, ncu = 0, occ = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, threads, 0) != hipSuccess) return 0;
-    return occ * ncu;
+// One launch refines one level of each job (one graph per job).  Kernels
+// are specialised by traversal and storage precision (kind = 2*(VAR-1) +
+// fp32) to keep registers and LDS low; a packed launch holds one kind.
+template <int VAR, typename T>
+__global__ void __launch_bounds__(kGridBlock) k_refine_jobs(const GridJob* __restrict__ jobs, int njobs) {
+    __shared__ double red[16 * 5 + 8];
+    MergeShared* sh = nullptr;
+    if constexpr (VAR == 2) {
+        __shared__ MergeShared msh;
+        sh = &msh;
+    }
+    const GridJob J = jobs[find_job(jobs, njobs)];
+    GridCtx c = make_ctx(J);
+    if (c.vb < 0 || c.vb >= c.nb) return;
+    refine_level<T, VAR>(J, c, red, sh);
+}
+
+// One launch finishes the finest level of each job.
+template <int VAR>
+__global__ void __launch_bounds__(kGridBlock) k_finish_jobs(const GridJob* __restrict__ jobs, int njobs) {
+    __shared__ double red[16 * 5 + 8];
+    MergeShared* sh = nullptr;
+    if constexpr (VAR == 2) {
+        __shared__ MergeShared msh;
+        sh = &msh;
+    }
+    const GridJob J = jobs[find_job(jobs, njobs)];
+    GridCtx c = make_ctx(J);
+    if (c.vb < 0 || c.vb >= c.nb) return;
+    finish_level<VAR>(J, c, red, sh);
 }
 
 }  // namespace
@@ -1112,26 +1143,49 @@ hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, hipStream_t s) {
     return hipGetLastError();
 }
 
-int refine_jobs_max_blocks() {
-    static int r = -1;
-    if (r < 0) r = max_blocks_of(k_refine_jobs, kGridBlock);
-    return r;
+namespace {
+const void* refine_kernel(int kind) {
+    switch (kind) {
+        case 0: return (const void*)k_refine_jobs<1, double>;
+        case 1: return (const void*)k_refine_jobs<1, float>;
+        case 2: return (const void*)k_refine_jobs<2, double>;
+        default: return (const void*)k_refine_jobs<2, float>;
+    }
+}
+const void* finish_kernel(int kind) {
+    return (kind >= 2) ? (const void*)k_finish_jobs<2> : (const void*)k_finish_jobs<1>;
+}
+int max_blocks_ptr(const void* k) {
+    int dev = 0, ncu = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, kGridBlock, 0) != hipSuccess) return 0;
+    return occ * ncu;
+}
+}  // namespace
+
+int job_kind(int variant, int fp32) { return 2 * (variant == 2 ? 1 : 0) + (fp32 ? 1 : 0); }
+
+int refine_jobs_max_blocks(int kind) {
+    static int r[4] = {-1, -1, -1, -1};
+    if (r[kind] < 0) r[kind] = max_blocks_ptr(refine_kernel(kind));
+    return r[kind];
 }
 
-int finish_jobs_max_blocks() {
-    static int r = -1;
-    if (r < 0) r = max_blocks_of(k_finish_jobs, kGridBlock);
-    return r;
+int finish_jobs_max_blocks(int kind) {
+    static int r[4] = {-1, -1, -1, -1};
+    if (r[kind] < 0) r[kind] = max_blocks_ptr(finish_kernel(kind));
+    return r[kind];
 }
 
-hipError_t launch_refine_jobs(const GridJob* jobs, int njobs, int nblocks, hipStream_t s) {
+hipError_t launch_refine_jobs(const GridJob* jobs, int njobs, int nblocks, int kind, hipStream_t s) {
     void* args[] = {(void*)&jobs, &njobs};
-    return hipLaunchCooperativeKernel((const void*)k_refine_jobs, dim3(nblocks), dim3(kGridBlock), args, 0, s);
+    return hipLaunchCooperativeKernel(refine_kernel(kind), dim3(nblocks), dim3(kGridBlock), args, 0, s);
 }
 
-hipError_t launch_finish_jobs(const GridJob* jobs, int njobs, int nblocks, hipStream_t s) {
+hipError_t launch_finish_jobs(const GridJob* jobs, int njobs, int nblocks, int kind, hipStream_t s) {
     void* args[] = {(void*)&jobs, &njobs};
-    return hipLaunchCooperativeKernel((const void*)k_finish_jobs, dim3(nblocks), dim3(kGridBlock), args, 0, s);
+    return hipLaunchCooperativeKernel(finish_kernel(kind), dim3(nblocks), dim3(kGridBlock), args, 0, s);
 }
 
 hipError_t launch_reset_sync(GridSync* gs, GridSlot* slots, int nslots, hipStream_t s) {

@@ -109,6 +109,7 @@ struct cmg_ctx {
     double* d_fb = nullptr;
     double* d_y = nullptr;
     int coarse_dense = 1;
+    double clock_khz = 100000.0;  // constant-clock ticks per ms
     int block_lo = -1;  // levels >= block_lo (and < coarsest or the PI coarsest) run in one workgroup
     int collapsed = 0;
     int hec_rounds = 0;
@@ -472,6 +473,12 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         CK(hipMemcpyAsync(c->d_bjob, &bj, sizeof(bj), hipMemcpyHostToDevice, c->stream));
     }
     c->h_st.resize(J + 1);
+    {
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            c->clock_khz = khz;
+    }
     c->events.resize(2 * (J + 1));
     for (auto& e : c->events) CK(hipEventCreate(&e));
     CK(hipStreamSynchronize(c->stream));
@@ -594,6 +601,7 @@ cmg_status finalize(cmg_ctx* c, double t0, bool timed, double* lambda, cmg_stats
             if (c->h_st[j].maxit) status = CMG_W_MAXIT;
         }
         L.pi_ms = 0.0;
+        if (L.in_block && c->h_st[j].ticks > 0) L.pi_ms = c->h_st[j].ticks / c->clock_khz;
         if (timed && !L.in_block && j <= c->top) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, c->events[2 * j], c->events[2 * j + 1]) == hipSuccess) L.pi_ms = ms;

@@ -130,6 +130,7 @@ struct LevelState {
     int32_t k;      // PI steps
     int32_t maxit;  // 1 if the cap was hit
     int32_t err;    // device-side failure (barrier timeout)
+    long long ticks;  // single-workgroup levels: duration in constant-clock ticks
 };
 
 // Result of the finishing pass.

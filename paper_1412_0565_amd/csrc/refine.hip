@@ -348,6 +348,7 @@ __global__ void __launch_bounds__(256) k_coarse_jobs(const CoarseJob* __restrict
         s0.k = -1;
         s0.maxit = 0;
         s0.err = 0;
+        s0.ticks = 0;
         *st = s0;
         fo->coarse_lambda2 = l2;
         fo->coarse_mult = mult;
@@ -449,6 +450,7 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
     }
     __syncthreads();
     for (int j = jhi; j >= jlo; --j) {
+        const long long t_start = wall_clock64();
         const LevelDev L = lv[j];
         const int n = L.n;
         // ---- choose where the level lives
@@ -571,6 +573,7 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
             o.k = k;
             o.maxit = hit;
             o.err = 0;
+            o.ticks = wall_clock64() - t_start;
             st[j] = o;
             s_cm = mu;
             s_cs = s;
@@ -614,9 +617,7 @@ struct PiOp {
     double acc[4];
     __device__ __forceinline__ double xi(int i) const { return (double)win[i]; }
     __device__ __forceinline__ double entry(int e, double x) const {
-        const int c = __builtin_nontemporal_load(col + e);
-        const T a = __builtin_nontemporal_load(wv + e);
-        return (double)a * ((double)win[c] - x);
+        return (double)wv[e] * ((double)win[col[e]] - x);
     }
     __device__ __forceinline__ void row(int i, double x, double t) {
         const double v = (x - mu) * s;
@@ -706,8 +707,8 @@ __device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r
     int i = r0 + (int)(threadIdx.x / G);
     for (; i + ngroups < r1; i += 2 * ngroups) {
         const int i2 = i + ngroups;
-        const int a1 = __builtin_nontemporal_load(rp + i), b1 = __builtin_nontemporal_load(rp + i + 1);
-        const int a2 = __builtin_nontemporal_load(rp + i2), b2 = __builtin_nontemporal_load(rp + i2 + 1);
+        const int a1 = rp[i], b1 = rp[i + 1];
+        const int a2 = rp[i2], b2 = rp[i2 + 1];
         const double x1 = op.xi(i), x2 = op.xi(i2);
         double t1 = 0.0, t2 = 0.0;
         int e1 = a1 + lane, e2 = a2 + lane;
@@ -961,6 +962,7 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
         o.k = k;
         o.maxit = hit;
         o.err = 0;
+        o.ticks = 0;
         *J.st = o;
     }
 }

@@ -368,14 +368,15 @@ cmg_status build_refine_plan(cmg_ctx* c) {
             ALLOC(L.w32, float, std::max<int64_t>(L.nnz, 1));
             CK(launch_to_f32(L.nnz, L.w64, L.w32, c->stream));
         }
-        // grid size: about 8k rows+entries per workgroup, multiple of 8,
-        // at most what can be co-resident
+        // grid size: about 2k rows+entries per workgroup (short per-group
+        // latency chains on mid-size levels), multiple of 8, at most what
+        // can be co-resident
         const int kind = job_kind(L.variant, L.fp32);
         int cap = refine_jobs_max_blocks(kind);
         if (j == 0) cap = std::min(cap, finish_jobs_max_blocks(kind));
         cap = std::max(8, (cap / 8) * 8);
         int64_t work = (int64_t)L.n + L.nnz;
-        int64_t want = (work + 8191) / 8192;
+        int64_t want = (work + 2047) / 2048;
         want = ((want + 7) / 8) * 8;
         L.grid = (int)std::min<int64_t>(std::max<int64_t>(want, 8), cap);
         maxgrid = std::max(maxgrid, L.grid);

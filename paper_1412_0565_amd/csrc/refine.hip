@@ -357,19 +357,10 @@ __global__ void __launch_bounds__(256) k_coarse_jobs(const CoarseJob* __restrict
 
 // ------------------------------------------------ single-workgroup levels
 
-// LDS image of one small level: vectors first (8-byte aligned), then
-// weights, row pointers and columns.
-struct StagedLevel {
-    double* x0;
-    double* x1;
-    const void* w;  // float if w32, else double
-    const int32_t* rp;
-    const void* col;  // uint16 if col16, else int32
-};
-
 __device__ __forceinline__ size_t align8(size_t b) { return (b + 7) & ~(size_t)7; }
 
-// bytes of the LDS image; 0 if it does not fit in `budget`
+// Bytes of the LDS image of a level: two vectors, weights (FP32 when that
+// is exact), row pointers, columns (uint16 when n <= 65536).
 __device__ __forceinline__ size_t staged_bytes(const LevelDev& L, int w32, int col16) {
     size_t b = align8(16 * (size_t)L.n);
     b += align8((size_t)L.nnz * (w32 ? 4 : 8));
@@ -378,19 +369,58 @@ __device__ __forceinline__ size_t staged_bytes(const LevelDev& L, int w32, int c
     return b;
 }
 
-// One PI step reading the LDS image; lane 0 of each G-lane group owns a row.
+// Levels up to this size run on one wavefront with no workgroup barrier.
+constexpr int kWaveRows = 256;
+
+// Sum of NV (<= 4) doubles over the active threads, identical in every
+// thread.  Wave mode: butterfly, value of lane 0.  Workgroup mode: waves
+// post their sums (one barrier, alternating slots); each wave reads the
+// posts with one LDS access per lane and adds them by a 16-lane butterfly.
+template <int NV, bool WAVE>
+__device__ __forceinline__ void small_sum(double (&v)[NV], double* red, int& parity) {
+    const int lane = threadIdx.x & 63;
+    if constexpr (WAVE) {
+        // LDS writes of this step become visible to the other lanes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] = __shfl(group_sum_t<64>(v[q]), 0, 64);
+    } else {
+        const int wv = threadIdx.x >> 6;
+        const int nw = blockDim.x >> 6;
+        double* slot = red + parity * 64;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] = group_sum_t<64>(v[q]);
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) slot[q * 16 + wv] = v[q];
+        }
+        __syncthreads();
+        double t = (lane < NV * 16 && (lane & 15) < nw) ? slot[lane] : 0.0;
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] = __shfl(t, q * 16, 64);
+        parity ^= 1;
+    }
+}
+
+// One PI step of a small level, rows shared by `nthr` threads in G-lane
+// groups.  Pointers are either all LDS (staged modes) or all global.
 template <int G, bool W32, bool C16>
-__device__ __forceinline__ void pi_rows_lds(const StagedLevel& S, int n, double g, const double* win,
-                                            double* wout, double mu, double s, double (&acc)[4]) {
+__device__ __forceinline__ void pi_small(int n, int nthr, const int32_t* rp, const void* colp,
+                                         const void* wp, double g, const double* win, double* wout,
+                                         double mu, double s, double (&acc)[4]) {
     const int lane = threadIdx.x & (G - 1);
-    const int ngroups = blockDim.x / G;
+    const int ngroups = nthr / G;
     for (int i = (int)(threadIdx.x / G); i < n; i += ngroups) {
-        const int a = S.rp[i], b = S.rp[i + 1];
+        const int a = rp[i], b = rp[i + 1];
         const double wi = win[i];
         double t = 0.0;
         for (int e = a + lane; e < b; e += G) {
-            const int c = C16 ? (int)((const uint16_t*)S.col)[e] : ((const int32_t*)S.col)[e];
-            const double wt = W32 ? (double)((const float*)S.w)[e] : ((const double*)S.w)[e];
+            const int c = C16 ? (int)((const uint16_t*)colp)[e] : ((const int32_t*)colp)[e];
+            const double wt = W32 ? (double)((const float*)wp)[e] : ((const double*)wp)[e];
             t += wt * (win[c] - wi);
         }
         t = group_sum_t<G>(t);
@@ -406,54 +436,156 @@ __device__ __forceinline__ void pi_rows_lds(const StagedLevel& S, int n, double 
     }
 }
 
-template <bool W32, bool C16>
-__device__ __forceinline__ void pi_rows_lds_dispatch(int G, const StagedLevel& S, int n, double g,
-                                                     const double* win, double* wout, double mu, double s,
-                                                     double (&acc)[4]) {
-    switch (G) {
-        case 1: pi_rows_lds<1, W32, C16>(S, n, g, win, wout, mu, s, acc); break;
-        case 2: pi_rows_lds<2, W32, C16>(S, n, g, win, wout, mu, s, acc); break;
-        case 4: pi_rows_lds<4, W32, C16>(S, n, g, win, wout, mu, s, acc); break;
-        case 8: pi_rows_lds<8, W32, C16>(S, n, g, win, wout, mu, s, acc); break;
-        case 16: pi_rows_lds<16, W32, C16>(S, n, g, win, wout, mu, s, acc); break;
-        case 32: pi_rows_lds<32, W32, C16>(S, n, g, win, wout, mu, s, acc); break;
-        default: pi_rows_lds<64, W32, C16>(S, n, g, win, wout, mu, s, acc); break;
+struct SmallIn {
+    const void* cbuf;  // final vector of the coarser level
+    int cfp32;
+    int uniform;
+    double cm, cs;     // its transform (v - cm) * cs
+    uint64_t seed;
+    double tol;
+    int maxit;
+};
+
+// Prolongation, deflation, normalisation and PI steps of one small level.
+// MODE 0: LDS image, one wavefront; 1: LDS image, whole workgroup;
+// 2: global memory, whole workgroup.
+template <int MODE, bool W32, bool C16>
+__device__ void small_level(const LevelDev& L, const SmallIn& in, double* lds, double* red, int& parity,
+                            LevelState& out) {
+    constexpr bool WAVE = (MODE == 0);
+    const int n = L.n;
+    const int nthr = WAVE ? 64 : (int)blockDim.x;
+    double* b0;
+    double* b1;
+    const int32_t* rp;
+    const void* colp;
+    const void* wp;
+    if constexpr (MODE != 2) {
+        char* p = (char*)lds;
+        b0 = (double*)p;
+        b1 = b0 + n;
+        p += align8(16 * (size_t)n);
+        wp = p;
+        p += align8((size_t)L.nnz * (W32 ? 4 : 8));
+        rp = (const int32_t*)p;
+        p += align8(4 * ((size_t)n + 1));
+        colp = p;
+    } else {
+        b0 = (double*)L.buf0;
+        b1 = (double*)L.buf1;
+        rp = L.rp;
+        colp = L.col;
+        wp = L.w64;
     }
+    double sum[1] = {0.0};
+    if (in.uniform) {
+        for (int i = threadIdx.x; i < n; i += nthr) {
+            const double v = hashed_uniform(in.seed, i) - 0.5;
+            b0[i] = v;
+            sum[0] += v;
+        }
+    } else {
+        for (int i = threadIdx.x; i < n; i += nthr) {
+            const double v = (ld_any(in.cbuf, in.cfp32, L.agg[i]) - in.cm) * in.cs;
+            b0[i] = v;
+            sum[0] += v;
+        }
+    }
+    small_sum<1, WAVE>(sum, red, parity);
+    double mu = sum[0] / (double)n;
+    double ss[1] = {0.0};
+    for (int i = threadIdx.x; i < n; i += nthr) {
+        const double d = b0[i] - mu;
+        ss[0] += d * d;
+    }
+    small_sum<1, WAVE>(ss, red, parity);
+    double s = 1.0 / sqrt(ss[0]);
+    int cur = 0, k = 0, hit = 0;
+    double utv = 0.0, pmu = mu, ps = s;
+    while (true) {
+        const double* win = cur ? b1 : b0;
+        double* wout = cur ? b0 : b1;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        switch (L.lanes) {
+            case 1: pi_small<1, W32, C16>(n, nthr, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+            case 2: pi_small<2, W32, C16>(n, nthr, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+            case 4: pi_small<4, W32, C16>(n, nthr, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+            case 8: pi_small<8, W32, C16>(n, nthr, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+            case 16: pi_small<16, W32, C16>(n, nthr, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+            case 32: pi_small<32, W32, C16>(n, nthr, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+            default: pi_small<64, W32, C16>(n, nthr, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+        }
+        small_sum<4, WAVE>(acc, red, parity);
+        const double mu2 = acc[0] / (double)n;
+        const double s2 = 1.0 / sqrt(acc[1] - acc[0] * mu2);
+        utv = s2 * (acc[2] - mu2 * acc[3]);
+        ++k;
+        cur ^= 1;
+        pmu = mu;
+        ps = s;
+        mu = mu2;
+        s = s2;
+        if (!(utv < 1.0 - in.tol)) break;
+        if (k >= in.maxit) {
+            hit = 1;
+            break;
+        }
+    }
+    int fin = cur;
+    if constexpr (MODE != 2) {
+        // the LDS image is discarded: final vector to buf0, previous to buf1
+        const double* src = cur ? b1 : b0;
+        const double* prv = cur ? b0 : b1;
+        double* g0 = (double*)L.buf0;
+        double* g1 = (double*)L.buf1;
+        for (int i = threadIdx.x; i < n; i += nthr) {
+            g0[i] = src[i];
+            g1[i] = prv[i];
+        }
+        fin = 0;
+    }
+    out.mu = mu;
+    out.s = s;
+    out.mu_prev = pmu;
+    out.s_prev = ps;
+    out.utv = utv;
+    out.margin = utv - (1.0 - in.tol);
+    out.fin = fin;
+    out.k = k;
+    out.maxit = hit;
+    out.err = 0;
+    out.ticks = 0;
 }
 
 // Levels jhi down to jlo (all FP64, small) refined inside one workgroup:
 // prolongation, deflation, normalisation and every PI step separated only
-// by workgroup barriers, so thousands of steps cost no launches.  A level
-// whose CSR and two vectors fit in `lds_budget` bytes is first copied to
-// LDS (columns as uint16 when n <= 65536, weights as FP32 when that is
-// exact), so its steps touch no global memory; larger levels stream from
-// global memory (L2).  The final vector of each level goes to buf0.
+// by workgroup (or wavefront) barriers, so thousands of steps cost no
+// launches.  A level whose CSR and two vectors fit in `lds_budget` bytes
+// is first copied to LDS (columns as uint16 when n <= 65536, weights as
+// FP32 when that is exact) and its steps touch no global memory; levels of
+// at most kWaveRows vertices then run on a single wavefront.  Larger levels
+// stream from global memory (L2).  The final vector of each level goes to
+// buf0 (its predecessor to buf1).
 __global__ void __launch_bounds__(kBlockKernelThreads)
     k_block_jobs(const BlockJob* __restrict__ jobs, int lds_budget) {
     extern __shared__ double lds[];
-    const BlockJob Jb = jobs[blockIdx.x];
-    const LevelDev* __restrict__ lv = Jb.lv;
-    LevelState* st = Jb.st;
-    const int jhi = Jb.jhi, jlo = Jb.jlo, uniform_start = Jb.uniform;
-    const double tol = Jb.tol;
-    const int maxit = Jb.maxit;
-    const uint64_t seed = Jb.seed;
-    __shared__ double red[2 * 4 * 16];
+    __shared__ double red[2 * 64];
     __shared__ double s_cm, s_cs;
     __shared__ int s_cfin;
+    const BlockJob Jb = jobs[blockIdx.x];
+    const LevelDev* __restrict__ lv = Jb.lv;
     int parity = 0;
-    if (threadIdx.x == 0 && !uniform_start) {
-        LevelState c = st[jhi + 1];
+    if (threadIdx.x == 0 && !Jb.uniform) {
+        LevelState c = Jb.st[Jb.jhi + 1];
         s_cm = c.mu;
         s_cs = c.s;
         s_cfin = c.fin;
     }
     __syncthreads();
-    for (int j = jhi; j >= jlo; --j) {
+    for (int j = Jb.jhi; j >= Jb.jlo; --j) {
         const long long t_start = wall_clock64();
         const LevelDev L = lv[j];
         const int n = L.n;
-        // ---- choose where the level lives
         const int c16 = (n <= 65536) ? 1 : 0;
         int w32 = 0;
         size_t need = staged_bytes(L, 0, c16);
@@ -462,122 +594,67 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
             need = staged_bytes(L, 1, c16);
         }
         const bool staged = need <= (size_t)lds_budget;
-        StagedLevel S;
-        double* b0;
-        double* b1;
+        const int mode = staged ? (n <= kWaveRows ? 0 : 1) : 2;
         if (staged) {
             char* p = (char*)lds;
-            S.x0 = (double*)p;
-            S.x1 = S.x0 + n;
             p += align8(16 * (size_t)n);
-            S.w = p;
+            void* wdst = p;
             p += align8((size_t)L.nnz * (w32 ? 4 : 8));
-            S.rp = (const int32_t*)p;
+            int32_t* rdst = (int32_t*)p;
             p += align8(4 * ((size_t)n + 1));
-            S.col = p;
-            for (int i = threadIdx.x; i <= n; i += blockDim.x) ((int32_t*)S.rp)[i] = L.rp[i];
+            void* cdst = p;
+            for (int i = threadIdx.x; i <= n; i += blockDim.x) rdst[i] = L.rp[i];
             for (int e = threadIdx.x; e < (int)L.nnz; e += blockDim.x) {
-                if (c16) ((uint16_t*)S.col)[e] = (uint16_t)L.col[e];
-                else ((int32_t*)S.col)[e] = L.col[e];
-                if (w32) ((float*)S.w)[e] = (float)L.w64[e];
-                else ((double*)S.w)[e] = L.w64[e];
+                if (c16) ((uint16_t*)cdst)[e] = (uint16_t)L.col[e];
+                else ((int32_t*)cdst)[e] = L.col[e];
+                if (w32) ((float*)wdst)[e] = (float)L.w64[e];
+                else ((double*)wdst)[e] = L.w64[e];
             }
-            b0 = S.x0;
-            b1 = S.x1;
-        } else {
-            b0 = (double*)L.buf0;
-            b1 = (double*)L.buf1;
+            __syncthreads();
         }
-        // ---- prolongation (or hashed uniform start), deflation, norm
-        double sum[1] = {0.0};
-        if (uniform_start && j == jhi) {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                double v = hashed_uniform(seed, i) - 0.5;
-                b0[i] = v;
-                sum[0] += v;
-            }
-        } else {
+        SmallIn in;
+        in.uniform = (Jb.uniform && j == Jb.jhi) ? 1 : 0;
+        if (!in.uniform) {
             const LevelDev C = lv[j + 1];
-            const void* cb = s_cfin ? C.buf1 : C.buf0;
-            const double cm = s_cm, cs = s_cs;
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                double v = (ld_any(cb, C.fp32, L.agg[i]) - cm) * cs;
-                b0[i] = v;
-                sum[0] += v;
-            }
+            in.cbuf = s_cfin ? C.buf1 : C.buf0;
+            in.cfp32 = C.fp32;
+        } else {
+            in.cbuf = nullptr;
+            in.cfp32 = 0;
         }
-        block_sum1<1>(sum, red, parity);
-        double mu = sum[0] / (double)n;
-        double ss[1] = {0.0};
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            double d = b0[i] - mu;
-            ss[0] += d * d;
-        }
-        block_sum1<1>(ss, red, parity);
-        double s = 1.0 / sqrt(ss[0]);
-        int cur = 0, k = 0, hit = 0;
-        double utv = 0.0, pmu = mu, ps = s;
-        while (true) {
-            const double* win = cur ? b1 : b0;
-            double* wout = cur ? b0 : b1;
-            double acc[4] = {0.0, 0.0, 0.0, 0.0};
-            if (staged) {
+        in.cm = s_cm;
+        in.cs = s_cs;
+        in.seed = Jb.seed;
+        in.tol = Jb.tol;
+        in.maxit = Jb.maxit;
+        LevelState o;
+        if (mode == 0) {
+            if (threadIdx.x < 64) {
                 if (w32) {
-                    if (c16) pi_rows_lds_dispatch<true, true>(L.lanes, S, n, L.g, win, wout, mu, s, acc);
-                    else pi_rows_lds_dispatch<true, false>(L.lanes, S, n, L.g, win, wout, mu, s, acc);
+                    if (c16) small_level<0, true, true>(L, in, lds, red, parity, o);
+                    else small_level<0, true, false>(L, in, lds, red, parity, o);
                 } else {
-                    if (c16) pi_rows_lds_dispatch<false, true>(L.lanes, S, n, L.g, win, wout, mu, s, acc);
-                    else pi_rows_lds_dispatch<false, false>(L.lanes, S, n, L.g, win, wout, mu, s, acc);
+                    if (c16) small_level<0, false, true>(L, in, lds, red, parity, o);
+                    else small_level<0, false, false>(L, in, lds, red, parity, o);
                 }
+            }
+        } else if (mode == 1) {
+            if (w32) {
+                if (c16) small_level<1, true, true>(L, in, lds, red, parity, o);
+                else small_level<1, true, false>(L, in, lds, red, parity, o);
             } else {
-                pi_rows_dispatch<double>(L.lanes, L, win, wout, mu, s, 0, n, acc);
+                if (c16) small_level<1, false, true>(L, in, lds, red, parity, o);
+                else small_level<1, false, false>(L, in, lds, red, parity, o);
             }
-            block_sum1<4>(acc, red, parity);
-            const double mu2 = acc[0] / (double)n;
-            const double s2 = 1.0 / sqrt(acc[1] - acc[0] * mu2);
-            utv = s2 * (acc[2] - mu2 * acc[3]);
-            ++k;
-            cur ^= 1;
-            pmu = mu;
-            ps = s;
-            mu = mu2;
-            s = s2;
-            if (!(utv < 1.0 - tol)) break;
-            if (k >= maxit) {
-                hit = 1;
-                break;
-            }
-        }
-        // final vector to global buf0 (staged levels live in LDS until here)
-        int fin = cur;
-        if (staged) {
-            const double* src = cur ? b1 : b0;
-            const double* prv = cur ? b0 : b1;
-            double* g0 = (double*)L.buf0;
-            double* g1 = (double*)L.buf1;
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                g0[i] = src[i];
-                g1[i] = prv[i];
-            }
-            fin = 0;
+        } else {
+            small_level<2, false, false>(L, in, lds, red, parity, o);
         }
         if (threadIdx.x == 0) {
-            LevelState o;
-            o.mu = mu;
-            o.s = s;
-            o.mu_prev = pmu;
-            o.s_prev = ps;
-            o.utv = utv;
-            o.margin = utv - (1.0 - tol);
-            o.fin = fin;
-            o.k = k;
-            o.maxit = hit;
-            o.err = 0;
             o.ticks = wall_clock64() - t_start;
-            st[j] = o;
-            s_cm = mu;
-            s_cs = s;
-            s_cfin = fin;
+            Jb.st[j] = o;
+            s_cm = o.mu;
+            s_cs = o.s;
+            s_cfin = o.fin;
         }
         __syncthreads();
     }

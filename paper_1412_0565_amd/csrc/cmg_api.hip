@@ -371,7 +371,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         // grid size: about 2k rows+entries per workgroup (short per-group
         // latency chains on mid-size levels), multiple of 8, at most what
         // can be co-resident
-        const int kind = job_kind(L.variant, L.fp32);
+        const int kind = job_kind(L.variant, L.lanes, L.fp32);
         int cap = refine_jobs_max_blocks(kind);
         if (j == 0) cap = std::min(cap, finish_jobs_max_blocks(kind));
         cap = std::max(8, (cap / 8) * 8);
@@ -390,7 +390,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
     ALLOC(c->d_st, LevelState, J + 1);
     ALLOC(c->d_sync, GridSync, 1);
     c->nslots = maxgrid;
-    ALLOC(c->d_slots, GridSlot, maxgrid);
+    ALLOC(c->d_slots, GridSlot, 2 * maxgrid);
     CK(launch_reset_sync(c->d_sync, c->d_slots, c->nslots, c->stream));
     ALLOC(c->d_bcast, double, 8);
     ALLOC(c->d_fo, FinishOut, 1);
@@ -647,10 +647,10 @@ cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where,
     // grid levels: one cooperative launch per level
     for (int j = std::min(c->top, c->block_lo - 1); j >= 0; --j) {
         CK(hipEventRecord(c->events[2 * j], s));
-        CK(launch_refine_jobs(c->d_jobs + j, 1, c->lv[j].grid, job_kind(c->lv[j].variant, c->lv[j].fp32), s));
+        CK(launch_refine_jobs(c->d_jobs + j, 1, c->lv[j].grid, job_kind(c->lv[j].variant, c->lv[j].lanes, c->lv[j].fp32), s));
         CK(hipEventRecord(c->events[2 * j + 1], s));
     }
-    CK(launch_finish_jobs(c->d_jobs + J + 1, 1, c->lv[0].grid, job_kind(c->lv[0].variant, c->lv[0].fp32), s));
+    CK(launch_finish_jobs(c->d_jobs + J + 1, 1, c->lv[0].grid, job_kind(c->lv[0].variant, c->lv[0].lanes, c->lv[0].fp32), s));
     cmg_status st = enqueue_readback(c, x, where, s);
     if (st != CMG_OK) return st;
     CK(hipStreamSynchronize(s));
@@ -685,10 +685,10 @@ cmg_status batch_impl(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
     std::vector<int> launch_jk;    // job kernel kind
     auto pack = [&](std::vector<GridJob>& round, int kind) {
         // one launch per job kernel kind, jobs packed up to its co-resident capacity
-        for (int jk = 0; jk < 4; ++jk) {
+        for (int jk = 0; jk < kJobKinds; ++jk) {
             std::vector<GridJob> sel;
             for (const GridJob& g : round)
-                if (job_kind(g.L.variant, g.L.fp32) == jk) sel.push_back(g);
+                if (job_kind(g.L.variant, g.L.lanes, g.L.fp32) == jk) sel.push_back(g);
             const int cap = kind ? finish_jobs_max_blocks(jk) : refine_jobs_max_blocks(jk);
             size_t i = 0;
             while (i < sel.size()) {

@@ -68,16 +68,18 @@ hipError_t launch_fill_u32(unsigned* p, unsigned v, int64_t m, hipStream_t s);
 hipError_t launch_coarse_jobs(const CoarseJob* jobs, int njobs, hipStream_t s);
 // coarse levels of each job inside one workgroup (FP64 levels only)
 hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, hipStream_t s);
-// Job kernels are specialised by traversal and precision: kind =
-// 2*(variant == 2) + fp32 (finishing kernels depend on the traversal only).
-int job_kind(int variant, int fp32);
+// Job kernels are specialised by traversal (merge path or G lanes per
+// row) and precision: kind = 2 * t + fp32, t = 0 for the merge path, else
+// 1 + log2(G); finishing kernels depend on the traversal only.
+constexpr int kJobKinds = 16;
+int job_kind(int variant, int lanes, int fp32);
 // co-resident workgroups of a job kernel kind (cooperative launch limit)
 int refine_jobs_max_blocks(int kind);
 int finish_jobs_max_blocks(int kind);
 // one level of each job (all of one kind); nblocks = sum of the jobs' grids
 hipError_t launch_refine_jobs(const GridJob* jobs, int njobs, int nblocks, int kind, hipStream_t s);
 hipError_t launch_finish_jobs(const GridJob* jobs, int njobs, int nblocks, int kind, hipStream_t s);
-// zero the barrier state and the slots (at setup, and after an abort)
+// zero the barrier state and the slots (2 * nslots; at setup, and after an abort)
 hipError_t launch_reset_sync(GridSync* gs, GridSlot* slots, int nslots, hipStream_t s);
 
 constexpr int kGridBlock = 512;

@@ -45,13 +45,22 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // the grid is co-resident (cooperative launch).
 constexpr long long kSpinTicks = 200000000LL;
 
+// Grids up to this many workgroups use the all-read form below.
+constexpr int kAllReadMax = 64;
+
 // Grid-wide sum of NV (<= 7) doubles with a barrier, free of contended
 // atomics: every workgroup writes its block sums and the barrier epoch into
-// its own 64-byte slot (release); workgroup 0 polls all slots in parallel,
-// adds them in slot order (a fixed tree, independent of arrival order) and
-// publishes the totals and the epoch (release); the others wait for the
-// epoch and read the totals.  Returns false if the barrier timed out or was
-// aborted; then every workgroup leaves.
+// its own 64-byte slot (release); slots alternate between two banks by
+// epoch parity, so a slot is rewritten only after every workgroup has
+// passed the barrier in between.
+//  * Small grids (nb <= kAllReadMax): every workgroup polls all slots and
+//    adds them itself (one memory round trip less).
+//  * Larger grids: workgroup 0 polls all slots, adds them, publishes the
+//    totals and the epoch (release); the others wait for the epoch.
+// Either way the totals are the slot values added in slot order by the
+// same fixed tree, so they do not depend on which workgroup adds them or
+// on arrival order.  Returns false if the barrier timed out or was aborted;
+// then every workgroup leaves.
 template <int NV>
 __device__ bool grid_allreduce_impl(double (&v)[NV], GridSync* gs, GridSlot* slots, double* bcast,
                                     unsigned long long& epoch, int lb, bool master, int nb,
@@ -59,22 +68,24 @@ __device__ bool grid_allreduce_impl(double (&v)[NV], GridSync* gs, GridSlot* slo
     __shared__ double s_tot[NV];
     __shared__ int s_ok;
     const unsigned long long e = ++epoch;
+    GridSlot* bank = slots + (e & 1ull) * (unsigned long long)nb;
     block_sum<NV>(v, red);
     if (threadIdx.x == 0) {
-        GridSlot* my = slots + lb;
+        GridSlot* my = bank + lb;
 #pragma unroll
         for (int q = 0; q < NV; ++q) my->v[q] = v[q];
         __hip_atomic_store(&my->epoch, e, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         s_ok = 1;
     }
     __syncthreads();
-    if (master) {
+    const bool allread = nb <= kAllReadMax;
+    if (allread || master) {
         double acc[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) acc[q] = 0.0;
         for (int b = threadIdx.x; b < nb; b += blockDim.x) {
             const long long t0 = wall_clock64();
-            while (__hip_atomic_load(&slots[b].epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != e) {
+            while (__hip_atomic_load(&bank[b].epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != e) {
                 __builtin_amdgcn_s_sleep(1);
                 if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
                     wall_clock64() - t0 > kSpinTicks) {
@@ -85,16 +96,19 @@ __device__ bool grid_allreduce_impl(double (&v)[NV], GridSync* gs, GridSlot* slo
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 #pragma unroll
-            for (int q = 0; q < NV; ++q) acc[q] += ld_agent(&slots[b].v[q]);
+            for (int q = 0; q < NV; ++q) acc[q] += ld_agent(&bank[b].v[q]);
         }
         block_sum<NV>(acc, red);
-        if (threadIdx.x == 0 && s_ok) {
+        if (threadIdx.x == 0) {
 #pragma unroll
-            for (int q = 0; q < NV; ++q) {
-                st_agent(bcast + q, acc[q]);
-                s_tot[q] = acc[q];
+            for (int q = 0; q < NV; ++q) s_tot[q] = acc[q];
+            if (allread) {
+                if (master) __hip_atomic_store(&gs->epoch, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else if (s_ok) {
+#pragma unroll
+                for (int q = 0; q < NV; ++q) st_agent(bcast + q, acc[q]);
+                __hip_atomic_store(&gs->epoch, e, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
-            __hip_atomic_store(&gs->epoch, e, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     } else if (threadIdx.x == 0) {
         const long long t0 = wall_clock64();
@@ -943,26 +957,19 @@ __device__ __forceinline__ void drive_merge(const int32_t* __restrict__ rp, int 
     }
 }
 
-template <int VAR, class Op>
+// TRAV = 0: merge path; TRAV = G > 0: G lanes per row.
+template <int TRAV, class Op>
 __device__ __forceinline__ void drive(const LevelDev& L, int r0, int r1, Op& op, MergeShared* sh) {
-    if constexpr (VAR == 2) {
+    if constexpr (TRAV == 0) {
         drive_merge(L.rp, r0, r1, op, *sh);
     } else {
-        switch (L.lanes) {
-            case 1: drive_rows<1>(L.rp, r0, r1, op); break;
-            case 2: drive_rows<2>(L.rp, r0, r1, op); break;
-            case 4: drive_rows<4>(L.rp, r0, r1, op); break;
-            case 8: drive_rows<8>(L.rp, r0, r1, op); break;
-            case 16: drive_rows<16>(L.rp, r0, r1, op); break;
-            case 32: drive_rows<32>(L.rp, r0, r1, op); break;
-            default: drive_rows<64>(L.rp, r0, r1, op); break;
-        }
+        drive_rows<TRAV>(L.rp, r0, r1, op);
     }
 }
 
 // ---- refinement of one level by a job's workgroups
 
-template <typename T, int VAR>
+template <typename T, int TRAV>
 __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeShared* sh) {
     const LevelDev& L = J.L;
     const double tol = J.tol;
@@ -1010,7 +1017,7 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
         op.mu = mu;
         op.s = s;
         op.acc[0] = op.acc[1] = op.acc[2] = op.acc[3] = 0.0;
-        drive<VAR>(L, r0, r1, op, sh);
+        drive<TRAV>(L, r0, r1, op, sh);
         if (!job_allreduce<4>(op.acc, c, red)) return;
         const double mu2 = op.acc[0] / n;
         const double s2 = 1.0 / sqrt(op.acc[1] - op.acc[0] * mu2);
@@ -1052,7 +1059,7 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
 // rounding.  Then the output y = deflated, normalised iterate, the
 // edge-form Rayleigh quotient r = sum_edges w (y_i - y_k)^2 and the
 // residual ||L y - r y||, all in FP64.
-template <int VAR>
+template <int TRAV>
 __device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeShared* sh) {
     const LevelDev& L = J.L;
     const int r0 = L.part[c.lb], r1 = L.part[c.lb + 1];
@@ -1072,7 +1079,7 @@ __device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeSha
         op.s = st.s_prev;
         op.g = L.g;
         op.acc[0] = op.acc[1] = 0.0;
-        drive<VAR>(L, r0, r1, op, sh);
+        drive<TRAV>(L, r0, r1, op, sh);
         if (!job_allreduce<2>(op.acc, c, red)) return;
         mu = op.acc[0] / n;
         s = 1.0 / sqrt(op.acc[1] - op.acc[0] * mu);
@@ -1087,7 +1094,7 @@ __device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     eo.mu = mu;
     eo.s = s;
     eo.acc[0] = eo.acc[1] = eo.acc[2] = 0.0;
-    drive<VAR>(L, r0, r1, eo, sh);
+    drive<TRAV>(L, r0, r1, eo, sh);
     if (!job_allreduce<3>(eo.acc, c, red)) return;
     const double mean_u = eo.acc[0] / n;
     const double nrm2 = eo.acc[1] - eo.acc[0] * mean_u;
@@ -1105,7 +1112,7 @@ __device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     ro.lam = lam;
     ro.yout = J.yout;
     ro.acc[0] = 0.0;
-    drive<VAR>(L, r0, r1, ro, sh);
+    drive<TRAV>(L, r0, r1, ro, sh);
     if (!job_allreduce<1>(ro.acc, c, red)) return;
     if (c.vb == 0 && threadIdx.x == 0) {
         J.fo->lambda = lam;
@@ -1140,7 +1147,9 @@ __device__ __forceinline__ GridCtx make_ctx(const GridJob& J) {
     return c;
 }
 
+// nslots: the slot array holds two banks of nslots
 __global__ void k_reset_sync(GridSync* gs, GridSlot* slots, int nslots) {
+    nslots *= 2;
     for (int b = threadIdx.x; b < nslots; b += blockDim.x) {
         for (int q = 0; q < 7; ++q) slots[b].v[q] = 0.0;
         slots[b].epoch = 0ull;
@@ -1153,35 +1162,35 @@ __global__ void k_reset_sync(GridSync* gs, GridSlot* slots, int nslots) {
 }
 
 // One launch refines one level of each job (one graph per job).  Kernels
-// are specialised by traversal and storage precision (kind = 2*(VAR-1) +
-// fp32) to keep registers and LDS low; a packed launch holds one kind.
-template <int VAR, typename T>
+// are specialised by traversal (merge path, or G lanes per row) and
+// storage precision to keep registers low; a packed launch holds one kind.
+template <int TRAV, typename T>
 __global__ void __launch_bounds__(kGridBlock) k_refine_jobs(const GridJob* __restrict__ jobs, int njobs) {
     __shared__ double red[16 * 5 + 8];
     MergeShared* sh = nullptr;
-    if constexpr (VAR == 2) {
+    if constexpr (TRAV == 0) {
         __shared__ MergeShared msh;
         sh = &msh;
     }
     const GridJob J = jobs[find_job(jobs, njobs)];
     GridCtx c = make_ctx(J);
     if (c.vb < 0 || c.vb >= c.nb) return;
-    refine_level<T, VAR>(J, c, red, sh);
+    refine_level<T, TRAV>(J, c, red, sh);
 }
 
 // One launch finishes the finest level of each job.
-template <int VAR>
+template <int TRAV>
 __global__ void __launch_bounds__(kGridBlock) k_finish_jobs(const GridJob* __restrict__ jobs, int njobs) {
     __shared__ double red[16 * 5 + 8];
     MergeShared* sh = nullptr;
-    if constexpr (VAR == 2) {
+    if constexpr (TRAV == 0) {
         __shared__ MergeShared msh;
         sh = &msh;
     }
     const GridJob J = jobs[find_job(jobs, njobs)];
     GridCtx c = make_ctx(J);
     if (c.vb < 0 || c.vb >= c.nb) return;
-    finish_level<VAR>(J, c, red, sh);
+    finish_level<TRAV>(J, c, red, sh);
 }
 
 }  // namespace
@@ -1223,16 +1232,35 @@ hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, hipStream_t s) {
 }
 
 namespace {
+// kind = 2 * t + fp32 with t = 0 (merge path) or 1 + log2(G)
+template <int TRAV>
+const void* refine_kernel_t(int fp32) {
+    return fp32 ? (const void*)k_refine_jobs<TRAV, float> : (const void*)k_refine_jobs<TRAV, double>;
+}
 const void* refine_kernel(int kind) {
-    switch (kind) {
-        case 0: return (const void*)k_refine_jobs<1, double>;
-        case 1: return (const void*)k_refine_jobs<1, float>;
-        case 2: return (const void*)k_refine_jobs<2, double>;
-        default: return (const void*)k_refine_jobs<2, float>;
+    const int fp32 = kind & 1;
+    switch (kind >> 1) {
+        case 0: return refine_kernel_t<0>(fp32);
+        case 1: return refine_kernel_t<1>(fp32);
+        case 2: return refine_kernel_t<2>(fp32);
+        case 3: return refine_kernel_t<4>(fp32);
+        case 4: return refine_kernel_t<8>(fp32);
+        case 5: return refine_kernel_t<16>(fp32);
+        case 6: return refine_kernel_t<32>(fp32);
+        default: return refine_kernel_t<64>(fp32);
     }
 }
 const void* finish_kernel(int kind) {
-    return (kind >= 2) ? (const void*)k_finish_jobs<2> : (const void*)k_finish_jobs<1>;
+    switch (kind >> 1) {
+        case 0: return (const void*)k_finish_jobs<0>;
+        case 1: return (const void*)k_finish_jobs<1>;
+        case 2: return (const void*)k_finish_jobs<2>;
+        case 3: return (const void*)k_finish_jobs<4>;
+        case 4: return (const void*)k_finish_jobs<8>;
+        case 5: return (const void*)k_finish_jobs<16>;
+        case 6: return (const void*)k_finish_jobs<32>;
+        default: return (const void*)k_finish_jobs<64>;
+    }
 }
 int max_blocks_ptr(const void* k) {
     int dev = 0, ncu = 0, occ = 0;
@@ -1243,16 +1271,23 @@ int max_blocks_ptr(const void* k) {
 }
 }  // namespace
 
-int job_kind(int variant, int fp32) { return 2 * (variant == 2 ? 1 : 0) + (fp32 ? 1 : 0); }
+int job_kind(int variant, int lanes, int fp32) {
+    int t = 0;
+    if (variant != 2) {
+        t = 1;
+        for (int g = lanes; g > 1 && t < 7; g >>= 1) ++t;
+    }
+    return 2 * t + (fp32 ? 1 : 0);
+}
 
 int refine_jobs_max_blocks(int kind) {
-    static int r[4] = {-1, -1, -1, -1};
+    static int r[kJobKinds] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
     if (r[kind] < 0) r[kind] = max_blocks_ptr(refine_kernel(kind));
     return r[kind];
 }
 
 int finish_jobs_max_blocks(int kind) {
-    static int r[4] = {-1, -1, -1, -1};
+    static int r[kJobKinds] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
     if (r[kind] < 0) r[kind] = max_blocks_ptr(finish_kernel(kind));
     return r[kind];
 }

@@ -193,6 +193,11 @@ void cmg_free(cmg_handle h);
 /* Static string for a status code. */
 const char* cmg_status_string(cmg_status s);
 
+/* Description of the last failure reported by a call on this thread
+ * (which step failed and the HIP error, or a grid-barrier timeout); ""
+ * if the last call succeeded.  Valid until the next call. */
+const char* cmg_last_error(void);
+
 /* Diagnostics: evaluate on the GPU the counter-based hash the library uses
  * for HEC priorities, key(v) = mix64(seed ^ (level << 40) ^ v) with mix64
  * the SplitMix64 output function, for v = 0..count-1 into host out[].

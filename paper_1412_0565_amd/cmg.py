@@ -26,7 +26,7 @@ CMG_VAL_F64, CMG_VAL_F32 = 0, 1
 # functions declared in include/cmg.h
 EXPORTS = ["cmg_options_default", "cmg_setup", "cmg_fiedler", "cmg_fiedler_batch", "cmg_level_info",
            "cmg_level_copy", "cmg_set_stream", "cmg_footprint", "cmg_free", "cmg_status_string",
-           "cmg_hash_probe"]
+           "cmg_last_error", "cmg_hash_probe"]
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 _FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
@@ -124,6 +124,8 @@ def lib():
         L.cmg_free.restype = None
         L.cmg_status_string.argtypes = [C.c_int]
         L.cmg_status_string.restype = C.c_char_p
+        L.cmg_last_error.argtypes = []
+        L.cmg_last_error.restype = C.c_char_p
         L.cmg_hash_probe.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_void_p]
         L.cmg_hash_probe.restype = C.c_int
         _lib = L
@@ -133,7 +135,8 @@ def lib():
 class CmgError(RuntimeError):
     def __init__(self, status: int, where: str = ""):
         self.status = status
-        super().__init__(f"{where}: {cmg_status_string(status)}")
+        detail = cmg_last_error()
+        super().__init__(f"{where}: {cmg_status_string(status)}" + (f" [{detail}]" if detail else ""))
 
 
 def _check(st: int, where: str) -> int:
@@ -144,6 +147,10 @@ def _check(st: int, where: str) -> int:
 
 def cmg_status_string(status: int) -> str:
     return lib().cmg_status_string(status).decode()
+
+
+def cmg_last_error() -> str:
+    return lib().cmg_last_error().decode()
 
 
 def cmg_options_default(**overrides) -> cmg_options:

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -140,10 +141,18 @@ struct cmg_ctx {
 
 namespace {
 
+thread_local char g_last_error[512] = "";
+
+void set_error(const char* what, hipError_t e, int line) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s (line %d): %s", what, line,
+                  e == hipSuccess ? "" : hipGetErrorString(e));
+}
+
 #define CK(x)                                                                                      \
     do {                                                                                           \
         hipError_t e_ = (x);                                                                       \
         if (e_ != hipSuccess) {                                                                    \
+            set_error(#x, e_, __LINE__);                                                           \
             (void)hipGetLastError();                                                               \
             return CMG_E_DEVICE;                                                                   \
         }                                                                                          \
@@ -423,6 +432,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         g.seed = o.seed;
         g.maxit = o.max_iters_per_level;
         g.b0 = 0;
+        g.tag = j;
         jobs[j] = g;
     }
     {
@@ -439,6 +449,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         g.fo = c->d_fo;
         g.redo = (c->lv[0].fp32 && c->d_fa && o.fp64_final_sweeps > 0) ? 1 : 0;
         g.b0 = 0;
+        g.tag = -1;
         jobs[J + 1] = g;
     }
     c->h_jobs = jobs;
@@ -585,6 +596,11 @@ cmg_status enqueue_readback(cmg_ctx* c, void* x, cmg_memspace where, hipStream_t
 cmg_status finalize(cmg_ctx* c, double t0, bool timed, double* lambda, cmg_stats* stats) {
     const int J = (int)c->lv.size() - 1;
     if (c->h_gs.abort) {
+        const int tag = (int)(c->h_gs.where >> 16) - 2;
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "grid barrier timed out (%s %d, %u workgroups, barrier epoch %llu, last %llu)",
+                      tag < 0 ? "finishing pass" : "level", tag < 0 ? 0 : tag, c->h_gs.where & 0xffffu,
+                      c->h_gs.abort_epoch, c->h_gs.epoch);
         // barrier state is unusable: start the epoch sequence afresh
         CK(launch_reset_sync(c->d_sync, c->d_slots, c->nslots, c->stream));
         CK(hipStreamSynchronize(c->stream));
@@ -751,6 +767,7 @@ cmg_status batch_impl(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     c0->dfree(d);
     if (e != hipSuccess) {
+        set_error("batch launch", e, __LINE__);
         (void)hipGetLastError();
         return CMG_E_DEVICE;
     }
@@ -774,6 +791,8 @@ void cmg_options_default(cmg_options* o) {
     if (o) fill_defaults(o);
 }
 
+const char* cmg_last_error(void) { return g_last_error; }
+
 const char* cmg_status_string(cmg_status s) {
     switch (s) {
         case CMG_OK: return "CMG_OK";
@@ -789,6 +808,7 @@ const char* cmg_status_string(cmg_status s) {
 
 cmg_status cmg_setup(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, const void* w,
                      cmg_valtype wtype, cmg_memspace where, const cmg_options* opt, cmg_handle* out) {
+    g_last_error[0] = 0;
     if (!out) return CMG_E_ARG;
     *out = nullptr;
     if (n < 2 || nnz < 1 || nnz >= 2147483647LL || !row_ptr || !col || !w) return CMG_E_ARG;
@@ -822,6 +842,7 @@ cmg_status cmg_setup(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
 }
 
 cmg_status cmg_fiedler(cmg_handle h, double* lambda, void* x, cmg_memspace where, cmg_stats* stats) {
+    g_last_error[0] = 0;
     if (!h) return CMG_E_ARG;
     if (where != CMG_MEM_HOST && where != CMG_MEM_DEVICE) return CMG_E_ARG;
     return fiedler_impl(h, lambda, x, where, stats);
@@ -829,6 +850,7 @@ cmg_status cmg_fiedler(cmg_handle h, double* lambda, void* x, cmg_memspace where
 
 cmg_status cmg_fiedler_batch(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
                              cmg_memspace where, cmg_stats* stats) {
+    g_last_error[0] = 0;
     if (!hs || count < 0) return CMG_E_ARG;
     if (where != CMG_MEM_HOST && where != CMG_MEM_DEVICE) return CMG_E_ARG;
     if (count == 0) return CMG_OK;

@@ -151,7 +151,8 @@ struct FinishOut {
 struct GridSync {
     unsigned long long epoch;
     unsigned int abort;
-    unsigned int pad;
+    unsigned int where;             // first timeout: workgroups | (job tag + 2) << 16
+    unsigned long long abort_epoch;  // first timeout: the barrier's epoch
 };
 
 // One workgroup's contribution to a grid all-reduce: its partial sums and
@@ -180,7 +181,15 @@ struct GridJob {
     int32_t b0;
     int32_t uniform;        // refine: hashed uniform start instead of prolongation
     int32_t redo;           // finish: recompute the last step in FP64
+    int32_t tag;            // level index of a refinement job, -1 for finishing,
+                            // kResidencyTag for a residency count
+    unsigned* count;        // residency count: {live, peak}
+    long long hold;         // residency count: wall-clock ticks each workgroup stays
 };
+
+// A job with this tag only counts how many of its workgroups are resident
+// at once; no workgroup waits for another.
+constexpr int32_t kResidencyTag = -100;
 
 // Coarse levels jhi .. jlo of one graph, refined by one workgroup.
 struct BlockJob {

@@ -12,6 +12,7 @@
 // and the stopping quantity (u, v) = s' (Syx - mu' Sx) for u = (y-mu')s'.
 // Every reduction has a fixed order, so results are reproducible bitwise.
 #include <algorithm>
+#include <mutex>
 
 #include "cmg_internal.h"
 
@@ -64,7 +65,7 @@ constexpr int kAllReadMax = 64;
 template <int NV>
 __device__ bool grid_allreduce_impl(double (&v)[NV], GridSync* gs, GridSlot* slots, double* bcast,
                                     unsigned long long& epoch, int lb, bool master, int nb,
-                                    double* red) {
+                                    double* red, int tag) {
     __shared__ double s_tot[NV];
     __shared__ int s_ok;
     const unsigned long long e = ++epoch;
@@ -89,7 +90,10 @@ __device__ bool grid_allreduce_impl(double (&v)[NV], GridSync* gs, GridSlot* slo
                 __builtin_amdgcn_s_sleep(1);
                 if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
                     wall_clock64() - t0 > kSpinTicks) {
-                    atomicOr(&gs->abort, 1u);
+                    if (atomicOr(&gs->abort, 1u) == 0u) {
+                        gs->where = (unsigned)nb | ((unsigned)(tag + 2) << 16);
+                        gs->abort_epoch = e;
+                    }
                     s_ok = 0;
                     break;
                 }
@@ -116,7 +120,10 @@ __device__ bool grid_allreduce_impl(double (&v)[NV], GridSync* gs, GridSlot* slo
             __builtin_amdgcn_s_sleep(1);
             if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
                 wall_clock64() - t0 > kSpinTicks) {
-                atomicOr(&gs->abort, 1u);
+                if (atomicOr(&gs->abort, 1u) == 0u) {
+                        gs->where = (unsigned)nb | ((unsigned)(tag + 2) << 16);
+                        gs->abort_epoch = e;
+                    }
                 s_ok = 0;
                 break;
             }
@@ -687,11 +694,12 @@ struct GridCtx {
     int nb;  // workgroups of the job
     int vb;  // this workgroup within the job
     int lb;  // row block of this workgroup
+    int tag;
 };
 
 template <int NV>
 __device__ __forceinline__ bool job_allreduce(double (&v)[NV], GridCtx& c, double* red) {
-    return grid_allreduce_impl<NV>(v, c.gs, c.slots, c.bcast, c.epoch, c.lb, c.vb == 0, c.nb, red);
+    return grid_allreduce_impl<NV>(v, c.gs, c.slots, c.bcast, c.epoch, c.lb, c.vb == 0, c.nb, red, c.tag);
 }
 
 // ---- per-row operations fed by the two traversal drivers
@@ -1144,6 +1152,7 @@ __device__ __forceinline__ GridCtx make_ctx(const GridJob& J) {
     c.vb = (int)blockIdx.x - J.b0;
     c.lb = xcd_remap(c.vb, c.nb);
     c.epoch = start_epoch(J.gs);
+    c.tag = J.tag;
     return c;
 }
 
@@ -1157,8 +1166,24 @@ __global__ void k_reset_sync(GridSync* gs, GridSlot* slots, int nslots) {
     if (threadIdx.x == 0) {
         gs->epoch = 0ull;
         gs->abort = 0u;
-        gs->pad = 0u;
+        gs->where = 0u;
+        gs->abort_epoch = 0ull;
     }
+}
+
+// Residency count: each workgroup counts itself in, raises the recorded
+// peak, stays `hold` ticks and counts itself out.  The peak is how many
+// workgroups of this kernel the device keeps resident at once.
+__device__ void residency_count(const GridJob& J) {
+    if (threadIdx.x == 0) {
+        const unsigned now = atomicAdd(J.count, 1u) + 1u;
+        atomicMax(J.count + 1, now);
+    }
+    __syncthreads();
+    const long long t0 = wall_clock64();
+    while (wall_clock64() - t0 < J.hold) __builtin_amdgcn_s_sleep(2);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicSub(J.count, 1u);
 }
 
 // One launch refines one level of each job (one graph per job).  Kernels
@@ -1173,6 +1198,10 @@ __global__ void __launch_bounds__(kGridBlock) k_refine_jobs(const GridJob* __res
         sh = &msh;
     }
     const GridJob J = jobs[find_job(jobs, njobs)];
+    if (J.tag == kResidencyTag) {
+        residency_count(J);
+        return;
+    }
     GridCtx c = make_ctx(J);
     if (c.vb < 0 || c.vb >= c.nb) return;
     refine_level<T, TRAV>(J, c, red, sh);
@@ -1188,6 +1217,10 @@ __global__ void __launch_bounds__(kGridBlock) k_finish_jobs(const GridJob* __res
         sh = &msh;
     }
     const GridJob J = jobs[find_job(jobs, njobs)];
+    if (J.tag == kResidencyTag) {
+        residency_count(J);
+        return;
+    }
     GridCtx c = make_ctx(J);
     if (c.vb < 0 || c.vb >= c.nb) return;
     finish_level<TRAV>(J, c, red, sh);
@@ -1262,12 +1295,51 @@ const void* finish_kernel(int kind) {
         default: return (const void*)k_finish_jobs<64>;
     }
 }
+// Workgroups of kernel `k` that can be resident at once.  The occupancy
+// query alone can promise more than the device delivers (for kernels at
+// 64 VGPRs and about 90 SGPRs it reports 4 workgroups of 512 threads per CU
+// where 3 are resident), and a grid barrier over workgroups that are not
+// all resident never completes.  So the kernel itself is launched once in
+// residency-count mode at the queried size and the observed peak is used,
+// rounded down to a multiple of 8.  Returns 0 on any error.
 int max_blocks_ptr(const void* k) {
-    int dev = 0, ncu = 0, occ = 0;
+    int dev = 0, ncu = 0, occ = 0, khz = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, kGridBlock, 0) != hipSuccess) return 0;
-    return occ * ncu;
+    const int want = occ * ncu;
+    if (want <= 0) return 0;
+    unsigned* cnt = nullptr;
+    GridJob* dj = nullptr;
+    hipStream_t s = nullptr;
+    unsigned peak[2] = {0u, 0u};
+    bool ok = hipMalloc((void**)&cnt, 2 * sizeof(unsigned)) == hipSuccess &&
+              hipMalloc((void**)&dj, sizeof(GridJob)) == hipSuccess &&
+              hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    if (ok) {
+        GridJob j{};
+        j.tag = kResidencyTag;
+        j.count = cnt;
+        j.hold = (long long)khz;  // 1 ms: dispatch of the grid takes microseconds
+        j.b0 = 0;
+        int njobs = 1;
+        void* args[] = {(void*)&dj, &njobs};
+        ok = hipMemsetAsync(cnt, 0, 2 * sizeof(unsigned), s) == hipSuccess &&
+             hipMemcpyAsync(dj, &j, sizeof(GridJob), hipMemcpyHostToDevice, s) == hipSuccess &&
+             hipLaunchCooperativeKernel(k, dim3(want), dim3(kGridBlock), args, 0, s) == hipSuccess &&
+             hipMemcpyAsync(peak, cnt, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, s) == hipSuccess &&
+             hipStreamSynchronize(s) == hipSuccess;
+    }
+    if (s) (void)hipStreamDestroy(s);
+    if (dj) (void)hipFree(dj);
+    if (cnt) (void)hipFree(cnt);
+    if (!ok) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const int got = std::min<int>(want, (int)peak[1]);
+    return got >= 8 ? (got / 8) * 8 : got;
 }
 }  // namespace
 
@@ -1280,16 +1352,23 @@ int job_kind(int variant, int lanes, int fp32) {
     return 2 * t + (fp32 ? 1 : 0);
 }
 
+namespace {
+std::mutex g_cap_mutex;
+int g_refine_cap[kJobKinds] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+int g_finish_cap[kJobKinds] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+}  // namespace
+
+// Measured once per kernel and process (the first call launches it).
 int refine_jobs_max_blocks(int kind) {
-    static int r[kJobKinds] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
-    if (r[kind] < 0) r[kind] = max_blocks_ptr(refine_kernel(kind));
-    return r[kind];
+    std::lock_guard<std::mutex> lock(g_cap_mutex);
+    if (g_refine_cap[kind] < 0) g_refine_cap[kind] = max_blocks_ptr(refine_kernel(kind));
+    return g_refine_cap[kind];
 }
 
 int finish_jobs_max_blocks(int kind) {
-    static int r[kJobKinds] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
-    if (r[kind] < 0) r[kind] = max_blocks_ptr(finish_kernel(kind));
-    return r[kind];
+    std::lock_guard<std::mutex> lock(g_cap_mutex);
+    if (g_finish_cap[kind] < 0) g_finish_cap[kind] = max_blocks_ptr(finish_kernel(kind));
+    return g_finish_cap[kind];
 }
 
 hipError_t launch_refine_jobs(const GridJob* jobs, int njobs, int nblocks, int kind, hipStream_t s) {

@@ -59,10 +59,25 @@ struct HostLevel {
 
 // Lanes per row for the row-group kernels: about five entries per lane
 // (two lanes per row on 6-10-regular meshes measured best on gfx950).
+// Lanes per row: about 2.5 entries per lane (measured best for degree
+// 6 to 16 meshes and geometric graphs: fewer lanes leave the loads of a
+// row serialised, more leave lanes idle).
 int pick_lanes(double avg_deg) {
-    double t = avg_deg / 5.0;
+    double t = avg_deg / 2.5;
     int g = 1;
     while (g < t && g < 64) g <<= 1;
+    return g;
+}
+
+// Lanes per row on a level refined inside one workgroup: a step there is
+// one latency chain, so idle lanes are spread over the rows only while
+// every row still has a lane group of its own (threads = 64 for the
+// one-wavefront mode of levels up to 256 vertices, else the workgroup).
+int pick_lanes_block(int n, double avg_deg) {
+    const int threads = n <= 256 ? 64 : 1024;
+    const int cap = pick_lanes(avg_deg);
+    int g = 1;
+    while (2 * g * (int64_t)n <= threads && 2 * g <= cap) g <<= 1;
     return g;
 }
 
@@ -100,7 +115,7 @@ struct cmg_ctx {
     FinishOut h_fo{};
     std::vector<LevelState> h_st;
     GridSync h_gs{};
-    double* d_bcast = nullptr;
+    GridSlot* d_bcast = nullptr;
     FinishOut* d_fo = nullptr;
     double* d_A = nullptr;
     double* d_V = nullptr;
@@ -364,6 +379,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
     for (int j = 0; j <= J; ++j) {
         HostLevel& L = c->lv[j];
         L.in_block = (j >= c->block_lo && j <= top) ? 1 : 0;
+        if (L.in_block) L.lanes = pick_lanes_block(L.n, L.nnz / (double)std::max(L.n, 1));
         L.fp32 = 0;
         if (o.precision == CMG_MIXED && !L.in_block && j <= top && L.nnz >= mixed_min &&
             L.wmax < 16777216.0 && !(j == J && c->coarse_dense))
@@ -400,8 +416,9 @@ cmg_status build_refine_plan(cmg_ctx* c) {
     ALLOC(c->d_sync, GridSync, 1);
     c->nslots = maxgrid;
     ALLOC(c->d_slots, GridSlot, 2 * maxgrid);
-    CK(launch_reset_sync(c->d_sync, c->d_slots, c->nslots, c->stream));
-    ALLOC(c->d_bcast, double, 8);
+    c->d_bcast = (GridSlot*)c->dalloc(kBcastBytes);
+    if (!c->d_bcast) return CMG_E_OOM;
+    CK(launch_reset_sync(c->d_sync, c->d_slots, c->nslots, c->d_bcast, c->stream));
     ALLOC(c->d_fo, FinishOut, 1);
     const int dm = std::max(CJ.n, 2);
     if (c->coarse_dense) {
@@ -602,7 +619,7 @@ cmg_status finalize(cmg_ctx* c, double t0, bool timed, double* lambda, cmg_stats
                       tag < 0 ? "finishing pass" : "level", tag < 0 ? 0 : tag, c->h_gs.where & 0xffffu,
                       c->h_gs.abort_epoch, c->h_gs.epoch);
         // barrier state is unusable: start the epoch sequence afresh
-        CK(launch_reset_sync(c->d_sync, c->d_slots, c->nslots, c->stream));
+        CK(launch_reset_sync(c->d_sync, c->d_slots, c->nslots, c->d_bcast, c->stream));
         CK(hipStreamSynchronize(c->stream));
         return CMG_E_DEVICE;
     }

@@ -162,6 +162,12 @@ struct alignas(64) GridSlot {
     unsigned long long epoch;
 };
 
+// Broadcast of grid all-reduce totals: this many lines, this many bytes
+// apart (so they map to different memory channels).
+constexpr int kBcastLines = 32;
+constexpr int kBcastStride = 4096 + 64;
+constexpr size_t kBcastBytes = (size_t)kBcastLines * kBcastStride;
+
 // One unit of a (possibly packed) grid launch: a level of one graph,
 // refined (or finished) by workgroups [b0, b0 + L.grid) of the launch.
 struct GridJob {
@@ -171,7 +177,7 @@ struct GridJob {
     const LevelState* stc;  // refine: state of C; finish: state of L
     GridSync* gs;           // barrier state of this graph
     GridSlot* slots;
-    double* bcast;
+    GridSlot* bcast;        // kBcastLines lines, kBcastStride bytes apart
     double* fa;             // finish: FP64 scratch of n entries (mixed redo)
     double* yout;           // finish: output vector
     FinishOut* fo;          // finish: scalars out

@@ -80,7 +80,7 @@ int finish_jobs_max_blocks(int kind);
 hipError_t launch_refine_jobs(const GridJob* jobs, int njobs, int nblocks, int kind, hipStream_t s);
 hipError_t launch_finish_jobs(const GridJob* jobs, int njobs, int nblocks, int kind, hipStream_t s);
 // zero the barrier state and the slots (2 * nslots; at setup, and after an abort)
-hipError_t launch_reset_sync(GridSync* gs, GridSlot* slots, int nslots, hipStream_t s);
+hipError_t launch_reset_sync(GridSync* gs, GridSlot* slots, int nslots, GridSlot* bcast, hipStream_t s);
 
 constexpr int kGridBlock = 512;
 constexpr int kBlockKernelThreads = 1024;

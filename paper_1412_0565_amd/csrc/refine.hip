@@ -49,6 +49,33 @@ constexpr long long kSpinTicks = 200000000LL;
 // Grids up to this many workgroups use the all-read form below.
 constexpr int kAllReadMax = 64;
 
+// Spin until *p == e.  The abort flag and the time bound are checked only
+// every 64 polls: the flag shares one line that every waiter would hit.
+// Returns false (after raising the abort flag, recording the first
+// timeout) if the wait was given up.
+__device__ __forceinline__ bool spin_until(const unsigned long long* p, unsigned long long e,
+                                           GridSync* gs, int nb, int tag) {
+    const long long t0 = wall_clock64();
+    unsigned polls = 0;
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != e) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++polls & 63u) == 0u &&
+            (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+             wall_clock64() - t0 > kSpinTicks)) {
+            if (atomicOr(&gs->abort, 1u) == 0u) {
+                gs->where = (unsigned)nb | ((unsigned)(tag + 2) << 16);
+                gs->abort_epoch = e;
+            }
+            return false;
+        }
+    }
+    return true;
+}
+
+__device__ __forceinline__ GridSlot* bcast_line(GridSlot* bcast, int q) {
+    return (GridSlot*)((char*)bcast + (size_t)q * kBcastStride);
+}
+
 // Grid-wide sum of NV (<= 7) doubles with a barrier, free of contended
 // atomics: every workgroup writes its block sums and the barrier epoch into
 // its own 64-byte slot (release); slots alternate between two banks by
@@ -56,20 +83,23 @@ constexpr int kAllReadMax = 64;
 // passed the barrier in between.
 //  * Small grids (nb <= kAllReadMax): every workgroup polls all slots and
 //    adds them itself (one memory round trip less).
-//  * Larger grids: workgroup 0 polls all slots, adds them, publishes the
-//    totals and the epoch (release); the others wait for the epoch.
+//  * Larger grids: workgroup 0 polls all slots, adds them and publishes
+//    the totals with the epoch on kBcastLines lines that sit on different
+//    memory channels (release); workgroup b waits on line b % kBcastLines,
+//    so no line has more than nb / kBcastLines pollers.
 // Either way the totals are the slot values added in slot order by the
 // same fixed tree, so they do not depend on which workgroup adds them or
 // on arrival order.  Returns false if the barrier timed out or was aborted;
 // then every workgroup leaves.
 template <int NV>
-__device__ bool grid_allreduce_impl(double (&v)[NV], GridSync* gs, GridSlot* slots, double* bcast,
-                                    unsigned long long& epoch, int lb, bool master, int nb,
-                                    double* red, int tag) {
+__device__ bool grid_allreduce_impl(double (&v)[NV], GridSync* gs, GridSlot* slots, GridSlot* bcast,
+                                    unsigned long long& epoch, int vb, int lb, int nb, double* red,
+                                    int tag) {
     __shared__ double s_tot[NV];
     __shared__ int s_ok;
     const unsigned long long e = ++epoch;
     GridSlot* bank = slots + (e & 1ull) * (unsigned long long)nb;
+    const bool master = vb == 0;
     block_sum<NV>(v, red);
     if (threadIdx.x == 0) {
         GridSlot* my = bank + lb;
@@ -85,18 +115,9 @@ __device__ bool grid_allreduce_impl(double (&v)[NV], GridSync* gs, GridSlot* slo
 #pragma unroll
         for (int q = 0; q < NV; ++q) acc[q] = 0.0;
         for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-            const long long t0 = wall_clock64();
-            while (__hip_atomic_load(&bank[b].epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != e) {
-                __builtin_amdgcn_s_sleep(1);
-                if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
-                    wall_clock64() - t0 > kSpinTicks) {
-                    if (atomicOr(&gs->abort, 1u) == 0u) {
-                        gs->where = (unsigned)nb | ((unsigned)(tag + 2) << 16);
-                        gs->abort_epoch = e;
-                    }
-                    s_ok = 0;
-                    break;
-                }
+            if (!spin_until(&bank[b].epoch, e, gs, nb, tag)) {
+                s_ok = 0;
+                break;
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 #pragma unroll
@@ -106,32 +127,26 @@ __device__ bool grid_allreduce_impl(double (&v)[NV], GridSync* gs, GridSlot* slo
         if (threadIdx.x == 0) {
 #pragma unroll
             for (int q = 0; q < NV; ++q) s_tot[q] = acc[q];
+        }
+        if (master && s_ok) {
             if (allread) {
-                if (master) __hip_atomic_store(&gs->epoch, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else if (s_ok) {
+                if (threadIdx.x == 0)
+                    __hip_atomic_store(&gs->epoch, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else if (threadIdx.x < kBcastLines) {
+                GridSlot* line = bcast_line(bcast, threadIdx.x);
 #pragma unroll
-                for (int q = 0; q < NV; ++q) st_agent(bcast + q, acc[q]);
-                __hip_atomic_store(&gs->epoch, e, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                for (int q = 0; q < NV; ++q) st_agent(&line->v[q], acc[q]);
+                __hip_atomic_store(&line->epoch, e, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                if (threadIdx.x == 0)
+                    __hip_atomic_store(&gs->epoch, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     } else if (threadIdx.x == 0) {
-        const long long t0 = wall_clock64();
-        while (__hip_atomic_load(&gs->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != e) {
-            __builtin_amdgcn_s_sleep(1);
-            if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
-                wall_clock64() - t0 > kSpinTicks) {
-                if (atomicOr(&gs->abort, 1u) == 0u) {
-                        gs->where = (unsigned)nb | ((unsigned)(tag + 2) << 16);
-                        gs->abort_epoch = e;
-                    }
-                s_ok = 0;
-                break;
-            }
-        }
+        GridSlot* line = bcast_line(bcast, vb % kBcastLines);
+        if (!spin_until(&line->epoch, e, gs, nb, tag)) s_ok = 0;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (__hip_atomic_load(&gs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) s_ok = 0;
 #pragma unroll
-        for (int q = 0; q < NV; ++q) s_tot[q] = ld_agent(bcast + q);
+        for (int q = 0; q < NV; ++q) s_tot[q] = ld_agent(&line->v[q]);
     }
     __syncthreads();
 #pragma unroll
@@ -689,7 +704,7 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
 struct GridCtx {
     GridSync* gs;
     GridSlot* slots;
-    double* bcast;
+    GridSlot* bcast;
     unsigned long long epoch;
     int nb;  // workgroups of the job
     int vb;  // this workgroup within the job
@@ -699,7 +714,7 @@ struct GridCtx {
 
 template <int NV>
 __device__ __forceinline__ bool job_allreduce(double (&v)[NV], GridCtx& c, double* red) {
-    return grid_allreduce_impl<NV>(v, c.gs, c.slots, c.bcast, c.epoch, c.lb, c.vb == 0, c.nb, red, c.tag);
+    return grid_allreduce_impl<NV>(v, c.gs, c.slots, c.bcast, c.epoch, c.vb, c.lb, c.nb, red, c.tag);
 }
 
 // ---- per-row operations fed by the two traversal drivers
@@ -1157,11 +1172,16 @@ __device__ __forceinline__ GridCtx make_ctx(const GridJob& J) {
 }
 
 // nslots: the slot array holds two banks of nslots
-__global__ void k_reset_sync(GridSync* gs, GridSlot* slots, int nslots) {
+__global__ void k_reset_sync(GridSync* gs, GridSlot* slots, int nslots, GridSlot* bcast) {
     nslots *= 2;
     for (int b = threadIdx.x; b < nslots; b += blockDim.x) {
         for (int q = 0; q < 7; ++q) slots[b].v[q] = 0.0;
         slots[b].epoch = 0ull;
+    }
+    if (threadIdx.x < kBcastLines) {
+        GridSlot* line = bcast_line(bcast, threadIdx.x);
+        for (int q = 0; q < 7; ++q) line->v[q] = 0.0;
+        line->epoch = 0ull;
     }
     if (threadIdx.x == 0) {
         gs->epoch = 0ull;
@@ -1381,8 +1401,8 @@ hipError_t launch_finish_jobs(const GridJob* jobs, int njobs, int nblocks, int k
     return hipLaunchCooperativeKernel(finish_kernel(kind), dim3(nblocks), dim3(kGridBlock), args, 0, s);
 }
 
-hipError_t launch_reset_sync(GridSync* gs, GridSlot* slots, int nslots, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(256), 0, s, gs, slots, nslots);
+hipError_t launch_reset_sync(GridSync* gs, GridSlot* slots, int nslots, GridSlot* bcast, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(256), 0, s, gs, slots, nslots, bcast);
     return hipGetLastError();
 }
 

@@ -70,6 +70,38 @@ def solve_once(cmg, g_dev, n, opt, x):
     return lam, st, levels
 
 
+def kernel_source_hash():
+    """Hash of the HIP sources; HBM counter figures taken on other sources
+    no longer describe the kernel."""
+    import hashlib
+
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1412_0565_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, level0):
+    """HBM bytes per level-0 refinement launch from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel), or None if
+    there is none for this workload and these kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_level0_refine_hbm_counters.md")
+    try:
+        kv = {}
+        for line in open(path):
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                kv[k.strip()] = v.strip().strip("`")
+    except OSError:
+        return None, None
+    if kv.get("kernel sources") != kernel_source_hash() or int(kv.get("level-0 k", -1)) != level0.k:
+        return None, f"{os.path.relpath(path, ROOT)} (stale: taken on other kernel sources)"
+    return int(float(kv["HBM bytes per launch"])), os.path.relpath(path, ROOT)
+
+
 def launch_bytes(levels, j=0):
     """Algorithmic bytes of the level-j refinement launch: k PI steps of
     4(n+1) + nnz(4+s_v) + 2 s_x n, plus the prolongation (agg read, coarse
@@ -107,8 +139,10 @@ def serve_leg(args):
     m = min(len(pool), 16)
     for i in range(m):
         _, g = pool[int(picks[i])]
+        t1 = time.perf_counter()
         with cmg.Fiedler(g.n, g.row_ptr, g.col, g.w) as F:
             F.solve()
+        log(f"[serve] closed loop {i + 1}/{m}: n={g.n} nnz={g.nnz} {1e3 * (time.perf_counter() - t1):.1f} ms")
     x_fp64 = m / (time.perf_counter() - t)
     qps = 0.7 * x_fp64
     budget = int(args.serve_budget_gb * (1 << 30))
@@ -119,8 +153,10 @@ def serve_leg(args):
         stream = [Request(i, pool[int(p)][0], pool[int(p)][1].n, pool[int(p)][1].row_ptr, pool[int(p)][1].col,
                           pool[int(p)][1].w, precision=prec) for i, p in enumerate(picks)]
         srv = Server(backend, budget_bytes=budget, max_batch=maxb)
+        log(f"[serve] {label}: {len(stream)} requests at {qps:.1f}/s")
         try:
-            replay(srv, stream, qps=qps, seed=7)
+            replay(srv, stream, qps=qps, seed=7,
+                   progress=lambda d, tot: log(f"[serve] {label}: {d}/{tot} completed"))
         finally:
             srv.close()
         summ = latency_summary(stream)
@@ -146,6 +182,9 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=12)
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="finish with one device-to-device copy of this many MiB (the reference kernel that "
+                         "scales the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -236,9 +275,12 @@ def main():
     pi_ms = statistics.mean(pis)
     bytes_launch = statistics.mean(byts)
     achieved = bytes_launch / (pi_ms * 1e-3) / 1e9
+    traffic, traffic_src = measured_traffic(args.workload, levels[0])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_refine_grid<double,G> on level 0 (PI steps + prolongation)",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_source": traffic_src,
+                "kernel": f"k_refine_jobs<{levels[0].lanes},double> on level 0 (prolongation, deflation, "
+                          f"{ks[-1]} PI steps)",
                 "bytes_per_launch": int(bytes_launch), "avg_launch_ms": round(pi_ms, 4),
                 "pi_steps_per_launch": ks[-1]}
 
@@ -287,6 +329,14 @@ def main():
         "mixed": mixed,
         "serve": serve,
     }
+    if args.copy_mib > 0:
+        nb = args.copy_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] reference copy: {nb} bytes read, {nb} bytes written")
     print(json.dumps(out), flush=True)
 
 

@@ -69,16 +69,27 @@ int pick_lanes(double avg_deg) {
     return g;
 }
 
-// Lanes per row on a level refined inside one workgroup: a step there is
-// one latency chain, so idle lanes are spread over the rows only while
-// every row still has a lane group of its own (threads = 64 for the
-// one-wavefront mode of levels up to 256 vertices, else the workgroup).
-int pick_lanes_block(int n, double avg_deg) {
+// Lanes per row on a level refined inside one workgroup, where a step is
+// one latency chain: G minimises the critical path of the slowest lane
+// group, (rows per group - 1) (avg/G + c) + maxlen/G + c, with c = 8 entry
+// visits standing for the per-row reduction and bookkeeping (threads = 64
+// for the one-wavefront mode of levels up to 256 vertices, else the
+// workgroup).  Meshes get 1-2 lanes; levels with hub rows get more.
+int pick_lanes_block(int n, double avg_deg, int maxlen) {
     const int threads = n <= 256 ? 64 : 1024;
-    const int cap = pick_lanes(avg_deg);
-    int g = 1;
-    while (2 * g * (int64_t)n <= threads && 2 * g <= cap) g <<= 1;
-    return g;
+    const double c = 8.0;
+    int best = 1;
+    double best_cost = 0.0;
+    for (int g = 1; g <= 64; g <<= 1) {
+        const double groups = threads / g;
+        const double rows = std::ceil(n / groups);
+        const double cost = (rows - 1.0) * (avg_deg / g + c) + (double)maxlen / g + c;
+        if (g == 1 || cost < best_cost) {
+            best = g;
+            best_cost = cost;
+        }
+    }
+    return best;
 }
 
 int bitlen(unsigned long long x) {
@@ -361,6 +372,26 @@ int choose_variant(const HostLevel& L, int requested) {
     return (L.maxlen > 256 && L.maxlen > 32.0 * avg) ? 2 : 1;
 }
 
+size_t align8h(size_t b) { return (b + 7) & ~(size_t)7; }
+
+// A level is refined inside one workgroup if it has at most block_rows
+// vertices and its steps stay cheap there: its LDS image (two vectors,
+// weights, row pointers, columns; FP32 weights when exact, uint16 columns
+// when n <= 65536) fits the LDS budget, or it has at most kBlockGlobalNnz
+// entries to stream from L2.  A dense coarse level (hub rows of a
+// power-law graph) is left to the grid kernels, whose bandwidth it needs.
+constexpr int64_t kBlockGlobalNnz = 32768;
+
+bool block_level(const HostLevel& L, int block_rows) {
+    if (L.n > block_rows) return false;
+    if (L.nnz <= kBlockGlobalNnz) return true;
+    const size_t wb = L.w32exact ? 4 : 8;
+    const size_t cb = L.n <= 65536 ? 2 : 4;
+    const size_t img = align8h(16 * (size_t)L.n) + align8h((size_t)L.nnz * wb) +
+                       align8h(4 * ((size_t)L.n + 1)) + align8h((size_t)L.nnz * cb);
+    return img <= (size_t)refine_block_lds_budget();
+}
+
 cmg_status build_refine_plan(cmg_ctx* c) {
     const int J = (int)c->lv.size() - 1;
     const cmg_options& o = c->opt;
@@ -372,14 +403,14 @@ cmg_status build_refine_plan(cmg_ctx* c) {
     int top = c->coarse_dense ? J - 1 : J;
     c->block_lo = top + 1;
     for (int j = top; j >= 0; --j) {
-        if (c->lv[j].n <= block_rows) c->block_lo = j;
+        if (block_level(c->lv[j], block_rows)) c->block_lo = j;
         else break;
     }
     int maxgrid = 8;
     for (int j = 0; j <= J; ++j) {
         HostLevel& L = c->lv[j];
         L.in_block = (j >= c->block_lo && j <= top) ? 1 : 0;
-        if (L.in_block) L.lanes = pick_lanes_block(L.n, L.nnz / (double)std::max(L.n, 1));
+        if (L.in_block) L.lanes = pick_lanes_block(L.n, L.nnz / (double)std::max(L.n, 1), L.maxlen);
         L.fp32 = 0;
         if (o.precision == CMG_MIXED && !L.in_block && j <= top && L.nnz >= mixed_min &&
             L.wmax < 16777216.0 && !(j == J && c->coarse_dense))

@@ -301,10 +301,11 @@ def latency_summary(reqs) -> dict:
     }
 
 
-def replay(server: Server, stream, qps: float, seed: int = 0):
+def replay(server: Server, stream, qps: float, seed: int = 0, progress=None, every: int = 25):
     """Submit `stream` (list of Request) with Poisson arrivals at `qps`;
     returns the requests after all completed.  Interarrival times are
-    -ln(1-U)/qps with U from a seeded generator."""
+    -ln(1-U)/qps with U from a seeded generator.  `progress(done, total)`
+    is called after every `every` completions."""
     rng = np.random.default_rng(seed)
     gaps = -np.log1p(-rng.random(len(stream))) / qps
     t = time.perf_counter()
@@ -315,6 +316,8 @@ def replay(server: Server, stream, qps: float, seed: int = 0):
             time.sleep(d)
         req.t_arrive = t
         server.submit(req)
-    for req in stream:
+    for i, req in enumerate(stream):
         req.event.wait()
+        if progress is not None and (i + 1) % every == 0:
+            progress(i + 1, len(stream))
     return stream

@@ -94,8 +94,9 @@ typedef struct {
     int32_t validate_full;       /* 1: also check symmetry of the input (O(nnz log deg)) */
     void* stream;                /* hipStream_t; NULL = null stream */
     const cmg_allocator* allocator; /* NULL = hipMalloc/hipFree */
-    int32_t block_rows;          /* levels with n <= block_rows are refined inside one
-                                    workgroup; 0 = library default */
+    int32_t block_rows;          /* > 0: levels with n <= block_rows are refined inside one
+                                    workgroup; 0 = library default (n <= 4096 and the
+                                    level's CSR fits LDS or has <= 32768 entries) */
     int64_t mixed_min_nnz;       /* MIXED: levels with nnz >= this run FP32 (0 = default) */
     int32_t spmv_variant;        /* 0 = auto (tuned), 1 = rows per lane group, 2 = merge path */
 } cmg_options;

@@ -403,7 +403,8 @@ cmg_status build_refine_plan(cmg_ctx* c) {
     int top = c->coarse_dense ? J - 1 : J;
     c->block_lo = top + 1;
     for (int j = top; j >= 0; --j) {
-        if (block_level(c->lv[j], block_rows)) c->block_lo = j;
+        const bool in = o.block_rows > 0 ? c->lv[j].n <= o.block_rows : block_level(c->lv[j], block_rows);
+        if (in) c->block_lo = j;
         else break;
     }
     int maxgrid = 8;

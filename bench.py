@@ -279,8 +279,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_source": traffic_src,
-                "kernel": f"k_refine_jobs<{levels[0].lanes},double> on level 0 (prolongation, deflation, "
-                          f"{ks[-1]} PI steps)",
+                "kernel": (f"k_refine_rows<{levels[0].lanes},double>" if levels[0].variant != 2 else
+                           "k_refine_merge<double>") + f" on level 0 (prolongation, deflation, {ks[-1]} PI steps)",
                 "bytes_per_launch": int(bytes_launch), "avg_launch_ms": round(pi_ms, 4),
                 "pi_steps_per_launch": ks[-1]}
 

@@ -98,7 +98,13 @@ typedef struct {
                                     workgroup; 0 = library default (n <= 4096 and the
                                     level's CSR fits LDS or has <= 32768 entries) */
     int64_t mixed_min_nnz;       /* MIXED: levels with nnz >= this run FP32 (0 = default) */
-    int32_t spmv_variant;        /* 0 = auto (tuned), 1 = rows per lane group, 2 = merge path */
+    int32_t spmv_variant;        /* 0 = auto, 1 = rows per lane group, 2 = merge path */
+    int32_t autotune;            /* 1: cmg_setup times candidate lanes-per-row and workgroup
+                                    counts of every grid-refined level with a few power-
+                                    iteration steps of the real kernel and keeps the fastest;
+                                    choices are cached per process by level shape, so results
+                                    are reproducible within a process but may differ (within
+                                    rounding) between processes.  0 (default): fixed rules. */
 } cmg_options;
 
 /* Per-level information (available after cmg_setup; PI fields after

@@ -52,6 +52,7 @@ class cmg_options(C.Structure):
         ("block_rows", C.c_int32),
         ("mixed_min_nnz", C.c_int64),
         ("spmv_variant", C.c_int32),
+        ("autotune", C.c_int32),
     ]
 
 

@@ -9,7 +9,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "cmg.h"
@@ -59,11 +62,11 @@ struct HostLevel {
 
 // Lanes per row for the row-group kernels: about five entries per lane
 // (two lanes per row on 6-10-regular meshes measured best on gfx950).
-// Lanes per row: about 2.5 entries per lane (measured best for degree
-// 6 to 16 meshes and geometric graphs: fewer lanes leave the loads of a
-// row serialised, more leave lanes idle).
+// Lanes per row: about 3 entries per lane (measured best for degree 6
+// to 16 meshes and geometric graphs: fewer lanes leave the loads of a row
+// serialised, more leave lanes idle).
 int pick_lanes(double avg_deg) {
-    double t = avg_deg / 2.5;
+    double t = avg_deg / 3.0;
     int g = 1;
     while (g < t && g < 64) g <<= 1;
     return g;
@@ -392,6 +395,153 @@ bool block_level(const HostLevel& L, int block_rows) {
     return img <= (size_t)refine_block_lds_budget();
 }
 
+// Largest co-resident workgroup count of the level's kernels (a multiple
+// of 8, at least 8); level 0 also runs the finishing kernel on its grid.
+int grid_cap(const HostLevel& L, int j, int lanes) {
+    const int kind = job_kind(L.variant, lanes, L.fp32);
+    int cap = refine_jobs_max_blocks(kind);
+    if (j == 0) cap = std::min(cap, finish_jobs_max_blocks(kind));
+    return std::max(8, (cap / 8) * 8);
+}
+
+int64_t step_bytes(const HostLevel& L) {
+    const int64_t sv = L.fp32 ? 4 : 8;
+    return 4 * ((int64_t)L.n + 1) + L.nnz * (4 + sv) + 2 * sv * (int64_t)L.n;
+}
+
+// Default workgroup count: about 2k rows+entries per workgroup (short
+// per-group latency chains on mid-size levels), a multiple of 8, at most
+// 3 per CU for levels whose step fits the 256 MB last-level cache (there
+// the cost of the grid barrier, which grows with the workgroup count,
+// outweighs more waves) and at most what can be co-resident.
+int default_grid(const HostLevel& L, int j, int ncu) {
+    int cap = grid_cap(L, j, L.lanes);
+    if (step_bytes(L) <= ((int64_t)256 << 20)) cap = std::min(cap, 3 * ncu);
+    int64_t want = ((int64_t)L.n + L.nnz + 2047) / 2048;
+    want = ((want + 7) / 8) * 8;
+    return (int)std::min<int64_t>(std::max<int64_t>(want, 8), cap);
+}
+
+// ---- autotuner: lanes per row and workgroup count of a grid level
+//
+// Candidates: lanes G/2, G, 2G around the rule's G (G only for the merge
+// path) and, for each, the default workgroup count and the co-resident
+// maximum (and 3/4 of it).  Each candidate runs kTuneSteps power-iteration
+// steps of the real refinement kernel from the hashed uniform start with
+// the stopping test disabled (tol = -1), twice; the faster run counts.
+// The choice is cached per process by level shape.
+constexpr int kTuneSteps = 4;
+
+struct TuneKey {
+    int variant, fp32, finest, n2, deg2, ml;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(variant, fp32, finest, n2, deg2, ml) <
+               std::tie(o.variant, o.fp32, o.finest, o.n2, o.deg2, o.ml);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;  // -> (lanes, grid)
+
+cmg_status tune_level(cmg_ctx* c, int j, int maxgrid) {
+    HostLevel& L = c->lv[j];
+    const double avg = L.nnz / (double)std::max(L.n, 1);
+    const TuneKey key{L.variant, L.fp32, j == 0 ? 1 : 0, (int)std::lround(2.0 * std::log2((double)L.n)),
+                      (int)std::lround(2.0 * avg), bitlen((unsigned long long)L.maxlen)};
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            L.lanes = it->second.first;
+            L.grid = it->second.second;
+            return CMG_OK;
+        }
+    }
+    std::vector<std::pair<int, int>> cand;
+    std::vector<int> lanes_c;
+    if (L.variant == 2) lanes_c.push_back(L.lanes);
+    else
+        for (int g : {L.lanes / 2, L.lanes, 2 * L.lanes})
+            if (g >= 1 && g <= 64) lanes_c.push_back(g);
+    int64_t want = ((int64_t)L.n + L.nnz + 2047) / 2048;
+    want = std::max<int64_t>(8, ((want + 7) / 8) * 8);
+    for (int g : lanes_c) {
+        const int cap = std::min(grid_cap(L, j, g), maxgrid);
+        for (int64_t nb : {want, (int64_t)cap, (int64_t)(cap * 3 / 4 / 8 * 8)}) {
+            const int gb = (int)std::max<int64_t>(8, std::min<int64_t>(nb, cap));
+            if (std::find(cand.begin(), cand.end(), std::make_pair(g, gb)) == cand.end())
+                cand.push_back({g, gb});
+        }
+    }
+    hipStream_t s = c->stream;
+    int32_t* part = nullptr;
+    LevelState* st = nullptr;
+    GridJob* dj = nullptr;
+    ALLOC(part, int32_t, maxgrid + 1);
+    ALLOC(st, LevelState, 1);
+    ALLOC(dj, GridJob, 1);
+    hipEvent_t e0, e1;
+    CK(hipEventCreate(&e0));
+    CK(hipEventCreate(&e1));
+    float best_ms = 0.f;
+    std::pair<int, int> best{L.lanes, L.grid};
+    bool have = false;
+    for (const auto& cg : cand) {
+        HostLevel T = L;
+        T.lanes = cg.first;
+        T.grid = cg.second;
+        T.part = part;
+        CK(launch_partition(L.n, L.nnz, L.rp, T.grid, part, s));
+        GridJob g{};
+        g.L = level_dev(T);
+        g.C = g.L;
+        g.st = st;
+        g.stc = nullptr;
+        g.gs = c->d_sync;
+        g.slots = c->d_slots;
+        g.bcast = c->d_bcast;
+        g.tol = -1.0;  // never converges: exactly maxit steps
+        g.seed = c->opt.seed;
+        g.maxit = kTuneSteps;
+        g.uniform = 1;
+        g.tag = j;
+        CK(hipMemcpyAsync(dj, &g, sizeof(GridJob), hipMemcpyHostToDevice, s));
+        const int kind = job_kind(T.variant, T.lanes, T.fp32);
+        float ms_min = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {
+            CK(hipEventRecord(e0, s));
+            CK(launch_refine_jobs(dj, 1, T.grid, kind, s));
+            CK(hipEventRecord(e1, s));
+            CK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            CK(hipEventElapsedTime(&ms, e0, e1));
+            if (rep == 0 || ms < ms_min) ms_min = ms;
+        }
+        if (!have || ms_min < best_ms) {
+            best_ms = ms_min;
+            best = cg;
+            have = true;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    GridSync hg{};
+    CK(hipMemcpyAsync(&hg, c->d_sync, sizeof(GridSync), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    c->dfree(dj);
+    c->dfree(st);
+    c->dfree(part);
+    if (hg.abort) {
+        // a trial did not complete its barriers: keep the rules' choice
+        CK(launch_reset_sync(c->d_sync, c->d_slots, c->nslots, c->d_bcast, s));
+        return CMG_OK;
+    }
+    L.lanes = best.first;
+    L.grid = best.second;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[key] = best;
+    return CMG_OK;
+}
+
 cmg_status build_refine_plan(cmg_ctx* c) {
     const int J = (int)c->lv.size() - 1;
     const cmg_options& o = c->opt;
@@ -407,7 +557,20 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         if (in) c->block_lo = j;
         else break;
     }
-    int maxgrid = 8;
+    // barrier state first: the autotuner launches the refinement kernel
+    int ncu = 256;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    }
+    const int maxgrid = std::max(8, 4 * ncu);  // 4 workgroups of 512 threads fill a CU
+    ALLOC(c->d_sync, GridSync, 1);
+    c->nslots = maxgrid;
+    ALLOC(c->d_slots, GridSlot, 2 * maxgrid);
+    c->d_bcast = (GridSlot*)c->dalloc(kBcastBytes);
+    if (!c->d_bcast) return CMG_E_OOM;
+    CK(launch_reset_sync(c->d_sync, c->d_slots, c->nslots, c->d_bcast, c->stream));
     for (int j = 0; j <= J; ++j) {
         HostLevel& L = c->lv[j];
         L.in_block = (j >= c->block_lo && j <= top) ? 1 : 0;
@@ -425,18 +588,11 @@ cmg_status build_refine_plan(cmg_ctx* c) {
             ALLOC(L.w32, float, std::max<int64_t>(L.nnz, 1));
             CK(launch_to_f32(L.nnz, L.w64, L.w32, c->stream));
         }
-        // grid size: about 2k rows+entries per workgroup (short per-group
-        // latency chains on mid-size levels), multiple of 8, at most what
-        // can be co-resident
-        const int kind = job_kind(L.variant, L.lanes, L.fp32);
-        int cap = refine_jobs_max_blocks(kind);
-        if (j == 0) cap = std::min(cap, finish_jobs_max_blocks(kind));
-        cap = std::max(8, (cap / 8) * 8);
-        int64_t work = (int64_t)L.n + L.nnz;
-        int64_t want = (work + 2047) / 2048;
-        want = ((want + 7) / 8) * 8;
-        L.grid = (int)std::min<int64_t>(std::max<int64_t>(want, 8), cap);
-        maxgrid = std::max(maxgrid, L.grid);
+        L.grid = default_grid(L, j, ncu);
+        if (o.autotune && !L.in_block && j <= top) {
+            cmg_status st = tune_level(c, j, maxgrid);
+            if (st != CMG_OK) return st;
+        }
         ALLOC(L.part, int32_t, L.grid + 1);
         CK(launch_partition(L.n, L.nnz, L.rp, L.grid, L.part, c->stream));
     }
@@ -445,12 +601,6 @@ cmg_status build_refine_plan(cmg_ctx* c) {
     ALLOC(c->d_lv, LevelDev, J + 1);
     CK(hipMemcpyAsync(c->d_lv, ld.data(), sizeof(LevelDev) * (J + 1), hipMemcpyHostToDevice, c->stream));
     ALLOC(c->d_st, LevelState, J + 1);
-    ALLOC(c->d_sync, GridSync, 1);
-    c->nslots = maxgrid;
-    ALLOC(c->d_slots, GridSlot, 2 * maxgrid);
-    c->d_bcast = (GridSlot*)c->dalloc(kBcastBytes);
-    if (!c->d_bcast) return CMG_E_OOM;
-    CK(launch_reset_sync(c->d_sync, c->d_slots, c->nslots, c->d_bcast, c->stream));
     ALLOC(c->d_fo, FinishOut, 1);
     const int dm = std::max(CJ.n, 2);
     if (c->coarse_dense) {
@@ -626,6 +776,7 @@ void fill_defaults(cmg_options* o) {
     o->block_rows = 0;
     o->mixed_min_nnz = 0;
     o->spmv_variant = 0;
+    o->autotune = 0;
 }
 
 // Device results of the last solve -> host staging (asynchronous).

@@ -37,11 +37,47 @@ __device__ __forceinline__ T group_sum(T v, int G) {
     return v;
 }
 
+// A double moved between lanes by DPP (a row of 16 lanes at most): vector
+// ALU only, no LDS traffic.  CTRL is the DPP control (0xB1 and 0x4E: quad
+// permutations to lane ^ 1 and lane ^ 2; 0x141: mirror within 8 lanes;
+// 0x140: mirror within 16 lanes).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Value of a lane, identical in every lane (needs that lane active).
+__device__ __forceinline__ double read_lane(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the aligned G-lane group (G a power of two <= 64; the whole
+// group active).  Each step adds a lane's partial to its partner's, so all
+// lanes of a group end with bitwise the same sum.  Doubles: quad
+// permutations and row mirrors by DPP up to 16 lanes, one shuffle for 32,
+// the four row sums by readlane for 64.
 template <int G, typename T>
 __device__ __forceinline__ T group_sum_t(T v) {
+    if constexpr (sizeof(T) == 8) {
+        double d = v;
+        if constexpr (G >= 2) d += dpp_move<0xB1>(d);
+        if constexpr (G >= 4) d += dpp_move<0x4E>(d);
+        if constexpr (G >= 8) d += dpp_move<0x141>(d);
+        if constexpr (G >= 16) d += dpp_move<0x140>(d);
+        if constexpr (G == 32) d += __shfl_xor(d, 16, kWave);
+        if constexpr (G == 64) d = (read_lane(d, 0) + read_lane(d, 16)) + (read_lane(d, 32) + read_lane(d, 48));
+        return (T)d;
+    } else {
 #pragma unroll
-    for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+        for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+        return v;
+    }
 }
 
 // Deterministic block reduction of NV doubles.  `red` is LDS scratch of at

@@ -409,9 +409,9 @@ __device__ __forceinline__ size_t staged_bytes(const LevelDev& L, int w32, int c
 constexpr int kWaveRows = 256;
 
 // Sum of NV (<= 4) doubles over the active threads, identical in every
-// thread.  Wave mode: butterfly, value of lane 0.  Workgroup mode: waves
-// post their sums (one barrier, alternating slots); each wave reads the
-// posts with one LDS access per lane and adds them by a 16-lane butterfly.
+// thread.  Wave mode: wave sum.  Workgroup mode: waves post their sums
+// (one barrier, alternating slots); each wave reads the posts with one LDS
+// access per lane, adds them within rows of 16 lanes and reads row q.
 template <int NV, bool WAVE>
 __device__ __forceinline__ void small_sum(double (&v)[NV], double* red, int& parity) {
     const int lane = threadIdx.x & 63;
@@ -421,7 +421,7 @@ __device__ __forceinline__ void small_sum(double (&v)[NV], double* red, int& par
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-        for (int q = 0; q < NV; ++q) v[q] = __shfl(group_sum_t<64>(v[q]), 0, 64);
+        for (int q = 0; q < NV; ++q) v[q] = group_sum_t<64>(v[q]);
     } else {
         const int wv = threadIdx.x >> 6;
         const int nw = blockDim.x >> 6;
@@ -434,10 +434,9 @@ __device__ __forceinline__ void small_sum(double (&v)[NV], double* red, int& par
         }
         __syncthreads();
         double t = (lane < NV * 16 && (lane & 15) < nw) ? slot[lane] : 0.0;
+        t = group_sum_t<16>(t);
 #pragma unroll
-        for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-#pragma unroll
-        for (int q = 0; q < NV; ++q) v[q] = __shfl(t, q * 16, 64);
+        for (int q = 0; q < NV; ++q) v[q] = read_lane(t, q * 16);
         parity ^= 1;
     }
 }
@@ -1210,13 +1209,8 @@ __device__ void residency_count(const GridJob& J) {
 // are specialised by traversal (merge path, or G lanes per row) and
 // storage precision to keep registers low; a packed launch holds one kind.
 template <int TRAV, typename T>
-__global__ void __launch_bounds__(kGridBlock) k_refine_jobs(const GridJob* __restrict__ jobs, int njobs) {
-    __shared__ double red[16 * 5 + 8];
-    MergeShared* sh = nullptr;
-    if constexpr (TRAV == 0) {
-        __shared__ MergeShared msh;
-        sh = &msh;
-    }
+__device__ __forceinline__ void refine_entry(const GridJob* __restrict__ jobs, int njobs, double* red,
+                                             MergeShared* sh) {
     const GridJob J = jobs[find_job(jobs, njobs)];
     if (J.tag == kResidencyTag) {
         residency_count(J);
@@ -1225,6 +1219,23 @@ __global__ void __launch_bounds__(kGridBlock) k_refine_jobs(const GridJob* __res
     GridCtx c = make_ctx(J);
     if (c.vb < 0 || c.vb >= c.nb) return;
     refine_level<T, TRAV>(J, c, red, sh);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kGridBlock) k_refine_merge(const GridJob* __restrict__ jobs, int njobs) {
+    __shared__ double red[16 * 5 + 8];
+    __shared__ MergeShared msh;
+    refine_entry<0, T>(jobs, njobs, red, &msh);
+}
+
+// G lanes per row.  Held to 8 waves per SIMD (at most 64 VGPRs and about
+// 80 SGPRs): with more SGPRs the device keeps only 3 workgroups of 512
+// threads per CU resident although the occupancy query reports 4.
+template <int G, typename T>
+__global__ void __launch_bounds__(kGridBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_refine_rows(const GridJob* __restrict__ jobs, int njobs) {
+    __shared__ double red[16 * 5 + 8];
+    refine_entry<G, T>(jobs, njobs, red, nullptr);
 }
 
 // One launch finishes the finest level of each job.
@@ -1288,7 +1299,10 @@ namespace {
 // kind = 2 * t + fp32 with t = 0 (merge path) or 1 + log2(G)
 template <int TRAV>
 const void* refine_kernel_t(int fp32) {
-    return fp32 ? (const void*)k_refine_jobs<TRAV, float> : (const void*)k_refine_jobs<TRAV, double>;
+    if constexpr (TRAV == 0)
+        return fp32 ? (const void*)k_refine_merge<float> : (const void*)k_refine_merge<double>;
+    else
+        return fp32 ? (const void*)k_refine_rows<TRAV, float> : (const void*)k_refine_rows<TRAV, double>;
 }
 const void* refine_kernel(int kind) {
     const int fp32 = kind & 1;

@@ -118,7 +118,11 @@ def from_edges(n: int, u, v, w=None, name: str = "") -> CSR:
     order = np.argsort(key, kind="stable")
     key = key[order]
     w = w[order]
-    uniq, start = np.unique(key, return_index=True)
+    # key is sorted: runs of equal keys are the parallel edges
+    first = np.ones(key.shape[0], dtype=bool)
+    first[1:] = key[1:] != key[:-1]
+    start = np.nonzero(first)[0]
+    uniq = key[start]
     wsum = np.add.reduceat(w, start) if len(key) else w
     a = uniq // n
     b = uniq % n
@@ -324,7 +328,10 @@ def chung_lu(n: int, gamma: float = 2.1, mean_deg: float = 16.0, cap: float = 50
         cnt = min(chunk, m - s0)
         idx = np.arange(2 * s0, 2 * (s0 + cnt), dtype=np.uint64)
         uu = stream_uniform(seed, TAG_CL, idx)
-        e = np.searchsorted(cdf, uu, side="right")
+        # inverse CDF; queries in sorted order (same result, cache-friendly)
+        order = np.argsort(uu)
+        e = np.empty(uu.shape[0], dtype=np.int64)
+        e[order] = np.searchsorted(cdf, uu[order], side="right")
         e = np.minimum(e, n - 1)
         out_u.append(e[0::2])
         out_v.append(e[1::2])

@@ -4,8 +4,8 @@
     python -m paper_1412_0565_amd.profsum counters <fetch counter_collection.csv> <write counter_collection.csv>
 
 `trace` prints the busiest kernels and the duration of the finest-level
-refinement launches: in every solve the last k_refine_jobs dispatch before
-the k_finish_jobs dispatch refines level 0.  `counters` prints FETCH_SIZE
+refinement launches: in every solve the last k_refine_rows/k_refine_merge
+dispatch before the k_finish_jobs dispatch refines level 0.  `counters` prints FETCH_SIZE
 and WRITE_SIZE (KiB per dispatch) of those launches, each divided by what
 the same counter reads per byte of the reference device copy that ends
 the run (bench.py --copy-mib), i.e. HBM bytes per level-0 launch.
@@ -18,14 +18,14 @@ import sys
 
 
 def _level0_dispatch_ids(rows, name_key, id_key):
-    """Dispatch ids of the level-0 refinement launches: a k_refine_jobs
-    dispatch whose very next dispatch is k_finish_jobs (the one-off
+    """Dispatch ids of the level-0 refinement launches: a k_refine_rows or
+    k_refine_merge dispatch whose very next dispatch is k_finish_jobs (the one-off
     residency measurements of the same kernels run on streams of their
     own and are never adjacent)."""
     out = []
     prev = None
     for r in rows:
-        if (prev is not None and "k_finish_jobs" in r[name_key] and "k_refine_jobs" in prev[name_key]
+        if (prev is not None and "k_finish_jobs" in r[name_key] and "k_refine_" in prev[name_key]
                 and int(r[id_key]) == int(prev[id_key]) + 1):
             out.append(prev[id_key])
         prev = r

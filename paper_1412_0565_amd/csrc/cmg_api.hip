@@ -223,7 +223,11 @@ struct SetupTmp {
     long long* totals = nullptr;         // [0] scan total
     unsigned* vflags = nullptr;
     double* bmax = nullptr;              // per-block maxima of the row pass
+    unsigned long long* ri = nullptr;    // row information of level j at ri[4j .. 4j+3]
+    std::vector<int> ri_pending;         // levels whose row information is still on the device
 };
+
+constexpr int kMaxLevels = 64;
 
 cmg_status alloc_tmp(cmg_ctx* c, SetupTmp& t, int32_t n, int64_t nnz) {
     ALLOC(t.h, int32_t, n);
@@ -248,13 +252,14 @@ cmg_status alloc_tmp(cmg_ctx* c, SetupTmp& t, int32_t n, int64_t nnz) {
     ALLOC(t.totals, long long, 4);
     ALLOC(t.vflags, unsigned, 4);
     ALLOC(t.bmax, double, 4 * kRowinfoMaxBlocks);
+    ALLOC(t.ri, unsigned long long, 4 * kMaxLevels);
     return CMG_OK;
 }
 
 void free_tmp(cmg_ctx* c, SetupTmp& t) {
     void* ps[] = {t.h, t.slot, t.live, t.state, t.pairseed, t.rootseed, t.flags, t.rank, t.scan_tmp,
                   t.k0, t.k1, t.v0, t.v1, t.heads, t.idx, t.sort_counts, t.sort_scan, t.scal, t.totals,
-                  t.vflags, t.bmax};
+                  t.vflags, t.bmax, t.ri};
     size_t bytes = 0;
     (void)bytes;
     (void)hipStreamSynchronize(c->stream);
@@ -262,21 +267,35 @@ void free_tmp(cmg_ctx* c, SetupTmp& t) {
     t = SetupTmp{};
 }
 
-// Gershgorin shift, heaviest neighbours and largest weight of one level.
-cmg_status level_rowinfo(cmg_ctx* c, SetupTmp& t, HostLevel& L) {
-    CK(launch_rowinfo(L.n, L.lanes, L.rp, L.col, L.w64, t.h, t.bmax, t.scal + 4, c->stream));
-    unsigned long long hb[4];
-    cmg_status st = d2h(c, hb, t.scal + 4, 4);
+// Gershgorin shift, heaviest neighbours, largest weight, FP32 exactness and
+// longest row of level j: enqueued; the values stay on the device until
+// finish_rowinfo reads those of every level at once.
+cmg_status level_rowinfo(cmg_ctx* c, SetupTmp& t, int j) {
+    HostLevel& L = c->lv[j];
+    if (j >= kMaxLevels) return CMG_E_DEVICE;
+    CK(launch_rowinfo(L.n, L.lanes, L.rp, L.col, L.w64, t.h, t.bmax, t.ri + 4 * j, c->stream));
+    t.ri_pending.push_back(j);
+    return CMG_OK;
+}
+
+cmg_status finish_rowinfo(cmg_ctx* c, SetupTmp& t) {
+    if (t.ri_pending.empty()) return CMG_OK;
+    std::vector<unsigned long long> hb(4 * kMaxLevels);
+    cmg_status st = d2h(c, hb.data(), t.ri, hb.size());
     if (st != CMG_OK) return st;
-    double gv, wm, ex, ml;
-    std::memcpy(&gv, &hb[0], 8);
-    std::memcpy(&wm, &hb[1], 8);
-    std::memcpy(&ex, &hb[2], 8);
-    std::memcpy(&ml, &hb[3], 8);
-    L.g = gv;
-    L.wmax = wm;
-    L.w32exact = (ex == 0.0) ? 1 : 0;
-    L.maxlen = (int64_t)ml;
+    for (int j : t.ri_pending) {
+        HostLevel& L = c->lv[j];
+        double gv, wm, ex, ml;
+        std::memcpy(&gv, &hb[4 * j], 8);
+        std::memcpy(&wm, &hb[4 * j + 1], 8);
+        std::memcpy(&ex, &hb[4 * j + 2], 8);
+        std::memcpy(&ml, &hb[4 * j + 3], 8);
+        L.g = gv;
+        L.wmax = wm;
+        L.w32exact = (ex == 0.0) ? 1 : 0;
+        L.maxlen = (int64_t)ml;
+    }
+    t.ri_pending.clear();
     return CMG_OK;
 }
 
@@ -287,48 +306,55 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
     hipStream_t s = c->stream;
     const uint64_t seed = c->opt.seed;
     *stop = false;
-    cmg_status st = level_rowinfo(c, t, L);
+    cmg_status st = level_rowinfo(c, t, j);
     if (st != CMG_OK) return st;
     CK(launch_hec_init(L.n, t.h, seed, j, t.live, t.state, t.pairseed, t.slot, s));
-    for (int round = 0;; ++round) {
-        if (round > 100000) return CMG_E_DEVICE;
-        CK(hipMemsetAsync(t.scal + 2, 0, sizeof(unsigned long long), s));
-        CK(launch_hec_round(L.n, t.h, seed, j, t.live, t.state, t.pairseed, t.slot, t.scal + 2, s));
+    // greedy rounds in batches between host checks; a round after the last
+    // live candidate edge changes nothing
+    for (int batch = 4, total = 0;; batch = 2) {
+        for (int r = 0; r < batch; ++r) {
+            CK(hipMemsetAsync(t.scal + 2, 0, sizeof(unsigned long long), s));
+            CK(launch_hec_round(L.n, t.h, seed, j, t.live, t.state, t.pairseed, t.slot, t.scal + 2, s));
+        }
+        total += batch;
+        c->hec_rounds += batch;
         unsigned long long live = 0;
         st = d2h(c, &live, t.scal + 2, 1);
         if (st != CMG_OK) return st;
-        ++c->hec_rounds;
         if (live == 0) break;
+        if (total > 100000) return CMG_E_DEVICE;
     }
     CK(launch_hec_attach(L.n, t.h, t.state, t.pairseed, t.rootseed, t.flags, s));
-    CK(launch_scan(t.flags, t.rank, L.n, t.scan_tmp, t.totals, s));
-    long long nc = 0;
-    st = d2h(c, &nc, t.totals, 1);
-    if (st != CMG_OK) return st;
-    if (nc < 2) {
-        c->collapsed = 1;
-        *stop = true;
-        return CMG_OK;
-    }
+    CK(launch_scan(t.flags, t.rank, L.n, t.scan_tmp, t.totals, s));  // totals[0]: aggregates
     ALLOC(L.agg, int32_t, L.n);
     CK(launch_hec_label(L.n, t.rootseed, t.rank, L.agg, s));
-    // Galerkin product
-    CK(launch_gal_emit(L.n, L.lanes, L.rp, L.col, L.w64, L.agg, (int)nc, t.k0, t.v0, s));
-    const unsigned long long sent = (unsigned long long)nc * (unsigned long long)nc;
-    int bits = bitlen(sent);
+    // Galerkin product with the aggregate count left on the device: keys
+    // a * mult + b with mult = n/2 + 1 >= the count (aggregates have two
+    // vertices or more), sorted on enough bits that the sentinel's low
+    // bits exceed every key
+    const int64_t mult = (int64_t)L.n / 2 + 1;
+    CK(launch_gal_emit(L.n, L.lanes, L.rp, L.col, L.w64, L.agg, mult, t.k0, t.v0, s));
+    const int bits = bitlen((unsigned long long)mult * (unsigned long long)mult);
     int second = 0;
     CK(launch_sort(t.k0, t.v0, t.k1, t.v1, L.nnz, bits, t.sort_counts, t.sort_scan, &second, s));
     const unsigned long long* ks = second ? t.k1 : t.k0;
     const double* vs = second ? t.v1 : t.v0;
-    CK(launch_count_below(ks, L.nnz, sent, t.scal + 3, s));
+    CK(launch_count_below(ks, L.nnz, kGalSentinel, t.scal + 3, s));
+    CK(launch_gal_heads(L.nnz, t.scal + 3, ks, t.heads, s));
+    CK(launch_scan(t.heads, t.idx, L.nnz, t.scan_tmp, t.totals + 1, s));  // totals[1]: coarse entries
+    long long tot[2] = {0, 0};
     unsigned long long nvalid = 0;
+    CK(hipMemcpyAsync(tot, t.totals, sizeof(tot), hipMemcpyDeviceToHost, s));
     st = d2h(c, &nvalid, t.scal + 3, 1);
     if (st != CMG_OK) return st;
-    CK(launch_gal_heads((int64_t)nvalid, ks, t.heads, s));
-    CK(launch_scan(t.heads, t.idx, (int64_t)nvalid, t.scan_tmp, t.totals, s));
-    long long zc = 0;
-    st = d2h(c, &zc, t.totals, 1);
-    if (st != CMG_OK) return st;
+    const long long nc = tot[0], zc = tot[1];
+    if (nc < 2) {
+        c->dfree(L.agg);
+        L.agg = nullptr;
+        c->collapsed = 1;
+        *stop = true;
+        return CMG_OK;
+    }
     HostLevel C;
     C.n = (int32_t)nc;
     C.nnz = zc;
@@ -338,10 +364,106 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
     if (zc == 0) {
         CK(hipMemsetAsync(C.rp, 0, sizeof(int32_t) * (C.n + 1), s));
     } else {
-        CK(launch_gal_reduce((int64_t)nvalid, ks, vs, t.heads, t.idx, (int)nc, zc, C.rp, C.col, C.w64, s));
+        CK(launch_gal_reduce((int64_t)nvalid, ks, vs, t.heads, t.idx, mult, (int)nc, zc, C.rp, C.col, C.w64,
+                             s));
     }
     C.lanes = pick_lanes(C.nnz / (double)C.n);
     c->lv.push_back(C);
+    return CMG_OK;
+}
+
+// ---- small levels: one launch for the rest of the hierarchy
+bool chain_level(const HostLevel& L) { return L.n <= kChainMaxN && L.nnz <= kChainMaxNnz; }
+
+// Coarsens level j0 and the levels below it in one workgroup.  *next = -1
+// if the hierarchy is complete, else the index of a level left to the grid
+// kernels (a coarse row too long for the single-workgroup Galerkin step).
+cmg_status coarsen_chain(cmg_ctx* c, SetupTmp& t, int j0, int* next) {
+    HostLevel L = c->lv[j0];
+    hipStream_t s = c->stream;
+    const int max_levels = 61 - j0;  // coarsening stops at level index 60
+    // arena bounds: n_{k+1} <= n_k / 2; nnz_{k+1} <= min(nnz_k, n_{k+1} (n_{k+1} - 1))
+    int64_t cw = 0;
+    {
+        int64_t prev = L.nnz, nk = L.n;
+        for (int k = 1; k < max_levels; ++k) {
+            nk /= 2;
+            if (nk < 2) break;
+            const int64_t b = std::min<int64_t>(prev, nk * (nk - 1));
+            cw += b;
+            prev = b;
+        }
+    }
+    cw = std::max<int64_t>(cw, 1);
+    const int64_t i32cap = 4 * (int64_t)L.n + 2 * (int64_t)max_levels + 64;
+    ChainJob job{};
+    job.n0 = L.n;
+    job.level0 = j0;
+    job.nnz0 = L.nnz;
+    job.rp0 = L.rp;
+    job.col0 = L.col;
+    job.w0 = L.w64;
+    job.seed = c->opt.seed;
+    job.coarsest_n = c->opt.coarsest_n;
+    job.max_levels = max_levels;
+    // scratch: the level-0 setup buffers (n0 >= n and nnz0 >= nnz, and
+    // nnz0 >= n0 since every vertex has a neighbour)
+    job.h = t.h;
+    job.pairseed = t.pairseed;
+    job.rootseed = t.rootseed;
+    job.rank = t.rank;
+    job.members = t.idx;
+    job.astart = (int32_t*)t.k0;  // 2 nnz0 ints
+    job.soff = job.astart + L.n;
+    job.rcount = (int32_t*)t.v1;  // 2 nnz0 ints
+    job.mb = (int32_t*)t.k1;
+    job.slot = t.slot;
+    job.live = t.live;
+    job.state = t.state;
+    job.mw = t.v0;
+    ALLOC(job.ai32, int32_t, i32cap);
+    job.ai32_cap = i32cap;
+    ALLOC(job.acol, int32_t, cw);
+    ALLOC(job.aw, double, cw);
+    job.acw_cap = cw;
+    const size_t hbytes = sizeof(ChainHdr) * max_levels + 16;
+    char* hd_dev = (char*)c->dalloc(hbytes);
+    if (!hd_dev) return CMG_E_OOM;
+    job.hdr = (ChainHdr*)hd_dev;
+    job.out = (int32_t*)(hd_dev + sizeof(ChainHdr) * max_levels);
+    CK(launch_coarsen_chain(job, s));
+    std::vector<char> hb(hbytes);
+    cmg_status st = d2h(c, hb.data(), hd_dev, hbytes);
+    c->dfree(hd_dev);
+    if (st != CMG_OK) return st;
+    const ChainHdr* hdr = (const ChainHdr*)hb.data();
+    const int32_t* out = (const int32_t*)(hb.data() + sizeof(ChainHdr) * max_levels);
+    const int K = out[0], reason = out[2];
+    if (K < 1 || K > max_levels) return CMG_E_DEVICE;
+    for (int k = 0; k < K; ++k) {
+        const ChainHdr& h = hdr[k];
+        if (k > 0) {
+            HostLevel C;
+            C.n = h.n;
+            C.nnz = h.nnz;
+            C.rp = job.ai32 + h.rp_off;
+            C.col = job.acol + h.cw_off;
+            C.w64 = job.aw + h.cw_off;
+            C.lanes = pick_lanes(C.nnz / (double)std::max(C.n, 1));
+            c->lv.push_back(C);
+        }
+        HostLevel& Lk = c->lv[j0 + k];
+        Lk.g = h.g;
+        Lk.wmax = h.wmax;
+        Lk.w32exact = (h.w32err == 0.0) ? 1 : 0;
+        Lk.maxlen = (int64_t)h.maxlen;
+        if (h.agg_off >= 0) {
+            Lk.agg = job.ai32 + h.agg_off;
+            c->hec_rounds += h.rounds;
+        }
+    }
+    if (out[1]) c->collapsed = 1;
+    *next = (reason == 3 || reason == 4) ? j0 + K - 1 : -1;
     return CMG_OK;
 }
 
@@ -740,21 +862,36 @@ cmg_status setup_impl(cmg_ctx* c, int32_t n, int64_t nnz, const int32_t* row_ptr
     st = alloc_tmp(c, t, n, nnz);
     if (st != CMG_OK) return st;
     int j = 0;
+    bool grid_only = false;  // a level the single-workgroup chain handed back
     while (c->lv[j].n > c->opt.coarsest_n && j < 60) {
+        if (!grid_only && chain_level(c->lv[j])) {
+            int next = -1;
+            st = coarsen_chain(c, t, j, &next);
+            if (st != CMG_OK) return st;
+            if (next < 0) break;
+            j = next;
+            grid_only = true;
+            continue;
+        }
+        grid_only = false;
         bool stop = false;
         st = coarsen_once(c, t, j, &stop);
         if (st != CMG_OK) return st;
         if (stop) break;
         ++j;
     }
-    // Gershgorin shift of the coarsest level (not yet computed if the
-    // loop ended on the size test)
+    // row information of the coarsest level (not yet computed if the loop
+    // ended on the size test), then of every level at once
     {
-        HostLevel& CJ = c->lv.back();
-        if (CJ.g == 0.0) {
-            st = level_rowinfo(c, t, CJ);
+        const int J = (int)c->lv.size() - 1;
+        const bool have = c->lv[J].g != 0.0 ||
+                          std::find(t.ri_pending.begin(), t.ri_pending.end(), J) != t.ri_pending.end();
+        if (!have) {
+            st = level_rowinfo(c, t, J);
             if (st != CMG_OK) return st;
         }
+        st = finish_rowinfo(c, t);
+        if (st != CMG_OK) return st;
     }
     free_tmp(c, t);
     return build_refine_plan(c);

@@ -14,6 +14,51 @@ constexpr unsigned kBadGraph = 1u;
 constexpr unsigned kIsolated = 2u;
 constexpr unsigned kAsym = 4u;
 
+// ---- coarsen_small.hip: the setup of small levels in one workgroup
+constexpr int kChainThreads = 1024;
+constexpr int kChainMaxN = 8192;         // levels with at most this many vertices
+constexpr int64_t kChainMaxNnz = 262144; // ... and at most this many entries
+constexpr int kChainMaxRow = 1024;       // longest coarse row (member entries) one thread forms
+
+// One level visited by the chain: its row information, and where its
+// arrays were written (offsets into the arenas; -1 for the first level,
+// whose arrays are the input, and agg_off = -1 if it was not coarsened).
+struct ChainHdr {
+    int32_t n;
+    int32_t rounds;   // HEC rounds of this level's coarsening
+    int64_t nnz;
+    double g, wmax, w32err, maxlen;
+    int64_t rp_off, cw_off, agg_off;
+};
+
+struct ChainJob {
+    int32_t n0;
+    int32_t level0;
+    int64_t nnz0;
+    const int32_t* rp0;
+    const int32_t* col0;
+    const double* w0;
+    uint64_t seed;
+    int32_t coarsest_n;
+    int32_t max_levels;  // levels that may be visited, the first included
+    // scratch (sized for level 0 of the graph)
+    int32_t *h, *pairseed, *rootseed, *rank, *members, *astart, *soff, *rcount, *mb;
+    unsigned long long* slot;
+    uint8_t *live, *state;
+    double* mw;
+    // arenas for the levels produced: agg and row pointers (ai32), columns
+    // and weights (acol, aw)
+    int32_t* ai32;
+    int64_t ai32_cap;
+    int32_t* acol;
+    double* aw;
+    int64_t acw_cap;
+    ChainHdr* hdr;  // [max_levels]
+    int32_t* out;   // [0] levels visited, [1] collapsed, [2] stop reason
+                    // (1 size, 2 collapse, 3 arena, 4 long coarse row, 5 level cap)
+};
+hipError_t launch_coarsen_chain(const ChainJob& job, hipStream_t s);
+
 // ---- setup.hip
 hipError_t launch_validate(int n, int64_t nnz, const int32_t* rp, const int32_t* col, const void* w,
                            int wf32, int full, unsigned* flags, hipStream_t s);
@@ -41,8 +86,11 @@ hipError_t launch_hec_label(int n, const int32_t* rootseed, const int32_t* rank,
 int64_t scan_tmp_elems(int64_t m);
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, long long* tmp, long long* total,
                        hipStream_t s);
+// Galerkin keys: a * mult + b (mult >= coarse vertex count), or
+// kGalSentinel for entries inside an aggregate (they sort last)
+constexpr unsigned long long kGalSentinel = 0xFFFFFFFFFFFFFFFFull;
 hipError_t launch_gal_emit(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w,
-                           const int32_t* agg, int nc, unsigned long long* keys, double* vals,
+                           const int32_t* agg, int64_t mult, unsigned long long* keys, double* vals,
                            hipStream_t s);
 // *out = number of keys[0..m) below `sent` (keys sorted ascending)
 hipError_t launch_count_below(const unsigned long long* keys, int64_t m, unsigned long long sent,
@@ -53,9 +101,12 @@ int64_t sort_tmp_elems(int64_t m);
 hipError_t launch_sort(unsigned long long* k0, double* v0, unsigned long long* k1, double* v1,
                        int64_t m, int bits, int32_t* tmp_counts, long long* tmp_scan,
                        int* in_second, hipStream_t s);
-hipError_t launch_gal_heads(int64_t m, const unsigned long long* keys, int32_t* heads, hipStream_t s);
+// heads[t] = 1 where a run of equal keys starts among the first *nvalid
+// keys (read on the device), 0 elsewhere in [0, m)
+hipError_t launch_gal_heads(int64_t m, const unsigned long long* nvalid, const unsigned long long* keys,
+                            int32_t* heads, hipStream_t s);
 hipError_t launch_gal_reduce(int64_t m, const unsigned long long* keys, const double* vals,
-                             const int32_t* heads, const int32_t* idx, int nc, int64_t zc,
+                             const int32_t* heads, const int32_t* idx, int64_t mult, int nc, int64_t zc,
                              int32_t* rp_out, int32_t* col_out, double* w_out, hipStream_t s);
 hipError_t launch_partition(int n, int64_t nnz, const int32_t* rp, int nb, int32_t* part,
                             hipStream_t s);

@@ -369,19 +369,22 @@ __global__ void k_scan_down(const int32_t* __restrict__ in, int32_t* __restrict_
 // nc*nc when both ends are in one aggregate (those entries only feed the
 // implicit diagonal).  Keys keep the CSR position, so a stable sort leaves
 // equal keys in fine CSR order.
+// key of a fine entry: a * mult + b for the coarse entry (a, b), with mult
+// at least the coarse vertex count (so keys order by (a, b)); entries
+// inside an aggregate get kGalSentinel and sort last
 template <int G>
 __global__ void k_gal_emit(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                           const double* __restrict__ w, const int32_t* __restrict__ agg, int nc,
+                           const double* __restrict__ w, const int32_t* __restrict__ agg, int64_t mult,
                            unsigned long long* __restrict__ keys, double* __restrict__ vals) {
     const int lane = threadIdx.x & (G - 1);
     const int gpb = blockDim.x / G;
-    const unsigned long long sent = (unsigned long long)nc * (unsigned long long)nc;
     for (int row = blockIdx.x * gpb + threadIdx.x / G; row < n; row += gridDim.x * gpb) {
         int a = agg[row];
         int e0 = rp[row], e1 = rp[row + 1];
         for (int e = e0 + lane; e < e1; e += G) {
             int b = agg[col[e]];
-            unsigned long long k = (a == b) ? sent : (unsigned long long)a * (unsigned long long)nc + b;
+            unsigned long long k =
+                (a == b) ? kGalSentinel : (unsigned long long)a * (unsigned long long)mult + (unsigned long long)b;
             keys[e] = k;
             vals[e] = w[e];
         }
@@ -401,11 +404,13 @@ __global__ void k_count_below(const unsigned long long* __restrict__ keys, int64
     *out = (unsigned long long)lo;
 }
 
-__global__ void k_gal_heads(int64_t m, const unsigned long long* __restrict__ keys,
-                            int32_t* __restrict__ heads) {
+// run heads among the first *nvalid sorted keys (0 beyond), over m entries
+__global__ void k_gal_heads(int64_t m, const unsigned long long* __restrict__ nvalid,
+                            const unsigned long long* __restrict__ keys, int32_t* __restrict__ heads) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m) return;
-    heads[t] = (t == 0 || keys[t] != keys[t - 1]) ? 1 : 0;
+    const int64_t mv = (int64_t)*nvalid;
+    heads[t] = (t < mv && (t == 0 || keys[t] != keys[t - 1])) ? 1 : 0;
 }
 
 // Each run of equal keys is summed in order (fine CSR order); the first
@@ -413,14 +418,14 @@ __global__ void k_gal_heads(int64_t m, const unsigned long long* __restrict__ ke
 // coarse rows that start there.
 __global__ void k_gal_reduce(int64_t m, const unsigned long long* __restrict__ keys,
                              const double* __restrict__ vals, const int32_t* __restrict__ heads,
-                             const int32_t* __restrict__ idx, int nc, int64_t zc,
+                             const int32_t* __restrict__ idx, int64_t mult, int nc, int64_t zc,
                              int32_t* __restrict__ rp, int32_t* __restrict__ col,
                              double* __restrict__ w) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m || !heads[t]) return;
     unsigned long long k = keys[t];
-    int row = (int)(k / (unsigned long long)nc);
-    int c = (int)(k - (unsigned long long)row * nc);
+    int row = (int)(k / (unsigned long long)mult);
+    int c = (int)(k - (unsigned long long)row * (unsigned long long)mult);
     double s = vals[t];
     int64_t u = t + 1;
     while (u < m && keys[u] == k) {
@@ -430,7 +435,7 @@ __global__ void k_gal_reduce(int64_t m, const unsigned long long* __restrict__ k
     int32_t o = idx[t];
     col[o] = c;
     w[o] = s;
-    int prow = (t == 0) ? -1 : (int)(keys[t - 1] / (unsigned long long)nc);
+    int prow = (t == 0) ? -1 : (int)(keys[t - 1] / (unsigned long long)mult);
     for (int r = prow + 1; r <= row; ++r) rp[r] = o;
     if (u == m) {
         for (int r = row + 1; r <= nc; ++r) rp[r] = (int32_t)zc;
@@ -643,14 +648,14 @@ hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, long long* tm
 }
 
 hipError_t launch_gal_emit(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w,
-                           const int32_t* agg, int nc, unsigned long long* keys, double* vals,
+                           const int32_t* agg, int64_t mult, unsigned long long* keys, double* vals,
                            hipStream_t s) {
     int gpb = kBlk / lanes;
     unsigned nb = (unsigned)std::min<int64_t>(nblocks(n, gpb), 65536);
     switch (lanes) {
 #define CMG_GE(G)                                                                                  \
     case G:                                                                                        \
-        hipLaunchKernelGGL(k_gal_emit<G>, dim3(nb), dim3(kBlk), 0, s, n, rp, col, w, agg, nc, keys, \
+        hipLaunchKernelGGL(k_gal_emit<G>, dim3(nb), dim3(kBlk), 0, s, n, rp, col, w, agg, mult, keys, \
                            vals);                                                                  \
         break;
         CMG_GE(1) CMG_GE(2) CMG_GE(4) CMG_GE(8) CMG_GE(16) CMG_GE(32) CMG_GE(64)
@@ -695,18 +700,19 @@ hipError_t launch_count_below(const unsigned long long* keys, int64_t m, unsigne
     return hipGetLastError();
 }
 
-hipError_t launch_gal_heads(int64_t m, const unsigned long long* keys, int32_t* heads, hipStream_t s) {
+hipError_t launch_gal_heads(int64_t m, const unsigned long long* nvalid, const unsigned long long* keys,
+                            int32_t* heads, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gal_heads, dim3(nblocks(m, kBlk)), dim3(kBlk), 0, s, m, keys, heads);
+    hipLaunchKernelGGL(k_gal_heads, dim3(nblocks(m, kBlk)), dim3(kBlk), 0, s, m, nvalid, keys, heads);
     return hipGetLastError();
 }
 
 hipError_t launch_gal_reduce(int64_t m, const unsigned long long* keys, const double* vals,
-                             const int32_t* heads, const int32_t* idx, int nc, int64_t zc,
+                             const int32_t* heads, const int32_t* idx, int64_t mult, int nc, int64_t zc,
                              int32_t* rp_out, int32_t* col_out, double* w_out, hipStream_t s) {
     if (m == 0) return hipSuccess;
     hipLaunchKernelGGL(k_gal_reduce, dim3(nblocks(m, kBlk)), dim3(kBlk), 0, s, m, keys, vals, heads, idx,
-                       nc, zc, rp_out, col_out, w_out);
+                       mult, nc, zc, rp_out, col_out, w_out);
     return hipGetLastError();
 }
 

@@ -96,7 +96,7 @@ typedef struct {
     const cmg_allocator* allocator; /* NULL = hipMalloc/hipFree */
     int32_t block_rows;          /* > 0: levels with n <= block_rows are refined inside one
                                     workgroup; 0 = library default (n <= 4096 and the
-                                    level's CSR fits LDS or has <= 32768 entries) */
+                                    level's CSR fits LDS or has <= 8192 entries) */
     int64_t mixed_min_nnz;       /* MIXED: levels with nnz >= this run FP32 (0 = default) */
     int32_t spmv_variant;        /* 0 = auto, 1 = rows per lane group, 2 = merge path */
     int32_t autotune;            /* 1: cmg_setup times candidate lanes-per-row and workgroup

@@ -503,9 +503,10 @@ size_t align8h(size_t b) { return (b + 7) & ~(size_t)7; }
 // vertices and its steps stay cheap there: its LDS image (two vectors,
 // weights, row pointers, columns; FP32 weights when exact, uint16 columns
 // when n <= 65536) fits the LDS budget, or it has at most kBlockGlobalNnz
-// entries to stream from L2.  A dense coarse level (hub rows of a
-// power-law graph) is left to the grid kernels, whose bandwidth it needs.
-constexpr int64_t kBlockGlobalNnz = 32768;
+// entries to stream from L2 (one CU streaming more is slower than the grid
+// kernels).  A dense coarse level (hub rows of a power-law graph) is left
+// to the grid kernels, whose bandwidth it needs.
+constexpr int64_t kBlockGlobalNnz = 8192;
 
 bool block_level(const HostLevel& L, int block_rows) {
     if (L.n > block_rows) return false;

@@ -453,7 +453,24 @@ __device__ __forceinline__ void pi_small(int n, int nthr, const int32_t* rp, con
         const int a = rp[i], b = rp[i + 1];
         const double wi = win[i];
         double t = 0.0;
-        for (int e = a + lane; e < b; e += G) {
+        int e = a + lane;
+        // four entries per trip: their column and value loads, then their
+        // gathers, are in flight together; the sum keeps the entry order
+        for (; e + 3 * G < b; e += 4 * G) {
+            int c[4];
+            double wt[4], x[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int f = e + q * G;
+                c[q] = C16 ? (int)((const uint16_t*)colp)[f] : ((const int32_t*)colp)[f];
+                wt[q] = W32 ? (double)((const float*)wp)[f] : ((const double*)wp)[f];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[q] = win[c[q]];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t += wt[q] * (x[q] - wi);
+        }
+        for (; e < b; e += G) {
             const int c = C16 ? (int)((const uint16_t*)colp)[e] : ((const int32_t*)colp)[e];
             const double wt = W32 ? (double)((const float*)wp)[e] : ((const double*)wp)[e];
             t += wt * (win[c] - wi);

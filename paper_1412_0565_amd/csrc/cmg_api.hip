@@ -333,14 +333,22 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
     // vertices or more), sorted on enough bits that the sentinel's low
     // bits exceed every key
     const int64_t mult = (int64_t)L.n / 2 + 1;
-    CK(launch_gal_emit(L.n, L.lanes, L.rp, L.col, L.w64, L.agg, mult, t.k0, t.v0, s));
     const int bits = bitlen((unsigned long long)mult * (unsigned long long)mult);
+    // packed words (key << pbits | fine position) when they fit 64 bits:
+    // the sort then moves 8 bytes per entry instead of 16
+    const int pbits = std::max(1, bitlen((unsigned long long)std::max<int64_t>(L.nnz - 1, 1)));
+    const bool packed = bits + pbits <= 64;
+    const int pshift = packed ? pbits : 0;
+    const unsigned long long sent = packed ? (~0ull >> (64 - bits)) : kGalSentinel;
+    CK(launch_gal_emit(L.n, L.lanes, L.rp, L.col, L.w64, L.agg, mult, pshift, sent, t.k0,
+                       packed ? nullptr : t.v0, s));
     int second = 0;
-    CK(launch_sort(t.k0, t.v0, t.k1, t.v1, L.nnz, bits, t.sort_counts, t.sort_scan, &second, s));
+    CK(launch_sort(t.k0, packed ? nullptr : t.v0, t.k1, packed ? nullptr : t.v1, L.nnz, pshift, bits,
+                   t.sort_counts, t.sort_scan, &second, s));
     const unsigned long long* ks = second ? t.k1 : t.k0;
-    const double* vs = second ? t.v1 : t.v0;
-    CK(launch_count_below(ks, L.nnz, kGalSentinel, t.scal + 3, s));
-    CK(launch_gal_heads(L.nnz, t.scal + 3, ks, t.heads, s));
+    const double* vs = packed ? nullptr : (second ? t.v1 : t.v0);
+    CK(launch_count_below(ks, L.nnz, packed ? (sent << pshift) : kGalSentinel, t.scal + 3, s));
+    CK(launch_gal_heads(L.nnz, t.scal + 3, ks, pshift, t.heads, s));
     CK(launch_scan(t.heads, t.idx, L.nnz, t.scan_tmp, t.totals + 1, s));  // totals[1]: coarse entries
     long long tot[2] = {0, 0};
     unsigned long long nvalid = 0;
@@ -364,8 +372,8 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
     if (zc == 0) {
         CK(hipMemsetAsync(C.rp, 0, sizeof(int32_t) * (C.n + 1), s));
     } else {
-        CK(launch_gal_reduce((int64_t)nvalid, ks, vs, t.heads, t.idx, mult, (int)nc, zc, C.rp, C.col, C.w64,
-                             s));
+        CK(launch_gal_reduce((int64_t)nvalid, ks, vs, L.w64, pshift, t.heads, t.idx, mult, (int)nc, zc, C.rp,
+                             C.col, C.w64, s));
     }
     C.lanes = pick_lanes(C.nnz / (double)C.n);
     c->lv.push_back(C);

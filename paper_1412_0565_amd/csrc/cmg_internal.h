@@ -86,28 +86,32 @@ hipError_t launch_hec_label(int n, const int32_t* rootseed, const int32_t* rank,
 int64_t scan_tmp_elems(int64_t m);
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, long long* tmp, long long* total,
                        hipStream_t s);
-// Galerkin keys: a * mult + b (mult >= coarse vertex count), or
-// kGalSentinel for entries inside an aggregate (they sort last)
+// Galerkin keys: a * mult + b (mult >= coarse vertex count), or `sent`
+// (all ones in the sorted bits) for entries inside an aggregate, which
+// sort last.  With vals == nullptr the keys are packed as
+// key << pshift | fine position.
 constexpr unsigned long long kGalSentinel = 0xFFFFFFFFFFFFFFFFull;
 hipError_t launch_gal_emit(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w,
-                           const int32_t* agg, int64_t mult, unsigned long long* keys, double* vals,
-                           hipStream_t s);
+                           const int32_t* agg, int64_t mult, int pshift, unsigned long long sent,
+                           unsigned long long* keys, double* vals, hipStream_t s);
 // *out = number of keys[0..m) below `sent` (keys sorted ascending)
 hipError_t launch_count_below(const unsigned long long* keys, int64_t m, unsigned long long sent,
                               unsigned long long* out, hipStream_t s);
-// stable LSD radix sort of (key, val) pairs on the low `bits` bits; the
-// result ends in (k0, v0) or (k1, v1): returns which through *in_second.
+// stable LSD radix sort of keys (with values unless v0 == nullptr) on
+// bits [shift0, shift0 + bits); the result ends in (k0, v0) or (k1, v1):
+// returns which through *in_second.
 int64_t sort_tmp_elems(int64_t m);
 hipError_t launch_sort(unsigned long long* k0, double* v0, unsigned long long* k1, double* v1,
-                       int64_t m, int bits, int32_t* tmp_counts, long long* tmp_scan,
+                       int64_t m, int shift0, int bits, int32_t* tmp_counts, long long* tmp_scan,
                        int* in_second, hipStream_t s);
 // heads[t] = 1 where a run of equal keys starts among the first *nvalid
 // keys (read on the device), 0 elsewhere in [0, m)
 hipError_t launch_gal_heads(int64_t m, const unsigned long long* nvalid, const unsigned long long* keys,
-                            int32_t* heads, hipStream_t s);
+                            int kshift, int32_t* heads, hipStream_t s);
 hipError_t launch_gal_reduce(int64_t m, const unsigned long long* keys, const double* vals,
-                             const int32_t* heads, const int32_t* idx, int64_t mult, int nc, int64_t zc,
-                             int32_t* rp_out, int32_t* col_out, double* w_out, hipStream_t s);
+                             const double* wfine, int kshift, const int32_t* heads, const int32_t* idx,
+                             int64_t mult, int nc, int64_t zc, int32_t* rp_out, int32_t* col_out,
+                             double* w_out, hipStream_t s);
 hipError_t launch_partition(int n, int64_t nnz, const int32_t* rp, int nb, int32_t* part,
                             hipStream_t s);
 hipError_t launch_hash_probe(uint64_t seed, int level, int count, unsigned long long* out,

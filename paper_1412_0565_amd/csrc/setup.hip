@@ -372,9 +372,14 @@ __global__ void k_scan_down(const int32_t* __restrict__ in, int32_t* __restrict_
 // key of a fine entry: a * mult + b for the coarse entry (a, b), with mult
 // at least the coarse vertex count (so keys order by (a, b)); entries
 // inside an aggregate get kGalSentinel and sort last
+// Packed form (vals == nullptr, pshift > 0): the word is key << pshift | e
+// (e the fine entry's position, pshift bits), the sentinel's key part all
+// ones; sorting words on the key bits keeps positions in fine CSR order
+// within a key, and the weights are read back by position.
 template <int G>
 __global__ void k_gal_emit(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                            const double* __restrict__ w, const int32_t* __restrict__ agg, int64_t mult,
+                           int pshift, unsigned long long sent,
                            unsigned long long* __restrict__ keys, double* __restrict__ vals) {
     const int lane = threadIdx.x & (G - 1);
     const int gpb = blockDim.x / G;
@@ -384,9 +389,13 @@ __global__ void k_gal_emit(int n, const int32_t* __restrict__ rp, const int32_t*
         for (int e = e0 + lane; e < e1; e += G) {
             int b = agg[col[e]];
             unsigned long long k =
-                (a == b) ? kGalSentinel : (unsigned long long)a * (unsigned long long)mult + (unsigned long long)b;
-            keys[e] = k;
-            vals[e] = w[e];
+                (a == b) ? sent : (unsigned long long)a * (unsigned long long)mult + (unsigned long long)b;
+            if (vals) {
+                keys[e] = k;
+                vals[e] = w[e];
+            } else {
+                keys[e] = (k << pshift) | (unsigned long long)e;
+            }
         }
     }
 }
@@ -406,36 +415,41 @@ __global__ void k_count_below(const unsigned long long* __restrict__ keys, int64
 
 // run heads among the first *nvalid sorted keys (0 beyond), over m entries
 __global__ void k_gal_heads(int64_t m, const unsigned long long* __restrict__ nvalid,
-                            const unsigned long long* __restrict__ keys, int32_t* __restrict__ heads) {
+                            const unsigned long long* __restrict__ keys, int kshift,
+                            int32_t* __restrict__ heads) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m) return;
     const int64_t mv = (int64_t)*nvalid;
-    heads[t] = (t < mv && (t == 0 || keys[t] != keys[t - 1])) ? 1 : 0;
+    heads[t] = (t < mv && (t == 0 || (keys[t] >> kshift) != (keys[t - 1] >> kshift))) ? 1 : 0;
 }
 
 // Each run of equal keys is summed in order (fine CSR order); the first
 // entry of a run writes the coarse entry and fills the row pointers of the
 // coarse rows that start there.
+// vals == nullptr: packed words (key << kshift | fine position), weights
+// read from the fine level's w by position
 __global__ void k_gal_reduce(int64_t m, const unsigned long long* __restrict__ keys,
-                             const double* __restrict__ vals, const int32_t* __restrict__ heads,
+                             const double* __restrict__ vals, const double* __restrict__ wfine,
+                             int kshift, const int32_t* __restrict__ heads,
                              const int32_t* __restrict__ idx, int64_t mult, int nc, int64_t zc,
                              int32_t* __restrict__ rp, int32_t* __restrict__ col,
                              double* __restrict__ w) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m || !heads[t]) return;
-    unsigned long long k = keys[t];
+    const unsigned long long pmask = (kshift > 0) ? (~0ull >> (64 - kshift)) : 0ull;
+    unsigned long long k = keys[t] >> kshift;
     int row = (int)(k / (unsigned long long)mult);
     int c = (int)(k - (unsigned long long)row * (unsigned long long)mult);
-    double s = vals[t];
+    double s = vals ? vals[t] : wfine[keys[t] & pmask];
     int64_t u = t + 1;
-    while (u < m && keys[u] == k) {
-        s += vals[u];
+    while (u < m && (keys[u] >> kshift) == k) {
+        s += vals ? vals[u] : wfine[keys[u] & pmask];
         ++u;
     }
     int32_t o = idx[t];
     col[o] = c;
     w[o] = s;
-    int prow = (t == 0) ? -1 : (int)(keys[t - 1] / (unsigned long long)mult);
+    int prow = (t == 0) ? -1 : (int)((keys[t - 1] >> kshift) / (unsigned long long)mult);
     for (int r = prow + 1; r <= row; ++r) rp[r] = o;
     if (u == m) {
         for (int r = row + 1; r <= nc; ++r) rp[r] = (int32_t)zc;
@@ -464,6 +478,7 @@ __global__ void k_sort_hist(const unsigned long long* __restrict__ keys, int64_t
 // Stable scatter: elements of a tile are ranked in index order; within a
 // wave by ballot match on the 8 digit bits, across waves and rounds through
 // per-digit running counts in LDS.
+template <bool VALS>
 __global__ void k_sort_scatter(const unsigned long long* __restrict__ kin,
                                const double* __restrict__ vin, unsigned long long* __restrict__ kout,
                                double* __restrict__ vout, int64_t m, int shift,
@@ -505,7 +520,7 @@ __global__ void k_sort_scatter(const unsigned long long* __restrict__ kin,
         if (valid) {
             int64_t pos = (int64_t)base[d] + wcnt[wv][d] + rank;
             kout[pos] = key;
-            vout[pos] = vin[i];
+            if constexpr (VALS) vout[pos] = vin[i];
         }
         __syncthreads();
     }
@@ -648,14 +663,15 @@ hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, long long* tm
 }
 
 hipError_t launch_gal_emit(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w,
-                           const int32_t* agg, int64_t mult, unsigned long long* keys, double* vals,
-                           hipStream_t s) {
+                           const int32_t* agg, int64_t mult, int pshift, unsigned long long sent,
+                           unsigned long long* keys, double* vals, hipStream_t s) {
     int gpb = kBlk / lanes;
     unsigned nb = (unsigned)std::min<int64_t>(nblocks(n, gpb), 65536);
     switch (lanes) {
 #define CMG_GE(G)                                                                                  \
     case G:                                                                                        \
-        hipLaunchKernelGGL(k_gal_emit<G>, dim3(nb), dim3(kBlk), 0, s, n, rp, col, w, agg, mult, keys, \
+        hipLaunchKernelGGL(k_gal_emit<G>, dim3(nb), dim3(kBlk), 0, s, n, rp, col, w, agg, mult, pshift, \
+                           sent, keys, \
                            vals);                                                                  \
         break;
         CMG_GE(1) CMG_GE(2) CMG_GE(4) CMG_GE(8) CMG_GE(16) CMG_GE(32) CMG_GE(64)
@@ -669,8 +685,8 @@ hipError_t launch_gal_emit(int n, int lanes, const int32_t* rp, const int32_t* c
 int64_t sort_tmp_elems(int64_t m) { return 256 * ((m + kSortTile - 1) / kSortTile) + 1; }
 
 hipError_t launch_sort(unsigned long long* k0, double* v0, unsigned long long* k1, double* v1,
-                       int64_t m, int bits, int32_t* tmp_counts, long long* tmp_scan, int* in_second,
-                       hipStream_t s) {
+                       int64_t m, int shift0, int bits, int32_t* tmp_counts, long long* tmp_scan,
+                       int* in_second, hipStream_t s) {
     *in_second = 0;
     if (m <= 1 || bits <= 0) return hipSuccess;
     int nb = (int)((m + kSortTile - 1) / kSortTile);
@@ -681,12 +697,16 @@ hipError_t launch_sort(unsigned long long* k0, double* v0, unsigned long long* k
     double* vout = v1;
     long long* scan_tmp = tmp_scan;
     long long* scan_total = tmp_scan + scan_tmp_elems(ncounts);
-    for (int shift = 0; shift < bits; shift += 8) {
+    for (int shift = shift0; shift < shift0 + bits; shift += 8) {
         hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(kBlk), 0, s, kin, m, shift, tmp_counts, nb);
         hipError_t e = launch_scan(tmp_counts, tmp_counts, ncounts, scan_tmp, scan_total, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(kBlk), 0, s, kin, vin, kout, vout, m, shift,
-                           tmp_counts, nb);
+        if (v0)
+            hipLaunchKernelGGL(k_sort_scatter<true>, dim3(nb), dim3(kBlk), 0, s, kin, vin, kout, vout, m,
+                               shift, tmp_counts, nb);
+        else
+            hipLaunchKernelGGL(k_sort_scatter<false>, dim3(nb), dim3(kBlk), 0, s, kin, vin, kout, vout, m,
+                               shift, tmp_counts, nb);
         std::swap(kin, kout);
         std::swap(vin, vout);
         *in_second ^= 1;
@@ -701,18 +721,19 @@ hipError_t launch_count_below(const unsigned long long* keys, int64_t m, unsigne
 }
 
 hipError_t launch_gal_heads(int64_t m, const unsigned long long* nvalid, const unsigned long long* keys,
-                            int32_t* heads, hipStream_t s) {
+                            int kshift, int32_t* heads, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gal_heads, dim3(nblocks(m, kBlk)), dim3(kBlk), 0, s, m, nvalid, keys, heads);
+    hipLaunchKernelGGL(k_gal_heads, dim3(nblocks(m, kBlk)), dim3(kBlk), 0, s, m, nvalid, keys, kshift, heads);
     return hipGetLastError();
 }
 
 hipError_t launch_gal_reduce(int64_t m, const unsigned long long* keys, const double* vals,
-                             const int32_t* heads, const int32_t* idx, int64_t mult, int nc, int64_t zc,
-                             int32_t* rp_out, int32_t* col_out, double* w_out, hipStream_t s) {
+                             const double* wfine, int kshift, const int32_t* heads, const int32_t* idx,
+                             int64_t mult, int nc, int64_t zc, int32_t* rp_out, int32_t* col_out,
+                             double* w_out, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gal_reduce, dim3(nblocks(m, kBlk)), dim3(kBlk), 0, s, m, keys, vals, heads, idx,
-                       mult, nc, zc, rp_out, col_out, w_out);
+    hipLaunchKernelGGL(k_gal_reduce, dim3(nblocks(m, kBlk)), dim3(kBlk), 0, s, m, keys, vals, wfine, kshift,
+                       heads, idx, mult, nc, zc, rp_out, col_out, w_out);
     return hipGetLastError();
 }
 

@@ -55,13 +55,14 @@ struct HostLevel {
     void* buf0 = nullptr;
     void* buf1 = nullptr;
     int32_t* part = nullptr;
+    int step = 0;              // 1: refined with one launch per PI step
+    int fgrid = 0;             // level 0 in step mode: finishing pass grid
+    int32_t* fpart = nullptr;  // ... and its row split
     int k = 0;
     double margin = 0.0;
     double pi_ms = 0.0;
 };
 
-// Lanes per row for the row-group kernels: about five entries per lane
-// (two lanes per row on 6-10-regular meshes measured best on gfx950).
 // Lanes per row: about 3 entries per lane (measured best for degree 6
 // to 16 meshes and geometric graphs: fewer lanes leave the loads of a row
 // serialised, more leave lanes idle).
@@ -146,6 +147,12 @@ struct cmg_ctx {
     double setup_ms = 0.0;
     cmg_stats last{};
     std::vector<hipEvent_t> events;
+    // levels refined with one launch per step
+    StepJob* d_step = nullptr;  // [J+1]
+    StepCtl* d_ctl = nullptr;
+    double* d_part = nullptr;   // 4 partial sums per workgroup
+    int* h_flags = nullptr;     // pinned: done flag after each chunk of steps
+    std::vector<hipEvent_t> chunk_ev;
 
     void* dalloc(size_t bytes) {
         void* p = alloc.alloc(bytes == 0 ? 8 : bytes, (void*)stream, alloc.user);
@@ -165,6 +172,8 @@ struct cmg_ctx {
         if (stream || true) (void)hipStreamSynchronize(stream);
         for (void* p : owned) alloc.free(p, (void*)stream, alloc.user);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (hipEvent_t e : chunk_ev) (void)hipEventDestroy(e);
+        if (h_flags) (void)hipHostFree(h_flags);
     }
 };
 
@@ -540,6 +549,19 @@ int64_t step_bytes(const HostLevel& L) {
     return 4 * ((int64_t)L.n + 1) + L.nnz * (4 + sv) + 2 * sv * (int64_t)L.n;
 }
 
+// Levels at depth >= kStepModeDepth whose PI step streams at least
+// kStepModeBytes are refined with one launch per step (kernel boundaries
+// and a one-workgroup reduction in place of the grid barrier), with a
+// workgroup of kStepBlock threads per kStepWork rows + entries.  A step
+// there costs less than with the barrier, but the level pays about 70-100
+// us of fixed launches and host checks, which only levels with many steps
+// recover; in a cascadic cycle those are the coarser ones.
+constexpr int64_t kStepModeBytes = (int64_t)16 << 20;
+constexpr int kStepModeDepth = 2;
+constexpr int64_t kStepWork = 4096;
+constexpr int kMaxChunks = 256;
+constexpr int kChunkEvents = 16;
+
 // Default workgroup count: about 2k rows+entries per workgroup (short
 // per-group latency chains on mid-size levels), a multiple of 8, at most
 // 3 per CU for levels whose step fits the 256 MB last-level cache (there
@@ -702,6 +724,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
     c->d_bcast = (GridSlot*)c->dalloc(kBcastBytes);
     if (!c->d_bcast) return CMG_E_OOM;
     CK(launch_reset_sync(c->d_sync, c->d_slots, c->nslots, c->d_bcast, c->stream));
+    int max_step_grid = 0;
     for (int j = 0; j <= J; ++j) {
         HostLevel& L = c->lv[j];
         L.in_block = (j >= c->block_lo && j <= top) ? 1 : 0;
@@ -720,12 +743,34 @@ cmg_status build_refine_plan(cmg_ctx* c) {
             CK(launch_to_f32(L.nnz, L.w64, L.w32, c->stream));
         }
         L.grid = default_grid(L, j, ncu);
-        if (o.autotune && !L.in_block && j <= top) {
+        L.step = (!L.in_block && j <= top && j >= kStepModeDepth && L.variant != 2 &&
+                  step_bytes(L) >= kStepModeBytes) ? 1 : 0;
+        if (o.autotune && !L.in_block && !L.step && j <= top) {
             cmg_status st = tune_level(c, j, maxgrid);
             if (st != CMG_OK) return st;
         }
+        if (L.step) {
+            if (j == 0) {  // the finishing pass keeps a co-resident grid
+                L.fgrid = L.grid;
+                ALLOC(L.fpart, int32_t, L.fgrid + 1);
+                CK(launch_partition(L.n, L.nnz, L.rp, L.fgrid, L.fpart, c->stream));
+            }
+            const int64_t nb = ((int64_t)L.n + L.nnz + kStepWork - 1) / kStepWork;
+            L.grid = (int)std::min<int64_t>(std::max<int64_t>(nb, 8), 65535);
+            max_step_grid = std::max(max_step_grid, L.grid);
+        }
         ALLOC(L.part, int32_t, L.grid + 1);
         CK(launch_partition(L.n, L.nnz, L.rp, L.grid, L.part, c->stream));
+    }
+    if (max_step_grid > 0) {
+        ALLOC(c->d_ctl, StepCtl, 1);
+        ALLOC(c->d_part, double, 4 * (size_t)max_step_grid);
+        ALLOC(c->d_step, StepJob, J + 1);
+        if (!c->h_flags) {
+            CK(hipHostMalloc((void**)&c->h_flags, sizeof(int) * kMaxChunks, hipHostMallocDefault));
+            c->chunk_ev.resize(kChunkEvents);
+            for (auto& e : c->chunk_ev) CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        }
     }
     std::vector<LevelDev> ld(J + 1);
     for (int j = 0; j <= J; ++j) ld[j] = level_dev(c->lv[j]);
@@ -768,6 +813,10 @@ cmg_status build_refine_plan(cmg_ctx* c) {
     {
         GridJob g{};
         g.L = ld[0];
+        if (c->lv[0].step) {
+            g.L.grid = c->lv[0].fgrid;
+            g.L.part = c->lv[0].fpart;
+        }
         g.C = ld[0];
         g.st = nullptr;
         g.stc = c->d_st;
@@ -785,6 +834,24 @@ cmg_status build_refine_plan(cmg_ctx* c) {
     c->h_jobs = jobs;
     ALLOC(c->d_jobs, GridJob, J + 2);
     CK(hipMemcpyAsync(c->d_jobs, jobs.data(), sizeof(GridJob) * (J + 2), hipMemcpyHostToDevice, c->stream));
+    if (c->d_step) {
+        std::vector<StepJob> sj(J + 1);
+        for (int j = 0; j <= J; ++j) {
+            StepJob t{};
+            t.L = ld[j];
+            t.C = (j < J) ? ld[j + 1] : ld[j];
+            t.stc = (j < J) ? c->d_st + j + 1 : nullptr;
+            t.st = c->d_st + j;
+            t.ctl = c->d_ctl;
+            t.part = c->d_part;
+            t.tol = o.tol;
+            t.seed = o.seed;
+            t.maxit = o.max_iters_per_level;
+            t.uniform = (j == J) ? 1 : 0;
+            sj[j] = t;
+        }
+        CK(hipMemcpyAsync(c->d_step, sj.data(), sizeof(StepJob) * (J + 1), hipMemcpyHostToDevice, c->stream));
+    }
     c->top = top;
     if (c->coarse_dense) {
         CoarseJob cj{};
@@ -1000,6 +1067,45 @@ cmg_status finalize(cmg_ctx* c, double t0, bool timed, double* lambda, cmg_stats
     return status;
 }
 
+// A level refined with one launch per PI step.  The step count is decided
+// on the device, so steps go out in chunks (8, 16, 32, ...); once the first
+// chunk is known not to suffice, one chunk stays queued behind the one
+// whose done flag the host waits for.  Steps launched after the stopping
+// test passed return at once.
+cmg_status run_step_level(cmg_ctx* c, int j, hipStream_t s) {
+    const HostLevel& L = c->lv[j];
+    const StepJob* job = c->d_step + j;
+    const int kind = job_kind(L.variant, L.lanes, L.fp32);
+    const int maxit = c->opt.max_iters_per_level;
+    CK(launch_step_begin(job, L.grid, kind, s));
+    int launched = 0, chunks = 0, chunk = 8;
+    auto enqueue = [&]() -> cmg_status {
+        if (chunks >= kMaxChunks) return CMG_E_DEVICE;
+        const int q = std::min(chunk, maxit - launched);
+        for (int i = 0; i < q; ++i) CK(launch_step_pi(job, L.grid, kind, s));
+        launched += q;
+        CK(hipMemcpyAsync(c->h_flags + chunks, &c->d_ctl->done, sizeof(int), hipMemcpyDeviceToHost, s));
+        CK(hipEventRecord(c->chunk_ev[chunks % kChunkEvents], s));
+        ++chunks;
+        chunk = std::min(chunk * 2, 1024);
+        return CMG_OK;
+    };
+    // the first chunk alone (a level that stops within it wastes no more);
+    // after that one chunk stays queued behind the one waited for
+    cmg_status st = enqueue();
+    if (st != CMG_OK) return st;
+    for (int w = 0;; ++w) {
+        CK(hipEventSynchronize(c->chunk_ev[w % kChunkEvents]));
+        if (c->h_flags[w]) break;  // done at or before chunk w
+        if (w + 1 == chunks && launched >= maxit) break;
+        for (int more = (w == 0) ? 2 : 1; more > 0 && launched < maxit; --more) {
+            st = enqueue();
+            if (st != CMG_OK) return st;
+        }
+    }
+    return CMG_OK;
+}
+
 cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where, cmg_stats* stats) {
     const double t0 = now_ms();
     hipStream_t s = c->stream;
@@ -1008,11 +1114,19 @@ cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where,
     if (c->d_bjob) CK(launch_block_jobs(c->d_bjob, 1, s));
     // grid levels: one cooperative launch per level
     for (int j = std::min(c->top, c->block_lo - 1); j >= 0; --j) {
+        const HostLevel& L = c->lv[j];
         CK(hipEventRecord(c->events[2 * j], s));
-        CK(launch_refine_jobs(c->d_jobs + j, 1, c->lv[j].grid, job_kind(c->lv[j].variant, c->lv[j].lanes, c->lv[j].fp32), s));
+        if (L.step) {
+            cmg_status st = run_step_level(c, j, s);
+            if (st != CMG_OK) return st;
+        } else {
+            CK(launch_refine_jobs(c->d_jobs + j, 1, L.grid, job_kind(L.variant, L.lanes, L.fp32), s));
+        }
         CK(hipEventRecord(c->events[2 * j + 1], s));
     }
-    CK(launch_finish_jobs(c->d_jobs + J + 1, 1, c->lv[0].grid, job_kind(c->lv[0].variant, c->lv[0].lanes, c->lv[0].fp32), s));
+    const HostLevel& L0 = c->lv[0];
+    CK(launch_finish_jobs(c->d_jobs + J + 1, 1, L0.step ? L0.fgrid : L0.grid, job_kind(L0.variant, L0.lanes, L0.fp32),
+                          s));
     cmg_status st = enqueue_readback(c, x, where, s);
     if (st != CMG_OK) return st;
     CK(hipStreamSynchronize(s));
@@ -1071,15 +1185,21 @@ cmg_status batch_impl(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
             }
         }
     };
+    // per round: its packed launches, then the step-by-step levels
+    std::vector<size_t> round_end;
+    std::vector<std::vector<std::pair<int, int>>> step_runs(maxrounds);
     for (int r = 0; r < maxrounds; ++r) {
         std::vector<GridJob> round;
         for (int i = 0; i < count; ++i) {
             cmg_ctx* c = hs[i];
             const int lo = std::min(c->top, c->block_lo - 1);  // coarsest grid level
             const int j = lo - r;
-            if (lo >= 0 && j >= 0) round.push_back(c->h_jobs[j]);
+            if (lo < 0 || j < 0) continue;
+            if (c->lv[j].step) step_runs[r].push_back({i, j});
+            else round.push_back(c->h_jobs[j]);
         }
         pack(round, 0);
+        round_end.push_back(launches.size());
     }
     {
         std::vector<GridJob> round;
@@ -1103,10 +1223,19 @@ cmg_status batch_impl(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
     hipError_t e = hipMemcpyAsync(d, h.data(), bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !cj.empty()) e = launch_coarse_jobs(d_cj, (int)cj.size(), s);
     if (e == hipSuccess && !bj.empty()) e = launch_block_jobs(d_bj, (int)bj.size(), s);
-    for (size_t q = 0; e == hipSuccess && q < launches.size(); ++q) {
-        const GridJob* jp = d_gj + launches[q].first;
-        e = launch_kind[q] ? launch_finish_jobs(jp, launches[q].second, launch_blocks[q], launch_jk[q], s)
-                           : launch_refine_jobs(jp, launches[q].second, launch_blocks[q], launch_jk[q], s);
+    size_t q = 0;
+    for (int r = 0; r <= maxrounds && e == hipSuccess && status == CMG_OK; ++r) {
+        const size_t qend = (r < maxrounds) ? round_end[r] : launches.size();
+        for (; e == hipSuccess && q < qend; ++q) {
+            const GridJob* jp = d_gj + launches[q].first;
+            e = launch_kind[q] ? launch_finish_jobs(jp, launches[q].second, launch_blocks[q], launch_jk[q], s)
+                               : launch_refine_jobs(jp, launches[q].second, launch_blocks[q], launch_jk[q], s);
+        }
+        if (r < maxrounds)
+            for (const auto& sr : step_runs[r]) {
+                if (e != hipSuccess || status != CMG_OK) break;
+                status = run_step_level(hs[sr.first], sr.second, s);
+            }
     }
     for (int i = 0; e == hipSuccess && i < count && status == CMG_OK; ++i)
         status = enqueue_readback(hs[i], xs ? xs[i] : nullptr, where, s);

@@ -233,6 +233,28 @@ struct GridJob {
 // at once; no workgroup waits for another.
 constexpr int32_t kResidencyTag = -100;
 
+// Large levels refined with one launch per power-iteration step: the
+// running state between the launches (device written).
+struct StepCtl {
+    double mu, s;         // current vector = (buf[cur] - mu) * s
+    double pmu, ps;       // the same for the previous vector
+    double utv;
+    int32_t k, cur, done, hit;
+};
+
+// One large level refined step by step.
+struct StepJob {
+    LevelDev L;              // the level (L.grid workgroups, L.part row split)
+    LevelDev C;              // next coarser level (prolongation source)
+    const LevelState* stc;   // state of C
+    LevelState* st;          // written when the level is done
+    StepCtl* ctl;
+    double* part;            // per-workgroup partial sums, 4 per workgroup
+    double tol;
+    uint64_t seed;
+    int32_t maxit, uniform;
+};
+
 // Coarse levels jhi .. jlo of one graph, refined by one workgroup.
 struct BlockJob {
     const LevelDev* lv;

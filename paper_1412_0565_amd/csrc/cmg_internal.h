@@ -137,6 +137,14 @@ hipError_t launch_finish_jobs(const GridJob* jobs, int njobs, int nblocks, int k
 // zero the barrier state and the slots (2 * nslots; at setup, and after an abort)
 hipError_t launch_reset_sync(GridSync* gs, GridSlot* slots, int nslots, GridSlot* bcast, hipStream_t s);
 
+// Large levels, one launch per step (rows traversal; kind as job_kind).
+// Sequence: step_begin (prolongation, mean and norm), then step_pi per
+// power-iteration step; a step launched after the stopping test passed
+// does nothing.  job points to device memory.
+hipError_t launch_step_begin(const StepJob* job, int nblocks, int kind, hipStream_t s);
+hipError_t launch_step_pi(const StepJob* job, int nblocks, int kind, hipStream_t s);
+constexpr int kStepBlock = 512;
+
 constexpr int kGridBlock = 512;
 constexpr int kBlockKernelThreads = 1024;
 constexpr int kBlockLdsMax = 144 * 1024;  // LDS image budget of the single-workgroup kernel

@@ -1274,6 +1274,178 @@ __global__ void __launch_bounds__(kGridBlock) k_finish_jobs(const GridJob* __res
     finish_level<TRAV>(J, c, red, sh);
 }
 
+// ------------------------------------------ large levels: a launch per step
+//
+// The same arithmetic as refine_level, with the grid-wide sums formed by a
+// one-workgroup kernel after each launch instead of a grid barrier inside
+// it: each workgroup posts its block sums, the check kernel adds the posts
+// in workgroup order, applies the stopping test and leaves (mu, s) for the
+// next step.  A step launched after the test passed returns at once.
+
+constexpr int kCheckThreads = 1024;
+
+template <int NV>
+__device__ __forceinline__ void post_part(double (&v)[NV], double* red, double* part) {
+    block_sum<NV>(v, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) part[4 * (size_t)blockIdx.x + q] = v[q];
+    }
+}
+
+// fixed-order total of the posts of nb workgroups, in every thread
+template <int NV>
+__device__ __forceinline__ void sum_parts(const double* part, int nb, double (&v)[NV], double* red) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] += part[4 * (size_t)b + q];
+    }
+    block_sum<NV>(v, red);
+}
+
+// prolongation (or the hashed uniform start) into buf0; posts its sum
+template <typename T>
+__global__ void __launch_bounds__(kStepBlock) k_step_prolong(const StepJob* __restrict__ jp) {
+    __shared__ double red[16 * 5 + 8];
+    const StepJob J = *jp;
+    const LevelDev& L = J.L;
+    const int r0 = L.part[blockIdx.x], r1 = L.part[blockIdx.x + 1];
+    T* b0 = (T*)L.buf0;
+    double sum[1] = {0.0};
+    if (J.uniform) {
+        for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+            const T v = (T)(hashed_uniform(J.seed, i) - 0.5);
+            b0[i] = v;
+            sum[0] += (double)v;
+        }
+    } else {
+        const LevelState cst = *J.stc;
+        const void* cb = cst.fin ? J.C.buf1 : J.C.buf0;
+        for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+            const T v = (T)((ld_any(cb, J.C.fp32, L.agg[i]) - cst.mu) * cst.s);
+            b0[i] = v;
+            sum[0] += (double)v;
+        }
+    }
+    post_part<1>(sum, red, J.part);
+}
+
+// mean of the start vector
+__global__ void __launch_bounds__(kCheckThreads) k_step_mean(const StepJob* __restrict__ jp, int nb) {
+    __shared__ double red[16 * 5 + 8];
+    const StepJob J = *jp;
+    double v[1];
+    sum_parts<1>(J.part, nb, v, red);
+    if (threadIdx.x == 0) J.ctl->mu = v[0] / (double)J.L.n;
+}
+
+// squared distance of the start vector from its mean
+template <typename T>
+__global__ void __launch_bounds__(kStepBlock) k_step_sumsq(const StepJob* __restrict__ jp) {
+    __shared__ double red[16 * 5 + 8];
+    const StepJob J = *jp;
+    const LevelDev& L = J.L;
+    const int r0 = L.part[blockIdx.x], r1 = L.part[blockIdx.x + 1];
+    const T* b0 = (const T*)L.buf0;
+    const double mu = J.ctl->mu;
+    double ss[1] = {0.0};
+    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        const double d = (double)b0[i] - mu;
+        ss[0] += d * d;
+    }
+    post_part<1>(ss, red, J.part);
+}
+
+// normalisation of the start vector; arms the step loop
+__global__ void __launch_bounds__(kCheckThreads) k_step_norm(const StepJob* __restrict__ jp, int nb) {
+    __shared__ double red[16 * 5 + 8];
+    const StepJob J = *jp;
+    double v[1];
+    sum_parts<1>(J.part, nb, v, red);
+    if (threadIdx.x == 0) {
+        StepCtl* c = J.ctl;
+        const double mu = c->mu;
+        const double s = 1.0 / sqrt(v[0]);
+        c->s = s;
+        c->pmu = mu;
+        c->ps = s;
+        c->utv = 0.0;
+        c->k = 0;
+        c->cur = 0;
+        c->done = 0;
+        c->hit = 0;
+    }
+}
+
+// one power-iteration step: buf[cur] -> buf[cur ^ 1], posts {y, y^2, y v, v}
+template <int G, typename T>
+__global__ void __launch_bounds__(kStepBlock) k_step_spmv(const StepJob* __restrict__ jp) {
+    __shared__ double red[16 * 5 + 8];
+    const StepJob J = *jp;
+    const StepCtl c = *J.ctl;
+    if (c.done) return;
+    const LevelDev& L = J.L;
+    const int r0 = L.part[blockIdx.x], r1 = L.part[blockIdx.x + 1];
+    PiOp<T> op;
+    op.col = L.col;
+    op.wv = (const T*)(sizeof(T) == 4 ? (const void*)L.w32 : (const void*)L.w64);
+    op.g = L.g;
+    op.win = (const T*)(c.cur ? L.buf1 : L.buf0);
+    op.wout = (T*)(c.cur ? L.buf0 : L.buf1);
+    op.mu = c.mu;
+    op.s = c.s;
+    op.acc[0] = op.acc[1] = op.acc[2] = op.acc[3] = 0.0;
+    drive_rows<G>(L.rp, r0, r1, op);
+    post_part<4>(op.acc, red, J.part);
+}
+
+// sums of the step, stopping test, state for the next step; writes the
+// level state when the level is done
+__global__ void __launch_bounds__(kCheckThreads) k_step_check(const StepJob* __restrict__ jp, int nb) {
+    __shared__ double red[16 * 5 + 8];
+    const StepJob J = *jp;
+    if (J.ctl->done) return;
+    double acc[4];
+    sum_parts<4>(J.part, nb, acc, red);
+    if (threadIdx.x == 0) {
+        StepCtl c = *J.ctl;
+        const double n = (double)J.L.n;
+        const double mu2 = acc[0] / n;
+        const double s2 = 1.0 / sqrt(acc[1] - acc[0] * mu2);
+        c.utv = s2 * (acc[2] - mu2 * acc[3]);
+        ++c.k;
+        c.cur ^= 1;
+        c.pmu = c.mu;
+        c.ps = c.s;
+        c.mu = mu2;
+        c.s = s2;
+        if (!(c.utv < 1.0 - J.tol)) {
+            c.done = 1;
+        } else if (c.k >= J.maxit) {
+            c.done = 1;
+            c.hit = 1;
+        }
+        *J.ctl = c;
+        if (c.done) {
+            LevelState o;
+            o.mu = c.mu;
+            o.s = c.s;
+            o.mu_prev = c.pmu;
+            o.s_prev = c.ps;
+            o.utv = c.utv;
+            o.margin = c.utv - (1.0 - J.tol);
+            o.fin = c.cur;
+            o.k = c.k;
+            o.maxit = c.hit;
+            o.err = 0;
+            o.ticks = 0;
+            *J.st = o;
+        }
+    }
+}
+
 }  // namespace
 
 // ================================================================ launchers
@@ -1430,6 +1602,44 @@ hipError_t launch_refine_jobs(const GridJob* jobs, int njobs, int nblocks, int k
 hipError_t launch_finish_jobs(const GridJob* jobs, int njobs, int nblocks, int kind, hipStream_t s) {
     void* args[] = {(void*)&jobs, &njobs};
     return hipLaunchCooperativeKernel(finish_kernel(kind), dim3(nblocks), dim3(kGridBlock), args, 0, s);
+}
+
+hipError_t launch_step_begin(const StepJob* job, int nblocks, int kind, hipStream_t s) {
+    if (kind & 1) {
+        hipLaunchKernelGGL(k_step_prolong<float>, dim3(nblocks), dim3(kStepBlock), 0, s, job);
+        hipLaunchKernelGGL(k_step_mean, dim3(1), dim3(kCheckThreads), 0, s, job, nblocks);
+        hipLaunchKernelGGL(k_step_sumsq<float>, dim3(nblocks), dim3(kStepBlock), 0, s, job);
+    } else {
+        hipLaunchKernelGGL(k_step_prolong<double>, dim3(nblocks), dim3(kStepBlock), 0, s, job);
+        hipLaunchKernelGGL(k_step_mean, dim3(1), dim3(kCheckThreads), 0, s, job, nblocks);
+        hipLaunchKernelGGL(k_step_sumsq<double>, dim3(nblocks), dim3(kStepBlock), 0, s, job);
+    }
+    hipLaunchKernelGGL(k_step_norm, dim3(1), dim3(kCheckThreads), 0, s, job, nblocks);
+    return hipGetLastError();
+}
+
+namespace {
+template <int G>
+void step_spmv_g(const StepJob* job, int nblocks, int fp32, hipStream_t s) {
+    if (fp32) hipLaunchKernelGGL((k_step_spmv<G, float>), dim3(nblocks), dim3(kStepBlock), 0, s, job);
+    else hipLaunchKernelGGL((k_step_spmv<G, double>), dim3(nblocks), dim3(kStepBlock), 0, s, job);
+}
+}  // namespace
+
+hipError_t launch_step_pi(const StepJob* job, int nblocks, int kind, hipStream_t s) {
+    const int fp32 = kind & 1;
+    switch (kind >> 1) {
+        case 1: step_spmv_g<1>(job, nblocks, fp32, s); break;
+        case 2: step_spmv_g<2>(job, nblocks, fp32, s); break;
+        case 3: step_spmv_g<4>(job, nblocks, fp32, s); break;
+        case 4: step_spmv_g<8>(job, nblocks, fp32, s); break;
+        case 5: step_spmv_g<16>(job, nblocks, fp32, s); break;
+        case 6: step_spmv_g<32>(job, nblocks, fp32, s); break;
+        case 7: step_spmv_g<64>(job, nblocks, fp32, s); break;
+        default: return hipErrorInvalidValue;  // the merge path has no step form
+    }
+    hipLaunchKernelGGL(k_step_check, dim3(1), dim3(kCheckThreads), 0, s, job, nblocks);
+    return hipGetLastError();
 }
 
 hipError_t launch_reset_sync(GridSync* gs, GridSlot* slots, int nslots, GridSlot* bcast, hipStream_t s) {

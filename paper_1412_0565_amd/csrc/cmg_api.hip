@@ -559,7 +559,7 @@ int64_t step_bytes(const HostLevel& L) {
 constexpr int64_t kStepModeBytes = (int64_t)16 << 20;
 constexpr int kStepModeDepth = 2;
 constexpr int64_t kStepWork = 4096;
-constexpr int kMaxChunks = 256;
+constexpr int kStepChunk = 8;
 constexpr int kChunkEvents = 16;
 
 // Default workgroup count: about 2k rows+entries per workgroup (short
@@ -767,7 +767,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         ALLOC(c->d_part, double, 4 * (size_t)max_step_grid);
         ALLOC(c->d_step, StepJob, J + 1);
         if (!c->h_flags) {
-            CK(hipHostMalloc((void**)&c->h_flags, sizeof(int) * kMaxChunks, hipHostMallocDefault));
+            CK(hipHostMalloc((void**)&c->h_flags, sizeof(int) * kChunkEvents, hipHostMallocDefault));
             c->chunk_ev.resize(kChunkEvents);
             for (auto& e : c->chunk_ev) CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         }
@@ -1068,37 +1068,40 @@ cmg_status finalize(cmg_ctx* c, double t0, bool timed, double* lambda, cmg_stats
 }
 
 // A level refined with one launch per PI step.  The step count is decided
-// on the device, so steps go out in chunks (8, 16, 32, ...); once the first
-// chunk is known not to suffice, one chunk stays queued behind the one
-// whose done flag the host waits for.  Steps launched after the stopping
-// test passed return at once.
+// on the device, so steps go out in chunks of kStepChunk with one chunk
+// queued behind the one whose done flag the host waits for.  Steps
+// launched after the stopping test passed return at once.
 cmg_status run_step_level(cmg_ctx* c, int j, hipStream_t s) {
     const HostLevel& L = c->lv[j];
     const StepJob* job = c->d_step + j;
     const int kind = job_kind(L.variant, L.lanes, L.fp32);
     const int maxit = c->opt.max_iters_per_level;
     CK(launch_step_begin(job, L.grid, kind, s));
-    int launched = 0, chunks = 0, chunk = 8;
+    int launched = 0, chunks = 0;
+    const int chunk = kStepChunk;
     auto enqueue = [&]() -> cmg_status {
-        if (chunks >= kMaxChunks) return CMG_E_DEVICE;
         const int q = std::min(chunk, maxit - launched);
         for (int i = 0; i < q; ++i) CK(launch_step_pi(job, L.grid, kind, s));
         launched += q;
-        CK(hipMemcpyAsync(c->h_flags + chunks, &c->d_ctl->done, sizeof(int), hipMemcpyDeviceToHost, s));
+        CK(hipMemcpyAsync(c->h_flags + chunks % kChunkEvents, &c->d_ctl->done, sizeof(int), hipMemcpyDeviceToHost, s));
         CK(hipEventRecord(c->chunk_ev[chunks % kChunkEvents], s));
         ++chunks;
-        chunk = std::min(chunk * 2, 1024);
         return CMG_OK;
     };
-    // the first chunk alone (a level that stops within it wastes no more);
-    // after that one chunk stays queued behind the one waited for
+    // two chunks queued; each one the host sees finish without the stopping
+    // test passed is replaced by another, so the device never waits for the
+    // host and at most two chunks of steps run empty
     cmg_status st = enqueue();
     if (st != CMG_OK) return st;
+    if (launched < maxit) {
+        st = enqueue();
+        if (st != CMG_OK) return st;
+    }
     for (int w = 0;; ++w) {
         CK(hipEventSynchronize(c->chunk_ev[w % kChunkEvents]));
-        if (c->h_flags[w]) break;  // done at or before chunk w
+        if (c->h_flags[w % kChunkEvents]) break;  // done at or before chunk w
         if (w + 1 == chunks && launched >= maxit) break;
-        for (int more = (w == 0) ? 2 : 1; more > 0 && launched < maxit; --more) {
+        if (launched < maxit) {
             st = enqueue();
             if (st != CMG_OK) return st;
         }

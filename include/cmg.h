@@ -105,6 +105,10 @@ typedef struct {
                                     choices are cached per process by level shape, so results
                                     are reproducible within a process but may differ (within
                                     rounding) between processes.  0 (default): fixed rules. */
+    int32_t block_regs;          /* levels refined inside one workgroup: 0 (default) holds each
+                                    level's rows in registers for all its PI steps where a
+                                    layout fits (rows of at most 64 entries); -1 always reads
+                                    the CSR arrays.  Both give the same lambda to rounding. */
 } cmg_options;
 
 /* Per-level information (available after cmg_setup; PI fields after
@@ -123,6 +127,8 @@ typedef struct {
     int32_t grid;        /* workgroups of the grid kernel */
     double pi_ms;        /* device time of this level's refinement launch (grid levels) */
     double bytes_per_iter; /* algorithmic bytes of one PI step: 4(n+1)+nnz(4+s_v)+2 s_x n */
+    int32_t block_waves;   /* in_block: wavefronts running the PI steps (0: all) */
+    int32_t block_regs;    /* in_block: rows per lane group held in registers (0: CSR reads) */
 } cmg_level_stats;
 
 typedef struct {

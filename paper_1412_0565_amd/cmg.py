@@ -53,6 +53,7 @@ class cmg_options(C.Structure):
         ("mixed_min_nnz", C.c_int64),
         ("spmv_variant", C.c_int32),
         ("autotune", C.c_int32),
+        ("block_regs", C.c_int32),
     ]
 
 
@@ -71,6 +72,8 @@ class cmg_level_stats(C.Structure):
         ("grid", C.c_int32),
         ("pi_ms", C.c_double),
         ("bytes_per_iter", C.c_double),
+        ("block_waves", C.c_int32),
+        ("block_regs", C.c_int32),
     ]
 
 

@@ -55,6 +55,7 @@ struct HostLevel {
     void* buf0 = nullptr;
     void* buf1 = nullptr;
     int32_t* part = nullptr;
+    int bwaves = 0, bregs = 0, bslots = 0;  // single-workgroup level: waves, register rows, slots
     int step = 0;              // 1: refined with one launch per PI step
     int fgrid = 0;             // level 0 in step mode: finishing pass grid
     int32_t* fpart = nullptr;  // ... and its row split
@@ -79,8 +80,8 @@ int pick_lanes(double avg_deg) {
 // visits standing for the per-row reduction and bookkeeping (threads = 64
 // for the one-wavefront mode of levels up to 256 vertices, else the
 // workgroup).  Meshes get 1-2 lanes; levels with hub rows get more.
-int pick_lanes_block(int n, double avg_deg, int maxlen) {
-    const int threads = n <= 256 ? 64 : 1024;
+int pick_lanes_block(int n, double avg_deg, int maxlen, int block_threads) {
+    const int threads = n <= 256 ? 64 : block_threads;
     const double c = 8.0;
     int best = 1;
     double best_cost = 0.0;
@@ -105,6 +106,51 @@ int bitlen(unsigned long long x) {
     return b;
 }
 
+// Register-row layout of a single-workgroup level (kernels of
+// kBlockRegsThreads threads): W wavefronts run the steps; layout l gives G
+// lanes per row and E entry slots per lane and row (rows of up to G E
+// entries); R rows per lane group; one wavefront only with G = R = 1;
+// weights exact in FP32.  The layout of least modelled step time wins:
+// a cost per wave count (barrier and cross-wave sums; none for one wave),
+// the latency of R E gathers, and their LDS bandwidth (W R E 64 gathers of
+// 8 bytes).  Fitted to MI355X measurements: 0.41 us per step for 62 rows
+// on one wave (E = 8), 0.64 us for 171 rows on 4 waves, 0.92 us for 400
+// rows of 12 to 16 entries on 4 to 8 waves, 1.46 us for 1536 rows on
+// 8 waves (R = 4, E = 8).
+struct BlockPlan {
+    int waves = 0, lanes = 1, regs = 0, slots = 0, layout = -1;
+};
+
+BlockPlan plan_block_regs(const HostLevel& L) {
+    static const double wave_cost[9] = {0, 0.31, 0.45, 0, 0.52, 0, 0, 0, 0.70};
+    const double slot_cost = 0.0125, lds_cost = 0.0012, lane_sum_cost = 0.02;
+    BlockPlan best;
+    double best_cost = 0.0;
+    if (L.n < 1 || L.n > 65536 || !L.w32exact) return best;
+    for (int W : {1, 2, 4, 8}) {
+        for (int l = 0; l < kRegLayouts; ++l) {
+            const int G = kRegLayoutG[l], E = kRegLayoutE[l];
+            if (L.maxlen > (int64_t)G * E) continue;
+            const int groups = 64 * W / G;
+            const int need = (L.n + groups - 1) / groups;
+            const int R = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 0;
+            if (R == 0) continue;
+            if (W == 1 && (G != 1 || R != 1)) continue;
+            const double cost = wave_cost[W] + R * E * slot_cost + W * R * E * lds_cost +
+                                R * (bitlen((unsigned)G) - 1) * lane_sum_cost;
+            if (best.regs == 0 || cost < best_cost) {
+                best.waves = W;
+                best.lanes = G;
+                best.regs = R;
+                best.slots = E;
+                best.layout = l;
+                best_cost = cost;
+            }
+        }
+    }
+    return best;
+}
+
 }  // namespace
 
 struct cmg_ctx {
@@ -122,9 +168,10 @@ struct cmg_ctx {
     GridJob* d_jobs = nullptr;  // [j] refines level j, [J+1] finishes level 0
     std::vector<GridJob> h_jobs;
     CoarseJob* d_cjob = nullptr;
-    BlockJob* d_bjob = nullptr;
+    BlockJob* d_bruns = nullptr;  // single-workgroup levels: runs of levels, coarsest run first
     CoarseJob h_cjob{};
-    BlockJob h_bjob{};
+    std::vector<BlockJob> h_bruns;
+    std::vector<int> brun_kind;   // kernel of each run (launch_block_jobs kind)
     int top = 0;       // finest-to-coarsest: levels top .. 0 are refined
     // host staging of the results of the last solve
     FinishOut h_fo{};
@@ -503,6 +550,9 @@ LevelDev level_dev(const HostLevel& L) {
     d.mpart = nullptr;
     d.grid = L.grid;
     d.w32exact = L.w32exact;
+    d.bwaves = L.bwaves;
+    d.bregs = L.bregs;
+    d.bslots = L.bslots;
     return d;
 }
 
@@ -724,11 +774,26 @@ cmg_status build_refine_plan(cmg_ctx* c) {
     c->d_bcast = (GridSlot*)c->dalloc(kBcastBytes);
     if (!c->d_bcast) return CMG_E_OOM;
     CK(launch_reset_sync(c->d_sync, c->d_slots, c->nslots, c->d_bcast, c->stream));
-    int max_step_grid = 0;
+    // single-workgroup levels: rows in registers where a layout fits, else
+    // the CSR traversal
     for (int j = 0; j <= J; ++j) {
         HostLevel& L = c->lv[j];
         L.in_block = (j >= c->block_lo && j <= top) ? 1 : 0;
-        if (L.in_block) L.lanes = pick_lanes_block(L.n, L.nnz / (double)std::max(L.n, 1), L.maxlen);
+        L.bwaves = L.bregs = L.bslots = 0;
+        if (!L.in_block) continue;
+        const BlockPlan p = o.block_regs < 0 ? BlockPlan{} : plan_block_regs(L);
+        if (p.regs > 0) {
+            L.bwaves = p.waves;
+            L.lanes = p.lanes;
+            L.bregs = p.regs;
+            L.bslots = p.slots;
+        } else {
+            L.lanes = pick_lanes_block(L.n, L.nnz / (double)std::max(L.n, 1), (int)L.maxlen, kBlockKernelThreads);
+        }
+    }
+    int max_step_grid = 0;
+    for (int j = 0; j <= J; ++j) {
+        HostLevel& L = c->lv[j];
         L.fp32 = 0;
         if (o.precision == CMG_MIXED && !L.in_block && j <= top && L.nnz >= mixed_min &&
             L.wmax < 16777216.0 && !(j == J && c->coarse_dense))
@@ -867,19 +932,38 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         ALLOC(c->d_cjob, CoarseJob, 1);
         CK(hipMemcpyAsync(c->d_cjob, &cj, sizeof(cj), hipMemcpyHostToDevice, c->stream));
     }
-    if (top >= 0 && c->block_lo <= top) {
+    // single-workgroup levels: maximal runs of levels on the same kernel,
+    // coarsest first; each run starts from the state its coarser level left
+    c->h_bruns.clear();
+    c->brun_kind.clear();
+    auto block_kind = [&](int j) {
+        const HostLevel& L = c->lv[j];
+        if (L.bregs <= 0) return 0;
+        int l = 0;
+        while (l < kRegLayouts && !(kRegLayoutG[l] == L.lanes && kRegLayoutE[l] == L.bslots)) ++l;
+        return 1 + 3 * l + (bitlen((unsigned)L.bregs) - 1);
+    };
+    for (int j = top; top >= 0 && j >= c->block_lo;) {
+        const int kind = block_kind(j);
+        int lo = j;
+        while (lo - 1 >= c->block_lo && block_kind(lo - 1) == kind) --lo;
         BlockJob bj{};
         bj.lv = c->d_lv;
         bj.st = c->d_st;
         bj.tol = o.tol;
         bj.seed = o.seed;
         bj.maxit = o.max_iters_per_level;
-        bj.jhi = top;
-        bj.jlo = c->block_lo;
-        bj.uniform = (!c->coarse_dense && top == J) ? 1 : 0;
-        c->h_bjob = bj;
-        ALLOC(c->d_bjob, BlockJob, 1);
-        CK(hipMemcpyAsync(c->d_bjob, &bj, sizeof(bj), hipMemcpyHostToDevice, c->stream));
+        bj.jhi = j;
+        bj.jlo = lo;
+        bj.uniform = (!c->coarse_dense && j == J) ? 1 : 0;
+        c->h_bruns.push_back(bj);
+        c->brun_kind.push_back(kind);
+        j = lo - 1;
+    }
+    if (!c->h_bruns.empty()) {
+        ALLOC(c->d_bruns, BlockJob, c->h_bruns.size());
+        CK(hipMemcpyAsync(c->d_bruns, c->h_bruns.data(), sizeof(BlockJob) * c->h_bruns.size(), hipMemcpyHostToDevice,
+                          c->stream));
     }
     c->h_st.resize(J + 1);
     {
@@ -990,6 +1074,7 @@ void fill_defaults(cmg_options* o) {
     o->mixed_min_nnz = 0;
     o->spmv_variant = 0;
     o->autotune = 0;
+    o->block_regs = 0;
 }
 
 // Device results of the last solve -> host staging (asynchronous).
@@ -1029,6 +1114,12 @@ cmg_status finalize(cmg_ctx* c, double t0, bool timed, double* lambda, cmg_stats
             L.k = c->h_st[j].k;
             L.margin = c->h_st[j].margin;
             if (c->h_st[j].maxit) status = CMG_W_MAXIT;
+            if (L.in_block && c->h_st[j].err) {
+                std::snprintf(g_last_error, sizeof(g_last_error),
+                              "level %d: a row longer than its register layout (%d slots of %d lanes)", j, L.bslots,
+                              L.lanes);
+                return CMG_E_DEVICE;
+            }
         }
         L.pi_ms = 0.0;
         if (L.in_block && c->h_st[j].ticks > 0) L.pi_ms = c->h_st[j].ticks / c->clock_khz;
@@ -1114,7 +1205,7 @@ cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where,
     hipStream_t s = c->stream;
     const int J = (int)c->lv.size() - 1;
     if (c->d_cjob) CK(launch_coarse_jobs(c->d_cjob, 1, s));
-    if (c->d_bjob) CK(launch_block_jobs(c->d_bjob, 1, s));
+    for (size_t r = 0; r < c->h_bruns.size(); ++r) CK(launch_block_jobs(c->d_bruns + r, 1, c->brun_kind[r], s));
     // grid levels: one cooperative launch per level
     for (int j = std::min(c->top, c->block_lo - 1); j >= 0; --j) {
         const HostLevel& L = c->lv[j];
@@ -1148,13 +1239,30 @@ cmg_status batch_impl(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
     cmg_ctx* c0 = hs[0];
     hipStream_t s = c0->stream;
     std::vector<CoarseJob> cj;
+    // single-workgroup runs: round q holds the q-th run of every graph,
+    // grouped by kernel
     std::vector<BlockJob> bj;
+    std::vector<std::pair<int, int>> blaunch;  // (kernel, jobs) in launch order
     int maxrounds = 0;
+    size_t maxruns = 0;
     for (int i = 0; i < count; ++i) {
         cmg_ctx* c = hs[i];
         if (c->d_cjob) cj.push_back(c->h_cjob);
-        if (c->d_bjob) bj.push_back(c->h_bjob);
+        maxruns = std::max(maxruns, c->h_bruns.size());
         maxrounds = std::max(maxrounds, std::min(c->top, c->block_lo - 1) + 1);
+    }
+    for (size_t q = 0; q < maxruns; ++q) {
+        for (int kind = 0; kind < kBlockKinds; ++kind) {
+            int nk = 0;
+            for (int i = 0; i < count; ++i) {
+                const cmg_ctx* c = hs[i];
+                if (q < c->h_bruns.size() && c->brun_kind[q] == kind) {
+                    bj.push_back(c->h_bruns[q]);
+                    ++nk;
+                }
+            }
+            if (nk > 0) blaunch.push_back({kind, nk});
+        }
     }
     // device tables: coarse | block | grid rounds | finish
     std::vector<GridJob> gj;
@@ -1225,7 +1333,13 @@ cmg_status batch_impl(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
     cmg_status status = CMG_OK;
     hipError_t e = hipMemcpyAsync(d, h.data(), bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !cj.empty()) e = launch_coarse_jobs(d_cj, (int)cj.size(), s);
-    if (e == hipSuccess && !bj.empty()) e = launch_block_jobs(d_bj, (int)bj.size(), s);
+    {
+        const BlockJob* q = d_bj;
+        for (const auto& bl : blaunch) {
+            if (e == hipSuccess) e = launch_block_jobs(q, bl.second, bl.first, s);
+            q += bl.second;
+        }
+    }
     size_t q = 0;
     for (int r = 0; r <= maxrounds && e == hipSuccess && status == CMG_OK; ++r) {
         const size_t qend = (r < maxrounds) ? round_end[r] : launches.size();
@@ -1362,6 +1476,8 @@ cmg_status cmg_level_info(cmg_handle h, cmg_level_stats* out, int32_t cap, int32
         li.pi_ms = L.pi_ms;
         double sv = L.fp32 ? 4 : 8;
         li.bytes_per_iter = 4.0 * (L.n + 1) + (double)L.nnz * (4 + sv) + 2 * sv * L.n;
+        li.block_waves = L.bwaves;
+        li.block_regs = L.bregs;
         out[j] = li;
     }
     return CMG_OK;

@@ -40,13 +40,34 @@ __device__ __forceinline__ T group_sum(T v, int G) {
 // A double moved between lanes by DPP (a row of 16 lanes at most): vector
 // ALU only, no LDS traffic.  CTRL is the DPP control (0xB1 and 0x4E: quad
 // permutations to lane ^ 1 and lane ^ 2; 0x141: mirror within 8 lanes;
-// 0x140: mirror within 16 lanes).
+// 0x140: mirror within 16 lanes; 0x124 and 0x128: rotation of the 16
+// lanes of a row by 4 and by 8).
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// x[l] + x[l ^ 16] (ROWS = 16) or x[l] + x[l ^ 32] (ROWS = 32) in every
+// lane l of a full wavefront: the gfx950 lane-swap instructions hand each
+// lane both values, so the two lanes of a pair hold the same bits.
+template <int ROWS>
+__device__ __forceinline__ double pair_sum_rows(double v) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)(b & 0xffffffffll), hi = (unsigned)(b >> 32);
+    if constexpr (ROWS == 16) {
+        const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        return __longlong_as_double(((long long)h[0] << 32) | (long long)l[0]) +
+               __longlong_as_double(((long long)h[1] << 32) | (long long)l[1]);
+    } else {
+        const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        return __longlong_as_double(((long long)h[0] << 32) | (long long)l[0]) +
+               __longlong_as_double(((long long)h[1] << 32) | (long long)l[1]);
+    }
 }
 
 // Value of a lane, identical in every lane (needs that lane active).
@@ -152,6 +173,9 @@ struct LevelDev {
     const int32_t* mpart;// merge path: diagonal split of each workgroup (2*(grid+1))
     int32_t grid;
     int32_t w32exact;    // 1 if every weight is exactly representable in FP32
+    int32_t bwaves;      // single-workgroup refinement: wavefronts that run the PI steps
+    int32_t bregs;       // single-workgroup refinement: rows per lane group held in registers (0: CSR)
+    int32_t bslots;      // register rows: entry slots per lane and row (E of the layout)
 };
 
 // State a refinement launch leaves for the next level (device written).

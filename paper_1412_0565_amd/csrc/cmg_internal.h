@@ -122,7 +122,16 @@ hipError_t launch_fill_u32(unsigned* p, unsigned v, int64_t m, hipStream_t s);
 // dense coarsest solves, one workgroup per job
 hipError_t launch_coarse_jobs(const CoarseJob* jobs, int njobs, hipStream_t s);
 // coarse levels of each job inside one workgroup (FP64 levels only)
-hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, hipStream_t s);
+// Register-row layouts of single-workgroup levels: G lanes per row and E
+// entry slots per lane and row (rows of up to G E entries).
+constexpr int kRegLayouts = 7;
+constexpr int kRegLayoutG[kRegLayouts] = {1, 2, 4, 8, 1, 2, 4};
+constexpr int kRegLayoutE[kRegLayouts] = {8, 8, 8, 8, 16, 16, 16};
+// kind 0: CSR traversal on kBlockKernelThreads threads; 1 + 3 l + log2(R)
+// (layout l, R = 1, 2 or 4 rows per lane group): register rows on
+// kBlockRegsThreads threads.
+constexpr int kBlockKinds = 1 + 3 * kRegLayouts;
+hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, int kind, hipStream_t s);
 // Job kernels are specialised by traversal (merge path or G lanes per
 // row) and precision: kind = 2 * t + fp32, t = 0 for the merge path, else
 // 1 + log2(G); finishing kernels depend on the traversal only.
@@ -147,6 +156,7 @@ constexpr int kStepBlock = 512;
 
 constexpr int kGridBlock = 512;
 constexpr int kBlockKernelThreads = 1024;
+constexpr int kBlockRegsThreads = 512;   // 256 VGPRs per lane for register rows
 constexpr int kBlockLdsMax = 144 * 1024;  // LDS image budget of the single-workgroup kernel
 int refine_block_lds_budget();
 

@@ -441,6 +441,63 @@ __device__ __forceinline__ void small_sum(double (&v)[NV], double* red, int& par
     }
 }
 
+// The four sums of a PI step over one wavefront, identical in every lane.
+// Lanes trade halves of their partials so that each exchange adds one
+// value per lane: after the two quad exchanges lane p of a quad holds the
+// quad sum of value 2 (p & 1) + (p >> 1); rotations of each row by 4 and 8
+// lanes, then the row and half swaps, complete the sums.
+__device__ __forceinline__ void wave_sum4(double (&v)[4]) {
+    const int lane = threadIdx.x & 63;
+    const bool odd = (lane & 1) != 0;
+    double k0 = odd ? v[2] : v[0];
+    double k1 = odd ? v[3] : v[1];
+    const double s0 = odd ? v[0] : v[2];
+    const double s1 = odd ? v[1] : v[3];
+    k0 += dpp_move<0xB1>(s0);
+    k1 += dpp_move<0xB1>(s1);
+    const bool hi = (lane & 2) != 0;
+    double k = hi ? k1 : k0;
+    k += dpp_move<0x4E>(hi ? k0 : k1);
+    k += dpp_move<0x124>(k);
+    k += dpp_move<0x128>(k);
+    k = pair_sum_rows<16>(k);
+    k = pair_sum_rows<32>(k);
+    v[0] = read_lane(k, 0);
+    v[2] = read_lane(k, 1);
+    v[1] = read_lane(k, 2);
+    v[3] = read_lane(k, 3);
+}
+
+// Sums of a PI step over the `nw` wavefronts that run the steps (the first
+// nw of the workgroup), identical in each of their lanes.  nw == 1: no
+// workgroup barrier.  Otherwise every such wave posts its four sums (one
+// barrier, alternating slots) and adds the posts within rows of 16 lanes.
+template <bool WAVE>
+__device__ __forceinline__ void step_sum4(double (&v)[4], double* red, int& parity, int nw) {
+    if constexpr (WAVE) {
+        // LDS writes of this step become visible to the other lanes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sum4(v);
+    } else {
+        const int lane = threadIdx.x & 63;
+        const int wv = threadIdx.x >> 6;
+        double* slot = red + parity * 64;
+        wave_sum4(v);
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) slot[q * 16 + wv] = v[q];
+        }
+        __syncthreads();
+        double t = ((lane & 15) < nw) ? slot[lane] : 0.0;
+        t = group_sum_t<16>(t);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = read_lane(t, q * 16);
+        parity ^= 1;
+    }
+}
+
 // One PI step of a small level, rows shared by `nthr` threads in G-lane
 // groups.  Pointers are either all LDS (staged modes) or all global.
 template <int G, bool W32, bool C16>
@@ -498,12 +555,96 @@ struct SmallIn {
     int maxit;
 };
 
-// Prolongation, deflation, normalisation and PI steps of one small level.
-// MODE 0: LDS image, one wavefront; 1: LDS image, whole workgroup;
-// 2: global memory, whole workgroup.
+// Rows of a small level read from its CSR arrays every step (an LDS image
+// or global memory), in G-lane groups with G = L.lanes.
+// Rows of a small level held in registers for all its steps: each G-lane
+// group owns rows grp + r * ngroups (r < R) and each lane E entries of
+// every such row (entry a + lane + m G in slot m; columns as uint16 pairs,
+// weights as FP32, which the level's weights equal exactly), so a step is
+// one round of independent gathers from the LDS vector.  Unused slots point
+// at the row's own vertex with weight 0 and add an exact zero, which keeps
+// the sums bit for bit those of the CSR traversal with the same G.
+template <int G, int R, int E>
+struct RegRows {
+    uint32_t c2[R][E / 2];
+    float w[R][E];
+    int row[R];
+    int n;
+    double g;
+
+    __device__ __forceinline__ void load(const LevelDev& L, int nact, int* bad) {
+        n = L.n;
+        g = L.g;
+        const int lane = (int)threadIdx.x & (G - 1);
+        const int ngroups = nact / G;
+        const int grp = (int)threadIdx.x / G;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = grp + r * ngroups;
+            row[r] = i < n ? i : -1;
+            int a = 0, b = 0;
+            if (i < n) {
+                a = L.rp[i];
+                b = L.rp[i + 1];
+                if (b - a > G * E) *bad = 1;
+            }
+            const uint32_t self = i < n ? (uint32_t)i : 0u;
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int e = a + lane + m * G;
+                uint32_t cv = self;
+                float wv = 0.0f;
+                if (e < b) {
+                    cv = (uint32_t)L.col[e];
+                    wv = (float)L.w64[e];
+                }
+                if (m & 1) c2[r][m >> 1] |= cv << 16;
+                else c2[r][m >> 1] = cv;
+                w[r][m] = wv;
+            }
+        }
+    }
+
+    __device__ __forceinline__ void step(const double* win, double* wout, double mu, double s, double (&acc)[4]) {
+        const int lane = (int)threadIdx.x & (G - 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = row[r];
+            const double wi = win[i < 0 ? 0 : i];
+            if constexpr (R * E > 32) {
+                // decode the columns and widen the weights every step:
+                // hoisted out of the step loop they would not fit
+#pragma unroll
+                for (int q = 0; q < E / 2; ++q) asm volatile("" : "+v"(c2[r][q]));
+#pragma unroll
+                for (int q = 0; q < E; ++q) asm volatile("" : "+v"(w[r][q]));
+            }
+            double x[E];
+#pragma unroll
+            for (int m = 0; m < E; ++m) x[m] = win[(m & 1) ? (c2[r][m >> 1] >> 16) : (c2[r][m >> 1] & 0xffffu)];
+            double t = 0.0;
+#pragma unroll
+            for (int m = 0; m < E; ++m) t += (double)w[r][m] * (x[m] - wi);
+            t = group_sum_t<G>(t);
+            if (lane == 0 && i >= 0) {
+                const double xv = (wi - mu) * s;
+                const double y = s * (g * (wi - mu) + t);
+                wout[i] = y;
+                acc[0] += y;
+                acc[1] += y * y;
+                acc[2] += y * xv;
+                acc[3] += xv;
+            }
+        }
+    }
+};
+
+// Prolongation, deflation, normalisation and PI steps of one small level
+// read from its CSR arrays.  MODE 0: LDS image, one wavefront; 1: LDS
+// image, whole workgroup; 2: global memory, whole workgroup.
 template <int MODE, bool W32, bool C16>
 __device__ void small_level(const LevelDev& L, const SmallIn& in, double* lds, double* red, int& parity,
-                            LevelState& out) {
+                            int* stop_flag, int nw_run, LevelState& out) {
     constexpr bool WAVE = (MODE == 0);
     const int n = L.n;
     const int nthr = WAVE ? 64 : (int)blockDim.x;
@@ -554,43 +695,63 @@ __device__ void small_level(const LevelDev& L, const SmallIn& in, double* lds, d
     double s = 1.0 / sqrt(ss[0]);
     int cur = 0, k = 0, hit = 0;
     double utv = 0.0, pmu = mu, ps = s;
-    while (true) {
-        const double* win = cur ? b1 : b0;
-        double* wout = cur ? b0 : b1;
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        switch (L.lanes) {
-            case 1: pi_small<1, W32, C16>(n, nthr, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
-            case 2: pi_small<2, W32, C16>(n, nthr, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
-            case 4: pi_small<4, W32, C16>(n, nthr, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
-            case 8: pi_small<8, W32, C16>(n, nthr, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
-            case 16: pi_small<16, W32, C16>(n, nthr, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
-            case 32: pi_small<32, W32, C16>(n, nthr, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
-            default: pi_small<64, W32, C16>(n, nthr, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+    // The PI steps run on the first `nw` wavefronts; the others only keep
+    // the barrier count: after each barrier they read the stop decision of
+    // the step before it, and the running waves end with one more barrier.
+    const int nw = WAVE ? 1 : nw_run;
+    const int nact = 64 * nw;
+    // wave-uniform test, taken as a scalar branch
+    if (WAVE || __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) < nw) {
+        while (true) {
+            const double* win = cur ? b1 : b0;
+            double* wout = cur ? b0 : b1;
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            switch (L.lanes) {
+                case 1: pi_small<1, W32, C16>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+                case 2: pi_small<2, W32, C16>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+                case 4: pi_small<4, W32, C16>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+                case 8: pi_small<8, W32, C16>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+                case 16: pi_small<16, W32, C16>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+                case 32: pi_small<32, W32, C16>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+                default: pi_small<64, W32, C16>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+            }
+            step_sum4<WAVE>(acc, red, parity, nw);
+            const double mu2 = acc[0] / (double)n;
+            const double s2 = 1.0 / sqrt(acc[1] - acc[0] * mu2);
+            utv = s2 * (acc[2] - mu2 * acc[3]);
+            ++k;
+            cur ^= 1;
+            pmu = mu;
+            ps = s;
+            mu = mu2;
+            s = s2;
+            bool stop = !(utv < 1.0 - in.tol);
+            if (!stop && k >= in.maxit) {
+                hit = 1;
+                stop = true;
+            }
+            if (!WAVE && threadIdx.x == 0) stop_flag[k & 1] = stop ? 1 : 0;
+            if (stop) break;
         }
-        small_sum<4, WAVE>(acc, red, parity);
-        const double mu2 = acc[0] / (double)n;
-        const double s2 = 1.0 / sqrt(acc[1] - acc[0] * mu2);
-        utv = s2 * (acc[2] - mu2 * acc[3]);
-        ++k;
-        cur ^= 1;
-        pmu = mu;
-        ps = s;
-        mu = mu2;
-        s = s2;
-        if (!(utv < 1.0 - in.tol)) break;
-        if (k >= in.maxit) {
-            hit = 1;
-            break;
+        if constexpr (!WAVE) __syncthreads();
+    } else {
+        // barrier q closes step q unless step q - 1 was the last one; the
+        // slot parity follows the steps, as in the running waves
+        for (int q = 1;; ++q) {
+            __syncthreads();
+            if (q > 1 && stop_flag[(q - 1) & 1]) break;
+            parity ^= 1;
         }
+        return;  // the state is kept by thread 0
     }
     int fin = cur;
     if constexpr (MODE != 2) {
-        // the LDS image is discarded: final vector to buf0, previous to buf1
+        // the LDS vectors are discarded: final vector to buf0, previous to buf1
         const double* src = cur ? b1 : b0;
         const double* prv = cur ? b0 : b1;
         double* g0 = (double*)L.buf0;
         double* g1 = (double*)L.buf1;
-        for (int i = threadIdx.x; i < n; i += nthr) {
+        for (int i = threadIdx.x; i < n; i += nact) {
             g0[i] = src[i];
             g1[i] = prv[i];
         }
@@ -615,15 +776,17 @@ __device__ void small_level(const LevelDev& L, const SmallIn& in, double* lds, d
 // launches.  A level whose CSR and two vectors fit in `lds_budget` bytes
 // is first copied to LDS (columns as uint16 when n <= 65536, weights as
 // FP32 when that is exact) and its steps touch no global memory; levels of
-// at most kWaveRows vertices then run on a single wavefront.  Larger levels
-// stream from global memory (L2).  The final vector of each level goes to
-// buf0 (its predecessor to buf1).
+// at most kWaveRows vertices then run on a single wavefront, larger ones on
+// LevelDev::bwaves wavefronts (0: all).  Larger levels stream from global
+// memory (L2).  The final vector of each level goes to buf0 (its
+// predecessor to buf1).
 __global__ void __launch_bounds__(kBlockKernelThreads)
     k_block_jobs(const BlockJob* __restrict__ jobs, int lds_budget) {
     extern __shared__ double lds[];
     __shared__ double red[2 * 64];
     __shared__ double s_cm, s_cs;
     __shared__ int s_cfin;
+    __shared__ int s_stop[2];
     const BlockJob Jb = jobs[blockIdx.x];
     const LevelDev* __restrict__ lv = Jb.lv;
     int parity = 0;
@@ -638,6 +801,8 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
         const long long t_start = wall_clock64();
         const LevelDev L = lv[j];
         const int n = L.n;
+        const int nwmax = (int)(blockDim.x >> 6);
+        const int nw = L.bwaves > 0 ? min(L.bwaves, nwmax) : (n <= kWaveRows ? 1 : nwmax);
         const int c16 = (n <= 65536) ? 1 : 0;
         int w32 = 0;
         size_t need = staged_bytes(L, 0, c16);
@@ -646,10 +811,9 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
             need = staged_bytes(L, 1, c16);
         }
         const bool staged = need <= (size_t)lds_budget;
-        const int mode = staged ? (n <= kWaveRows ? 0 : 1) : 2;
+        const int mode = staged ? (nw == 1 ? 0 : 1) : 2;
         if (staged) {
-            char* p = (char*)lds;
-            p += align8(16 * (size_t)n);
+            char* p = (char*)lds + align8(16 * (size_t)n);
             void* wdst = p;
             p += align8((size_t)L.nnz * (w32 ? 4 : 8));
             int32_t* rdst = (int32_t*)p;
@@ -683,23 +847,187 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
         if (mode == 0) {
             if (threadIdx.x < 64) {
                 if (w32) {
-                    if (c16) small_level<0, true, true>(L, in, lds, red, parity, o);
-                    else small_level<0, true, false>(L, in, lds, red, parity, o);
+                    if (c16) small_level<0, true, true>(L, in, lds, red, parity, s_stop, 1, o);
+                    else small_level<0, true, false>(L, in, lds, red, parity, s_stop, 1, o);
                 } else {
-                    if (c16) small_level<0, false, true>(L, in, lds, red, parity, o);
-                    else small_level<0, false, false>(L, in, lds, red, parity, o);
+                    if (c16) small_level<0, false, true>(L, in, lds, red, parity, s_stop, 1, o);
+                    else small_level<0, false, false>(L, in, lds, red, parity, s_stop, 1, o);
                 }
             }
         } else if (mode == 1) {
             if (w32) {
-                if (c16) small_level<1, true, true>(L, in, lds, red, parity, o);
-                else small_level<1, true, false>(L, in, lds, red, parity, o);
+                if (c16) small_level<1, true, true>(L, in, lds, red, parity, s_stop, nw, o);
+                else small_level<1, true, false>(L, in, lds, red, parity, s_stop, nw, o);
             } else {
-                if (c16) small_level<1, false, true>(L, in, lds, red, parity, o);
-                else small_level<1, false, false>(L, in, lds, red, parity, o);
+                if (c16) small_level<1, false, true>(L, in, lds, red, parity, s_stop, nw, o);
+                else small_level<1, false, false>(L, in, lds, red, parity, s_stop, nw, o);
             }
         } else {
-            small_level<2, false, false>(L, in, lds, red, parity, o);
+            small_level<2, false, false>(L, in, lds, red, parity, s_stop, nw, o);
+        }
+        if (threadIdx.x == 0) {
+            o.ticks = wall_clock64() - t_start;
+            Jb.st[j] = o;
+            s_cm = o.mu;
+            s_cs = o.s;
+            s_cfin = o.fin;
+        }
+        __syncthreads();
+    }
+}
+
+// One level on register rows with both vectors in LDS.  nw == 1: on
+// wavefront 0 alone with no workgroup barrier (the caller keeps the other
+// waves out); else the first nw waves run the steps and the others keep the
+// barrier count as in the CSR traversal.
+template <int G, int R, int E>
+__device__ void reg_level(const LevelDev& L, const SmallIn& in, double* b0, double* b1, double* red, int& parity,
+                          int* stop_flag, int* bad, int nw, LevelState& out) {
+    const bool wave = (nw == 1);
+    const int n = L.n;
+    const int nthr = wave ? 64 : (int)blockDim.x;
+    double sum[1] = {0.0};
+    if (in.uniform) {
+        for (int i = threadIdx.x; i < n; i += nthr) {
+            const double v = hashed_uniform(in.seed, i) - 0.5;
+            b0[i] = v;
+            sum[0] += v;
+        }
+    } else {
+        for (int i = threadIdx.x; i < n; i += nthr) {
+            const double v = (ld_any(in.cbuf, in.cfp32, L.agg[i]) - in.cm) * in.cs;
+            b0[i] = v;
+            sum[0] += v;
+        }
+    }
+    if (wave) small_sum<1, true>(sum, red, parity);
+    else small_sum<1, false>(sum, red, parity);
+    double mu = sum[0] / (double)n;
+    double ss[1] = {0.0};
+    for (int i = threadIdx.x; i < n; i += nthr) {
+        const double d = b0[i] - mu;
+        ss[0] += d * d;
+    }
+    if (wave) small_sum<1, true>(ss, red, parity);
+    else small_sum<1, false>(ss, red, parity);
+    double s = 1.0 / sqrt(ss[0]);
+    int cur = 0, k = 0, hit = 0;
+    double utv = 0.0, pmu = mu, ps = s;
+    const int nact = 64 * nw;
+    if (!(wave || __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) < nw)) {
+        // barrier q closes step q unless step q - 1 was the last one
+        for (int q = 1;; ++q) {
+            __syncthreads();
+            if (q > 1 && stop_flag[(q - 1) & 1]) break;
+            parity ^= 1;
+        }
+        return;  // the state is kept by thread 0
+    }
+    RegRows<G, R, E> rows;
+    rows.load(L, nact, bad);
+    while (true) {
+        const double* win = cur ? b1 : b0;
+        double* wout = cur ? b0 : b1;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        rows.step(win, wout, mu, s, acc);
+        if (wave) step_sum4<true>(acc, red, parity, 1);
+        else step_sum4<false>(acc, red, parity, nw);
+        const double mu2 = acc[0] / (double)n;
+        const double s2 = 1.0 / sqrt(acc[1] - acc[0] * mu2);
+        utv = s2 * (acc[2] - mu2 * acc[3]);
+        ++k;
+        cur ^= 1;
+        pmu = mu;
+        ps = s;
+        mu = mu2;
+        s = s2;
+        bool stop = !(utv < 1.0 - in.tol);
+        if (!stop && k >= in.maxit) {
+            hit = 1;
+            stop = true;
+        }
+        if (!wave && threadIdx.x == 0) stop_flag[k & 1] = stop ? 1 : 0;
+        if (stop) break;
+    }
+    if (!wave) __syncthreads();
+    // the LDS vectors are discarded: final vector to buf0, previous to buf1
+    const double* src = cur ? b1 : b0;
+    const double* prv = cur ? b0 : b1;
+    double* g0 = (double*)L.buf0;
+    double* g1 = (double*)L.buf1;
+    for (int i = threadIdx.x; i < n; i += nact) {
+        g0[i] = src[i];
+        g1[i] = prv[i];
+    }
+    if (wave) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    out.mu = mu;
+    out.s = s;
+    out.mu_prev = pmu;
+    out.s_prev = ps;
+    out.utv = utv;
+    out.margin = utv - (1.0 - in.tol);
+    out.fin = 0;
+    out.k = k;
+    out.maxit = hit;
+    out.err = *bad;
+    out.ticks = 0;
+}
+
+// Levels jhi down to jlo refined inside one workgroup on register rows of
+// G lanes per row, R rows per lane group and E slots per lane and row
+// (every level of the job has that layout and LevelDev::bwaves waves;
+// FP32-exact weights).  A level whose layout does not fit is skipped with err = 2 in
+// its state.
+template <int G, int R, int E>
+__global__ void __launch_bounds__(kBlockRegsThreads)
+    k_block_regs(const BlockJob* __restrict__ jobs, int lds_budget) {
+    extern __shared__ double lds[];
+    __shared__ double red[2 * 64];
+    __shared__ double s_cm, s_cs;
+    __shared__ int s_cfin;
+    __shared__ int s_stop[2];
+    __shared__ int s_bad;
+    const BlockJob Jb = jobs[blockIdx.x];
+    const LevelDev* __restrict__ lv = Jb.lv;
+    int parity = 0;
+    if (threadIdx.x == 0 && !Jb.uniform) {
+        LevelState c = Jb.st[Jb.jhi + 1];
+        s_cm = c.mu;
+        s_cs = c.s;
+        s_cfin = c.fin;
+    }
+    __syncthreads();
+    for (int j = Jb.jhi; j >= Jb.jlo; --j) {
+        const long long t_start = wall_clock64();
+        const LevelDev L = lv[j];
+        const int n = L.n;
+        const int nw = max(1, min(L.bwaves, (int)(blockDim.x >> 6)));
+        const bool fits = L.lanes == G && L.bregs == R && L.bslots == E && L.w32exact && n >= 1 && n <= 65536 &&
+                          16 * (size_t)n <= (size_t)lds_budget && n <= R * (64 * nw / G) &&
+                          (nw > 1 || (G == 1 && R == 1));
+        if (threadIdx.x == 0) s_bad = 0;
+        SmallIn in;
+        in.uniform = (Jb.uniform && j == Jb.jhi) ? 1 : 0;
+        if (!in.uniform) {
+            const LevelDev C = lv[j + 1];
+            in.cbuf = s_cfin ? C.buf1 : C.buf0;
+            in.cfp32 = C.fp32;
+        } else {
+            in.cbuf = nullptr;
+            in.cfp32 = 0;
+        }
+        in.cm = s_cm;
+        in.cs = s_cs;
+        in.seed = Jb.seed;
+        in.tol = Jb.tol;
+        in.maxit = Jb.maxit;
+        LevelState o{};
+        if (!fits) {
+            o.err = 2;
+        } else if (nw == 1) {
+            if (threadIdx.x < 64) reg_level<G, R, E>(L, in, lds, lds + n, red, parity, s_stop, &s_bad, 1, o);
+        } else {
+            reg_level<G, R, E>(L, in, lds, lds + n, red, parity, s_stop, &s_bad, nw, o);
         }
         if (threadIdx.x == 0) {
             o.ticks = wall_clock64() - t_start;
@@ -1456,32 +1784,59 @@ hipError_t launch_coarse_jobs(const CoarseJob* jobs, int njobs, hipStream_t s) {
     return hipGetLastError();
 }
 
+namespace {
+template <int G, int E>
+const void* block_regs_kernel(int ri) {
+    return ri == 0 ? (const void*)k_block_regs<G, 1, E> : ri == 1 ? (const void*)k_block_regs<G, 2, E>
+                                                                 : (const void*)k_block_regs<G, 4, E>;
+}
+// kind 0: CSR traversal; 1 + 3 l + log2(R): register rows of layout l
+const void* block_kernel(int kind) {
+    if (kind <= 0) return (const void*)k_block_jobs;
+    const int l = (kind - 1) / 3, ri = (kind - 1) % 3;
+    switch (l) {
+        case 0: return block_regs_kernel<1, 8>(ri);
+        case 1: return block_regs_kernel<2, 8>(ri);
+        case 2: return block_regs_kernel<4, 8>(ri);
+        case 3: return block_regs_kernel<8, 8>(ri);
+        case 4: return block_regs_kernel<1, 16>(ri);
+        case 5: return block_regs_kernel<2, 16>(ri);
+        default: return block_regs_kernel<4, 16>(ri);
+    }
+}
+}  // namespace
+
 int refine_block_lds_budget() {
     static int budget = -1;
     if (budget < 0) {
         int dev = 0, maxsh = 65536;
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-        hipFuncAttributes fa;
         size_t stat = 0;
-        if (hipFuncGetAttributes(&fa, (const void*)k_block_jobs) == hipSuccess) stat = fa.sharedSizeBytes;
+        for (int r = 0; r < kBlockKinds; ++r) {
+            hipFuncAttributes fa;
+            if (hipFuncGetAttributes(&fa, block_kernel(r)) == hipSuccess) stat = std::max(stat, fa.sharedSizeBytes);
+        }
         long b = std::min<long>(kBlockLdsMax, (long)maxsh - (long)stat - 256);
         b = std::max<long>(b, 0);
-        if (b > 65536 - (long)stat - 256 &&
-            hipFuncSetAttribute((const void*)k_block_jobs, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)b) != hipSuccess) {
-            (void)hipGetLastError();
-            b = std::max<long>(0, 65536 - (long)stat - 256);
+        for (int r = 0; r < kBlockKinds; ++r) {
+            if (b > 65536 - (long)stat - 256 &&
+                hipFuncSetAttribute(block_kernel(r), hipFuncAttributeMaxDynamicSharedMemorySize, (int)b) != hipSuccess) {
+                (void)hipGetLastError();
+                b = std::max<long>(0, 65536 - (long)stat - 256);
+            }
         }
         budget = (int)(b & ~7L);
     }
     return budget;
 }
 
-hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, hipStream_t s) {
+hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, int kind, hipStream_t s) {
+    if (kind < 0 || kind >= kBlockKinds) return hipErrorInvalidValue;
     const int budget = refine_block_lds_budget();
-    hipLaunchKernelGGL(k_block_jobs, dim3(njobs), dim3(kBlockKernelThreads), (size_t)budget, s, jobs, budget);
-    return hipGetLastError();
+    void* args[] = {(void*)&jobs, (void*)&budget};
+    return hipLaunchKernel(block_kernel(kind), dim3(njobs), dim3(kind ? kBlockRegsThreads : kBlockKernelThreads), args,
+                           (size_t)budget, s);
 }
 
 namespace {

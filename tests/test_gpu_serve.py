@@ -43,8 +43,21 @@ def test_served_results_equal_solo():
             name, g, prec = pool[(i * 7) % len(pool)]
             stream.append(Request(i, name, g.n, g.row_ptr, g.col, g.w, precision=prec))
         replay(srv, stream, qps=2000.0, seed=4)
+        # graphs still resident after the stream are served from their kept
+        # hierarchies (whether the stream itself hit depends on timing)
+        with srv.lock:
+            kept = list(srv.resident.keys())
+        assert kept
+        by_name = {name: (g, prec) for name, g, prec in pool}
+        again = []
+        for i, name in enumerate(kept):
+            g, prec = by_name[name]
+            again.append(Request(1000 + i, name, g.n, g.row_ptr, g.col, g.w, precision=prec))
+        replay(srv, again, qps=2000.0, seed=5)
     finally:
         srv.close()
+    assert all(r.resident_hit for r in again)
+    stream = stream + again
     for r in stream:
         assert r.status == "done", (r.rid, r.status, r.error)
         lam, x = solo[r.graph_id]
@@ -52,4 +65,3 @@ def test_served_results_equal_solo():
         assert np.array_equal(r.x, x), r.graph_id
     say(f"[serve] batches {srv.batches} summary {latency_summary(stream)}")
     assert max(srv.batches) >= 2
-    assert any(r.resident_hit for r in stream)

@@ -345,3 +345,22 @@ def test_batch_rejects_duplicates():
     with cmg.Fiedler(g.n, g.row_ptr, g.col, g.w) as F:
         with pytest.raises(cmg.CmgError):
             cmg.cmg_fiedler_batch([F.handle, F.handle])
+
+
+@pytest.mark.parametrize("name", ["rgg20k", "grid128", "grid3d_20", "er500", "star200", "cl30k"])
+def test_block_register_rows_and_csr_agree_with_oracle(name):
+    """Single-workgroup levels on register rows (default) and on the CSR
+    traversal (block_regs=-1): both bit-exact in hierarchy and step counts
+    against the oracle.  Graphs with short rows use register rows; a hub
+    row longer than any layout keeps its level on the CSR kernel."""
+    g = _named(name)
+    ref = oracle_of(g)
+    for regs in (0, -1):
+        lam, x, st, levels, arrays = run_gpu(g, block_regs=regs)
+        lay = [(j, l.lanes, l.block_waves, l.block_regs) for j, l in enumerate(levels) if l.in_block]
+        say(f"[parity] {name} block_regs={regs} block levels (j, lanes, waves, rows per group) {lay}")
+        if regs < 0:
+            assert all(l.block_regs == 0 for l in levels)
+        elif name in ("rgg20k", "grid128", "grid3d_20"):
+            assert any(l.block_regs > 0 for l in levels if l.in_block)
+        assert_fp64_parity(g, lam, x, st, levels, arrays, ref)

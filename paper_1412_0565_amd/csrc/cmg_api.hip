@@ -481,6 +481,7 @@ cmg_status coarsen_chain(cmg_ctx* c, SetupTmp& t, int j0, int* next) {
     job.soff = job.astart + L.n;
     job.rcount = (int32_t*)t.v1;  // 2 nnz0 ints
     job.mb = (int32_t*)t.k1;
+    job.bcol = t.heads;
     job.slot = t.slot;
     job.live = t.live;
     job.state = t.state;

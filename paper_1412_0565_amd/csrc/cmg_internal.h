@@ -43,6 +43,7 @@ struct ChainJob {
     int32_t max_levels;  // levels that may be visited, the first included
     // scratch (sized for level 0 of the graph)
     int32_t *h, *pairseed, *rootseed, *rank, *members, *astart, *soff, *rcount, *mb;
+    int32_t* bcol;  // aggregate of each entry's column (nnz0 ints)
     unsigned long long* slot;
     uint8_t *live, *state;
     double* mw;

@@ -85,18 +85,14 @@ __device__ void block_max4(double (&m)[4], double* sm) {
     __syncthreads();
 }
 
-// Coarse-row scratch of one thread in LDS: kChainSlots (column, sum) pairs,
-// slot-major so that the threads' slots of one index share no bank.
+// Columns a thread keeps in registers while it forms a coarse row.
 constexpr int kChainSlots = 12;
-constexpr size_t kChainCntBytes = sizeof(int32_t) * 2 * (kChainMaxN / 2 + 1);
-constexpr size_t kChainLds = kChainCntBytes + (size_t)kChainSlots * kChainThreads * (sizeof(double) + sizeof(uint16_t));
+constexpr size_t kChainLds = sizeof(int32_t) * 2 * (kChainMaxN / 2 + 1);
 
 __global__ void __launch_bounds__(kChainThreads) k_coarsen_chain(ChainJob J) {
-    extern __shared__ int32_t lds_cnt[];  // acnt, afill, then the row scratch
+    extern __shared__ int32_t lds_cnt[];  // acnt, afill
     int32_t* acnt = lds_cnt;
     int32_t* afill = lds_cnt + (kChainMaxN / 2 + 1);
-    double* sw = (double*)((char*)lds_cnt + kChainCntBytes);
-    uint16_t* sb = (uint16_t*)(sw + (size_t)kChainSlots * kChainThreads);
     __shared__ long long sh[17];
     __shared__ double sm[4 * 16];
     __shared__ int s_bad;
@@ -267,85 +263,111 @@ __global__ void __launch_bounds__(kChainThreads) k_coarsen_chain(ChainJob J) {
             break;
         }
         chain_scan(J.soff, J.soff, nc, sh);
+        // aggregate of every entry's column, all threads over all entries:
+        // the row loop below then reads its entries without a dependent load
+        for (int64_t e = tid; e < nnz; e += T) J.bcol[e] = agg[col[e]];
+        __syncthreads();
         // ---- Galerkin: one thread per coarse row, contributions added in
         // fine CSR order, row sorted by coarse column.  The row is formed in
         // the thread's LDS slots (coarse columns < 2^16 here); a row with
         // more distinct columns moves to its global scratch and goes on there.
         // rows of a level whose fine rows already exceed the slots start in
         // global scratch
-        const bool lds_rows = hd.maxlen <= kChainSlots;
+        const bool reg_rows = hd.maxlen <= kChainSlots;
         for (int a = tid; a < nc; a += T) {
             const int32_t* ms = J.members + J.astart[a];
             const int cnt = acnt[a];
             int32_t* mb = J.mb + J.soff[a];
             double* mw = J.mw + J.soff[a];
+            // the row in registers: columns rb[0..len) (unused: INT_MAX) and
+            // their sums; every slot operation is unrolled and branch-free
+            int rb[kChainSlots];
+            double rw[kChainSlots];
+#pragma unroll
+            for (int q = 0; q < kChainSlots; ++q) {
+                rb[q] = 0x7fffffff;
+                rw[q] = 0.0;
+            }
             int len = 0;
-            bool in_lds = lds_rows;
-            auto add = [&](int b, double x) {
-                if (in_lds) {
-                    int q = 0;
-                    while (q < len && (int)sb[q * T + tid] != b) ++q;
-                    if (q < len) {
-                        sw[q * T + tid] += x;
-                        return;
-                    }
-                    if (len < kChainSlots) {
-                        sb[len * T + tid] = (uint16_t)b;
-                        sw[len * T + tid] = x;
-                        ++len;
-                        return;
-                    }
-                    for (int q2 = 0; q2 < len; ++q2) {
-                        mb[q2] = sb[q2 * T + tid];
-                        mw[q2] = sw[q2 * T + tid];
-                    }
-                    in_lds = false;
-                }
-                int q = 0;
-                while (q < len && mb[q] != b) ++q;
-                if (q == len) {
-                    mb[len] = b;
-                    mw[len] = x;
-                    ++len;
-                } else {
-                    mw[q] += x;
-                }
-            };
+            bool in_regs = reg_rows;
             for (int i = 0; i < cnt; ++i) {
                 const int m = ms[i];
                 const int e0 = rp[m], e1 = rp[m + 1];
                 if (e0 >= e1) continue;
-                // one entry ahead: the next entry's column, weight and
-                // aggregate are loaded before this one is added
-                int bn = agg[col[e0]];
+                // one entry ahead: the next entry's coarse column and weight
+                // are loaded before this one is added
+                int bn = J.bcol[e0];
                 double xn = w[e0];
                 for (int e = e0; e < e1; ++e) {
                     const int b = bn;
                     const double x = xn;
                     if (e + 1 < e1) {
                         xn = w[e + 1];
-                        bn = agg[col[e + 1]];
+                        bn = J.bcol[e + 1];
                     }
-                    if (b != a) add(b, x);
+                    if (b == a) continue;
+                    if (in_regs) {
+                        bool found = false;
+#pragma unroll
+                        for (int q = 0; q < kChainSlots; ++q) {
+                            if (rb[q] == b) {
+                                rw[q] += x;
+                                found = true;
+                            }
+                        }
+                        if (found) continue;
+                        if (len < kChainSlots) {
+#pragma unroll
+                            for (int q = 0; q < kChainSlots; ++q) {
+                                if (q == len) {
+                                    rb[q] = b;
+                                    rw[q] = x;
+                                }
+                            }
+                            ++len;
+                            continue;
+                        }
+                        // more columns than slots: the row goes on in global scratch
+#pragma unroll
+                        for (int q = 0; q < kChainSlots; ++q) {
+                            mb[q] = rb[q];
+                            mw[q] = rw[q];
+                        }
+                        in_regs = false;
+                    }
+                    int q = 0;
+                    while (q < len && mb[q] != b) ++q;
+                    if (q == len) {
+                        mb[len] = b;
+                        mw[len] = x;
+                        ++len;
+                    } else {
+                        mw[q] += x;
+                    }
                 }
             }
-            if (in_lds) {
-                // sort the slots by column, then to the global scratch
-                for (int i = 1; i < len; ++i) {
-                    const uint16_t b = sb[i * T + tid];
-                    const double x = sw[i * T + tid];
-                    int j = i - 1;
-                    while (j >= 0 && sb[j * T + tid] > b) {
-                        sb[(j + 1) * T + tid] = sb[j * T + tid];
-                        sw[(j + 1) * T + tid] = sw[j * T + tid];
-                        --j;
+            if (in_regs) {
+                // odd-even transposition sort by column (unused slots last)
+#pragma unroll
+                for (int pass = 0; pass < kChainSlots; ++pass) {
+#pragma unroll
+                    for (int q = pass & 1; q + 1 < kChainSlots; q += 2) {
+                        if (rb[q] > rb[q + 1]) {
+                            const int tb = rb[q];
+                            rb[q] = rb[q + 1];
+                            rb[q + 1] = tb;
+                            const double tw = rw[q];
+                            rw[q] = rw[q + 1];
+                            rw[q + 1] = tw;
+                        }
                     }
-                    sb[(j + 1) * T + tid] = b;
-                    sw[(j + 1) * T + tid] = x;
                 }
-                for (int q = 0; q < len; ++q) {
-                    mb[q] = sb[q * T + tid];
-                    mw[q] = sw[q * T + tid];
+#pragma unroll
+                for (int q = 0; q < kChainSlots; ++q) {
+                    if (q < len) {
+                        mb[q] = rb[q];
+                        mw[q] = rw[q];
+                    }
                 }
                 J.rcount[a] = len;
                 continue;

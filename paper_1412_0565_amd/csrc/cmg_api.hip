@@ -201,15 +201,38 @@ struct cmg_ctx {
     int* h_flags = nullptr;     // pinned: done flag after each chunk of steps
     std::vector<hipEvent_t> chunk_ev;
 
+    // Device memory of the handle (hierarchy, refinement state, job
+    // tables) comes from a bump arena over a few large chunks of the
+    // caller's allocator, released by cmg_free: a setup makes a handful of
+    // allocator calls instead of about a hundred (each a callback into the
+    // caller, e.g. Python).  Transient buffers use dalloc_direct.
+    std::vector<void*> chunks;
+    char* acur = nullptr;
+    size_t aleft = 0;
+    size_t achunk = (size_t)4 << 20;  // first chunk; set from the input size by setup
     void* dalloc(size_t bytes) {
-        void* p = alloc.alloc(bytes == 0 ? 8 : bytes, (void*)stream, alloc.user);
-        if (p) {
-            owned.push_back(p);
-            footprint += bytes;
+        bytes = (std::max<size_t>(bytes, 8) + 255) & ~(size_t)255;
+        if (bytes > aleft) {
+            const size_t cs = std::max(bytes, chunks.empty() ? achunk : std::max<size_t>(achunk / 4, (size_t)1 << 20));
+            void* p = alloc.alloc(cs, (void*)stream, alloc.user);
+            if (!p) return nullptr;
+            chunks.push_back(p);
+            acur = (char*)p;
+            aleft = cs;
+            footprint += cs;
         }
+        void* r = acur;
+        acur += bytes;
+        aleft -= bytes;
+        return r;
+    }
+    void dfree(void*) {}  // arena memory goes back with the handle
+    void* dalloc_direct(size_t bytes) {
+        void* p = alloc.alloc(bytes == 0 ? 8 : bytes, (void*)stream, alloc.user);
+        if (p) owned.push_back(p);
         return p;
     }
-    void dfree(void* p) {
+    void dfree_direct(void* p) {
         if (!p) return;
         auto it = std::find(owned.begin(), owned.end(), p);
         if (it != owned.end()) owned.erase(it);
@@ -218,6 +241,7 @@ struct cmg_ctx {
     ~cmg_ctx() {
         if (stream || true) (void)hipStreamSynchronize(stream);
         for (void* p : owned) alloc.free(p, (void*)stream, alloc.user);
+        for (void* p : chunks) alloc.free(p, (void*)stream, alloc.user);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         for (hipEvent_t e : chunk_ev) (void)hipEventDestroy(e);
         if (h_flags) (void)hipHostFree(h_flags);
@@ -280,46 +304,65 @@ struct SetupTmp {
     unsigned* vflags = nullptr;
     double* bmax = nullptr;              // per-block maxima of the row pass
     unsigned long long* ri = nullptr;    // row information of level j at ri[4j .. 4j+3]
+    void* block = nullptr;               // the one allocation all of the above point into
     std::vector<int> ri_pending;         // levels whose row information is still on the device
 };
 
 constexpr int kMaxLevels = 64;
 
+// The setup scratch is one allocation, carved into 256-byte aligned pieces.
+struct Carver {
+    char* base = nullptr;
+    size_t off = 0;
+    template <typename T>
+    T* take(int64_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = (T*)(base ? base + off : nullptr);
+        off += sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+        return p;
+    }
+};
+
+void carve_tmp(Carver& cv, SetupTmp& t, int32_t n, int64_t nnz) {
+    t.h = cv.take<int32_t>(n);
+    t.slot = cv.take<unsigned long long>(n);
+    t.live = cv.take<uint8_t>(n);
+    t.state = cv.take<uint8_t>(n);
+    t.pairseed = cv.take<int32_t>(n);
+    t.rootseed = cv.take<int32_t>(n);
+    t.flags = cv.take<int32_t>(n);
+    t.rank = cv.take<int32_t>(n);
+    t.scan_tmp = cv.take<long long>(std::max<int64_t>(scan_tmp_elems(std::max<int64_t>(n, nnz)), 16));
+    t.k0 = cv.take<unsigned long long>(nnz);
+    t.k1 = cv.take<unsigned long long>(nnz);
+    t.v0 = cv.take<double>(nnz);
+    t.v1 = cv.take<double>(nnz);
+    t.heads = cv.take<int32_t>(nnz);
+    t.idx = cv.take<int32_t>(nnz);
+    const int64_t nsc = sort_tmp_elems(nnz);
+    t.sort_counts = cv.take<int32_t>(nsc);
+    t.sort_scan = cv.take<long long>(scan_tmp_elems(nsc) + 4);
+    t.scal = cv.take<unsigned long long>(8);
+    t.totals = cv.take<long long>(4);
+    t.vflags = cv.take<unsigned>(4);
+    t.bmax = cv.take<double>(4 * kRowinfoMaxBlocks);
+    t.ri = cv.take<unsigned long long>(4 * kMaxLevels);
+}
+
 cmg_status alloc_tmp(cmg_ctx* c, SetupTmp& t, int32_t n, int64_t nnz) {
-    ALLOC(t.h, int32_t, n);
-    ALLOC(t.slot, unsigned long long, n);
-    ALLOC(t.live, uint8_t, n);
-    ALLOC(t.state, uint8_t, n);
-    ALLOC(t.pairseed, int32_t, n);
-    ALLOC(t.rootseed, int32_t, n);
-    ALLOC(t.flags, int32_t, n);
-    ALLOC(t.rank, int32_t, n);
-    ALLOC(t.scan_tmp, long long, std::max<int64_t>(scan_tmp_elems(std::max<int64_t>(n, nnz)), 16));
-    ALLOC(t.k0, unsigned long long, nnz);
-    ALLOC(t.k1, unsigned long long, nnz);
-    ALLOC(t.v0, double, nnz);
-    ALLOC(t.v1, double, nnz);
-    ALLOC(t.heads, int32_t, nnz);
-    ALLOC(t.idx, int32_t, nnz);
-    int64_t nsc = sort_tmp_elems(nnz);
-    ALLOC(t.sort_counts, int32_t, nsc);
-    ALLOC(t.sort_scan, long long, scan_tmp_elems(nsc) + 4);
-    ALLOC(t.scal, unsigned long long, 8);
-    ALLOC(t.totals, long long, 4);
-    ALLOC(t.vflags, unsigned, 4);
-    ALLOC(t.bmax, double, 4 * kRowinfoMaxBlocks);
-    ALLOC(t.ri, unsigned long long, 4 * kMaxLevels);
+    Carver size;
+    carve_tmp(size, t, n, nnz);
+    Carver cv;
+    cv.base = (char*)c->dalloc_direct(size.off);
+    if (!cv.base) return CMG_E_OOM;
+    carve_tmp(cv, t, n, nnz);
+    t.block = cv.base;
     return CMG_OK;
 }
 
 void free_tmp(cmg_ctx* c, SetupTmp& t) {
-    void* ps[] = {t.h, t.slot, t.live, t.state, t.pairseed, t.rootseed, t.flags, t.rank, t.scan_tmp,
-                  t.k0, t.k1, t.v0, t.v1, t.heads, t.idx, t.sort_counts, t.sort_scan, t.scal, t.totals,
-                  t.vflags, t.bmax, t.ri};
-    size_t bytes = 0;
-    (void)bytes;
     (void)hipStreamSynchronize(c->stream);
-    for (void* p : ps) c->dfree(p);
+    c->dfree_direct(t.block);
     t = SetupTmp{};
 }
 
@@ -492,14 +535,14 @@ cmg_status coarsen_chain(cmg_ctx* c, SetupTmp& t, int j0, int* next) {
     ALLOC(job.aw, double, cw);
     job.acw_cap = cw;
     const size_t hbytes = sizeof(ChainHdr) * max_levels + 16;
-    char* hd_dev = (char*)c->dalloc(hbytes);
+    char* hd_dev = (char*)c->dalloc_direct(hbytes);
     if (!hd_dev) return CMG_E_OOM;
     job.hdr = (ChainHdr*)hd_dev;
     job.out = (int32_t*)(hd_dev + sizeof(ChainHdr) * max_levels);
     CK(launch_coarsen_chain(job, s));
     std::vector<char> hb(hbytes);
     cmg_status st = d2h(c, hb.data(), hd_dev, hbytes);
-    c->dfree(hd_dev);
+    c->dfree_direct(hd_dev);
     if (st != CMG_OK) return st;
     const ChainHdr* hdr = (const ChainHdr*)hb.data();
     const int32_t* out = (const int32_t*)(hb.data() + sizeof(ChainHdr) * max_levels);
@@ -982,6 +1025,9 @@ cmg_status build_refine_plan(cmg_ctx* c) {
 cmg_status setup_impl(cmg_ctx* c, int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
                       const void* w, cmg_valtype wtype, cmg_memspace where) {
     hipStream_t s = c->stream;
+    // first arena chunk: level 0's CSR copy, vectors and refinement state
+    // plus the coarser levels (together about half of level 0)
+    c->achunk = (size_t)(12 * nnz + 48 * (int64_t)n) + ((size_t)2 << 20);
     HostLevel L0;
     L0.n = n;
     L0.nnz = nnz;
@@ -996,7 +1042,7 @@ cmg_status setup_impl(cmg_ctx* c, int32_t n, int64_t nnz, const int32_t* row_ptr
     void* wtmp = nullptr;
     if (wf32) {
         if (where == CMG_MEM_HOST) {
-            wtmp = c->dalloc(sizeof(float) * nnz);
+            wtmp = c->dalloc_direct(sizeof(float) * nnz);
             if (!wtmp) return CMG_E_OOM;
             CK(hipMemcpyAsync(wtmp, w, sizeof(float) * nnz, hipMemcpyHostToDevice, s));
             wdev = wtmp;
@@ -1006,14 +1052,14 @@ cmg_status setup_impl(cmg_ctx* c, int32_t n, int64_t nnz, const int32_t* row_ptr
         CK(hipMemcpyAsync(L0.w64, w, sizeof(double) * nnz, kind, s));
     }
     // validation (on the handle's copy)
-    unsigned* vf = (unsigned*)c->dalloc(sizeof(unsigned) * 4);
+    unsigned* vf = (unsigned*)c->dalloc_direct(sizeof(unsigned) * 4);
     if (!vf) return CMG_E_OOM;
     CK(hipMemsetAsync(vf, 0, sizeof(unsigned), s));
     CK(launch_validate(n, nnz, L0.rp, L0.col, L0.w64, 0, c->opt.validate_full, vf, s));
     unsigned flags = 0;
     cmg_status st = d2h(c, &flags, vf, 1);
-    c->dfree(vf);
-    if (wtmp) c->dfree(wtmp);
+    c->dfree_direct(vf);
+    if (wtmp) c->dfree_direct(wtmp);
     if (st != CMG_OK) return st;
     if (flags & (kBadGraph | kAsym)) return CMG_E_GRAPH;
     if (flags & kIsolated) return CMG_E_ISOLATED;
@@ -1319,7 +1365,7 @@ cmg_status batch_impl(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
         pack(round, 1);
     }
     const size_t bytes = sizeof(CoarseJob) * cj.size() + sizeof(BlockJob) * bj.size() + sizeof(GridJob) * gj.size();
-    char* d = (char*)c0->dalloc(bytes + 64);
+    char* d = (char*)c0->dalloc_direct(bytes + 64);
     if (!d) return CMG_E_OOM;
     std::vector<char> h(bytes);
     size_t off = 0;
@@ -1358,7 +1404,7 @@ cmg_status batch_impl(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
     for (int i = 0; e == hipSuccess && i < count && status == CMG_OK; ++i)
         status = enqueue_readback(hs[i], xs ? xs[i] : nullptr, where, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    c0->dfree(d);
+    c0->dfree_direct(d);
     if (e != hipSuccess) {
         set_error("batch launch", e, __LINE__);
         (void)hipGetLastError();

@@ -428,28 +428,55 @@ __global__ void k_gal_heads(int64_t m, const unsigned long long* __restrict__ nv
 // coarse rows that start there.
 // vals == nullptr: packed words (key << kshift | fine position), weights
 // read from the fine level's w by position
-__global__ void k_gal_reduce(int64_t m, const unsigned long long* __restrict__ keys,
-                             const double* __restrict__ vals, const double* __restrict__ wfine,
-                             int kshift, const int32_t* __restrict__ heads,
-                             const int32_t* __restrict__ idx, int64_t mult, int nc, int64_t zc,
-                             int32_t* __restrict__ rp, int32_t* __restrict__ col,
-                             double* __restrict__ w) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= m || !heads[t]) return;
+// k / mult for keys of the Galerkin sort: a double estimate corrected by
+// one (exact below 2^52), else the integer division
+__device__ __forceinline__ unsigned long long key_row(unsigned long long k, unsigned long long mult, double inv) {
+    if (k >> 52) return k / mult;
+    unsigned long long q = (unsigned long long)((double)k * inv);
+    if (q * mult > k) --q;
+    else if ((q + 1) * mult <= k) ++q;
+    return q;
+}
+
+// The block's keys and weights are gathered into LDS by all its threads
+// first; a run is then summed from LDS, reaching into global memory only
+// where it continues past the block.
+__global__ void __launch_bounds__(kBlk)
+    k_gal_reduce(int64_t m, const unsigned long long* __restrict__ keys, const double* __restrict__ vals,
+                 const double* __restrict__ wfine, int kshift, const int32_t* __restrict__ heads,
+                 const int32_t* __restrict__ idx, int64_t mult, double inv_mult, int nc, int64_t zc,
+                 int32_t* __restrict__ rp, int32_t* __restrict__ col, double* __restrict__ w) {
+    __shared__ unsigned long long sk[kBlk];
+    __shared__ double sw[kBlk];
+    const int64_t b0 = (int64_t)blockIdx.x * kBlk;
+    const int64_t t = b0 + threadIdx.x;
     const unsigned long long pmask = (kshift > 0) ? (~0ull >> (64 - kshift)) : 0ull;
-    unsigned long long k = keys[t] >> kshift;
-    int row = (int)(k / (unsigned long long)mult);
-    int c = (int)(k - (unsigned long long)row * (unsigned long long)mult);
-    double s = vals ? vals[t] : wfine[keys[t] & pmask];
-    int64_t u = t + 1;
-    while (u < m && (keys[u] >> kshift) == k) {
-        s += vals ? vals[u] : wfine[keys[u] & pmask];
-        ++u;
+    if (t < m) {
+        const unsigned long long kw = keys[t];
+        sk[threadIdx.x] = kw >> kshift;
+        sw[threadIdx.x] = vals ? vals[t] : wfine[kw & pmask];
     }
-    int32_t o = idx[t];
+    __syncthreads();
+    if (t >= m || !heads[t]) return;
+    const unsigned long long k = sk[threadIdx.x];
+    const unsigned long long um = (unsigned long long)mult;
+    const int row = (int)key_row(k, um, inv_mult);
+    const int c = (int)(k - (unsigned long long)row * um);
+    double s = sw[threadIdx.x];
+    const int64_t bend = min(b0 + kBlk, m);
+    int64_t u = t + 1;
+    for (; u < bend && sk[u - b0] == k; ++u) s += sw[u - b0];
+    if (u == bend) {
+        for (; u < m && (keys[u] >> kshift) == k; ++u) s += vals ? vals[u] : wfine[keys[u] & pmask];
+    }
+    const int32_t o = idx[t];
     col[o] = c;
     w[o] = s;
-    int prow = (t == 0) ? -1 : (int)((keys[t - 1] >> kshift) / (unsigned long long)mult);
+    int prow = -1;
+    if (t > 0) {
+        const unsigned long long kp = (t > b0) ? sk[threadIdx.x - 1] : (keys[t - 1] >> kshift);
+        prow = (int)key_row(kp, um, inv_mult);
+    }
     for (int r = prow + 1; r <= row; ++r) rp[r] = o;
     if (u == m) {
         for (int r = row + 1; r <= nc; ++r) rp[r] = (int32_t)zc;
@@ -733,7 +760,7 @@ hipError_t launch_gal_reduce(int64_t m, const unsigned long long* keys, const do
                              double* w_out, hipStream_t s) {
     if (m == 0) return hipSuccess;
     hipLaunchKernelGGL(k_gal_reduce, dim3(nblocks(m, kBlk)), dim3(kBlk), 0, s, m, keys, vals, wfine, kshift,
-                       heads, idx, mult, nc, zc, rp_out, col_out, w_out);
+                       heads, idx, mult, 1.0 / (double)mult, nc, zc, rp_out, col_out, w_out);
     return hipGetLastError();
 }
 

@@ -1162,9 +1162,15 @@ cmg_status finalize(cmg_ctx* c, double t0, bool timed, double* lambda, cmg_stats
             L.margin = c->h_st[j].margin;
             if (c->h_st[j].maxit) status = CMG_W_MAXIT;
             if (L.in_block && c->h_st[j].err) {
-                std::snprintf(g_last_error, sizeof(g_last_error),
-                              "level %d: a row longer than its register layout (%d slots of %d lanes)", j, L.bslots,
-                              L.lanes);
+                if (c->h_st[j].err == 2)
+                    std::snprintf(g_last_error, sizeof(g_last_error),
+                                  "level %d: register layout (%d lanes, %d rows per group, %d slots, %d waves) does "
+                                  "not fit the level",
+                                  j, L.lanes, L.bregs, L.bslots, L.bwaves);
+                else
+                    std::snprintf(g_last_error, sizeof(g_last_error),
+                                  "level %d: a row longer than its register layout (%d slots of %d lanes)", j,
+                                  L.bslots, L.lanes);
                 return CMG_E_DEVICE;
             }
         }

@@ -423,9 +423,6 @@ __global__ void __launch_bounds__(kChainThreads) k_coarsen_chain(ChainJob J) {
 }  // namespace
 
 hipError_t launch_coarsen_chain(const ChainJob& job, hipStream_t s) {
-    static const hipError_t attr =
-        hipFuncSetAttribute((const void*)k_coarsen_chain, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kChainLds);
-    if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL(k_coarsen_chain, dim3(1), dim3(kChainThreads), kChainLds, s, job);
     return hipGetLastError();
 }

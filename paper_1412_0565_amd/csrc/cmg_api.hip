@@ -664,7 +664,16 @@ constexpr int kChunkEvents = 16;
 int default_grid(const HostLevel& L, int j, int ncu) {
     int cap = grid_cap(L, j, L.lanes);
     if (step_bytes(L) <= ((int64_t)256 << 20)) cap = std::min(cap, 3 * ncu);
-    int64_t want = ((int64_t)L.n + L.nnz + 2047) / 2048;
+    // about 2k rows + entries per workgroup; on mid-size levels (up to 4M
+    // rows + entries) no more than sqrt(work)/4.5 workgroups, since there the
+    // barrier's cost, which grows with the count, outweighs the step's work
+    // (measured on MI355X: rgg1m level 1, 2.9M rows + entries, 73 us per
+    // step on 384 workgroups against 90 on 768; grid3d128 level 3, 0.93M:
+    // 17.9 us on 216 against 21.2 on 456; at 8M, 768 workgroups beat 600)
+    const int64_t work = (int64_t)L.n + L.nnz;
+    int64_t want = (work + 2047) / 2048;
+    if (work <= ((int64_t)4 << 20))
+        want = std::min<int64_t>(want, std::max<int64_t>((int64_t)(std::sqrt((double)work) / 4.5), 8));
     want = ((want + 7) / 8) * 8;
     return (int)std::min<int64_t>(std::max<int64_t>(want, 8), cap);
 }

@@ -412,7 +412,6 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
     // live candidate edge changes nothing
     for (int batch = 4, total = 0;; batch = 2) {
         for (int r = 0; r < batch; ++r) {
-            CK(hipMemsetAsync(t.scal + 2, 0, sizeof(unsigned long long), s));
             CK(launch_hec_round(L.n, t.h, seed, j, t.live, t.state, t.pairseed, t.slot, t.scal + 2, s));
         }
         total += batch;

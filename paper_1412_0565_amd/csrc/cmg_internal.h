@@ -75,6 +75,8 @@ hipError_t launch_rowinfo(int n, int lanes, const int32_t* rp, const int32_t* co
                           int32_t* h, double* bmax, unsigned long long* out, hipStream_t s);
 hipError_t launch_hec_init(int n, const int32_t* h, uint64_t seed, int level, uint8_t* live,
                            uint8_t* state, int32_t* pairseed, unsigned long long* slot, hipStream_t s);
+// One greedy round; *any_live ends as 1 if a candidate edge survives it,
+// else 0.
 hipError_t launch_hec_round(int n, const int32_t* h, uint64_t seed, int level, uint8_t* live,
                             uint8_t* state, int32_t* pairseed, unsigned long long* slot,
                             unsigned long long* any_live, hipStream_t s);

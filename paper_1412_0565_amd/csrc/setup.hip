@@ -29,38 +29,43 @@ inline unsigned nblocks(int64_t m, int per) { return (unsigned)((m + per - 1) / 
 
 // ------------------------------------------------------------ validation
 
+// One group of kValidateLanes lanes per row (row n: the row-pointer ends);
+// each lane checks every kValidateLanes-th entry of the row against the
+// entry before it.
+constexpr int kValidateLanes = 8;
+
 template <typename W>
 __global__ void k_validate(int n, int64_t nnz, const int32_t* __restrict__ rp,
                            const int32_t* __restrict__ col, const W* __restrict__ w, int full,
                            unsigned* flags) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (kValidateLanes - 1);
+    const int i = blockIdx.x * (blockDim.x / kValidateLanes) + threadIdx.x / kValidateLanes;
     if (i > n) return;
     unsigned f = 0;
     if (i == n) {
-        if ((int64_t)rp[n] != nnz) f |= kBadGraph;
-        if (rp[0] != 0) f |= kBadGraph;
+        if (lane == 0 && ((int64_t)rp[n] != nnz || rp[0] != 0)) f |= kBadGraph;
     } else {
-        int a = rp[i], b = rp[i + 1];
+        const int a = rp[i], b = rp[i + 1];
         if (a < 0 || b < a || (int64_t)b > nnz) {
             f |= kBadGraph;
         } else if (a == b) {
             f |= kIsolated;
         } else {
-            int prev = -1;
-            for (int e = a; e < b; ++e) {
-                int c = col[e];
-                double x = (double)w[e];
-                if (c < 0 || c >= n || c == i || c <= prev) f |= kBadGraph;
-                if (!(x > 0.0) || !isfinite(x)) f |= kBadGraph;
-                prev = c;
-                if (full && c >= 0 && c < n && !(f & kBadGraph) && rp[c] >= 0 && rp[c] <= rp[c + 1] &&
-                    (int64_t)rp[c + 1] <= nnz) {
+            for (int e = a + lane; e < b; e += kValidateLanes) {
+                const int c = col[e];
+                const int prev = e > a ? col[e - 1] : -1;
+                const double x = (double)w[e];
+                bool bad = c < 0 || c >= n || c == i || c <= prev;
+                if (!(x > 0.0) || !isfinite(x)) bad = true;
+                if (bad) {
+                    f |= kBadGraph;
+                } else if (full && rp[c] >= 0 && rp[c] <= rp[c + 1] && (int64_t)rp[c + 1] <= nnz) {
                     // binary search i in row c, weights must agree
                     int lo = rp[c], hi = rp[c + 1] - 1;
                     bool found = false;
                     while (lo <= hi) {
-                        int mid = (lo + hi) >> 1;
-                        int cm = col[mid];
+                        const int mid = (lo + hi) >> 1;
+                        const int cm = col[mid];
                         if (cm == i) {
                             found = ((double)w[mid] == x);
                             break;
@@ -204,10 +209,14 @@ __global__ void k_hec_init(int n, const int32_t* __restrict__ h, uint64_t seed, 
     slot[v] = kNoKey;
 }
 
-// Each live candidate edge {v, h(v)} posts its key at both endpoints.
+// Each live candidate edge {v, h(v)} posts its key at both endpoints.  The
+// round's "any live" flag, raised only by k_hec_kill after this kernel, is
+// cleared here.
 __global__ void k_hec_post(int n, const int32_t* __restrict__ h, uint64_t seed, int level,
-                           const uint8_t* __restrict__ live, unsigned long long* slot) {
+                           const uint8_t* __restrict__ live, unsigned long long* slot,
+                           unsigned long long* any_live) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v == 0) *any_live = 0ull;
     if (v >= n || !live[v]) return;
     unsigned long long k = hec_key(seed, level, v);
     atomicMin(&slot[v], k);
@@ -599,7 +608,7 @@ __global__ void k_fill_u32(unsigned* p, unsigned v, int64_t m) {
 
 hipError_t launch_validate(int n, int64_t nnz, const int32_t* rp, const int32_t* col, const void* w,
                            int wf32, int full, unsigned* flags, hipStream_t s) {
-    unsigned nb = nblocks((int64_t)n + 1, kBlk);
+    unsigned nb = nblocks((int64_t)n + 1, kBlk / kValidateLanes);
     if (wf32)
         hipLaunchKernelGGL(k_validate<float>, dim3(nb), dim3(kBlk), 0, s, n, nnz, rp, col,
                            (const float*)w, full, flags);
@@ -655,7 +664,7 @@ hipError_t launch_hec_round(int n, const int32_t* h, uint64_t seed, int level, u
                             uint8_t* state, int32_t* pairseed, unsigned long long* slot,
                             unsigned long long* any_live, hipStream_t s) {
     unsigned nb = nblocks(n, kBlk);
-    hipLaunchKernelGGL(k_hec_post, dim3(nb), dim3(kBlk), 0, s, n, h, seed, level, live, slot);
+    hipLaunchKernelGGL(k_hec_post, dim3(nb), dim3(kBlk), 0, s, n, h, seed, level, live, slot, any_live);
     hipLaunchKernelGGL(k_hec_accept, dim3(nb), dim3(kBlk), 0, s, n, h, seed, level, live, state,
                        pairseed, slot);
     hipLaunchKernelGGL(k_hec_kill, dim3(nb), dim3(kBlk), 0, s, n, h, live, state, slot, any_live);

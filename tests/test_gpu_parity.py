@@ -205,6 +205,41 @@ def test_invalid_graphs(case):
     assert ei.value.status == exp
 
 
+@pytest.mark.parametrize("case", ["valid", "unsorted", "duplicate", "range", "selfloop", "zero", "asym"])
+def test_invalid_entry_deep_in_a_long_row(case):
+    """Faults past the first lanes of the row check: the hub row of a
+    40-vertex star holds 39 entries, each altered at positions 9-29."""
+    from paper_1412_0565_amd import cmg
+
+    g = G.star(40)
+    rp, col, w = g.row_ptr.copy(), g.col.copy(), g.w.copy()
+    hub = int(np.argmax(np.diff(rp)))
+    a = int(rp[hub])
+    assert rp[hub + 1] - a == 39
+    opts = {}
+    if case == "unsorted":
+        col[a + 12], col[a + 13] = col[a + 13], col[a + 12]
+    elif case == "duplicate":
+        col[a + 20] = col[a + 19]
+    elif case == "range":
+        col[a + 29] = 40
+    elif case == "selfloop":
+        col[a + 9] = hub
+    elif case == "zero":
+        w[a + 17] = 0.0
+    elif case == "asym":
+        w[a + 17] = 3.0
+        opts["validate_full"] = 1
+    if case == "valid":
+        opts["validate_full"] = 1
+        h = cmg.cmg_setup(40, rp, col, w, cmg.cmg_options_default(**opts))
+        cmg.cmg_free(h)
+        return
+    with pytest.raises(cmg.CmgError) as ei:
+        cmg.cmg_setup(40, rp, col, w, cmg.cmg_options_default(**opts))
+    assert ei.value.status == cmg.CMG_E_GRAPH
+
+
 def test_maxit_warning():
     from paper_1412_0565_amd import cmg
 

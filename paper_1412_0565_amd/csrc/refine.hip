@@ -1065,22 +1065,25 @@ __device__ __forceinline__ bool job_allreduce(double (&v)[NV], GridCtx& c, doubl
 
 // One PI step: y_i = s (g (w_i - mu) + sum_k a_ik (w_k - w_i)), stored as
 // T; acc += {y, y^2, y v, v} with v = (w_i - mu) s.
+// Rows and entries are numbered from the arrays the traversal reads (the
+// level's, or a workgroup's LDS stage); vector index = row + roff.
 template <typename T>
 struct PiOp {
     const int32_t* __restrict__ col;
     const T* __restrict__ wv;
     const T* __restrict__ win;
     T* __restrict__ wout;
+    int roff;
     double mu, s, g;
     double acc[4];
-    __device__ __forceinline__ double xi(int i) const { return (double)win[i]; }
+    __device__ __forceinline__ double xi(int i) const { return (double)win[roff + i]; }
     __device__ __forceinline__ double entry(int e, double x) const {
         return (double)wv[e] * ((double)win[col[e]] - x);
     }
     __device__ __forceinline__ void row(int i, double x, double t) {
         const double v = (x - mu) * s;
         const T ys = (T)(s * (g * (x - mu) + t));
-        wout[i] = ys;
+        wout[roff + i] = ys;
         const double yd = (double)ys;
         acc[0] += yd;
         acc[1] += yd * yd;
@@ -1334,10 +1337,28 @@ __device__ __forceinline__ void drive(const LevelDev& L, int r0, int r1, Op& op,
     }
 }
 
+// ---- a workgroup's rows staged in LDS
+//
+// A grid barrier's acquire invalidates the L2, so on a level whose
+// workgroup shares are small every step would fetch the row pointers,
+// columns and weights again before it can gather.  When a workgroup's rows
+// and entries fit the LDS stage (FP64 levels, G lanes per row) they are
+// copied there once per level and the steps read them from LDS through the
+// same traversal; only the vector gathers go to memory.  Rows and entries
+// are visited in the same order, so the sums are bit for bit those of the
+// global traversal.
+constexpr int kStageRows = 1024;
+constexpr int kStageEnts = 2560;
+struct StageLds {
+    int32_t rp[kStageRows + 1];  // row pointers relative to the first entry
+    int32_t col[kStageEnts];
+    double w[kStageEnts];
+};
+
 // ---- refinement of one level by a job's workgroups
 
 template <typename T, int TRAV>
-__device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeShared* sh) {
+__device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeShared* sh, StageLds* stg) {
     const LevelDev& L = J.L;
     const double tol = J.tol;
     const int maxit = J.maxit;
@@ -1346,6 +1367,29 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     T* b0 = (T*)L.buf0;
     T* b1 = (T*)L.buf1;
     const double n = (double)L.n;
+    // traversal arrays of the PI steps: the level's, or the LDS stage
+    const int32_t* trp = L.rp;
+    const int32_t* tcol = L.col;
+    const T* tw = (const T*)(sizeof(T) == 4 ? (const void*)L.w32 : (const void*)L.w64);
+    int tlo = r0, thi = r1, roff = 0;
+    if constexpr (TRAV > 0 && sizeof(T) == 8) {
+        const int a0 = L.rp[r0], a1 = L.rp[r1];
+        // the same in every thread of the workgroup
+        if (stg != nullptr && r1 - r0 <= kStageRows && a1 - a0 <= kStageEnts) {
+            for (int i = threadIdx.x; i <= r1 - r0; i += blockDim.x) stg->rp[i] = L.rp[r0 + i] - a0;
+            for (int e = threadIdx.x; e < a1 - a0; e += blockDim.x) {
+                stg->col[e] = L.col[a0 + e];
+                stg->w[e] = L.w64[a0 + e];
+            }
+            __syncthreads();
+            trp = stg->rp;
+            tcol = stg->col;
+            tw = (const T*)stg->w;
+            tlo = 0;
+            thi = r1 - r0;
+            roff = r0;
+        }
+    }
     // prolongation from level j+1 (or the hashed uniform start)
     double sum[1] = {0.0};
     if (J.uniform) {
@@ -1375,8 +1419,9 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     int cur = 0, k = 0, hit = 0;
     double utv = 0.0, pmu = mu, ps = s;
     PiOp<T> op;
-    op.col = L.col;
-    op.wv = (const T*)(sizeof(T) == 4 ? (const void*)L.w32 : (const void*)L.w64);
+    op.col = tcol;
+    op.wv = tw;
+    op.roff = roff;
     op.g = L.g;
     while (true) {
         op.win = cur ? b1 : b0;
@@ -1384,7 +1429,8 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
         op.mu = mu;
         op.s = s;
         op.acc[0] = op.acc[1] = op.acc[2] = op.acc[3] = 0.0;
-        drive<TRAV>(L, r0, r1, op, sh);
+        if constexpr (TRAV == 0) drive_merge(L.rp, r0, r1, op, *sh);
+        else drive_rows<TRAV>(trp, tlo, thi, op);
         if (!job_allreduce<4>(op.acc, c, red)) return;
         const double mu2 = op.acc[0] / n;
         const double s2 = 1.0 / sqrt(op.acc[1] - op.acc[0] * mu2);
@@ -1555,7 +1601,7 @@ __device__ void residency_count(const GridJob& J) {
 // storage precision to keep registers low; a packed launch holds one kind.
 template <int TRAV, typename T>
 __device__ __forceinline__ void refine_entry(const GridJob* __restrict__ jobs, int njobs, double* red,
-                                             MergeShared* sh) {
+                                             MergeShared* sh, StageLds* stg) {
     const GridJob J = jobs[find_job(jobs, njobs)];
     if (J.tag == kResidencyTag) {
         residency_count(J);
@@ -1563,14 +1609,14 @@ __device__ __forceinline__ void refine_entry(const GridJob* __restrict__ jobs, i
     }
     GridCtx c = make_ctx(J);
     if (c.vb < 0 || c.vb >= c.nb) return;
-    refine_level<T, TRAV>(J, c, red, sh);
+    refine_level<T, TRAV>(J, c, red, sh, stg);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kGridBlock) k_refine_merge(const GridJob* __restrict__ jobs, int njobs) {
     __shared__ double red[16 * 5 + 8];
     __shared__ MergeShared msh;
-    refine_entry<0, T>(jobs, njobs, red, &msh);
+    refine_entry<0, T>(jobs, njobs, red, &msh, nullptr);
 }
 
 // G lanes per row.  Held to 8 waves per SIMD (at most 64 VGPRs and about
@@ -1580,7 +1626,12 @@ template <int G, typename T>
 __global__ void __launch_bounds__(kGridBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_refine_rows(const GridJob* __restrict__ jobs, int njobs) {
     __shared__ double red[16 * 5 + 8];
-    refine_entry<G, T>(jobs, njobs, red, nullptr);
+    StageLds* stg = nullptr;
+    if constexpr (sizeof(T) == 8) {
+        __shared__ StageLds st;
+        stg = &st;
+    }
+    refine_entry<G, T>(jobs, njobs, red, nullptr, stg);
 }
 
 // One launch finishes the finest level of each job.
@@ -1719,6 +1770,7 @@ __global__ void __launch_bounds__(kStepBlock) k_step_spmv(const StepJob* __restr
     PiOp<T> op;
     op.col = L.col;
     op.wv = (const T*)(sizeof(T) == 4 ? (const void*)L.w32 : (const void*)L.w64);
+    op.roff = 0;
     op.g = L.g;
     op.win = (const T*)(c.cur ? L.buf1 : L.buf0);
     op.wout = (T*)(c.cur ? L.buf0 : L.buf1);

@@ -87,6 +87,10 @@ __device__ void block_max4(double (&m)[4], double* sm) {
 
 // Columns a thread keeps in registers while it forms a coarse row.
 constexpr int kChainSlots = 12;
+// Longest fine row of a level this kernel coarsens (measured on MI355X:
+// 3D-grid levels with 27-47 entries per row took 0.27-1.9 ms here against
+// a few hundred microseconds on the grid kernels).
+constexpr int kChainLongRow = 24;
 constexpr size_t kChainLds = sizeof(int32_t) * 2 * (kChainMaxN / 2 + 1);
 
 __global__ void __launch_bounds__(kChainThreads) k_coarsen_chain(ChainJob J) {
@@ -143,6 +147,14 @@ __global__ void __launch_bounds__(kChainThreads) k_coarsen_chain(ChainJob J) {
         K = k + 1;
         if (n <= J.coarsest_n || k + 1 >= J.max_levels) {
             stop_reason = (n <= J.coarsest_n) ? 1 : 5;
+            if (tid == 0) J.hdr[k] = hd;
+            break;
+        }
+        if (hd.maxlen > kChainLongRow) {
+            // rows this long make coarse rows that outgrow the register
+            // slots, and one thread per row then works in global scratch,
+            // slower than the grid kernels' sort: leave the level to them
+            stop_reason = 4;
             if (tid == 0) J.hdr[k] = hd;
             break;
         }
@@ -269,11 +281,8 @@ __global__ void __launch_bounds__(kChainThreads) k_coarsen_chain(ChainJob J) {
         __syncthreads();
         // ---- Galerkin: one thread per coarse row, contributions added in
         // fine CSR order, row sorted by coarse column.  The row is formed in
-        // the thread's LDS slots (coarse columns < 2^16 here); a row with
-        // more distinct columns moves to its global scratch and goes on there.
-        // rows of a level whose fine rows already exceed the slots start in
-        // global scratch
-        const bool reg_rows = hd.maxlen <= kChainSlots;
+        // the thread's register slots; a row with more distinct columns
+        // moves to its global scratch and goes on there.
         for (int a = tid; a < nc; a += T) {
             const int32_t* ms = J.members + J.astart[a];
             const int cnt = acnt[a];
@@ -289,7 +298,7 @@ __global__ void __launch_bounds__(kChainThreads) k_coarsen_chain(ChainJob J) {
                 rw[q] = 0.0;
             }
             int len = 0;
-            bool in_regs = reg_rows;
+            bool in_regs = true;
             for (int i = 0; i < cnt; ++i) {
                 const int m = ms[i];
                 const int e0 = rp[m], e1 = rp[m + 1];

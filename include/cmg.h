@@ -109,6 +109,12 @@ typedef struct {
                                     level's rows in registers for all its PI steps where a
                                     layout fits (rows of at most 64 entries); -1 always reads
                                     the CSR arrays.  Both give the same lambda to rounding. */
+    int32_t grid_stage;          /* FP64 levels refined by the whole grid with lanes per row:
+                                    1 (default) copies each workgroup's rows, columns and
+                                    weights to LDS once per level when they fit (at most 1024
+                                    rows and 2560 entries) and runs the PI steps from there;
+                                    0 always reads them from global memory.  Results are
+                                    bitwise equal. */
 } cmg_options;
 
 /* Per-level information (available after cmg_setup; PI fields after

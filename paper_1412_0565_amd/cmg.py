@@ -54,6 +54,7 @@ class cmg_options(C.Structure):
         ("spmv_variant", C.c_int32),
         ("autotune", C.c_int32),
         ("block_regs", C.c_int32),
+        ("grid_stage", C.c_int32),
     ]
 
 

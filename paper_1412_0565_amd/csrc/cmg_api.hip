@@ -52,6 +52,7 @@ struct HostLevel {
     int w32exact = 0;
     int64_t maxlen = 0;
     int fp32 = 0, in_block = 0, lanes = 8, grid = 0, variant = 1;
+    int stage = 1;  // grid levels: a workgroup's rows may be staged in LDS
     void* buf0 = nullptr;
     void* buf1 = nullptr;
     int32_t* part = nullptr;
@@ -596,6 +597,7 @@ LevelDev level_dev(const HostLevel& L) {
     d.bwaves = L.bwaves;
     d.bregs = L.bregs;
     d.bslots = L.bslots;
+    d.stage = L.stage;
     return d;
 }
 
@@ -831,6 +833,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
     for (int j = 0; j <= J; ++j) {
         HostLevel& L = c->lv[j];
         L.in_block = (j >= c->block_lo && j <= top) ? 1 : 0;
+        L.stage = o.grid_stage != 0 ? 1 : 0;
         L.bwaves = L.bregs = L.bslots = 0;
         if (!L.in_block) continue;
         const BlockPlan p = o.block_regs < 0 ? BlockPlan{} : plan_block_regs(L);
@@ -1130,6 +1133,7 @@ void fill_defaults(cmg_options* o) {
     o->spmv_variant = 0;
     o->autotune = 0;
     o->block_regs = 0;
+    o->grid_stage = 1;
 }
 
 // Device results of the last solve -> host staging (asynchronous).

@@ -1375,7 +1375,7 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     if constexpr (TRAV > 0 && sizeof(T) == 8) {
         const int a0 = L.rp[r0], a1 = L.rp[r1];
         // the same in every thread of the workgroup
-        if (stg != nullptr && r1 - r0 <= kStageRows && a1 - a0 <= kStageEnts) {
+        if (stg != nullptr && L.stage && r1 - r0 <= kStageRows && a1 - a0 <= kStageEnts) {
             for (int i = threadIdx.x; i <= r1 - r0; i += blockDim.x) stg->rp[i] = L.rp[r0 + i] - a0;
             for (int e = threadIdx.x; e < a1 - a0; e += blockDim.x) {
                 stg->col[e] = L.col[a0 + e];

@@ -382,6 +382,30 @@ def test_batch_rejects_duplicates():
             cmg.cmg_fiedler_batch([F.handle, F.handle])
 
 
+@pytest.mark.parametrize("name", ["rgg20k", "rgg60k", "grid128", "grid3d_20", "cl30k"])
+def test_grid_stage_is_bitwise_equal_to_global_reads(name):
+    """Grid levels whose workgroup shares are staged in LDS (default) give
+    bitwise the vector, lambda and step counts of the traversal that reads
+    the level's arrays from global memory (grid_stage=0), FP64 and mixed;
+    and both match the oracle."""
+    g = _named(name)
+    ref = oracle_of(g)
+    for prec in (0, 1):
+        res = {}
+        for stage in (1, 0):
+            lam, x, st, levels, arrays = run_gpu(g, want_levels=(prec == 0), precision=prec,
+                                                 grid_stage=stage)
+            res[stage] = (lam, np.asarray(x).copy(), [l.k for l in levels], arrays, levels, st)
+        say(f"[parity] {name} precision={prec} grid levels "
+            f"{[(j, l.grid) for j, l in enumerate(res[1][4]) if not l.in_block]} lam {res[1][0]!r}")
+        assert res[1][0] == res[0][0], (name, prec)
+        assert np.array_equal(res[1][1], res[0][1]), (name, prec)
+        assert res[1][2] == res[0][2], (name, prec)
+        if prec == 0:
+            lam, x, k, arrays, levels, st = res[1]
+            assert_fp64_parity(g, lam, x, st, levels, arrays, ref)
+
+
 @pytest.mark.parametrize("name", ["rgg20k", "grid128", "grid3d_20", "er500", "star200", "cl30k"])
 def test_block_register_rows_and_csr_agree_with_oracle(name):
     """Single-workgroup levels on register rows (default) and on the CSR

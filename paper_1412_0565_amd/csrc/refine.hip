@@ -1080,6 +1080,12 @@ struct PiOp {
     __device__ __forceinline__ double entry(int e, double x) const {
         return (double)wv[e] * ((double)win[col[e]] - x);
     }
+    // entry() on a column and weight read earlier (merge path LDS stage)
+    __device__ __forceinline__ int colof(int e) const { return col[e]; }
+    __device__ __forceinline__ double wof(int e) const { return (double)wv[e]; }
+    __device__ __forceinline__ double entry_cw(int c, double wt, double x) const {
+        return wt * ((double)win[c] - x);
+    }
     __device__ __forceinline__ void row(int i, double x, double t) {
         const double v = (x - mu) * s;
         const T ys = (T)(s * (g * (x - mu) + t));
@@ -1105,6 +1111,11 @@ struct RedoOp {
     __device__ __forceinline__ double entry(int e, double x) const {
         return w[e] * (ld_any(src, f32, col[e]) - x);
     }
+    __device__ __forceinline__ int colof(int e) const { return col[e]; }
+    __device__ __forceinline__ double wof(int e) const { return w[e]; }
+    __device__ __forceinline__ double entry_cw(int c, double wt, double x) const {
+        return wt * (ld_any(src, f32, c) - x);
+    }
     __device__ __forceinline__ void row(int i, double x, double t) {
         const double y = s * (g * (x - mu) + t);
         dst[i] = y;
@@ -1126,6 +1137,12 @@ struct EdgeOp {
         const double d = (ld_any(src, f32, col[e]) - x) * s;
         return w[e] * d * d;
     }
+    __device__ __forceinline__ int colof(int e) const { return col[e]; }
+    __device__ __forceinline__ double wof(int e) const { return w[e]; }
+    __device__ __forceinline__ double entry_cw(int c, double wt, double x) const {
+        const double d = (ld_any(src, f32, c) - x) * s;
+        return wt * d * d;
+    }
     __device__ __forceinline__ void row(int i, double x, double t) {
         const double u = (x - mu) * s;
         acc[0] += u;
@@ -1146,6 +1163,11 @@ struct ResidualOp {
     __device__ __forceinline__ double xi(int i) const { return ld_any(src, f32, i); }
     __device__ __forceinline__ double entry(int e, double x) const {
         return w[e] * (x - ld_any(src, f32, col[e]));
+    }
+    __device__ __forceinline__ int colof(int e) const { return col[e]; }
+    __device__ __forceinline__ double wof(int e) const { return w[e]; }
+    __device__ __forceinline__ double entry_cw(int c, double wt, double x) const {
+        return wt * (x - ld_any(src, f32, c));
     }
     __device__ __forceinline__ void row(int i, double x, double t) {
         const double yi = ((x - mu) * s - mean_u) / nrm;
@@ -1208,14 +1230,20 @@ __device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r
 // by many threads and a chunk of short rows by few (Merrill & Garland,
 // "Merge-based parallel sparse matrix-vector multiplication", SC 2016).
 // Per chunk the row ends are staged in LDS, every thread finds its start
-// by binary search on its diagonal, walks its items, and the partial sums
-// of rows split across threads are combined by a segmented scan in thread
-// order (deterministic), then added by the thread that completes the row.
+// by binary search on its diagonal, the chunk's entries (columns and
+// weights, a contiguous range) are copied to LDS with coalesced loads, every
+// thread walks its items from there, and the partial sums of rows split
+// across threads are combined by a segmented scan in thread order
+// (deterministic), then added by the thread that completes the row.  The
+// entry arithmetic is the operation's own, so staging changes no result.
 constexpr int kMergeIPT = 8;
 constexpr int kMergeChunk = kGridBlock * kMergeIPT;
 
 struct MergeShared {
     int win[kMergeChunk + 2];  // row starts/ends of rows ia .. ia + W (relative to the block's first entry)
+    int scol[kMergeChunk];     // the chunk's entries js .. je (relative to the block's first entry)
+    double sw[kMergeChunk];
+    int js, je;
     int crow[kGridBlock];
     double cval[kGridBlock];
     int wrow[16];
@@ -1253,6 +1281,26 @@ __device__ __forceinline__ void drive_merge(const int32_t* __restrict__ rp, int 
             else hi = mid;
         }
         int i = lo, j = diag - lo;
+        if (tid == 0) {
+            // the chunk's entry range: from this start to the coordinate of
+            // its last diagonal
+            const int dend = d0 + dl_end;
+            int lo2 = max(ia, dend - nent), hi2 = min(ia + W, dend);
+            while (lo2 < hi2) {
+                const int mid = (lo2 + hi2) >> 1;
+                if (sh.win[mid - ia + 1] <= dend - mid - 1) lo2 = mid + 1;
+                else hi2 = mid;
+            }
+            sh.js = j;
+            sh.je = dend - lo2;
+        }
+        __syncthreads();
+        const int js = sh.js;
+        for (int q = tid; q < sh.je - js; q += blockDim.x) {
+            sh.scol[q] = op.colof(e0 + js + q);
+            sh.sw[q] = op.wof(e0 + js + q);
+        }
+        __syncthreads();
         const int steps = min(dl + kMergeIPT, dl_end) - dl;
         double x = (i < nrows) ? op.xi(r0 + i) : 0.0;
         double part = 0.0;
@@ -1260,7 +1308,7 @@ __device__ __forceinline__ void drive_merge(const int32_t* __restrict__ rp, int 
         double fx = 0.0, fpart = 0.0;
         for (int q = 0; q < steps; ++q) {
             if (i < nrows && j < sh.win[i - ia + 1]) {
-                part += op.entry(e0 + j, x);
+                part += op.entry_cw(sh.scol[j - js], sh.sw[j - js], x);
                 ++j;
             } else {
                 if (frow < 0) {
@@ -1612,8 +1660,10 @@ __device__ __forceinline__ void refine_entry(const GridJob* __restrict__ jobs, i
     refine_level<T, TRAV>(J, c, red, sh, stg);
 }
 
+// At most 128 VGPRs: two workgroups of 512 threads per CU.
 template <typename T>
-__global__ void __launch_bounds__(kGridBlock) k_refine_merge(const GridJob* __restrict__ jobs, int njobs) {
+__global__ void __launch_bounds__(kGridBlock) __attribute__((amdgpu_waves_per_eu(4)))
+k_refine_merge(const GridJob* __restrict__ jobs, int njobs) {
     __shared__ double red[16 * 5 + 8];
     __shared__ MergeShared msh;
     refine_entry<0, T>(jobs, njobs, red, &msh, nullptr);

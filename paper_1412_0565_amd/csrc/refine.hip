@@ -1229,10 +1229,10 @@ __device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r
 // pieces of kMergeIPT items per thread, so a row of any length is shared
 // by many threads and a chunk of short rows by few (Merrill & Garland,
 // "Merge-based parallel sparse matrix-vector multiplication", SC 2016).
-// Per chunk the row ends are staged in LDS, every thread finds its start
-// by binary search on its diagonal, the chunk's entries (columns and
-// weights, a contiguous range) are copied to LDS with coalesced loads, every
-// thread walks its items from there, and the partial sums of rows split
+// Per chunk the row ends and the chunk's entries (columns and weights, a
+// contiguous range starting where the previous chunk's ended) are copied to
+// LDS with coalesced loads, every thread finds its start by binary search
+// on its diagonal and walks its items from there, and the partial sums of rows split
 // across threads are combined by a segmented scan in thread order
 // (deterministic), then added by the thread that completes the row.  The
 // entry arithmetic is the operation's own, so staging changes no result.
@@ -1241,9 +1241,8 @@ constexpr int kMergeChunk = kGridBlock * kMergeIPT;
 
 struct MergeShared {
     int win[kMergeChunk + 2];  // row starts/ends of rows ia .. ia + W (relative to the block's first entry)
-    int scol[kMergeChunk];     // the chunk's entries js .. je (relative to the block's first entry)
+    int scol[kMergeChunk];     // entries js .. js + kMergeChunk (relative to the block's first entry)
     double sw[kMergeChunk];
-    int js, je;
     int crow[kGridBlock];
     double cval[kGridBlock];
     int wrow[16];
@@ -1251,7 +1250,7 @@ struct MergeShared {
     double wtail[16];
     int inrow[17];
     double inval[17];
-    int s_ia;
+    int s_ia, s_js;
 };
 
 template <class Op>
@@ -1265,11 +1264,18 @@ __device__ __forceinline__ void drive_merge(const int32_t* __restrict__ rp, int 
     const int total = nrows + nent;
     int carry_row = -1;
     double carry_val = 0.0;
-    int ia = 0;
+    int ia = 0, js = 0;
     for (int d0 = 0; d0 < total; d0 += kMergeChunk) {
         const int dl_end = min(kMergeChunk, total - d0);
         const int W = min(kMergeChunk + 1, nrows - ia);  // rows whose ends can lie in this chunk
         for (int q = tid; q <= W; q += blockDim.x) sh.win[q] = rp[r0 + ia + q] - e0;
+        // the chunk's entries start where the previous chunk's ended and
+        // are at most kMergeChunk (those past its end serve the next one)
+        const int ns = min(kMergeChunk, nent - js);
+        for (int q = tid; q < ns; q += blockDim.x) {
+            sh.scol[q] = op.colof(e0 + js + q);
+            sh.sw[q] = op.wof(e0 + js + q);
+        }
         __syncthreads();
         // start coordinate (i, j) on my diagonal: i rows completed, j entries consumed
         const int dl = min(tid * kMergeIPT, dl_end);
@@ -1281,26 +1287,6 @@ __device__ __forceinline__ void drive_merge(const int32_t* __restrict__ rp, int 
             else hi = mid;
         }
         int i = lo, j = diag - lo;
-        if (tid == 0) {
-            // the chunk's entry range: from this start to the coordinate of
-            // its last diagonal
-            const int dend = d0 + dl_end;
-            int lo2 = max(ia, dend - nent), hi2 = min(ia + W, dend);
-            while (lo2 < hi2) {
-                const int mid = (lo2 + hi2) >> 1;
-                if (sh.win[mid - ia + 1] <= dend - mid - 1) lo2 = mid + 1;
-                else hi2 = mid;
-            }
-            sh.js = j;
-            sh.je = dend - lo2;
-        }
-        __syncthreads();
-        const int js = sh.js;
-        for (int q = tid; q < sh.je - js; q += blockDim.x) {
-            sh.scol[q] = op.colof(e0 + js + q);
-            sh.sw[q] = op.wof(e0 + js + q);
-        }
-        __syncthreads();
         const int steps = min(dl + kMergeIPT, dl_end) - dl;
         double x = (i < nrows) ? op.xi(r0 + i) : 0.0;
         double part = 0.0;
@@ -1323,7 +1309,10 @@ __device__ __forceinline__ void drive_merge(const int32_t* __restrict__ rp, int 
                 x = (i < nrows) ? op.xi(r0 + i) : 0.0;
             }
         }
-        if (tid * kMergeIPT < dl_end && min(tid * kMergeIPT + kMergeIPT, dl_end) == dl_end) sh.s_ia = i;
+        if (tid * kMergeIPT < dl_end && min(tid * kMergeIPT + kMergeIPT, dl_end) == dl_end) {
+            sh.s_ia = i;
+            sh.s_js = j;
+        }
         // inclusive segmented scan of the carries (rows are non-decreasing in tid)
         int myrow = i;
         double v = part;
@@ -1371,6 +1360,7 @@ __device__ __forceinline__ void drive_merge(const int32_t* __restrict__ rp, int 
         carry_row = sh.inrow[nw];
         carry_val = sh.inval[nw];
         ia = sh.s_ia;
+        js = sh.s_js;
         __syncthreads();
     }
 }

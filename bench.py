@@ -164,6 +164,9 @@ def serve_leg(args):
         summ["max_batch"] = int(max(srv.batches)) if srv.batches else 0
         summ["peak_reserved_bytes"] = int(srv.peak)
         summ["failed"] = sum(r.status != "done" for r in stream)
+        for r in stream:
+            if r.status != "done":
+                log(f"[serve] {label}: request {r.rid} (n={r.n}) {r.status}: {r.error}")
         res[label] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
         log(f"[serve] {label}: {res[label]}")
     return res

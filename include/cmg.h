@@ -177,7 +177,14 @@ cmg_status cmg_setup(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
  *   x        receives the unit-norm Fiedler approximation (n doubles, in
  *            memory space `where`; may be NULL)
  *   stats    optional (host pointer)
- * Returns CMG_OK or CMG_W_MAXIT on success. */
+ * Returns CMG_OK or CMG_W_MAXIT on success.
+ * Large levels run as cooperative launches whose workgroups meet at grid
+ * barriers, so all of them must be resident together.  Kernels that other
+ * streams keep launching on the same device can hold compute units long
+ * enough that a barrier's bounded wait (2 s) ends: the call then returns
+ * CMG_E_DEVICE (cmg_last_error() names the level) and the handle stays
+ * usable.  Callers that overlap work should keep other kernels off the
+ * device while a solve runs, e.g. by issuing both on one stream. */
 cmg_status cmg_fiedler(cmg_handle h, double* lambda, void* x, cmg_memspace where,
                        cmg_stats* stats);
 

@@ -79,8 +79,11 @@ class CmgBackend:
         self.cmg = cmg
         self.torch = torch
         torch.cuda.set_device(device)
+        # one device stream for both: a setup's kernels on a second stream
+        # can keep a solve's grid-barrier workgroups from all becoming
+        # resident (setup and solve still overlap on the host threads)
         self.setup_stream = torch.cuda.Stream()
-        self.solve_stream = torch.cuda.Stream()
+        self.solve_stream = self.setup_stream
         self.alloc = cmg.torch_allocator()
 
     def setup(self, req: Request):

@@ -668,9 +668,10 @@ int default_grid(const HostLevel& L, int j, int ncu) {
     // about 2k rows + entries per workgroup; on mid-size levels (up to 4M
     // rows + entries) no more than sqrt(work)/4.5 workgroups, since there the
     // barrier's cost, which grows with the count, outweighs the step's work
-    // (measured on MI355X: rgg1m level 1, 2.9M rows + entries, 73 us per
-    // step on 384 workgroups against 90 on 768; grid3d128 level 3, 0.93M:
-    // 17.9 us on 216 against 21.2 on 456; at 8M, 768 workgroups beat 600)
+    // (measured on MI355X: level 1 of a 1M-point random geometric graph,
+    // 2.9M rows + entries, 73 us per step on 384 workgroups against 90 on
+    // 768; level 3 of a 128^3 grid, 0.93M: 17.9 us on 216 against 21.2 on
+    // 456; at 8M, 768 workgroups beat 600)
     const int64_t work = (int64_t)L.n + L.nnz;
     int64_t want = (work + 2047) / 2048;
     if (work <= ((int64_t)4 << 20))

@@ -1232,10 +1232,11 @@ __device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r
 // Per chunk the row ends and the chunk's entries (columns and weights, a
 // contiguous range starting where the previous chunk's ended) are copied to
 // LDS with coalesced loads, every thread finds its start by binary search
-// on its diagonal and walks its items from there, and the partial sums of rows split
-// across threads are combined by a segmented scan in thread order
-// (deterministic), then added by the thread that completes the row.  The
-// entry arithmetic is the operation's own, so staging changes no result.
+// on its diagonal and walks its items from there, and the partial sums of
+// rows split across threads are combined by a segmented scan in thread
+// order (deterministic), then added by the thread that completes the row.
+// The entry arithmetic is the operation's own, so staging changes no
+// result.
 constexpr int kMergeIPT = 8;
 constexpr int kMergeChunk = kGridBlock * kMergeIPT;
 

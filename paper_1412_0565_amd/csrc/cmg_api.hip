@@ -171,6 +171,10 @@ struct cmg_ctx {
     CoarseJob* d_cjob = nullptr;
     BlockJob* d_bruns = nullptr;  // single-workgroup levels: runs of levels, coarsest run first
     CoarseJob h_cjob{};
+    // The dense coarsest solve depends on the hierarchy alone and nothing
+    // else writes its outputs (the coarsest level's vector and state), so it
+    // runs on the first solve of a handle only.
+    bool coarse_done = false;
     std::vector<BlockJob> h_bruns;
     std::vector<int> brun_kind;   // kernel of each run (launch_block_jobs kind)
     int top = 0;       // finest-to-coarsest: levels top .. 0 are refined
@@ -1270,7 +1274,10 @@ cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where,
     const double t0 = now_ms();
     hipStream_t s = c->stream;
     const int J = (int)c->lv.size() - 1;
-    if (c->d_cjob) CK(launch_coarse_jobs(c->d_cjob, 1, s));
+    if (c->d_cjob && !c->coarse_done) {
+        CK(launch_coarse_jobs(c->d_cjob, 1, s));
+        c->coarse_done = true;
+    }
     for (size_t r = 0; r < c->h_bruns.size(); ++r) CK(launch_block_jobs(c->d_bruns + r, 1, c->brun_kind[r], s));
     // grid levels: one cooperative launch per level
     for (int j = std::min(c->top, c->block_lo - 1); j >= 0; --j) {
@@ -1313,7 +1320,7 @@ cmg_status batch_impl(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
     size_t maxruns = 0;
     for (int i = 0; i < count; ++i) {
         cmg_ctx* c = hs[i];
-        if (c->d_cjob) cj.push_back(c->h_cjob);
+        if (c->d_cjob && !c->coarse_done) cj.push_back(c->h_cjob);
         maxruns = std::max(maxruns, c->h_bruns.size());
         maxrounds = std::max(maxrounds, std::min(c->top, c->block_lo - 1) + 1);
     }
@@ -1398,7 +1405,11 @@ cmg_status batch_impl(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
     GridJob* d_gj = (GridJob*)(d + off);
     cmg_status status = CMG_OK;
     hipError_t e = hipMemcpyAsync(d, h.data(), bytes, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && !cj.empty()) e = launch_coarse_jobs(d_cj, (int)cj.size(), s);
+    if (e == hipSuccess && !cj.empty()) {
+        e = launch_coarse_jobs(d_cj, (int)cj.size(), s);
+        if (e == hipSuccess)
+            for (int i = 0; i < count; ++i) hs[i]->coarse_done = true;
+    }
     {
         const BlockJob* q = d_bj;
         for (const auto& bl : blaunch) {

@@ -141,6 +141,29 @@ def test_deterministic_repeat():
     assert np.array_equal(x1, x2) and np.array_equal(x1, x3)
 
 
+def test_coarsest_solve_reused_by_later_solves():
+    """The dense coarsest solve runs on a handle's first solve only; later
+    solves, solo or in a batch, and a graph that is one dense level give
+    bitwise the results of the first solve."""
+    from paper_1412_0565_amd import cmg
+
+    for g in (G.complete(20), G.grid2d(40, 40)):
+        with cmg.Fiedler(g.n, g.row_ptr, g.col, g.w) as F:
+            l1, x1, _ = F.solve()
+            l2, x2, _ = F.solve()
+        assert l1 == l2 and np.array_equal(x1, x2), g.n
+    ga, gb = G.rgg(20000, 10.0, seed=3), G.grid2d(90, 77, wx=2.0, wy=1.0)
+    with cmg.Fiedler(ga.n, ga.row_ptr, ga.col, ga.w) as A, cmg.Fiedler(gb.n, gb.row_ptr, gb.col, gb.w) as B:
+        la, xa, _ = A.solve()
+        xs = [np.zeros(ga.n), np.zeros(gb.n)]
+        lams, _ = cmg.cmg_fiedler_batch([A.handle, B.handle], xs)
+        lb, xb, _ = B.solve()
+        assert lams[0] == la and np.array_equal(xs[0], xa)
+        assert lams[1] == lb and np.array_equal(xs[1], xb)
+        ref = oracle_of(gb)
+        assert abs(lb - ref.lam) <= 1e-9 * ref.lam
+
+
 def test_device_tensors_and_torch_allocator():
     import torch
     from paper_1412_0565_amd import cmg

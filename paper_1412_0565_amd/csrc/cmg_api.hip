@@ -173,7 +173,7 @@ struct cmg_ctx {
     CoarseJob h_cjob{};
     // The dense coarsest solve depends on the hierarchy alone and nothing
     // else writes its outputs (the coarsest level's vector and state), so it
-    // runs on the first solve of a handle only.
+    // runs once, at the end of setup (true from then on).
     bool coarse_done = false;
     std::vector<BlockJob> h_bruns;
     std::vector<int> brun_kind;   // kernel of each run (launch_block_jobs kind)
@@ -851,6 +851,35 @@ cmg_status build_refine_plan(cmg_ctx* c) {
             L.lanes = pick_lanes_block(L.n, L.nnz / (double)std::max(L.n, 1), (int)L.maxlen, kBlockKernelThreads);
         }
     }
+    // the dense coarsest solve depends on the hierarchy alone: it is
+    // launched now and runs while the rest of the plan is built
+    ALLOC(c->d_st, LevelState, J + 1);
+    ALLOC(c->d_fo, FinishOut, 1);
+    if (c->coarse_dense) {
+        HostLevel& LJ = c->lv[J];
+        LJ.buf0 = c->dalloc(sizeof(double) * (size_t)LJ.n);
+        LJ.buf1 = c->dalloc(sizeof(double) * (size_t)LJ.n);
+        if (!LJ.buf0 || !LJ.buf1) return CMG_E_OOM;
+        const int dm = std::max(CJ.n, 2);
+        ALLOC(c->d_A, double, (size_t)dm * dm);
+        ALLOC(c->d_V, double, (size_t)dm * dm);
+        ALLOC(c->d_ev, double, 2 * (size_t)dm);
+        ALLOC(c->d_idx, int32_t, dm);
+        CoarseJob cj{};
+        cj.L = level_dev(LJ);  // the kernel reads n, rp, col, w64 and buf0
+        cj.st = c->d_st + J;
+        cj.A = c->d_A;
+        cj.V = c->d_V;
+        cj.ev = c->d_ev;
+        cj.idx = c->d_idx;
+        cj.fo = c->d_fo;
+        cj.seed = o.seed;
+        c->h_cjob = cj;
+        ALLOC(c->d_cjob, CoarseJob, 1);
+        CK(hipMemcpyAsync(c->d_cjob, &cj, sizeof(cj), hipMemcpyHostToDevice, c->stream));
+        CK(launch_coarse_jobs(c->d_cjob, 1, c->stream));
+        c->coarse_done = true;
+    }
     int max_step_grid = 0;
     for (int j = 0; j <= J; ++j) {
         HostLevel& L = c->lv[j];
@@ -860,9 +889,11 @@ cmg_status build_refine_plan(cmg_ctx* c) {
             L.fp32 = 1;
         L.variant = choose_variant(L, o.spmv_variant);
         const size_t vb = L.fp32 ? 4 : 8;
-        L.buf0 = c->dalloc(vb * (size_t)L.n);
-        L.buf1 = c->dalloc(vb * (size_t)L.n);
-        if (!L.buf0 || !L.buf1) return CMG_E_OOM;
+        if (!(j == J && c->coarse_dense)) {  // else allocated above
+            L.buf0 = c->dalloc(vb * (size_t)L.n);
+            L.buf1 = c->dalloc(vb * (size_t)L.n);
+            if (!L.buf0 || !L.buf1) return CMG_E_OOM;
+        }
         if (L.fp32) {
             ALLOC(L.w32, float, std::max<int64_t>(L.nnz, 1));
             CK(launch_to_f32(L.nnz, L.w64, L.w32, c->stream));
@@ -901,15 +932,6 @@ cmg_status build_refine_plan(cmg_ctx* c) {
     for (int j = 0; j <= J; ++j) ld[j] = level_dev(c->lv[j]);
     ALLOC(c->d_lv, LevelDev, J + 1);
     CK(hipMemcpyAsync(c->d_lv, ld.data(), sizeof(LevelDev) * (J + 1), hipMemcpyHostToDevice, c->stream));
-    ALLOC(c->d_st, LevelState, J + 1);
-    ALLOC(c->d_fo, FinishOut, 1);
-    const int dm = std::max(CJ.n, 2);
-    if (c->coarse_dense) {
-        ALLOC(c->d_A, double, (size_t)dm * dm);
-        ALLOC(c->d_V, double, (size_t)dm * dm);
-        ALLOC(c->d_ev, double, 2 * (size_t)dm);
-        ALLOC(c->d_idx, int32_t, dm);
-    }
     const int32_t n0 = c->lv[0].n;
     ALLOC(c->d_y, double, n0);
     if (c->lv[0].fp32 && o.fp64_final_sweeps > 0) {
@@ -978,20 +1000,6 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         CK(hipMemcpyAsync(c->d_step, sj.data(), sizeof(StepJob) * (J + 1), hipMemcpyHostToDevice, c->stream));
     }
     c->top = top;
-    if (c->coarse_dense) {
-        CoarseJob cj{};
-        cj.L = ld[J];
-        cj.st = c->d_st + J;
-        cj.A = c->d_A;
-        cj.V = c->d_V;
-        cj.ev = c->d_ev;
-        cj.idx = c->d_idx;
-        cj.fo = c->d_fo;
-        cj.seed = o.seed;
-        c->h_cjob = cj;
-        ALLOC(c->d_cjob, CoarseJob, 1);
-        CK(hipMemcpyAsync(c->d_cjob, &cj, sizeof(cj), hipMemcpyHostToDevice, c->stream));
-    }
     // single-workgroup levels: maximal runs of levels on the same kernel,
     // coarsest first; each run starts from the state its coarser level left
     c->h_bruns.clear();

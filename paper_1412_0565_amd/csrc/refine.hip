@@ -1985,7 +1985,10 @@ int max_blocks_ptr(const void* k) {
     GridJob* dj = nullptr;
     hipStream_t s = nullptr;
     unsigned peak[2] = {0u, 0u};
-    bool ok = hipMalloc((void**)&cnt, 2 * sizeof(unsigned)) == hipSuccess &&
+    // the count needs an idle device: work already queued (a coarsest solve
+    // launched during setup, another thread's solve) finishes first
+    bool ok = hipDeviceSynchronize() == hipSuccess &&
+              hipMalloc((void**)&cnt, 2 * sizeof(unsigned)) == hipSuccess &&
               hipMalloc((void**)&dj, sizeof(GridJob)) == hipSuccess &&
               hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
     if (ok) {

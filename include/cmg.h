@@ -178,8 +178,9 @@ cmg_status cmg_setup(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
  *            memory space `where`; may be NULL)
  *   stats    optional (host pointer)
  * Returns CMG_OK or CMG_W_MAXIT on success.
- * Large levels run as cooperative launches whose workgroups meet at grid
- * barriers, so all of them must be resident together.  Kernels that other
+ * Large levels run as persistent launches whose workgroups meet at grid
+ * barriers, so all of them must be resident together (the library sizes
+ * each launch to the co-resident count it measured on the idle device).  Kernels that other
  * streams keep launching on the same device can hold compute units long
  * enough that a barrier's bounded wait (2 s) ends: the call then returns
  * CMG_E_DEVICE (cmg_last_error() names the level) and the handle stays

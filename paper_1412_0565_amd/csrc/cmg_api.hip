@@ -1287,7 +1287,7 @@ cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where,
         c->coarse_done = true;
     }
     for (size_t r = 0; r < c->h_bruns.size(); ++r) CK(launch_block_jobs(c->d_bruns + r, 1, c->brun_kind[r], s));
-    // grid levels: one cooperative launch per level
+    // grid levels: one persistent launch per level
     for (int j = std::min(c->top, c->block_lo - 1); j >= 0; --j) {
         const HostLevel& L = c->lv[j];
         CK(hipEventRecord(c->events[2 * j], s));

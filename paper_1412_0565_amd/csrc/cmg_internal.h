@@ -140,7 +140,7 @@ hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, int kind, hipStrea
 // 1 + log2(G); finishing kernels depend on the traversal only.
 constexpr int kJobKinds = 16;
 int job_kind(int variant, int lanes, int fp32);
-// co-resident workgroups of a job kernel kind (cooperative launch limit)
+// co-resident workgroups of a job kernel kind (measured once per process)
 int refine_jobs_max_blocks(int kind);
 int finish_jobs_max_blocks(int kind);
 // one level of each job (all of one kind); nblocks = sum of the jobs' grids

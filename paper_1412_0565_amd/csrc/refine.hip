@@ -43,7 +43,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 }
 
 // ~2 s at the 100 MHz constant clock: a safety bound, never reached when
-// the grid is co-resident (cooperative launch).
+// the grid is co-resident (launches are sized to the measured residency).
 constexpr long long kSpinTicks = 200000000LL;
 
 // Grids up to this many workgroups use the all-read form below.
@@ -2001,7 +2001,7 @@ int max_blocks_ptr(const void* k) {
         void* args[] = {(void*)&dj, &njobs};
         ok = hipMemsetAsync(cnt, 0, 2 * sizeof(unsigned), s) == hipSuccess &&
              hipMemcpyAsync(dj, &j, sizeof(GridJob), hipMemcpyHostToDevice, s) == hipSuccess &&
-             hipLaunchCooperativeKernel(k, dim3(want), dim3(kGridBlock), args, 0, s) == hipSuccess &&
+             hipLaunchKernel(k, dim3(want), dim3(kGridBlock), args, 0, s) == hipSuccess &&
              hipMemcpyAsync(peak, cnt, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, s) == hipSuccess &&
              hipStreamSynchronize(s) == hipSuccess;
     }
@@ -2045,14 +2045,20 @@ int finish_jobs_max_blocks(int kind) {
     return g_finish_cap[kind];
 }
 
+// Grid launches are plain launches of at most the measured co-resident
+// workgroup count: on an otherwise idle device every workgroup is resident
+// at once, which is all the grid barrier needs.  (A cooperative launch
+// costs about 17 us more per launch on MI355X and gave no protection from
+// kernels on other streams either; the barrier's bounded wait turns such
+// a case into CMG_E_DEVICE.)
 hipError_t launch_refine_jobs(const GridJob* jobs, int njobs, int nblocks, int kind, hipStream_t s) {
     void* args[] = {(void*)&jobs, &njobs};
-    return hipLaunchCooperativeKernel(refine_kernel(kind), dim3(nblocks), dim3(kGridBlock), args, 0, s);
+    return hipLaunchKernel(refine_kernel(kind), dim3(nblocks), dim3(kGridBlock), args, 0, s);
 }
 
 hipError_t launch_finish_jobs(const GridJob* jobs, int njobs, int nblocks, int kind, hipStream_t s) {
     void* args[] = {(void*)&jobs, &njobs};
-    return hipLaunchCooperativeKernel(finish_kernel(kind), dim3(nblocks), dim3(kGridBlock), args, 0, s);
+    return hipLaunchKernel(finish_kernel(kind), dim3(nblocks), dim3(kGridBlock), args, 0, s);
 }
 
 hipError_t launch_step_begin(const StepJob* job, int nblocks, int kind, hipStream_t s) {

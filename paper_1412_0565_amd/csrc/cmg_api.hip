@@ -175,6 +175,9 @@ struct cmg_ctx {
     // else writes its outputs (the coarsest level's vector and state), so it
     // runs once, at the end of setup (true from then on).
     bool coarse_done = false;
+    // every input weight an integer below 2^20: Galerkin sums are exact in
+    // any order, and runs of a long coarse entry are summed in pieces
+    bool int_weights = false;
     std::vector<BlockJob> h_bruns;
     std::vector<int> brun_kind;   // kernel of each run (launch_block_jobs kind)
     int top = 0;       // finest-to-coarsest: levels top .. 0 are refined
@@ -309,6 +312,7 @@ struct SetupTmp {
     unsigned* vflags = nullptr;
     double* bmax = nullptr;              // per-block maxima of the row pass
     unsigned long long* ri = nullptr;    // row information of level j at ri[4j .. 4j+3]
+    double* gpart = nullptr;             // Galerkin pieces of runs that cross workgroups
     void* block = nullptr;               // the one allocation all of the above point into
     std::vector<int> ri_pending;         // levels whose row information is still on the device
 };
@@ -352,6 +356,7 @@ void carve_tmp(Carver& cv, SetupTmp& t, int32_t n, int64_t nnz) {
     t.vflags = cv.take<unsigned>(4);
     t.bmax = cv.take<double>(4 * kRowinfoMaxBlocks);
     t.ri = cv.take<unsigned long long>(4 * kMaxLevels);
+    t.gpart = cv.take<double>(gal_part_elems(nnz));
 }
 
 cmg_status alloc_tmp(cmg_ctx* c, SetupTmp& t, int32_t n, int64_t nnz) {
@@ -476,7 +481,7 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
         CK(hipMemsetAsync(C.rp, 0, sizeof(int32_t) * (C.n + 1), s));
     } else {
         CK(launch_gal_reduce((int64_t)nvalid, ks, vs, L.w64, pshift, t.heads, t.idx, mult, (int)nc, zc, C.rp,
-                             C.col, C.w64, s));
+                             C.col, C.w64, c->int_weights ? t.gpart : nullptr, s));
     }
     C.lanes = pick_lanes(C.nnz / (double)C.n);
     c->lv.push_back(C);
@@ -1087,6 +1092,7 @@ cmg_status setup_impl(cmg_ctx* c, int32_t n, int64_t nnz, const int32_t* row_ptr
     if (st != CMG_OK) return st;
     if (flags & (kBadGraph | kAsym)) return CMG_E_GRAPH;
     if (flags & kIsolated) return CMG_E_ISOLATED;
+    c->int_weights = (flags & kWideWeight) == 0;
     L0.lanes = pick_lanes(nnz / (double)n);
     c->lv.push_back(L0);
     SetupTmp t;

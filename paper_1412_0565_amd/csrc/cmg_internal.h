@@ -13,6 +13,9 @@ namespace cmg {
 constexpr unsigned kBadGraph = 1u;
 constexpr unsigned kIsolated = 2u;
 constexpr unsigned kAsym = 4u;
+// Not an error: some weight is not an integer below 2^20.  Without it every
+// sum of weights of the hierarchy is an integer below 2^51, exact in any order.
+constexpr unsigned kWideWeight = 8u;
 
 // ---- coarsen_small.hip: the setup of small levels in one workgroup
 constexpr int kChainThreads = 1024;
@@ -111,10 +114,15 @@ hipError_t launch_sort(unsigned long long* k0, double* v0, unsigned long long* k
 // keys (read on the device), 0 elsewhere in [0, m)
 hipError_t launch_gal_heads(int64_t m, const unsigned long long* nvalid, const unsigned long long* keys,
                             int kshift, int32_t* heads, hipStream_t s);
+// part: nullptr sums every run in key order (fine CSR order, bit-exact for
+// any weights); else a scratch of gal_part_elems(m) doubles, and runs that
+// cross workgroups are summed in pieces (exact only for integer weights
+// whose sums stay below 2^53).
 hipError_t launch_gal_reduce(int64_t m, const unsigned long long* keys, const double* vals,
                              const double* wfine, int kshift, const int32_t* heads, const int32_t* idx,
                              int64_t mult, int nc, int64_t zc, int32_t* rp_out, int32_t* col_out,
-                             double* w_out, hipStream_t s);
+                             double* w_out, double* part, hipStream_t s);
+int64_t gal_part_elems(int64_t m);
 hipError_t launch_partition(int n, int64_t nnz, const int32_t* rp, int nb, int32_t* part,
                             hipStream_t s);
 hipError_t launch_hash_probe(uint64_t seed, int level, int count, unsigned long long* out,

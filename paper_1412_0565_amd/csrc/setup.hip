@@ -57,6 +57,7 @@ __global__ void k_validate(int n, int64_t nnz, const int32_t* __restrict__ rp,
                 const double x = (double)w[e];
                 bool bad = c < 0 || c >= n || c == i || c <= prev;
                 if (!(x > 0.0) || !isfinite(x)) bad = true;
+                if (!bad && (x != floor(x) || x >= 1048576.0)) f |= kWideWeight;
                 if (bad) {
                     f |= kBadGraph;
                 } else if (full && rp[c] >= 0 && rp[c] <= rp[c + 1] && (int64_t)rp[c + 1] <= nnz) {
@@ -454,7 +455,8 @@ __global__ void __launch_bounds__(kBlk)
     k_gal_reduce(int64_t m, const unsigned long long* __restrict__ keys, const double* __restrict__ vals,
                  const double* __restrict__ wfine, int kshift, const int32_t* __restrict__ heads,
                  const int32_t* __restrict__ idx, int64_t mult, double inv_mult, int nc, int64_t zc,
-                 int32_t* __restrict__ rp, int32_t* __restrict__ col, double* __restrict__ w) {
+                 int32_t* __restrict__ rp, int32_t* __restrict__ col, double* __restrict__ w,
+                 double* __restrict__ part) {
     __shared__ unsigned long long sk[kBlk];
     __shared__ double sw[kBlk];
     const int64_t b0 = (int64_t)blockIdx.x * kBlk;
@@ -466,16 +468,30 @@ __global__ void __launch_bounds__(kBlk)
         sw[threadIdx.x] = vals ? vals[t] : wfine[kw & pmask];
     }
     __syncthreads();
+    const unsigned long long um = (unsigned long long)mult;
+    const int64_t bend = min(b0 + kBlk, m);
+    if (part != nullptr && t < m) {
+        // pieces: a workgroup that starts inside a run leaves the sum of its
+        // entries of that run for k_gal_fix; the last entry's thread ends
+        // the row pointers
+        if (threadIdx.x == 0 && !heads[t]) {
+            double ps = 0.0;
+            for (int64_t u = b0; u < bend && sk[u - b0] == sk[0]; ++u) ps += sw[u - b0];
+            part[blockIdx.x] = ps;
+        }
+        if (t == m - 1) {
+            const int rl = (int)key_row(sk[threadIdx.x], um, inv_mult);
+            for (int r = rl + 1; r <= nc; ++r) rp[r] = (int32_t)zc;
+        }
+    }
     if (t >= m || !heads[t]) return;
     const unsigned long long k = sk[threadIdx.x];
-    const unsigned long long um = (unsigned long long)mult;
     const int row = (int)key_row(k, um, inv_mult);
     const int c = (int)(k - (unsigned long long)row * um);
     double s = sw[threadIdx.x];
-    const int64_t bend = min(b0 + kBlk, m);
     int64_t u = t + 1;
     for (; u < bend && sk[u - b0] == k; ++u) s += sw[u - b0];
-    if (u == bend) {
+    if (u == bend && part == nullptr) {
         for (; u < m && (keys[u] >> kshift) == k; ++u) s += vals ? vals[u] : wfine[keys[u] & pmask];
     }
     const int32_t o = idx[t];
@@ -487,9 +503,32 @@ __global__ void __launch_bounds__(kBlk)
         prow = (int)key_row(kp, um, inv_mult);
     }
     for (int r = prow + 1; r <= row; ++r) rp[r] = o;
-    if (u == m) {
+    if (u == m && part == nullptr) {
         for (int r = row + 1; r <= nc; ++r) rp[r] = (int32_t)zc;
     }
+}
+
+// Runs that cross workgroups, pieces mode: the thread of workgroup b whose
+// last run goes on into workgroup b + 1 (and starts in b) adds the pieces
+// of the following workgroups to the head's sum, in workgroup order.
+__global__ void k_gal_fix(int64_t m, int64_t nb, const int32_t* __restrict__ heads,
+                          const int32_t* __restrict__ idx, const double* __restrict__ part,
+                          double* __restrict__ w) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b + 1 >= nb) return;
+    const int64_t e = (b + 1) * kBlk;
+    if (heads[e]) return;                        // workgroup b + 1 starts a run
+    if (idx[e] - idx[b * kBlk] == 0) return;     // the run's head lies before workgroup b
+    const int32_t o = idx[e] - 1;
+    double s = w[o];
+    for (int64_t bb = b + 1; bb < nb; ++bb) {
+        const int64_t eb = bb * kBlk;
+        if (heads[eb]) break;
+        s += part[bb];
+        const int64_t ee = min(eb + kBlk, m);
+        if (idx[ee - 1] + heads[ee - 1] - idx[eb] > 0) break;  // the run ends in bb
+    }
+    w[o] = s;
 }
 
 // ------------------------------------------------------------ radix sort
@@ -763,13 +802,18 @@ hipError_t launch_gal_heads(int64_t m, const unsigned long long* nvalid, const u
     return hipGetLastError();
 }
 
+int64_t gal_part_elems(int64_t m) { return (m + kBlk - 1) / kBlk + 1; }
+
 hipError_t launch_gal_reduce(int64_t m, const unsigned long long* keys, const double* vals,
                              const double* wfine, int kshift, const int32_t* heads, const int32_t* idx,
                              int64_t mult, int nc, int64_t zc, int32_t* rp_out, int32_t* col_out,
-                             double* w_out, hipStream_t s) {
+                             double* w_out, double* part, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gal_reduce, dim3(nblocks(m, kBlk)), dim3(kBlk), 0, s, m, keys, vals, wfine, kshift,
-                       heads, idx, mult, 1.0 / (double)mult, nc, zc, rp_out, col_out, w_out);
+    const int64_t nb = nblocks(m, kBlk);
+    hipLaunchKernelGGL(k_gal_reduce, dim3((unsigned)nb), dim3(kBlk), 0, s, m, keys, vals, wfine, kshift,
+                       heads, idx, mult, 1.0 / (double)mult, nc, zc, rp_out, col_out, w_out, part);
+    if (part != nullptr && nb > 1)
+        hipLaunchKernelGGL(k_gal_fix, dim3(nblocks(nb, kBlk)), dim3(kBlk), 0, s, m, nb, heads, idx, part, w_out);
     return hipGetLastError();
 }
 

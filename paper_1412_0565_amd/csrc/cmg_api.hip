@@ -178,6 +178,7 @@ struct cmg_ctx {
     // every input weight an integer below 2^20: Galerkin sums are exact in
     // any order, and runs of a long coarse entry are summed in pieces
     bool int_weights = false;
+    unsigned maxlen0 = 0;  // longest input row if over 64 entries (else 0)
     std::vector<BlockJob> h_bruns;
     std::vector<int> brun_kind;   // kernel of each run (launch_block_jobs kind)
     int top = 0;       // finest-to-coarsest: levels top .. 0 are refined
@@ -448,8 +449,13 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
     const bool packed = bits + pbits <= 64;
     const int pshift = packed ? pbits : 0;
     const unsigned long long sent = packed ? (~0ull >> (64 - bits)) : kGalSentinel;
-    CK(launch_gal_emit(L.n, L.lanes, L.rp, L.col, L.w64, L.agg, mult, pshift, sent, t.k0,
-                       packed ? nullptr : t.v0, s));
+    if (j == 0 && c->maxlen0 > 64u * (unsigned)L.lanes) {  // a row of many lane-group trips
+        CK(launch_gal_emit_entries(L.n, L.nnz, L.rp, L.col, L.w64, L.agg, mult, pshift, sent, t.k0,
+                                   packed ? nullptr : t.v0, s));
+    } else {
+        CK(launch_gal_emit(L.n, L.lanes, L.rp, L.col, L.w64, L.agg, mult, pshift, sent, t.k0,
+                           packed ? nullptr : t.v0, s));
+    }
     int second = 0;
     CK(launch_sort(t.k0, packed ? nullptr : t.v0, t.k1, packed ? nullptr : t.v1, L.nnz, pshift, bits,
                    t.sort_counts, t.sort_scan, &second, s));
@@ -1083,10 +1089,12 @@ cmg_status setup_impl(cmg_ctx* c, int32_t n, int64_t nnz, const int32_t* row_ptr
     // validation (on the handle's copy)
     unsigned* vf = (unsigned*)c->dalloc_direct(sizeof(unsigned) * 4);
     if (!vf) return CMG_E_OOM;
-    CK(hipMemsetAsync(vf, 0, sizeof(unsigned), s));
+    CK(hipMemsetAsync(vf, 0, 2 * sizeof(unsigned), s));
     CK(launch_validate(n, nnz, L0.rp, L0.col, L0.w64, 0, c->opt.validate_full, vf, s));
-    unsigned flags = 0;
-    cmg_status st = d2h(c, &flags, vf, 1);
+    unsigned vres[2] = {0u, 0u};
+    cmg_status st = d2h(c, vres, vf, 2);
+    const unsigned flags = vres[0];
+    c->maxlen0 = vres[1];
     c->dfree_direct(vf);
     if (wtmp) c->dfree_direct(wtmp);
     if (st != CMG_OK) return st;

@@ -64,6 +64,8 @@ struct ChainJob {
 hipError_t launch_coarsen_chain(const ChainJob& job, hipStream_t s);
 
 // ---- setup.hip
+// flags[0]: kBadGraph | kIsolated | kAsym | kWideWeight; flags[1]: longest
+// row if it exceeds 64 entries, else left as it was (both zeroed by the caller)
 hipError_t launch_validate(int n, int64_t nnz, const int32_t* rp, const int32_t* col, const void* w,
                            int wf32, int full, unsigned* flags, hipStream_t s);
 hipError_t launch_convert_w(int64_t nnz, const void* w, int wf32, double* w64, hipStream_t s);
@@ -100,6 +102,11 @@ constexpr unsigned long long kGalSentinel = 0xFFFFFFFFFFFFFFFFull;
 hipError_t launch_gal_emit(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w,
                            const int32_t* agg, int64_t mult, int pshift, unsigned long long sent,
                            unsigned long long* keys, double* vals, hipStream_t s);
+// The same keys, entries spread evenly over the lanes (levels with very long rows).
+hipError_t launch_gal_emit_entries(int n, int64_t nnz, const int32_t* rp, const int32_t* col,
+                                   const double* w, const int32_t* agg, int64_t mult, int pshift,
+                                   unsigned long long sent, unsigned long long* keys, double* vals,
+                                   hipStream_t s);
 // *out = number of keys[0..m) below `sent` (keys sorted ascending)
 hipError_t launch_count_below(const unsigned long long* keys, int64_t m, unsigned long long sent,
                               unsigned long long* out, hipStream_t s);

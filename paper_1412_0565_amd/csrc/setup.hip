@@ -51,6 +51,7 @@ __global__ void k_validate(int n, int64_t nnz, const int32_t* __restrict__ rp,
         } else if (a == b) {
             f |= kIsolated;
         } else {
+            if (lane == 0 && b - a > 64) atomicMax(&flags[1], (unsigned)(b - a));  // long rows only
             for (int e = a + lane; e < b; e += kValidateLanes) {
                 const int c = col[e];
                 const int prev = e > a ? col[e - 1] : -1;
@@ -410,6 +411,51 @@ __global__ void k_gal_emit(int n, const int32_t* __restrict__ rp, const int32_t*
     }
 }
 
+// k_gal_emit over entries instead of rows, for a level whose longest row
+// would keep one lane group busy far longer than the others: each wave
+// takes 64 * kEmitPerLane consecutive entries, lane l the entries l, l + 64,
+// ...; a lane finds the row of its first entry by binary search on the row
+// pointers and follows them from there.  The keys are those of k_gal_emit.
+constexpr int kEmitPerLane = 8;
+
+__global__ void k_gal_emit_entries(int n, int64_t nnz, const int32_t* __restrict__ rp,
+                                   const int32_t* __restrict__ col, const double* __restrict__ w,
+                                   const int32_t* __restrict__ agg, int64_t mult, int pshift,
+                                   unsigned long long sent, unsigned long long* __restrict__ keys,
+                                   double* __restrict__ vals) {
+    const int lane = threadIdx.x & 63;
+    const int64_t span = 64 * kEmitPerLane;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t c0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * span; c0 < nnz;
+         c0 += nwaves * span) {
+        int64_t e = c0 + lane;
+        if (e >= nnz) continue;
+        int lo = 0, hi = n - 1;  // last row r with rp[r] <= e
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rp[mid] <= e) lo = mid;
+            else hi = mid - 1;
+        }
+        int r = lo;
+        int a = agg[r];
+        for (int q = 0; q < kEmitPerLane && e < nnz; ++q, e += 64) {
+            if (rp[r + 1] <= e) {
+                while (rp[r + 1] <= e) ++r;
+                a = agg[r];
+            }
+            const int b = agg[col[e]];
+            const unsigned long long k =
+                (a == b) ? sent : (unsigned long long)a * (unsigned long long)mult + (unsigned long long)b;
+            if (vals) {
+                keys[e] = k;
+                vals[e] = w[e];
+            } else {
+                keys[e] = (k << pshift) | (unsigned long long)e;
+            }
+        }
+    }
+}
+
 // number of sorted keys below the sentinel (binary search, one thread)
 __global__ void k_count_below(const unsigned long long* __restrict__ keys, int64_t m,
                               unsigned long long sent, unsigned long long* out) {
@@ -734,6 +780,17 @@ hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, long long* tm
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlk), 0, s, in, m, tmp);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlk), 0, s, tmp, nb, total);
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kBlk), 0, s, in, out, m, tmp);
+    return hipGetLastError();
+}
+
+hipError_t launch_gal_emit_entries(int n, int64_t nnz, const int32_t* rp, const int32_t* col,
+                                   const double* w, const int32_t* agg, int64_t mult, int pshift,
+                                   unsigned long long sent, unsigned long long* keys, double* vals,
+                                   hipStream_t s) {
+    if (nnz == 0) return hipSuccess;
+    const unsigned nb = (unsigned)std::min<int64_t>(nblocks(nnz, kBlk / 64 * 64 * kEmitPerLane), 65536);
+    hipLaunchKernelGGL(k_gal_emit_entries, dim3(nb), dim3(kBlk), 0, s, n, nnz, rp, col, w, agg, mult, pshift,
+                       sent, keys, vals);
     return hipGetLastError();
 }
 

@@ -115,6 +115,12 @@ typedef struct {
                                     rows and 2560 entries) and runs the PI steps from there;
                                     0 always reads them from global memory.  Results are
                                     bitwise equal. */
+    int32_t step_mode;           /* grid levels traversed by rows: 0 (default) refines the levels
+                                    at depth >= 2 whose PI step streams >= 16 MB with one launch
+                                    per step (no grid barrier), the others with one persistent
+                                    launch; 1 uses one launch per step on every such level; -1 on
+                                    none.  The same arithmetic in the same order either way:
+                                    results are equal to rounding of the sums' tree. */
 } cmg_options;
 
 /* Per-level information (available after cmg_setup; PI fields after
@@ -135,6 +141,7 @@ typedef struct {
     double bytes_per_iter; /* algorithmic bytes of one PI step: 4(n+1)+nnz(4+s_v)+2 s_x n */
     int32_t block_waves;   /* in_block: wavefronts running the PI steps (0: all) */
     int32_t block_regs;    /* in_block: rows per lane group held in registers (0: CSR reads) */
+    int32_t step;          /* 1 if refined with one launch per PI step (no grid barrier) */
 } cmg_level_stats;
 
 typedef struct {

@@ -55,6 +55,7 @@ class cmg_options(C.Structure):
         ("autotune", C.c_int32),
         ("block_regs", C.c_int32),
         ("grid_stage", C.c_int32),
+        ("step_mode", C.c_int32),
     ]
 
 
@@ -75,6 +76,7 @@ class cmg_level_stats(C.Structure):
         ("bytes_per_iter", C.c_double),
         ("block_waves", C.c_int32),
         ("block_regs", C.c_int32),
+        ("step", C.c_int32),
     ]
 
 

@@ -910,8 +910,9 @@ cmg_status build_refine_plan(cmg_ctx* c) {
             CK(launch_to_f32(L.nnz, L.w64, L.w32, c->stream));
         }
         L.grid = default_grid(L, j, ncu);
-        L.step = (!L.in_block && j <= top && j >= kStepModeDepth && L.variant != 2 &&
-                  step_bytes(L) >= kStepModeBytes) ? 1 : 0;
+        const bool auto_step = j >= kStepModeDepth && step_bytes(L) >= kStepModeBytes;
+        L.step = (!L.in_block && j <= top && L.variant != 2 &&
+                  (o.step_mode > 0 || (o.step_mode == 0 && auto_step))) ? 1 : 0;
         if (o.autotune && !L.in_block && !L.step && j <= top) {
             cmg_status st = tune_level(c, j, maxgrid);
             if (st != CMG_OK) return st;
@@ -1161,6 +1162,7 @@ void fill_defaults(cmg_options* o) {
     o->autotune = 0;
     o->block_regs = 0;
     o->grid_stage = 1;
+    o->step_mode = 0;
 }
 
 // Device results of the last solve -> host staging (asynchronous).
@@ -1514,7 +1516,8 @@ cmg_status cmg_setup(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
     }
     if (!(o.tol < 1.0) || !std::isfinite(o.tol) || o.coarsest_n < 2 || o.dense_max < 2 || o.dense_max > 128 ||
         o.max_iters_per_level < 1 || (o.precision != CMG_FP64 && o.precision != CMG_MIXED) ||
-        o.fp64_final_sweeps < 0 || o.fp64_final_sweeps > 1 || o.coarsest_n > o.dense_max)
+        o.fp64_final_sweeps < 0 || o.fp64_final_sweeps > 1 || o.coarsest_n > o.dense_max ||
+        o.step_mode < -1 || o.step_mode > 1)
         return CMG_E_ARG;
     const double t0 = now_ms();
     cmg_ctx* c = new (std::nothrow) cmg_ctx;
@@ -1577,6 +1580,7 @@ cmg_status cmg_level_info(cmg_handle h, cmg_level_stats* out, int32_t cap, int32
         li.bytes_per_iter = 4.0 * (L.n + 1) + (double)L.nnz * (4 + sv) + 2 * sv * L.n;
         li.block_waves = L.bwaves;
         li.block_regs = L.bregs;
+        li.step = L.step;
         out[j] = li;
     }
     return CMG_OK;

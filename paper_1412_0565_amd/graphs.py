@@ -196,6 +196,24 @@ def grid2d(rows: int, cols: int, wx: float = 1.0, wy: float = 1.0) -> CSR:
     return from_edges(n, u, v, w, name=f"grid{rows}x{cols}")
 
 
+def mirrored_prism(a: int) -> CSR:
+    """Two copies of the a x a five-point grid joined vertex to vertex (unit
+    weights).  Copy 0 labels (r, c) as a r + c, copy 1 as 2 a^2 - 1 - (a r + c),
+    so the label reversal i -> n-1-i swaps the copies: an automorphism under
+    which the ramp i - (n-1)/2 is odd, while every vector that is constant
+    across the copies (the whole lambda_2 eigenspace of the grid, for a >= 2)
+    is even."""
+    m = a * a
+    ids = np.arange(m, dtype=np.int64).reshape(a, a)
+    hu, vu = ids[:, :-1].ravel(), ids[:-1, :].ravel()
+    u0 = np.concatenate([hu, vu])
+    v0 = np.concatenate([hu + 1, vu + a])
+    mirror = lambda x: 2 * m - 1 - x  # noqa: E731
+    u = np.concatenate([u0, mirror(u0), np.arange(m)])
+    v = np.concatenate([v0, mirror(v0), mirror(np.arange(m))])
+    return from_edges(2 * m, u, v, name=f"prism{a}")
+
+
 def grid3d(s: int, dtype=np.float64) -> CSR:
     """3D 7-point grid graph s^3; id = (s*z + y)*s + x; unit weights.
 

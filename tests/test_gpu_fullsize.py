@@ -1,17 +1,19 @@
 """Full-size parity at the two largest configurations, in the launch
 configuration bench.py uses (device arrays, torch allocator and stream).
+The oracle's full solve (Algorithms 1-3, single-threaded C) runs in a
+thread of its own while the GPU solves.
 
 * 3D 256^3 seven-point grid (16.8M vertices, 100M stored entries, FP32
-  values), mixed precision: the whole hierarchy bit-exact against the oracle
-  and lambda within the mixed tolerance of the FP64 oracle solve.
+  input values): FP64 solve against the oracle at the FP64 bar (whole
+  hierarchy bit-exact, every step count equal, |cos| >= 1 - 1e-10, lambda
+  within 1e-9; its levels 2-4 run one launch per PI step), and the mixed
+  solve with every step count equal and lambda within 1e-5 of the oracle.
 * Chung-Lu, 4M vertices, exponent 2.1, mean degree 16, cap 50k (FP32
-  values), mixed and FP64: the hierarchy bit-exact against the oracle's
-  coarsening (the oracle's refinement needs thousands of steps per level at
-  this size, so it is not run); the outputs are checked through properties
-  that hold at any size: unit norm, orthogonality to the constant vector,
-  lambda equal to the edge-form Rayleigh quotient of the returned vector and
-  the residual equal to ||L x - lambda x|| recomputed in FP64 on the host,
-  and FP64 and mixed solves agreeing to the mixed tolerance.
+  values; merge-path levels): the same two bars.
+* Both: outputs also checked by properties that hold at any size: unit
+  norm, orthogonality to the constant vector, lambda equal to the
+  edge-form Rayleigh quotient of the returned vector and the residual equal
+  to ||L x - lambda x||, both recomputed in FP64 on the host.
 """
 from __future__ import annotations
 
@@ -20,7 +22,9 @@ import ctypes as C
 import numpy as np
 import pytest
 
-from gpu_compare import MIXED_LAM_RTOL, assert_hierarchy_equal, say
+from concurrent.futures import ThreadPoolExecutor
+
+from gpu_compare import MIXED_LAM_RTOL, assert_fp64_parity, assert_refinement_equal, say
 from paper_1412_0565_amd import graphs as G
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -71,26 +75,42 @@ def check_output_properties(g, lam, x, st):
     assert abs(st.residual - res_h) <= 1e-6 * res_h + 1e-12 * (1.0 + lam)
 
 
+def full_size_case(g, name, expect_step):
+    from oracle import oracle as O
+
+    say(f"[fullsize] {name} n={g.n} nnz={g.nnz}: oracle in a thread, GPU FP64 then mixed")
+    with ThreadPoolExecutor(1) as ex:
+        fut = ex.submit(O.cmg, g)
+        lam_d, x_d, st_d, levels_d, arrays = solve_device(g, precision=0)
+        say(f"  gpu fp64 lambda {lam_d!r} k {[l.k for l in levels_d]} "
+            f"step levels {[j for j, l in enumerate(levels_d) if l.step]} "
+            f"merge levels {[j for j, l in enumerate(levels_d) if l.variant == 2]}")
+        lam_m, x_m, st_m, levels_m, _ = solve_device(g, precision=1, with_arrays=False)
+        say(f"  gpu mixed lambda {lam_m!r} k {[l.k for l in levels_m]} "
+            f"fp32 levels {[j for j, l in enumerate(levels_m) if l.fp32]}")
+        ref = fut.result()
+    say(f"  oracle lambda {ref.lam!r} k {[l.k for l in ref.levels]} residual {ref.residual!r}")
+    assert_fp64_parity(g, lam_d, x_d, st_d, levels_d, arrays, ref)
+    assert float(np.dot(x_d, ref.y)) > 0
+    if expect_step:
+        assert any(l.step for l in levels_d)
+    check_output_properties(g, lam_d, x_d, st_d)
+    assert any(l.fp32 for l in levels_m)
+    assert_refinement_equal(ref, levels_m)
+    assert abs(lam_m - ref.lam) <= MIXED_LAM_RTOL * ref.lam, (lam_m, ref.lam)
+    check_output_properties(g, lam_m, x_m, st_m)
+    return levels_d
+
+
 @pytest.fixture(scope="module")
 def grid3d256():
     return G.workload("grid3d256")
 
 
-def test_fullsize_grid3d256_mixed(grid3d256):
-    from oracle import oracle as O
-
+def test_fullsize_grid3d256(grid3d256):
     g = grid3d256
-    say(f"[fullsize] grid3d256 n={g.n} nnz={g.nnz} mixed")
-    lam, x, st, levels, arrays = solve_device(g, precision=1)
-    say(f"  gpu lambda {lam!r} k {[l.k for l in levels]} fp32 levels {[j for j, l in enumerate(levels) if l.fp32]}")
-    assert any(l.fp32 for l in levels)
-    ref = O.cmg(g)
-    say(f"  oracle lambda {ref.lam!r} k {[l.k for l in ref.levels]}")
-    assert_hierarchy_equal(g, ref, levels, arrays)
-    assert abs(lam - ref.lam) <= MIXED_LAM_RTOL * ref.lam
-    # lambda_2 of the 256^3 grid is 2 - 2 cos(pi/256); the CMG estimate is above it
-    assert lam >= (2.0 - 2.0 * np.cos(np.pi / 256)) * (1.0 - 1e-12)
-    check_output_properties(g, lam, x, st)
+    levels = full_size_case(g, "grid3d256", expect_step=True)
+    assert levels[0].n == 256 ** 3
 
 
 @pytest.fixture(scope="module")
@@ -99,16 +119,5 @@ def chunglu4m():
 
 
 def test_fullsize_chunglu4m(chunglu4m):
-    from oracle import oracle as O
-
-    g = chunglu4m
-    say(f"[fullsize] chunglu4m n={g.n} nnz={g.nnz}")
-    lam_m, x_m, st_m, levels_m, arrays = solve_device(g, precision=1)
-    say(f"  mixed lambda {lam_m!r} k {[l.k for l in levels_m]} variants {[l.variant for l in levels_m]}")
-    ref = O.cmg(g, max_iters=1)  # coarsening only (one step per level)
-    assert_hierarchy_equal(g, ref, levels_m, arrays)
-    check_output_properties(g, lam_m, x_m, st_m)
-    lam_d, x_d, st_d, levels_d, _ = solve_device(g, precision=0, with_arrays=False)
-    say(f"  fp64 lambda {lam_d!r} k {[l.k for l in levels_d]}")
-    check_output_properties(g, lam_d, x_d, st_d)
-    assert abs(lam_m - lam_d) <= MIXED_LAM_RTOL * lam_d
+    levels = full_size_case(chunglu4m, "chunglu4m", expect_step=False)
+    assert any(l.variant == 2 for l in levels)

@@ -168,6 +168,35 @@ def test_coarsest_star_projection(orc):
     assert np.allclose(y, p / np.linalg.norm(p), atol=1e-12)
 
 
+def test_coarsest_fallback_when_ramp_is_orthogonal(orc):
+    # Two joined copies of the 3x3 grid, labelled so that reversing the
+    # labels swaps the copies: lambda_2 = 2 - 2cos(pi/3) = 1 twice, on the
+    # grid modes phi(r) and phi(c) constant across the copies, which are
+    # even under the reversal while the ramp is odd.  The ramp's projection
+    # is rounding noise, so the coarsest rule projects the hashed uniform
+    # start U(seed, i) - 1/2 instead; U is recomputed here from the
+    # published SplitMix64 output function.
+    g = G.mirrored_prism(3)
+    seed = 14120565
+    y, lam, mult = orc.coarsest_dense(g, seed)
+    assert mult == 2 and abs(lam - 1.0) < 1e-13
+    n, a = g.n, 3
+    t = np.cos(np.pi * (np.arange(a) + 0.5) / a)
+    t /= np.linalg.norm(t)
+    e1, e2 = np.zeros(n), np.zeros(n)
+    for s_ in range(2):
+        for r in range(a):
+            for c in range(a):
+                i = a * r + c if s_ == 0 else n - 1 - (a * r + c)
+                e1[i] = t[r] / np.sqrt(2 * a)
+                e2[i] = t[c] / np.sqrt(2 * a)
+    z = np.arange(n) - (n - 1) / 2
+    assert abs(e1 @ z) < 1e-12 and abs(e2 @ z) < 1e-12
+    u = np.array([(G.mix64(seed ^ 0x9E3779B97F4A7C15 ^ i) >> 11) * 2.0 ** -53 for i in range(n)]) - 0.5
+    p = (e1 @ u) * e1 + (e2 @ u) * e2
+    assert np.allclose(y, p / np.linalg.norm(p), atol=1e-12)
+
+
 # -------------------------------------------------------------------- HEC
 
 def _parse_hec_golden():

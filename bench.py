@@ -356,18 +356,19 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log(f"[bench] reference copy: {nb} bytes read, {nb} bytes written")
+        # a second reference with plain vector loads and stores: an
+        # elementwise kernel reading and writing the same byte counts
+        torch.add(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"[bench] reference elementwise add: {nb} bytes read, {nb} bytes written")
         del src, dst
+    # every handle is freed; leave nothing queued or cached on the device
+    # for the runtime's exit-time teardown
     del g_dev, x
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
     main()
-    # Every handle is freed and the device is idle here.  Leave without the
-    # interpreter's and the HIP runtime's exit-time teardown: under
-    # rocprofv3 that teardown runs after the profiler's own finalisation
-    # and ended the process with SIGSEGV once all output had been written.
-    sys.stdout.flush()
-    sys.stderr.flush()
-    os._exit(0)

@@ -160,10 +160,14 @@ static int orc_cmp_keyv(const void* a, const void* b)
 }
 
 /* Heavy edge coarsening with an explicit visit order (Algorithm 2 and the
- * text of Section 2.1).  Vertices are visited in the order given; an
- * unmapped vertex v looks at its heaviest neighbour m: if m is unmapped too,
- * v and m open a new aggregate (v is its "seed"); otherwise v joins m's
- * aggregate.  Already-mapped vertices are skipped.
+ * text of Section 2.1).  Definition: the vertices are taken in the given
+ * order; one that belongs to no aggregate yet looks at its heaviest
+ * neighbour m.  If m belongs to no aggregate either, the two form a new
+ * aggregate, which the visited vertex opens (its "seed"); otherwise the
+ * visited vertex joins the aggregate m belongs to.
+ *
+ * Here each vertex records the seed of its aggregate (owner[], -1 while it
+ * has none), so an aggregate is named by its seed throughout.
  *
  * READING: the paper numbers aggregates in visit order; here they are
  * renumbered by ascending index of their seed vertex (a permutation of the
@@ -175,42 +179,35 @@ int32_t orc_hec_order(int32_t n, const int32_t* rp, const int32_t* col, const do
                       const int32_t* order, int32_t* agg, uint8_t* is_seed)
 {
     int32_t* h = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-    int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-    int32_t* seedv = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* owner = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
     int32_t* rank = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-    if (!h || !q || !seedv || !rank) {
-        free(h); free(q); free(seedv); free(rank);
+    if (!h || !owner || !rank) {
+        free(h); free(owner); free(rank);
         return -1;
     }
     if (orc_heaviest(n, rp, col, w, h) != ORC_OK) {
-        free(h); free(q); free(seedv); free(rank);
+        free(h); free(owner); free(rank);
         return -1;
     }
-    for (int32_t i = 0; i < n; ++i) q[i] = -1;
-    int32_t c = 0;
+    for (int32_t v = 0; v < n; ++v) owner[v] = -1;
     for (int32_t t = 0; t < n; ++t) {
-        int32_t v = order[t];
-        if (q[v] >= 0) continue;
-        int32_t m = h[v];
-        if (q[m] < 0) {
-            q[m] = c;
-            q[v] = c;
-            seedv[c] = v;
-            ++c;
-        } else {
-            q[v] = q[m];
-        }
+        const int32_t v = order[t];
+        if (owner[v] >= 0) continue;             /* already in an aggregate */
+        const int32_t m = h[v];
+        /* m's aggregate if it has one, else a new one seeded at v */
+        const int32_t sd = owner[m] >= 0 ? owner[m] : v;
+        owner[v] = sd;
+        owner[m] = sd;
     }
-    memset(is_seed, 0, (size_t)n);
-    for (int32_t a = 0; a < c; ++a) is_seed[seedv[a]] = 1;
-    int32_t r = 0;
+    int32_t count = 0;
     for (int32_t v = 0; v < n; ++v) {
-        rank[v] = r;
-        r += is_seed[v];
+        is_seed[v] = (uint8_t)(owner[v] == v);
+        rank[v] = count;
+        count += is_seed[v];
     }
-    for (int32_t v = 0; v < n; ++v) agg[v] = rank[seedv[q[v]]];
-    free(h); free(q); free(seedv); free(rank);
-    return c;
+    for (int32_t v = 0; v < n; ++v) agg[v] = rank[owner[v]];
+    free(h); free(owner); free(rank);
+    return count;
 }
 
 /* HEC with the seeded visit order of level j: ascending orc_hec_key. */
@@ -230,6 +227,82 @@ int32_t orc_hec(int32_t n, const int32_t* rp, const int32_t* col, const double* 
     qsort(kv, (size_t)n, sizeof(orc_keyv), orc_cmp_keyv);
     for (int32_t t = 0; t < n; ++t) order[t] = kv[t].v;
     int32_t c = orc_hec_order(n, rp, col, w, order, agg, is_seed);
+    free(kv); free(order);
+    return c;
+}
+
+/* Heavy edge matching (HEM; the matching the paper contrasts HEC with in
+ * Section 2.1, after Karypis and Kumar), with an explicit visit order.
+ * Definition: the vertices are taken in the given order; one that is not
+ * matched yet is matched to its heaviest neighbour among those not matched
+ * yet (lowest index on ties), if it has any, else it stays alone.  Every
+ * aggregate is a matched pair or a single vertex, so n_{j+1} >= n_j / 2
+ * (the lemma on coarsening rates: k_M >= 1/2).
+ *
+ * READING (as for HEC): aggregates are numbered by ascending index of the
+ * vertex that opened them (the one visited first; a single vertex opens
+ * its own).  Ties between equal weights go to the lowest neighbour index.
+ *
+ * agg[n] receives coarse ids, is_seed[n] marks opening vertices; returns
+ * the number of aggregates, or -1 on an isolated vertex / allocation
+ * failure. */
+int32_t orc_hem_order(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                      const int32_t* order, int32_t* agg, uint8_t* is_seed)
+{
+    int32_t* opener = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* rank = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!opener || !rank) {
+        free(opener); free(rank);
+        return -1;
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        if (rp[v + 1] == rp[v]) { free(opener); free(rank); return -1; }
+        opener[v] = -1;
+    }
+    for (int32_t t = 0; t < n; ++t) {
+        const int32_t v = order[t];
+        if (opener[v] >= 0) continue;            /* matched earlier */
+        int32_t best = -1;
+        double bw = 0.0;
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+            const int32_t u = col[e];
+            if (opener[u] >= 0) continue;        /* only unmatched partners */
+            if (best < 0 || w[e] > bw || (w[e] == bw && u < best)) {
+                best = u;
+                bw = w[e];
+            }
+        }
+        opener[v] = v;
+        if (best >= 0) opener[best] = v;
+    }
+    int32_t count = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        is_seed[v] = (uint8_t)(opener[v] == v);
+        rank[v] = count;
+        count += is_seed[v];
+    }
+    for (int32_t v = 0; v < n; ++v) agg[v] = rank[opener[v]];
+    free(opener); free(rank);
+    return count;
+}
+
+/* HEM with the seeded visit order of level j (the HEC keys). */
+int32_t orc_hem(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                uint64_t seed, int32_t level, int32_t* agg, uint8_t* is_seed)
+{
+    orc_keyv* kv = (orc_keyv*)malloc(sizeof(orc_keyv) * (size_t)n);
+    int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!kv || !order) {
+        free(kv); free(order);
+        return -1;
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        kv[v].key = orc_hec_key(seed, level, v);
+        kv[v].v = v;
+    }
+    qsort(kv, (size_t)n, sizeof(orc_keyv), orc_cmp_keyv);
+    for (int32_t t = 0; t < n; ++t) order[t] = kv[t].v;
+    int32_t c = orc_hem_order(n, rp, col, w, order, agg, is_seed);
     free(kv); free(order);
     return c;
 }
@@ -516,6 +589,45 @@ int32_t orc_pi(int32_t n, const int32_t* rp, const int32_t* col, const double* w
     return k;
 }
 
+/* Number of smoothing steps on level j of the fixed schedule of the
+ * geometric cascadic method (Algorithm 4 and the main theorem of Section 3:
+ * k_j = beta^j k_0).  READING: a step count is an integer; k_j is the
+ * smallest integer >= k_0 beta^j, with beta^j formed by j multiplications
+ * in FP64 (exact for the integers and halves used in the tests), capped at
+ * max_iters. */
+int32_t orc_fixed_steps(int32_t k0, double beta, int32_t j, int32_t max_iters)
+{
+    double p = (double)k0;
+    for (int32_t t = 0; t < j; ++t) p *= beta;
+    double c = ceil(p);
+    if (c > (double)max_iters) return max_iters;
+    return (int32_t)c;
+}
+
+/* Fixed-schedule smoothing on one level (Algorithm 4, line "u_j = (I -
+ * omega_j A_j)^{k_j} u_{j+1}" with omega_j = 1 / ||A_j||_inf): exactly
+ * `steps` applications of B_g = g I - L, g = ||L||_inf (the Gershgorin
+ * bound), each followed by deflation and normalisation as in Algorithm 3.
+ * (I - L/g)^k u = g^{-k} (g I - L)^k u, so the direction is the same; no
+ * stopping test is applied.  *utv receives the last (u^k, u^{k-1}). */
+void orc_pi_fixed(int32_t n, const int32_t* rp, const int32_t* col, const double* w, double g,
+                  const double* y0, int32_t steps, double* y, double* utv)
+{
+    double* v = (double*)calloc((size_t)n, sizeof(double));
+    double* t = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!v || !t) { free(v); free(t); *utv = NAN; return; }
+    memcpy(y, y0, sizeof(double) * (size_t)n);
+    orc_deflate_normalise(n, y);
+    for (int32_t k = 0; k < steps; ++k) {
+        memcpy(v, y, sizeof(double) * (size_t)n);
+        orc_laplacian_apply(n, rp, col, w, v, t);
+        for (int32_t i = 0; i < n; ++i) y[i] = g * v[i] - t[i];
+        orc_deflate_normalise(n, y);
+    }
+    *utv = orc_dot(n, y, v);
+    free(v); free(t);
+}
+
 /* Rayleigh quotient in edge form r = sum_{edges} w_ik (y_i - y_k)^2 / ||y||^2
  * (equal to y^T L y / y^T y, the eigenvalue estimate of Section 4), and the
  * residual ||L y - r y|| / ||y|| reported as the error in Table 2. */
@@ -598,9 +710,29 @@ void orc_free(orc_result* r)
  * The returned vector is deflated and normalised once more; lambda is the
  * edge-form Rayleigh quotient and residual ||L y - lambda y||.
  * The level-0 arrays are borrowed from the caller (not copied). */
+orc_result* orc_cmg_ex(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
+                       const double* w, double tol, int32_t coarsest_n, int32_t dense_max,
+                       uint64_t seed, int32_t max_iters, int32_t fixed_k0, double fixed_beta,
+                       int32_t coarsen);
+
 orc_result* orc_cmg(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
                     const double* w, double tol, int32_t coarsest_n, int32_t dense_max,
                     uint64_t seed, int32_t max_iters)
+{
+    return orc_cmg_ex(n, nnz, rp, col, w, tol, coarsest_n, dense_max, seed, max_iters, 0, 0.0, 0);
+}
+
+/* The same driver with two variations:
+ *  fixed_k0 > 0: every refined level j runs exactly
+ *      k_j = orc_fixed_steps(fixed_k0, fixed_beta, j, max_iters) smoothing
+ *      steps (Algorithm 4's schedule) instead of Algorithm 3's stopping
+ *      test; the coarsest level, when it is refined by power iteration
+ *      (after a collapse), follows the same schedule.
+ *  coarsen = 1: heavy edge matching (orc_hem) instead of HEC in Step 1. */
+orc_result* orc_cmg_ex(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
+                       const double* w, double tol, int32_t coarsest_n, int32_t dense_max,
+                       uint64_t seed, int32_t max_iters, int32_t fixed_k0, double fixed_beta,
+                       int32_t coarsen)
 {
     orc_result* r = (orc_result*)calloc(1, sizeof(orc_result));
     if (!r) return NULL;
@@ -618,7 +750,8 @@ orc_result* orc_cmg(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* co
         int32_t* agg = (int32_t*)malloc(sizeof(int32_t) * (size_t)L->n);
         uint8_t* sd = (uint8_t*)malloc((size_t)L->n);
         if (!agg || !sd) { free(agg); free(sd); r->status = ORC_E_OOM; return r; }
-        int32_t nc = orc_hec(L->n, L->rp, L->col, L->w, seed, j, agg, sd);
+        int32_t nc = coarsen == 1 ? orc_hem(L->n, L->rp, L->col, L->w, seed, j, agg, sd)
+                                  : orc_hec(L->n, L->rp, L->col, L->w, seed, j, agg, sd);
         free(sd);
         if (nc < 0) { free(agg); r->status = ORC_E_ISOLATED; return r; }
         if (nc < 2) { free(agg); r->collapsed = 1; break; }
@@ -648,8 +781,14 @@ orc_result* orc_cmg(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* co
         double* st = (double*)malloc(sizeof(double) * (size_t)CJ->n);
         if (!st) { free(ycur); r->status = ORC_E_OOM; return r; }
         for (int32_t i = 0; i < CJ->n; ++i) st[i] = orc_uniform(seed, i) - 0.5;
-        CJ->k = orc_pi(CJ->n, CJ->rp, CJ->col, CJ->w, CJ->g, st, tol, max_iters, ycur, &CJ->margin);
-        if (CJ->k >= max_iters) r->status = ORC_W_MAXIT;
+        if (fixed_k0 > 0) {
+            CJ->k = orc_fixed_steps(fixed_k0, fixed_beta, J, max_iters);
+            orc_pi_fixed(CJ->n, CJ->rp, CJ->col, CJ->w, CJ->g, st, CJ->k, ycur, &CJ->margin);
+            CJ->margin -= 1.0;
+        } else {
+            CJ->k = orc_pi(CJ->n, CJ->rp, CJ->col, CJ->w, CJ->g, st, tol, max_iters, ycur, &CJ->margin);
+            if (CJ->k >= max_iters) r->status = ORC_W_MAXIT;
+        }
         free(st);
     }
     for (int32_t t = J - 1; t >= 0; --t) {
@@ -658,8 +797,14 @@ orc_result* orc_cmg(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* co
         double* yn = (double*)malloc(sizeof(double) * (size_t)F->n);
         if (!yh || !yn) { free(yh); free(yn); free(ycur); r->status = ORC_E_OOM; return r; }
         for (int32_t v = 0; v < F->n; ++v) yh[v] = ycur[F->agg[v]];
-        F->k = orc_pi(F->n, F->rp, F->col, F->w, F->g, yh, tol, max_iters, yn, &F->margin);
-        if (F->k >= max_iters) r->status = ORC_W_MAXIT;
+        if (fixed_k0 > 0) {
+            F->k = orc_fixed_steps(fixed_k0, fixed_beta, t, max_iters);
+            orc_pi_fixed(F->n, F->rp, F->col, F->w, F->g, yh, F->k, yn, &F->margin);
+            F->margin -= 1.0;   /* (u^k, u^{k-1}) - 1: no tolerance applies */
+        } else {
+            F->k = orc_pi(F->n, F->rp, F->col, F->w, F->g, yh, tol, max_iters, yn, &F->margin);
+            if (F->k >= max_iters) r->status = ORC_W_MAXIT;
+        }
         free(yh);
         free(ycur);
         ycur = yn;

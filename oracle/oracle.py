@@ -76,6 +76,18 @@ def lib():
                              _f64p, C.POINTER(C.c_double)]
         L.orc_rq_residual.argtypes = [C.c_int32, _i32p, _i32p, _f64p, _f64p, C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]
+        L.orc_hem_order.restype = C.c_int32
+        L.orc_hem_order.argtypes = [C.c_int32, _i32p, _i32p, _f64p, _i32p, _i32p, _u8p]
+        L.orc_hem.restype = C.c_int32
+        L.orc_hem.argtypes = [C.c_int32, _i32p, _i32p, _f64p, C.c_uint64, C.c_int32, _i32p, _u8p]
+        L.orc_fixed_steps.restype = C.c_int32
+        L.orc_fixed_steps.argtypes = [C.c_int32, C.c_double, C.c_int32, C.c_int32]
+        L.orc_pi_fixed.restype = None
+        L.orc_pi_fixed.argtypes = [C.c_int32, _i32p, _i32p, _f64p, C.c_double, _f64p, C.c_int32, _f64p,
+                                   C.POINTER(C.c_double)]
+        L.orc_cmg_ex.restype = C.c_void_p
+        L.orc_cmg_ex.argtypes = [C.c_int32, C.c_int64, _i32p, _i32p, _f64p, C.c_double, C.c_int32,
+                                 C.c_int32, C.c_uint64, C.c_int32, C.c_int32, C.c_double, C.c_int32]
         L.orc_cmg.restype = C.c_void_p
         L.orc_cmg.argtypes = [C.c_int32, C.c_int64, _i32p, _i32p, _f64p, C.c_double, C.c_int32,
                               C.c_int32, C.c_uint64, C.c_int32]
@@ -186,6 +198,41 @@ def hec(g, seed: int, level: int):
     return agg, sd.astype(bool), int(c)
 
 
+def hem_order(g, order):
+    rp, col, w = _csr_args(g)
+    agg = np.zeros(g.n, dtype=np.int32)
+    sd = np.zeros(g.n, dtype=np.uint8)
+    c = lib().orc_hem_order(g.n, rp, col, w, np.ascontiguousarray(order, dtype=np.int32), agg, sd)
+    if c < 0:
+        raise ValueError("hem failed")
+    return agg, sd.astype(bool), int(c)
+
+
+def hem(g, seed: int, level: int):
+    rp, col, w = _csr_args(g)
+    agg = np.zeros(g.n, dtype=np.int32)
+    sd = np.zeros(g.n, dtype=np.uint8)
+    c = lib().orc_hem(g.n, rp, col, w, seed, level, agg, sd)
+    if c < 0:
+        raise ValueError("hem failed")
+    return agg, sd.astype(bool), int(c)
+
+
+def fixed_steps(k0: int, beta: float, j: int, max_iters: int = 100000) -> int:
+    return int(lib().orc_fixed_steps(k0, beta, j, max_iters))
+
+
+def pi_fixed(g, y0, steps: int, gval: float | None = None):
+    rp, col, w = _csr_args(g)
+    if gval is None:
+        gval = gershgorin(g)
+    y = np.zeros(g.n)
+    utv = C.c_double()
+    lib().orc_pi_fixed(g.n, rp, col, w, gval, np.ascontiguousarray(y0, dtype=np.float64), steps, y,
+                       C.byref(utv))
+    return y, float(utv.value)
+
+
 def galerkin(g, agg, nc):
     """Returns (row_ptr, col, w) of the coarse graph."""
     rp, col, w = _csr_args(g)
@@ -272,11 +319,15 @@ class Result:
 
 
 def cmg(g, tol: float = 1e-8, coarsest_n: int = 25, dense_max: int = 128, seed: int = 14120565,
-        max_iters: int = 100000, keep_levels: bool = True) -> Result:
-    """Full CMG (Algorithm 1) on the CPU oracle."""
+        max_iters: int = 100000, keep_levels: bool = True, fixed_k0: int = 0, fixed_beta: float = 2.0,
+        coarsen: str = "hec") -> Result:
+    """Full CMG (Algorithm 1) on the CPU oracle.  fixed_k0 > 0: Algorithm
+    4's schedule k_j = ceil(fixed_k0 fixed_beta^j) steps per level instead
+    of the stopping test; coarsen "hem": heavy edge matching instead of HEC."""
     L = lib()
     rp, col, w = _csr_args(g)
-    r = L.orc_cmg(g.n, int(rp[-1]), rp, col, w, tol, coarsest_n, dense_max, seed, max_iters)
+    r = L.orc_cmg_ex(g.n, int(rp[-1]), rp, col, w, tol, coarsest_n, dense_max, seed, max_iters,
+                     int(fixed_k0), float(fixed_beta), {"hec": 0, "hem": 1}[coarsen])
     if not r:
         raise MemoryError
     try:

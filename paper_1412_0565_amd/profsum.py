@@ -72,6 +72,15 @@ def _copy_factor(per):
     return copies[-1], copies[-1]["v"] * 1024.0
 
 
+def _elementwise_counted(per):
+    """Counted bytes of the elementwise reference kernel that follows the
+    copy (same byte counts, plain vector loads and stores), or None."""
+    last = per[-1][1] if per else None
+    if last is None or "copyBuffer" in last["name"]:
+        return None
+    return last["v"] * 1024.0
+
+
 def counters(fetch_csv, write_csv, copy_bytes):
     out = {}
     for label, path, counter in [("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")]:
@@ -81,9 +90,17 @@ def counters(fetch_csv, write_csv, copy_bytes):
         rows = [{"Kernel_Name": d["name"], "Dispatch_Id": i} for i, d in per]
         ids = set(_level0_dispatch_ids(rows, "Kernel_Name", "Dispatch_Id"))
         vals = [d["v"] * 1024.0 for i, d in per if i in ids]
+        ew = _elementwise_counted(per)
         out[label] = {"factor": factor, "copy_counted": copy_counted, "raw_mean": statistics.mean(vals),
-                      "launches": len(vals), "bytes": statistics.mean(vals) / factor}
+                      "launches": len(vals), "bytes": statistics.mean(vals) / factor,
+                      "ew_factor": None if ew is None else ew / copy_bytes}
     f, w = out["fetch"], out["write"]
+    extra = []
+    if f["ew_factor"] is not None and w["ew_factor"] is not None:
+        extra = [f"- FETCH_SIZE factor of the elementwise reference: {f['ew_factor']:.4f}",
+                 f"- WRITE_SIZE factor of the elementwise reference: {w['ew_factor']:.4f}",
+                 f"- HBM bytes per launch with the elementwise factors: "
+                 f"{f['raw_mean'] / f['ew_factor'] + w['raw_mean'] / w['ew_factor']:.0f}"]
     return "\n".join([
         f"- reference copy bytes: {copy_bytes}",
         f"- FETCH_SIZE of the copy: {f['copy_counted']:.0f} bytes (factor {f['factor']:.4f})",
@@ -94,7 +111,7 @@ def counters(fetch_csv, write_csv, copy_bytes):
         f"- HBM read bytes per launch: {f['bytes']:.0f}",
         f"- HBM write bytes per launch: {w['bytes']:.0f}",
         f"- HBM bytes per launch: {f['bytes'] + w['bytes']:.0f}",
-    ])
+    ] + extra)
 
 
 if __name__ == "__main__":

@@ -121,6 +121,18 @@ typedef struct {
                                     launch; 1 uses one launch per step on every such level; -1 on
                                     none.  The same arithmetic in the same order either way:
                                     results are equal to rounding of the sums' tree. */
+    int32_t fixed_k0;            /* > 0: fixed smoothing schedule of the geometric cascadic method
+                                    (Algorithm 4; Section 3, main theorem): level j runs exactly
+                                    k_j = ceil(fixed_k0 * fixed_beta^j) power-iteration steps
+                                    (capped at max_iters_per_level) and no stopping test; the
+                                    launch sequence of a solve is then fixed.  0 (default): the
+                                    stopping test of Algorithm 3 with `tol`. */
+    double fixed_beta;           /* beta >= 1 of the fixed schedule (default 2) */
+    int32_t graph;               /* 1: the first cmg_fiedler on the handle captures its launch
+                                    sequence in a HIP graph and later solves replay it (only
+                                    when the sequence is fixed: a fixed schedule, or no level
+                                    refined one launch per step); per-level device times
+                                    (pi_ms) are then not measured.  0 (default): launches. */
 } cmg_options;
 
 /* Per-level information (available after cmg_setup; PI fields after

@@ -56,6 +56,9 @@ class cmg_options(C.Structure):
         ("block_regs", C.c_int32),
         ("grid_stage", C.c_int32),
         ("step_mode", C.c_int32),
+        ("fixed_k0", C.c_int32),
+        ("fixed_beta", C.c_double),
+        ("graph", C.c_int32),
     ]
 
 

@@ -58,6 +58,7 @@ struct HostLevel {
     int32_t* part = nullptr;
     int bwaves = 0, bregs = 0, bslots = 0;  // single-workgroup level: waves, register rows, slots
     int step = 0;              // 1: refined with one launch per PI step
+    int kfix = 0;              // fixed schedule: PI steps of this level (0: stopping test)
     int fgrid = 0;             // level 0 in step mode: finishing pass grid
     int32_t* fpart = nullptr;  // ... and its row split
     int k = 0;
@@ -209,6 +210,8 @@ struct cmg_ctx {
     double* d_part = nullptr;   // 4 partial sums per workgroup
     int* h_flags = nullptr;     // pinned: done flag after each chunk of steps
     std::vector<hipEvent_t> chunk_ev;
+    bool fixed = false;            // fixed smoothing schedule: every launch count known in advance
+    hipGraphExec_t gexec = nullptr;  // captured refinement launches (cmg_options.graph)
 
     // Device memory of the handle (hierarchy, refinement state, job
     // tables) comes from a bump arena over a few large chunks of the
@@ -254,6 +257,7 @@ struct cmg_ctx {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         for (hipEvent_t e : chunk_ev) (void)hipEventDestroy(e);
         if (h_flags) (void)hipHostFree(h_flags);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
     }
 };
 
@@ -613,6 +617,7 @@ LevelDev level_dev(const HostLevel& L) {
     d.bregs = L.bregs;
     d.bslots = L.bslots;
     d.stage = L.stage;
+    d.kfix = L.kfix;
     return d;
 }
 
@@ -815,6 +820,16 @@ cmg_status tune_level(cmg_ctx* c, int j, int maxgrid) {
     return CMG_OK;
 }
 
+// Fixed smoothing schedule of the geometric cascadic method (Algorithm 4;
+// Section 3, main theorem): level j runs the smallest integer number of
+// steps >= k0 beta^j, beta^j formed by j multiplications, at most cap.
+int fixed_steps(int k0, double beta, int j, int cap) {
+    double p = (double)k0;
+    for (int t = 0; t < j; ++t) p *= beta;
+    const double c = std::ceil(p);
+    return c > (double)cap ? cap : (int)c;
+}
+
 cmg_status build_refine_plan(cmg_ctx* c) {
     const int J = (int)c->lv.size() - 1;
     const cmg_options& o = c->opt;
@@ -824,6 +839,9 @@ cmg_status build_refine_plan(cmg_ctx* c) {
     const int64_t mixed_min = o.mixed_min_nnz > 0 ? o.mixed_min_nnz : (int64_t)1 << 20;
     // refinement levels: 0..J-1, plus J if the coarsest uses power iteration
     int top = c->coarse_dense ? J - 1 : J;
+    c->fixed = o.fixed_k0 > 0;
+    for (int j = 0; j <= J; ++j)
+        c->lv[j].kfix = (c->fixed && j <= top) ? fixed_steps(o.fixed_k0, o.fixed_beta, j, o.max_iters_per_level) : 0;
     c->block_lo = top + 1;
     for (int j = top; j >= 0; --j) {
         const bool in = o.block_rows > 0 ? c->lv[j].n <= o.block_rows : block_level(c->lv[j], block_rows);
@@ -962,9 +980,9 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         g.slots = c->d_slots;
         g.bcast = c->d_bcast;
         g.uniform = (j == J) ? 1 : 0;
-        g.tol = o.tol;
+        g.tol = c->lv[j].kfix > 0 ? -1.0 : o.tol;  // a fixed schedule never passes the test
         g.seed = o.seed;
-        g.maxit = o.max_iters_per_level;
+        g.maxit = c->lv[j].kfix > 0 ? c->lv[j].kfix : o.max_iters_per_level;
         g.b0 = 0;
         g.tag = j;
         jobs[j] = g;
@@ -1003,9 +1021,9 @@ cmg_status build_refine_plan(cmg_ctx* c) {
             t.st = c->d_st + j;
             t.ctl = c->d_ctl;
             t.part = c->d_part;
-            t.tol = o.tol;
+            t.tol = c->lv[j].kfix > 0 ? -1.0 : o.tol;
             t.seed = o.seed;
-            t.maxit = o.max_iters_per_level;
+            t.maxit = c->lv[j].kfix > 0 ? c->lv[j].kfix : o.max_iters_per_level;
             t.uniform = (j == J) ? 1 : 0;
             sj[j] = t;
         }
@@ -1163,6 +1181,9 @@ void fill_defaults(cmg_options* o) {
     o->block_regs = 0;
     o->grid_stage = 1;
     o->step_mode = 0;
+    o->fixed_k0 = 0;
+    o->fixed_beta = 2.0;
+    o->graph = 0;
 }
 
 // Device results of the last solve -> host staging (asynchronous).
@@ -1201,7 +1222,8 @@ cmg_status finalize(cmg_ctx* c, double t0, bool timed, double* lambda, cmg_stats
         } else {
             L.k = c->h_st[j].k;
             L.margin = c->h_st[j].margin;
-            if (c->h_st[j].maxit) status = CMG_W_MAXIT;
+            // a fixed schedule ends every level at its step count by design
+            if (c->h_st[j].maxit && L.kfix == 0) status = CMG_W_MAXIT;
             if (L.in_block && c->h_st[j].err) {
                 if (c->h_st[j].err == 2)
                     std::snprintf(g_last_error, sizeof(g_last_error),
@@ -1262,6 +1284,10 @@ cmg_status run_step_level(cmg_ctx* c, int j, hipStream_t s) {
     const int kind = job_kind(L.variant, L.lanes, L.fp32);
     const int maxit = c->opt.max_iters_per_level;
     CK(launch_step_begin(job, L.grid, kind, s));
+    if (L.kfix > 0) {  // fixed schedule: the step count is known, no host checks
+        for (int i = 0; i < L.kfix; ++i) CK(launch_step_pi(job, L.grid, kind, s));
+        return CMG_OK;
+    }
     int launched = 0, chunks = 0;
     const int chunk = kStepChunk;
     auto enqueue = [&]() -> cmg_status {
@@ -1294,34 +1320,88 @@ cmg_status run_step_level(cmg_ctx* c, int j, hipStream_t s) {
     return CMG_OK;
 }
 
-cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where, cmg_stats* stats) {
-    const double t0 = now_ms();
-    hipStream_t s = c->stream;
+// The launches of a solve after the coarsest solve: the single-workgroup
+// runs, the grid levels coarse to fine, the finishing pass.  timed: events
+// around each grid level (not inside a captured graph).
+cmg_status enqueue_refine(cmg_ctx* c, hipStream_t s, bool timed) {
     const int J = (int)c->lv.size() - 1;
-    if (c->d_cjob && !c->coarse_done) {
-        CK(launch_coarse_jobs(c->d_cjob, 1, s));
-        c->coarse_done = true;
-    }
     for (size_t r = 0; r < c->h_bruns.size(); ++r) CK(launch_block_jobs(c->d_bruns + r, 1, c->brun_kind[r], s));
     // grid levels: one persistent launch per level
     for (int j = std::min(c->top, c->block_lo - 1); j >= 0; --j) {
         const HostLevel& L = c->lv[j];
-        CK(hipEventRecord(c->events[2 * j], s));
+        if (timed) CK(hipEventRecord(c->events[2 * j], s));
         if (L.step) {
             cmg_status st = run_step_level(c, j, s);
             if (st != CMG_OK) return st;
         } else {
             CK(launch_refine_jobs(c->d_jobs + j, 1, L.grid, job_kind(L.variant, L.lanes, L.fp32), s));
         }
-        CK(hipEventRecord(c->events[2 * j + 1], s));
+        if (timed) CK(hipEventRecord(c->events[2 * j + 1], s));
     }
     const HostLevel& L0 = c->lv[0];
     CK(launch_finish_jobs(c->d_jobs + J + 1, 1, L0.step ? L0.fgrid : L0.grid, job_kind(L0.variant, L0.lanes, L0.fp32),
                           s));
+    return CMG_OK;
+}
+
+// The launch sequence is fixed when no level decides its step count on the
+// host: a fixed schedule, or no level refined one launch per step.
+bool static_sequence(const cmg_ctx* c) {
+    if (c->fixed) return true;
+    for (int j = std::min(c->top, c->block_lo - 1); j >= 0; --j)
+        if (c->lv[j].step) return false;
+    return true;
+}
+
+// Records enqueue_refine into c->gexec.  The capture runs on a private
+// stream (the null stream cannot be captured); the graph is launched on the
+// handle's stream.  Kernels only: no memset or copy nodes.
+cmg_status capture_refine(cmg_ctx* c) {
+    hipStream_t cs = nullptr;
+    CK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    cmg_status st = CMG_OK;
+    if (e == hipSuccess) st = enqueue_refine(c, cs, false);
+    hipGraph_t g = nullptr;
+    if (e == hipSuccess) {
+        const hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (st == CMG_OK && e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess && st == CMG_OK) e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (st != CMG_OK) return st;
+    if (e != hipSuccess) {
+        c->gexec = nullptr;
+        set_error("graph capture", e, __LINE__);
+        (void)hipGetLastError();
+        return CMG_E_DEVICE;
+    }
+    return CMG_OK;
+}
+
+cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where, cmg_stats* stats) {
+    const double t0 = now_ms();
+    hipStream_t s = c->stream;
+    if (c->d_cjob && !c->coarse_done) {
+        CK(launch_coarse_jobs(c->d_cjob, 1, s));
+        c->coarse_done = true;
+    }
+    const bool graph = c->opt.graph && static_sequence(c);
+    if (graph) {
+        if (!c->gexec) {
+            cmg_status st = capture_refine(c);
+            if (st != CMG_OK) return st;
+        }
+        CK(hipGraphLaunch(c->gexec, s));
+    } else {
+        cmg_status st = enqueue_refine(c, s, true);
+        if (st != CMG_OK) return st;
+    }
     cmg_status st = enqueue_readback(c, x, where, s);
     if (st != CMG_OK) return st;
     CK(hipStreamSynchronize(s));
-    return finalize(c, t0, true, lambda, stats);
+    return finalize(c, t0, !graph, lambda, stats);
 }
 
 // Several graphs: every stage of all graphs in packed launches (one
@@ -1517,7 +1597,8 @@ cmg_status cmg_setup(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
     if (!(o.tol < 1.0) || !std::isfinite(o.tol) || o.coarsest_n < 2 || o.dense_max < 2 || o.dense_max > 128 ||
         o.max_iters_per_level < 1 || (o.precision != CMG_FP64 && o.precision != CMG_MIXED) ||
         o.fp64_final_sweeps < 0 || o.fp64_final_sweeps > 1 || o.coarsest_n > o.dense_max ||
-        o.step_mode < -1 || o.step_mode > 1)
+        o.step_mode < -1 || o.step_mode > 1 || o.fixed_k0 < 0 ||
+        (o.fixed_k0 > 0 && !(o.fixed_beta >= 1.0 && std::isfinite(o.fixed_beta))) || o.graph < 0 || o.graph > 1)
         return CMG_E_ARG;
     const double t0 = now_ms();
     cmg_ctx* c = new (std::nothrow) cmg_ctx;

@@ -177,6 +177,7 @@ struct LevelDev {
     int32_t bregs;       // single-workgroup refinement: rows per lane group held in registers (0: CSR)
     int32_t bslots;      // register rows: entry slots per lane and row (E of the layout)
     int32_t stage;       // grid levels: 1 if a workgroup's rows may be staged in LDS
+    int32_t kfix;        // > 0: fixed schedule, exactly this many PI steps and no stopping test
 };
 
 // State a refinement launch leaves for the next level (device written).

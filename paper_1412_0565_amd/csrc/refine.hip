@@ -841,8 +841,8 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
         in.cm = s_cm;
         in.cs = s_cs;
         in.seed = Jb.seed;
-        in.tol = Jb.tol;
-        in.maxit = Jb.maxit;
+        in.tol = L.kfix > 0 ? -1.0 : Jb.tol;  // a fixed schedule never passes the test
+        in.maxit = L.kfix > 0 ? L.kfix : Jb.maxit;
         LevelState o;
         if (mode == 0) {
             if (threadIdx.x < 64) {
@@ -1019,8 +1019,8 @@ __global__ void __launch_bounds__(kBlockRegsThreads)
         in.cm = s_cm;
         in.cs = s_cs;
         in.seed = Jb.seed;
-        in.tol = Jb.tol;
-        in.maxit = Jb.maxit;
+        in.tol = L.kfix > 0 ? -1.0 : Jb.tol;  // a fixed schedule never passes the test
+        in.maxit = L.kfix > 0 ? L.kfix : Jb.maxit;
         LevelState o{};
         if (!fits) {
             o.err = 2;

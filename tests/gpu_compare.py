@@ -34,7 +34,8 @@ def oracle_of(g, **opts):
 
     kw = {}
     for k_src, k_dst in [("tol", "tol"), ("coarsest_n", "coarsest_n"), ("dense_max", "dense_max"),
-                         ("seed", "seed"), ("max_iters_per_level", "max_iters")]:
+                         ("seed", "seed"), ("max_iters_per_level", "max_iters"), ("fixed_k0", "fixed_k0"),
+                         ("fixed_beta", "fixed_beta")]:
         if k_src in opts:
             kw[k_dst] = opts[k_src]
     return O.cmg(g, **kw)

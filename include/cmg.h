@@ -244,6 +244,32 @@ const char* cmg_status_string(cmg_status s);
  * if the last call succeeded.  Valid until the next call. */
 const char* cmg_last_error(void);
 
+/* For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc; code under HIP graph capture is not
+ * supported, since the call synchronises): cmg_setup, cmg_fiedler and
+ * cmg_free of one graph in a single call that allocates nothing.  Every
+ * device buffer is carved from a static scratch array of 64 MiB that each
+ * device the library runs on holds until the process ends; the call makes
+ * no hipMalloc, hipFree, host-pinned, event or stream allocation (the
+ * allocator in `opt` is ignored).
+ *   Arguments as cmg_setup (n, nnz, row_ptr, col, w, wtype, where, opt)
+ *   followed by cmg_fiedler's outputs (lambda, x of n doubles in `where`,
+ *   stats).  The solve is the same as cmg_setup + cmg_fiedler with the same
+ *   options except that no level is refined one launch per step (step_mode
+ *   -1), autotune and graph are off, and per-level device times are not
+ *   measured.
+ *   Size limit: 64 nnz + 128 n + 4 MiB <= 64 MiB - 4 KiB (about 100k
+ *   vertices with 600k entries); a larger graph returns CMG_E_ARG with the
+ *   bound in cmg_last_error().  Running out of scratch returns CMG_E_OOM.
+ *   Calls on one device share its scratch: the library serialises the
+ *   calls of one process, and a caller must not read the scratch's
+ *   contents from one call in another (each call initialises what it
+ *   uses).  Work another thread queues on the same device while a call
+ *   runs can race with it through the grid barriers (see cmg_fiedler). */
+cmg_status cmg_fiedler_noalloc(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                               const void* w, cmg_valtype wtype, cmg_memspace where,
+                               const cmg_options* opt, double* lambda, void* x, cmg_stats* stats);
+
 /* Diagnostics: evaluate on the GPU the counter-based hash the library uses
  * for HEC priorities, key(v) = mix64(seed ^ (level << 40) ^ v) with mix64
  * the SplitMix64 output function, for v = 0..count-1 into host out[].

@@ -26,7 +26,7 @@ CMG_VAL_F64, CMG_VAL_F32 = 0, 1
 # functions declared in include/cmg.h
 EXPORTS = ["cmg_options_default", "cmg_setup", "cmg_fiedler", "cmg_fiedler_batch", "cmg_level_info",
            "cmg_level_copy", "cmg_set_stream", "cmg_footprint", "cmg_free", "cmg_status_string",
-           "cmg_last_error", "cmg_hash_probe"]
+           "cmg_last_error", "cmg_hash_probe", "cmg_fiedler_noalloc"]
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 _FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
@@ -138,6 +138,10 @@ def lib():
         L.cmg_last_error.restype = C.c_char_p
         L.cmg_hash_probe.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_void_p]
         L.cmg_hash_probe.restype = C.c_int
+        L.cmg_fiedler_noalloc.argtypes = [C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                          C.c_int, C.POINTER(cmg_options), C.POINTER(C.c_double), C.c_void_p,
+                                          C.POINTER(cmg_stats)]
+        L.cmg_fiedler_noalloc.restype = C.c_int
         _lib = L
     return _lib
 
@@ -297,6 +301,26 @@ def cmg_footprint(h: int) -> int:
 
 def cmg_free(h: int) -> None:
     lib().cmg_free(h)
+
+
+def cmg_fiedler_noalloc(n: int, row_ptr, col, w, x, opt: cmg_options | None = None,
+                        stats: cmg_stats | None = None):
+    """Setup + solve + free in one call that allocates no device memory
+    (static scratch).  Arrays as cmg_setup; x: float64 output of n entries
+    in the same memory space.  Returns (lambda, status)."""
+    prp, where = _ptr(row_ptr)
+    pcol, w2 = _ptr(col)
+    pw, w3 = _ptr(w)
+    px, w4 = _ptr(x)
+    if not (where == w2 == w3 == w4):
+        raise ValueError("row_ptr, col, w and x must share one memory space")
+    wtype = CMG_VAL_F32 if str(w.dtype).split(".")[-1] == "float32" else CMG_VAL_F64
+    lam = C.c_double()
+    st = lib().cmg_fiedler_noalloc(int(n), int(col.shape[0]), prp, pcol, pw, wtype, where,
+                                   C.byref(opt) if opt is not None else None, C.byref(lam), px,
+                                   C.byref(stats) if stats is not None else None)
+    _check(st, "cmg_fiedler_noalloc")
+    return lam.value, st
 
 
 def cmg_hash_probe(seed: int, level: int, count: int) -> np.ndarray:

@@ -211,6 +211,7 @@ struct cmg_ctx {
     int* h_flags = nullptr;     // pinned: done flag after each chunk of steps
     std::vector<hipEvent_t> chunk_ev;
     bool fixed = false;            // fixed smoothing schedule: every launch count known in advance
+    bool noalloc = false;          // cmg_fiedler_noalloc: no events, no host-pinned or stream objects
     hipGraphExec_t gexec = nullptr;  // captured refinement launches (cmg_options.graph)
 
     // Device memory of the handle (hierarchy, refinement state, job
@@ -1070,8 +1071,10 @@ cmg_status build_refine_plan(cmg_ctx* c) {
             hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
             c->clock_khz = khz;
     }
-    c->events.resize(2 * (J + 1));
-    for (auto& e : c->events) CK(hipEventCreate(&e));
+    if (!c->noalloc) {
+        c->events.resize(2 * (J + 1));
+        for (auto& e : c->events) CK(hipEventCreate(&e));
+    }
     CK(hipStreamSynchronize(c->stream));
     return CMG_OK;
 }
@@ -1395,13 +1398,13 @@ cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where,
         }
         CK(hipGraphLaunch(c->gexec, s));
     } else {
-        cmg_status st = enqueue_refine(c, s, true);
+        cmg_status st = enqueue_refine(c, s, !c->noalloc);
         if (st != CMG_OK) return st;
     }
     cmg_status st = enqueue_readback(c, x, where, s);
     if (st != CMG_OK) return st;
     CK(hipStreamSynchronize(s));
-    return finalize(c, t0, !graph, lambda, stats);
+    return finalize(c, t0, !graph && !c->noalloc, lambda, stats);
 }
 
 // Several graphs: every stage of all graphs in packed launches (one
@@ -1554,6 +1557,81 @@ cmg_status batch_impl(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
     return worst;
 }
 
+// ---- the entry point that allocates nothing
+//
+// All device memory of a cmg_fiedler_noalloc call (hierarchy, setup
+// temporaries, vectors, job tables, barrier state, and the buffers of a
+// first residency count) is carved from `scratch`, a static array that each
+// device holds for the life of the process.  Host code must not pass the
+// array's name to kernels (it is a host-side stand-in); the device address
+// comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+constexpr size_t kNoallocMeasureBytes = 4096;  // residency count buffers at the front
+constexpr int kNoallocMaxDevices = 64;
+
+static_assert(256 + sizeof(GridJob) <= kNoallocMeasureBytes, "residency count buffers");
+
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+std::mutex g_noalloc_mu;
+unsigned char* g_scratch_dev[kNoallocMaxDevices] = {};
+
+// Scratch a graph of n vertices and nnz entries may need: the handle's
+// arena (12 nnz + 48 n + 2 MiB, plus the coarse levels' share), the setup
+// temporaries (about 40 nnz + 40 n) and the refinement state.
+size_t noalloc_need(int32_t n, int64_t nnz) {
+    return (size_t)64 * (size_t)nnz + (size_t)128 * (size_t)n + ((size_t)4 << 20);
+}
+
+struct Bump {
+    unsigned char* base;
+    size_t cap, off;
+};
+
+void* bump_alloc(size_t bytes, void*, void* user) {
+    Bump* b = (Bump*)user;
+    const size_t o = (b->off + 255) & ~(size_t)255;
+    if (bytes > b->cap || o > b->cap - bytes) return nullptr;
+    b->off = o + bytes;
+    return b->base + o;
+}
+
+void bump_free(void*, void*, void*) {}
+
+cmg_status noalloc_impl(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, const void* w,
+                        cmg_valtype wtype, cmg_memspace where, const cmg_options& o, double* lambda, void* x,
+                        cmg_stats* stats) {
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoallocMaxDevices) return CMG_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        CK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_dev[dev] = (unsigned char*)p;
+    }
+    unsigned char* base = g_scratch_dev[dev];
+    Bump bump{base + kNoallocMeasureBytes, kNoallocScratchBytes - kNoallocMeasureBytes, 0};
+    const cmg_allocator alloc{bump_alloc, bump_free, &bump};
+    const MeasureBuffers mb{(unsigned*)base, (GridJob*)(base + 256), (hipStream_t)o.stream};
+    set_measure_buffers(&mb);
+    cmg_status st;
+    {
+        cmg_ctx c;
+        c.opt = o;
+        c.opt.allocator = nullptr;
+        c.stream = (hipStream_t)o.stream;
+        c.alloc = alloc;
+        c.noalloc = true;
+        const double t0 = now_ms();
+        st = setup_impl(&c, n, nnz, row_ptr, col, w, wtype, where);
+        c.setup_ms = now_ms() - t0;
+        if (st == CMG_OK) st = fiedler_impl(&c, lambda, x, where, stats);
+    }  // ~cmg_ctx waits for the stream; its frees are no-ops
+    set_measure_buffers(nullptr);
+    return st;
+}
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -1695,6 +1773,41 @@ cmg_status cmg_footprint(cmg_handle h, size_t* bytes) {
 }
 
 void cmg_free(cmg_handle h) { delete h; }
+
+cmg_status cmg_fiedler_noalloc(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, const void* w,
+                               cmg_valtype wtype, cmg_memspace where, const cmg_options* opt, double* lambda,
+                               void* x, cmg_stats* stats) {
+    g_last_error[0] = 0;
+    if (n < 2 || nnz < 1 || nnz >= 2147483647LL || !row_ptr || !col || !w) return CMG_E_ARG;
+    if (wtype != CMG_VAL_F64 && wtype != CMG_VAL_F32) return CMG_E_ARG;
+    if (where != CMG_MEM_HOST && where != CMG_MEM_DEVICE) return CMG_E_ARG;
+    cmg_options o;
+    fill_defaults(&o);
+    if (opt) {
+        size_t sz = opt->struct_size ? std::min<size_t>(opt->struct_size, sizeof(o)) : sizeof(o);
+        std::memcpy(&o, opt, sz);
+        o.struct_size = sizeof(o);
+    }
+    if (!(o.tol < 1.0) || !std::isfinite(o.tol) || o.coarsest_n < 2 || o.dense_max < 2 || o.dense_max > 128 ||
+        o.max_iters_per_level < 1 || (o.precision != CMG_FP64 && o.precision != CMG_MIXED) ||
+        o.fp64_final_sweeps < 0 || o.fp64_final_sweeps > 1 || o.coarsest_n > o.dense_max || o.fixed_k0 < 0 ||
+        (o.fixed_k0 > 0 && !(o.fixed_beta >= 1.0 && std::isfinite(o.fixed_beta))))
+        return CMG_E_ARG;
+    const size_t need = noalloc_need(n, nnz);
+    if (need > kNoallocScratchBytes - kNoallocMeasureBytes) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "cmg_fiedler_noalloc: a graph of %d vertices and %lld entries needs up to %zu bytes of "
+                      "scratch; the static scratch holds %zu",
+                      n, (long long)nnz, need, kNoallocScratchBytes - kNoallocMeasureBytes);
+        return CMG_E_ARG;
+    }
+    // launches only: no step-by-step levels (pinned flags, events), no
+    // autotuner (events), no graph (a capture stream)
+    o.step_mode = -1;
+    o.autotune = 0;
+    o.graph = 0;
+    return noalloc_impl(n, nnz, row_ptr, col, w, wtype, where, o, lambda, x, stats);
+}
 
 cmg_status cmg_hash_probe(uint64_t seed, int32_t level, int32_t count, uint64_t* out) {
     if (count < 0 || (count > 0 && !out)) return CMG_E_ARG;

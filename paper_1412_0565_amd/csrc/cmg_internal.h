@@ -161,6 +161,15 @@ int finish_jobs_max_blocks(int kind);
 // one level of each job (all of one kind); nblocks = sum of the jobs' grids
 hipError_t launch_refine_jobs(const GridJob* jobs, int njobs, int nblocks, int kind, hipStream_t s);
 hipError_t launch_finish_jobs(const GridJob* jobs, int njobs, int nblocks, int kind, hipStream_t s);
+// Device buffers a residency count may use instead of allocating its own,
+// and the stream it then runs on (set per thread by the entry point that
+// allocates nothing; nullptr clears).  cnt: 2 unsigned; job: one GridJob.
+struct MeasureBuffers {
+    unsigned* cnt;
+    GridJob* job;
+    hipStream_t stream;
+};
+void set_measure_buffers(const MeasureBuffers* b);
 // zero the barrier state and the slots (2 * nslots; at setup, and after an abort)
 hipError_t launch_reset_sync(GridSync* gs, GridSlot* slots, int nslots, GridSlot* bcast, hipStream_t s);
 

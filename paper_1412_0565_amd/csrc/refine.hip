@@ -1973,6 +1973,8 @@ const void* finish_kernel(int kind) {
 // all resident never completes.  So the kernel itself is launched once in
 // residency-count mode at the queried size and the observed peak is used,
 // rounded down to a multiple of 8.  Returns 0 on any error.
+thread_local MeasureBuffers t_meas{nullptr, nullptr, nullptr};
+
 int max_blocks_ptr(const void* k) {
     int dev = 0, ncu = 0, occ = 0, khz = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -1985,12 +1987,19 @@ int max_blocks_ptr(const void* k) {
     GridJob* dj = nullptr;
     hipStream_t s = nullptr;
     unsigned peak[2] = {0u, 0u};
+    const bool own = t_meas.cnt == nullptr;  // else buffers and stream given by the caller
     // the count needs an idle device: work already queued (a coarsest solve
     // launched during setup, another thread's solve) finishes first
-    bool ok = hipDeviceSynchronize() == hipSuccess &&
-              hipMalloc((void**)&cnt, 2 * sizeof(unsigned)) == hipSuccess &&
-              hipMalloc((void**)&dj, sizeof(GridJob)) == hipSuccess &&
-              hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    bool ok = hipDeviceSynchronize() == hipSuccess;
+    if (ok && own) {
+        ok = hipMalloc((void**)&cnt, 2 * sizeof(unsigned)) == hipSuccess &&
+             hipMalloc((void**)&dj, sizeof(GridJob)) == hipSuccess &&
+             hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    } else if (ok) {
+        cnt = t_meas.cnt;
+        dj = t_meas.job;
+        s = t_meas.stream;
+    }
     if (ok) {
         GridJob j{};
         j.tag = kResidencyTag;
@@ -2005,9 +2014,11 @@ int max_blocks_ptr(const void* k) {
              hipMemcpyAsync(peak, cnt, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, s) == hipSuccess &&
              hipStreamSynchronize(s) == hipSuccess;
     }
-    if (s) (void)hipStreamDestroy(s);
-    if (dj) (void)hipFree(dj);
-    if (cnt) (void)hipFree(cnt);
+    if (own) {
+        if (s) (void)hipStreamDestroy(s);
+        if (dj) (void)hipFree(dj);
+        if (cnt) (void)hipFree(cnt);
+    }
     if (!ok) {
         (void)hipGetLastError();
         return 0;
@@ -2016,6 +2027,8 @@ int max_blocks_ptr(const void* k) {
     return got >= 8 ? (got / 8) * 8 : got;
 }
 }  // namespace
+
+void set_measure_buffers(const MeasureBuffers* b) { t_meas = b ? *b : MeasureBuffers{nullptr, nullptr, nullptr}; }
 
 int job_kind(int variant, int lanes, int fp32) {
     int t = 0;

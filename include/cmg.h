@@ -133,6 +133,11 @@ typedef struct {
                                     when the sequence is fixed: a fixed schedule, or no level
                                     refined one launch per step); per-level device times
                                     (pi_ms) are then not measured.  0 (default): launches. */
+    int32_t coarsen;             /* 0 (default): heavy edge coarsening (Algorithm 2).  1: heavy
+                                    edge matching, the coarsening Section 2.1 contrasts HEC with
+                                    (each unmatched vertex, in the same visit order, is matched to
+                                    its heaviest unmatched neighbour or stays alone; aggregates of
+                                    one or two vertices, so n_{j+1} >= n_j / 2), for comparison. */
 } cmg_options;
 
 /* Per-level information (available after cmg_setup; PI fields after

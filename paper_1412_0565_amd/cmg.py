@@ -59,6 +59,7 @@ class cmg_options(C.Structure):
         ("fixed_k0", C.c_int32),
         ("fixed_beta", C.c_double),
         ("graph", C.c_int32),
+        ("coarsen", C.c_int32),
     ]
 
 

@@ -319,6 +319,7 @@ struct SetupTmp {
     double* bmax = nullptr;              // per-block maxima of the row pass
     unsigned long long* ri = nullptr;    // row information of level j at ri[4j .. 4j+3]
     double* gpart = nullptr;             // Galerkin pieces of runs that cross workgroups
+    unsigned* alive = nullptr;           // HEM: one flag per round
     void* block = nullptr;               // the one allocation all of the above point into
     std::vector<int> ri_pending;         // levels whose row information is still on the device
 };
@@ -363,6 +364,7 @@ void carve_tmp(Carver& cv, SetupTmp& t, int32_t n, int64_t nnz) {
     t.bmax = cv.take<double>(4 * kRowinfoMaxBlocks);
     t.ri = cv.take<unsigned long long>(4 * kMaxLevels);
     t.gpart = cv.take<double>(gal_part_elems(nnz));
+    t.alive = cv.take<unsigned>(kHemMaxRounds);
 }
 
 cmg_status alloc_tmp(cmg_ctx* c, SetupTmp& t, int32_t n, int64_t nnz) {
@@ -423,30 +425,55 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
     *stop = false;
     cmg_status st = level_rowinfo(c, t, j);
     if (st != CMG_OK) return st;
-    CK(launch_hec_init(L.n, t.h, seed, j, t.live, t.state, t.pairseed, t.slot, s));
-    // greedy rounds in batches between host checks; a round after the last
-    // live candidate edge changes nothing
-    for (int batch = 4, total = 0;; batch = 2) {
-        for (int r = 0; r < batch; ++r) {
-            CK(launch_hec_round(L.n, t.h, seed, j, t.live, t.state, t.pairseed, t.slot, t.scal + 2, s));
+    const bool hem = c->opt.coarsen == 1;
+    if (hem) {
+        // heavy edge matching: rounds in batches between host checks; the
+        // flag of a batch's last round tells whether any vertex was still
+        // unmatched when it began (a round with none changes nothing)
+        CK(launch_fill_u32((unsigned*)t.pairseed, 0xFFFFFFFFu, L.n, s));
+        CK(launch_fill_u32(t.alive, 0u, kHemMaxRounds, s));
+        int round = 0;
+        for (int batch = 4;; batch = 4) {
+            if (round + batch > kHemMaxRounds) return CMG_E_DEVICE;
+            for (int r = 0; r < batch; ++r, ++round)
+                CK(launch_hem_round(L.n, L.rp, L.col, L.w64, seed, j, t.pairseed, t.live, t.slot, t.alive, round,
+                                    s));
+            c->hec_rounds += batch;
+            unsigned last = 0;
+            st = d2h(c, &last, t.alive + round - 1, 1);
+            if (st != CMG_OK) return st;
+            if (last == 0) break;
         }
-        total += batch;
-        c->hec_rounds += batch;
-        unsigned long long live = 0;
-        st = d2h(c, &live, t.scal + 2, 1);
-        if (st != CMG_OK) return st;
-        if (live == 0) break;
-        if (total > 100000) return CMG_E_DEVICE;
+        CK(launch_hem_flags(L.n, t.pairseed, t.flags, s));
+        CK(launch_scan(t.flags, t.rank, L.n, t.scan_tmp, t.totals, s));  // totals[0]: aggregates
+        ALLOC(L.agg, int32_t, L.n);
+        CK(launch_hec_label(L.n, t.pairseed, t.rank, L.agg, s));
+    } else {
+        CK(launch_hec_init(L.n, t.h, seed, j, t.live, t.state, t.pairseed, t.slot, s));
+        // greedy rounds in batches between host checks; a round after the last
+        // live candidate edge changes nothing
+        for (int batch = 4, total = 0;; batch = 2) {
+            for (int r = 0; r < batch; ++r) {
+                CK(launch_hec_round(L.n, t.h, seed, j, t.live, t.state, t.pairseed, t.slot, t.scal + 2, s));
+            }
+            total += batch;
+            c->hec_rounds += batch;
+            unsigned long long live = 0;
+            st = d2h(c, &live, t.scal + 2, 1);
+            if (st != CMG_OK) return st;
+            if (live == 0) break;
+            if (total > 100000) return CMG_E_DEVICE;
+        }
+        CK(launch_hec_attach(L.n, t.h, t.state, t.pairseed, t.rootseed, t.flags, s));
+        CK(launch_scan(t.flags, t.rank, L.n, t.scan_tmp, t.totals, s));  // totals[0]: aggregates
+        ALLOC(L.agg, int32_t, L.n);
+        CK(launch_hec_label(L.n, t.rootseed, t.rank, L.agg, s));
     }
-    CK(launch_hec_attach(L.n, t.h, t.state, t.pairseed, t.rootseed, t.flags, s));
-    CK(launch_scan(t.flags, t.rank, L.n, t.scan_tmp, t.totals, s));  // totals[0]: aggregates
-    ALLOC(L.agg, int32_t, L.n);
-    CK(launch_hec_label(L.n, t.rootseed, t.rank, L.agg, s));
     // Galerkin product with the aggregate count left on the device: keys
-    // a * mult + b with mult = n/2 + 1 >= the count (aggregates have two
-    // vertices or more), sorted on enough bits that the sentinel's low
-    // bits exceed every key
-    const int64_t mult = (int64_t)L.n / 2 + 1;
+    // a * mult + b with mult >= the count (HEC aggregates have two vertices
+    // or more: n/2 + 1; HEM's one or two: n), sorted on enough bits that
+    // the sentinel's low bits exceed every key
+    const int64_t mult = hem ? (int64_t)L.n : (int64_t)L.n / 2 + 1;
     const int bits = bitlen((unsigned long long)mult * (unsigned long long)mult);
     // packed words (key << pbits | fine position) when they fit 64 bits:
     // the sort then moves 8 bytes per entry instead of 16
@@ -1130,8 +1157,9 @@ cmg_status setup_impl(cmg_ctx* c, int32_t n, int64_t nnz, const int32_t* row_ptr
     if (st != CMG_OK) return st;
     int j = 0;
     bool grid_only = false;  // a level the single-workgroup chain handed back
-    while (c->lv[j].n > c->opt.coarsest_n && j < 60) {
-        if (!grid_only && chain_level(c->lv[j])) {
+    while (c->lv[j].n > c->opt.coarsest_n && j < 63) {
+        // the single-workgroup chain implements HEC only
+        if (!grid_only && c->opt.coarsen == 0 && chain_level(c->lv[j])) {
             int next = -1;
             st = coarsen_chain(c, t, j, &next);
             if (st != CMG_OK) return st;
@@ -1187,6 +1215,7 @@ void fill_defaults(cmg_options* o) {
     o->fixed_k0 = 0;
     o->fixed_beta = 2.0;
     o->graph = 0;
+    o->coarsen = 0;
 }
 
 // Device results of the last solve -> host staging (asynchronous).
@@ -1676,7 +1705,8 @@ cmg_status cmg_setup(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
         o.max_iters_per_level < 1 || (o.precision != CMG_FP64 && o.precision != CMG_MIXED) ||
         o.fp64_final_sweeps < 0 || o.fp64_final_sweeps > 1 || o.coarsest_n > o.dense_max ||
         o.step_mode < -1 || o.step_mode > 1 || o.fixed_k0 < 0 ||
-        (o.fixed_k0 > 0 && !(o.fixed_beta >= 1.0 && std::isfinite(o.fixed_beta))) || o.graph < 0 || o.graph > 1)
+        (o.fixed_k0 > 0 && !(o.fixed_beta >= 1.0 && std::isfinite(o.fixed_beta))) || o.graph < 0 || o.graph > 1 ||
+        o.coarsen < 0 || o.coarsen > 1)
         return CMG_E_ARG;
     const double t0 = now_ms();
     cmg_ctx* c = new (std::nothrow) cmg_ctx;
@@ -1791,7 +1821,8 @@ cmg_status cmg_fiedler_noalloc(int32_t n, int64_t nnz, const int32_t* row_ptr, c
     if (!(o.tol < 1.0) || !std::isfinite(o.tol) || o.coarsest_n < 2 || o.dense_max < 2 || o.dense_max > 128 ||
         o.max_iters_per_level < 1 || (o.precision != CMG_FP64 && o.precision != CMG_MIXED) ||
         o.fp64_final_sweeps < 0 || o.fp64_final_sweeps > 1 || o.coarsest_n > o.dense_max || o.fixed_k0 < 0 ||
-        (o.fixed_k0 > 0 && !(o.fixed_beta >= 1.0 && std::isfinite(o.fixed_beta))))
+        (o.fixed_k0 > 0 && !(o.fixed_beta >= 1.0 && std::isfinite(o.fixed_beta))) || o.coarsen < 0 ||
+        o.coarsen > 1)
         return CMG_E_ARG;
     const size_t need = noalloc_need(n, nnz);
     if (need > kNoallocScratchBytes - kNoallocMeasureBytes) {

@@ -89,6 +89,15 @@ hipError_t launch_hec_attach(int n, const int32_t* h, const uint8_t* state, cons
                              int32_t* rootseed, int32_t* flags, hipStream_t s);
 hipError_t launch_hec_label(int n, const int32_t* rootseed, const int32_t* rank, int32_t* agg,
                             hipStream_t s);
+// One round of heavy edge matching (two passes; opener[v] = -1 while v is
+// unmatched, else the vertex that opened its aggregate); alive[round] is
+// raised if any vertex was unmatched when the round began.
+hipError_t launch_hem_round(int n, const int32_t* rp, const int32_t* col, const double* w, uint64_t seed, int level,
+                            int32_t* opener, uint8_t* live, unsigned long long* mkey, unsigned* alive, int round,
+                            hipStream_t s);
+// flags[v] = 1 where v opened its aggregate
+hipError_t launch_hem_flags(int n, const int32_t* opener, int32_t* flags, hipStream_t s);
+constexpr int kHemMaxRounds = 4096;
 // exclusive scan of int32 -> int32; *total (device int64) gets the sum.
 // tmp must hold scan_tmp_elems(m) int64 values.
 int64_t scan_tmp_elems(int64_t m);

@@ -285,6 +285,84 @@ __global__ void k_hec_label(int n, const int32_t* __restrict__ rootseed,
     agg[v] = rank[rootseed[v]];
 }
 
+// ------------------------------------------------------------------- HEM
+//
+// Heavy edge matching (Section 2.1, the coarsening HEC is contrasted with):
+// in visit order, an unmatched vertex is matched to its heaviest unmatched
+// neighbour (lowest index on ties) or stays alone.  When a vertex's turn
+// comes all its earlier neighbours are matched already, so the sequential
+// result is the greedy matching over edges ordered by (key of the endpoint
+// visited first, decreasing weight, other endpoint), and rounds reproduce
+// it exactly: a live vertex whose live neighbours all come later in key
+// order proposes to its heaviest live neighbour, and the proposal holds if
+// the proposer is that neighbour's earliest live neighbour; a live vertex
+// with no live neighbour stays alone.  Each round reads the state its first
+// pass recorded, so no decision depends on the order threads run in.
+// opener[v] = -1 while v is live, else the vertex that opened its aggregate.
+
+// pass 1: the round's live flags, and the smallest key among each live
+// vertex's live neighbours (kNoKey if none); raises alive[round] if any
+// vertex is live at the start of the round
+__global__ void k_hem_scan(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col, uint64_t seed,
+                           int level, const int32_t* __restrict__ opener, uint8_t* __restrict__ live,
+                           unsigned long long* __restrict__ mkey, unsigned* __restrict__ alive, int round) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    int lv = 0;
+    if (v < n) {
+        lv = opener[v] < 0 ? 1 : 0;
+        live[v] = (uint8_t)lv;
+        if (lv) {
+            unsigned long long m = kNoKey;
+            for (int e = rp[v]; e < rp[v + 1]; ++e) {
+                const int u = col[e];
+                if (opener[u] < 0) {
+                    const unsigned long long k = hec_key(seed, level, u);
+                    m = k < m ? k : m;
+                }
+            }
+            mkey[v] = m;
+        }
+    }
+    if (__syncthreads_or(lv) && threadIdx.x == 0) alive[round] = 1u;
+}
+
+// pass 2: proposals of the vertices whose live neighbours all come later
+__global__ void k_hem_match(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            const double* __restrict__ w, uint64_t seed, int level,
+                            const uint8_t* __restrict__ live, const unsigned long long* __restrict__ mkey,
+                            int32_t* __restrict__ opener) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n || !live[v]) return;
+    const unsigned long long mk = mkey[v];
+    if (mk == kNoKey) {  // no live neighbour left: a single-vertex aggregate
+        opener[v] = v;
+        return;
+    }
+    const unsigned long long kv = hec_key(seed, level, v);
+    if (kv > mk) return;  // an earlier live neighbour decides first
+    int best = -1;
+    double bw = 0.0;
+    for (int e = rp[v]; e < rp[v + 1]; ++e) {
+        const int u = col[e];
+        if (!live[u]) continue;
+        const double x = w[e];
+        if (best < 0 || x > bw || (x == bw && u < best)) {
+            best = u;
+            bw = x;
+        }
+    }
+    if (mkey[best] == kv) {  // v is best's earliest live neighbour: no other proposal reaches best
+        opener[v] = v;
+        opener[best] = v;
+    }
+}
+
+// opening vertices flagged for the numbering scan
+__global__ void k_hem_flags(int n, const int32_t* __restrict__ opener, int32_t* __restrict__ flags) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) flags[v] = opener[v] == v ? 1 : 0;
+}
+
 // ------------------------------------------------------------------ scan
 
 constexpr int kScanItems = 8;
@@ -766,6 +844,21 @@ hipError_t launch_hec_attach(int n, const int32_t* h, const uint8_t* state, cons
 hipError_t launch_hec_label(int n, const int32_t* rootseed, const int32_t* rank, int32_t* agg,
                             hipStream_t s) {
     hipLaunchKernelGGL(k_hec_label, dim3(nblocks(n, kBlk)), dim3(kBlk), 0, s, n, rootseed, rank, agg);
+    return hipGetLastError();
+}
+
+hipError_t launch_hem_round(int n, const int32_t* rp, const int32_t* col, const double* w, uint64_t seed, int level,
+                            int32_t* opener, uint8_t* live, unsigned long long* mkey, unsigned* alive, int round,
+                            hipStream_t s) {
+    const unsigned nb = nblocks(n, kBlk);
+    hipLaunchKernelGGL(k_hem_scan, dim3(nb), dim3(kBlk), 0, s, n, rp, col, seed, level, opener, live, mkey, alive,
+                       round);
+    hipLaunchKernelGGL(k_hem_match, dim3(nb), dim3(kBlk), 0, s, n, rp, col, w, seed, level, live, mkey, opener);
+    return hipGetLastError();
+}
+
+hipError_t launch_hem_flags(int n, const int32_t* opener, int32_t* flags, hipStream_t s) {
+    hipLaunchKernelGGL(k_hem_flags, dim3(nblocks(n, kBlk)), dim3(kBlk), 0, s, n, opener, flags);
     return hipGetLastError();
 }
 

@@ -38,6 +38,8 @@ def oracle_of(g, **opts):
                          ("fixed_beta", "fixed_beta")]:
         if k_src in opts:
             kw[k_dst] = opts[k_src]
+    if opts.get("coarsen", 0) == 1:
+        kw["coarsen"] = "hem"
     return O.cmg(g, **kw)
 
 

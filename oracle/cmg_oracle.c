@@ -30,6 +30,7 @@
 #define ORC_E_ISOLATED 3
 #define ORC_E_OOM 4
 #define ORC_W_MAXIT 6
+#define ORC_MAXP 8
 
 /* ------------------------------------------------------------------ hash */
 
@@ -729,15 +730,16 @@ orc_result* orc_cmg(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* co
  *      test; the coarsest level, when it is refined by power iteration
  *      (after a collapse), follows the same schedule.
  *  coarsen = 1: heavy edge matching (orc_hem) instead of HEC in Step 1. */
-orc_result* orc_cmg_ex(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
-                       const double* w, double tol, int32_t coarsest_n, int32_t dense_max,
-                       uint64_t seed, int32_t max_iters, int32_t fixed_k0, double fixed_beta,
-                       int32_t coarsen)
+/* Step 1 of Algorithm 1 into r->lv (level 0 borrows the caller's arrays):
+ * while n_j > coarsest_n, coarsen (HEC, or HEM with coarsen = 1) and form
+ * the Galerkin coarse graph; a coarsening to fewer than 2 aggregates is
+ * discarded and ends the loop.  Leaves r->status set. */
+static void orc_build_hierarchy(orc_result* r, int32_t n, int64_t nnz, const int32_t* rp,
+                                const int32_t* col, const double* w, int32_t coarsest_n,
+                                uint64_t seed, int32_t coarsen)
 {
-    orc_result* r = (orc_result*)calloc(1, sizeof(orc_result));
-    if (!r) return NULL;
     r->status = orc_validate(n, nnz, rp, col, w);
-    if (r->status != ORC_OK) return r;
+    if (r->status != ORC_OK) return;
     r->lv[0].n = n;
     r->lv[0].nnz = nnz;
     r->lv[0].rp = (int32_t*)rp;
@@ -749,24 +751,36 @@ orc_result* orc_cmg_ex(int32_t n, int64_t nnz, const int32_t* rp, const int32_t*
         orc_level* L = &r->lv[j];
         int32_t* agg = (int32_t*)malloc(sizeof(int32_t) * (size_t)L->n);
         uint8_t* sd = (uint8_t*)malloc((size_t)L->n);
-        if (!agg || !sd) { free(agg); free(sd); r->status = ORC_E_OOM; return r; }
+        if (!agg || !sd) { free(agg); free(sd); r->status = ORC_E_OOM; return; }
         int32_t nc = coarsen == 1 ? orc_hem(L->n, L->rp, L->col, L->w, seed, j, agg, sd)
                                   : orc_hec(L->n, L->rp, L->col, L->w, seed, j, agg, sd);
         free(sd);
-        if (nc < 0) { free(agg); r->status = ORC_E_ISOLATED; return r; }
+        if (nc < 0) { free(agg); r->status = ORC_E_ISOLATED; return; }
         if (nc < 2) { free(agg); r->collapsed = 1; break; }
         orc_level* C = &r->lv[j + 1];
         int64_t cnz = orc_galerkin(L->n, L->rp, L->col, L->w, agg, nc, &C->rp, &C->col, &C->w);
-        if (cnz < 0) { free(agg); r->status = ORC_E_OOM; return r; }
+        if (cnz < 0) { free(agg); r->status = ORC_E_OOM; return; }
         L->agg = agg;
         C->n = nc;
         C->nnz = cnz;
         r->nlevels = j + 2;
         ++j;
     }
+    for (int32_t t = 0; t < r->nlevels; ++t)
+        r->lv[t].g = orc_gershgorin(r->lv[t].n, r->lv[t].rp, r->lv[t].w);
+}
+
+orc_result* orc_cmg_ex(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
+                       const double* w, double tol, int32_t coarsest_n, int32_t dense_max,
+                       uint64_t seed, int32_t max_iters, int32_t fixed_k0, double fixed_beta,
+                       int32_t coarsen)
+{
+    orc_result* r = (orc_result*)calloc(1, sizeof(orc_result));
+    if (!r) return NULL;
+    orc_build_hierarchy(r, n, nnz, rp, col, w, coarsest_n, seed, coarsen);
+    if (r->status != ORC_OK) return r;
     int32_t J = r->nlevels - 1;
     for (int32_t t = 0; t <= J; ++t) {
-        r->lv[t].g = orc_gershgorin(r->lv[t].n, r->lv[t].rp, r->lv[t].w);
         r->lv[t].k = 0;
         r->lv[t].margin = 0.0;
     }
@@ -813,6 +827,224 @@ orc_result* orc_cmg_ex(int32_t n, int64_t nnz, const int32_t* rp, const int32_t*
     r->y = ycur;
     orc_rq_residual(n, rp, col, w, ycur, &r->lambda, &r->residual);
     return r;
+}
+
+/* ------------------------------------------- several eigenpairs (block) */
+
+/* Start vector c of the block variant: U(seed ^ (c + 1) * 0xD1B54A32D192ED03, i) - 1/2
+ * (hashed uniforms of a stream of their own per column). */
+static double orc_block_start(uint64_t seed, int32_t c, int32_t i)
+{
+    return orc_uniform(seed ^ ((uint64_t)(c + 1) * 0xD1B54A32D192ED03ull), i) - 0.5;
+}
+
+/* Orthonormalise the p columns of V (n x p, column c at V + c n) in column
+ * order: remove the column's mean (deflation against the constant vector),
+ * then its components along the earlier columns (modified Gram-Schmidt),
+ * then normalise. */
+static void orc_orthonormalise(int32_t n, int32_t p, double* V)
+{
+    for (int32_t c = 0; c < p; ++c) {
+        double* v = V + (size_t)c * n;
+        double mean = 0.0;
+        for (int32_t i = 0; i < n; ++i) mean += v[i];
+        mean /= (double)n;
+        for (int32_t i = 0; i < n; ++i) v[i] -= mean;
+        for (int32_t d = 0; d < c; ++d) {
+            const double* u = V + (size_t)d * n;
+            double dot = orc_dot(n, u, v);
+            for (int32_t i = 0; i < n; ++i) v[i] -= dot * u[i];
+        }
+        double nr = sqrt(orc_dot(n, v, v));
+        for (int32_t i = 0; i < n; ++i) v[i] /= nr;
+    }
+}
+
+/* Several approximate eigenpairs at the coarsest level (Remark after
+ * Algorithm 4: start from p approximate eigenpairs of the coarsest level).
+ * READING: dense L^J and Jacobi as in orc_coarsest_dense; E = the
+ * eigenvectors above the smallest eigenvalue whose eigenvalue is at most
+ * lambda_{p+1} + 1e-10 ||L||_F (whole clusters, so E does not depend on the
+ * eigensolver's basis); the p start vectors orc_block_start are projected
+ * onto E and orthonormalised in column order.  V: n x p; lams[c] receives
+ * the (c+2)-th smallest eigenvalue.  Needs p <= n - 1. */
+int orc_coarsest_block(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                       uint64_t seed, int32_t p, double* V, double* lams)
+{
+    if (p < 1 || p > n - 1) return ORC_E_ARG;
+    double* A = (double*)calloc((size_t)n * n, sizeof(double));
+    double* Q = (double*)malloc(sizeof(double) * (size_t)n * n);
+    double* ev = (double*)malloc(sizeof(double) * (size_t)n);
+    int32_t* idx = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!A || !Q || !ev || !idx) {
+        free(A); free(Q); free(ev); free(idx);
+        return ORC_E_OOM;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            A[(int64_t)i * n + col[e]] = -w[e];
+            d += w[e];
+        }
+        A[(int64_t)i * n + i] = d;
+    }
+    double fro = 0.0;
+    for (int64_t t = 0; t < (int64_t)n * n; ++t) fro += A[t] * A[t];
+    fro = sqrt(fro);
+    orc_jacobi(n, A, Q, ev);
+    for (int32_t i = 0; i < n; ++i) idx[i] = i;
+    for (int32_t i = 1; i < n; ++i) {
+        int32_t t = idx[i];
+        int32_t k = i - 1;
+        while (k >= 0 && ev[idx[k]] > ev[t]) { idx[k + 1] = idx[k]; --k; }
+        idx[k + 1] = t;
+    }
+    const double top = ev[idx[p]];
+    for (int32_t c = 0; c < p; ++c) {
+        double* v = V + (size_t)c * n;
+        for (int32_t i = 0; i < n; ++i) v[i] = 0.0;
+        for (int32_t r = 1; r < n; ++r) {
+            int32_t k = idx[r];
+            if (ev[k] > top + 1e-10 * fro) continue;
+            double dot = 0.0;
+            for (int32_t i = 0; i < n; ++i) dot += Q[(int64_t)i * n + k] * orc_block_start(seed, c, i);
+            for (int32_t i = 0; i < n; ++i) v[i] += dot * Q[(int64_t)i * n + k];
+        }
+        lams[c] = ev[idx[c + 1]];
+    }
+    orc_orthonormalise(n, p, V);
+    free(A); free(Q); free(ev); free(idx);
+    return ORC_OK;
+}
+
+/* Block power iteration on one level (Remark after Algorithm 4: smooth
+ * each approximate eigenfunction, orthogonalise them, take Rayleigh
+ * quotients).  READING: each step applies B_g = gI - L to every column and
+ * orthonormalises the result (orc_orthonormalise), i.e. orthogonal
+ * iteration; Algorithm 3's stopping test is applied to every column (stop
+ * once (u_c, v_c) >= 1 - tol for all c, the first step always runs), or,
+ * with steps > 0, exactly `steps` steps run (Algorithm 4's schedule).
+ * V0, V: n x p.  Returns the number of steps; *minutv the smallest
+ * (u_c, v_c) of the last step. */
+int32_t orc_block_pi(int32_t n, const int32_t* rp, const int32_t* col, const double* w, double g,
+                     int32_t p, const double* V0, double tol, int32_t maxit, int32_t steps,
+                     double* V, double* minutv)
+{
+    const size_t np = (size_t)n * (size_t)p;
+    double* Vold = (double*)calloc(np, sizeof(double));
+    double* t = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!Vold || !t) { free(Vold); free(t); return -1; }
+    memcpy(V, V0, sizeof(double) * np);
+    orc_orthonormalise(n, p, V);
+    int32_t k = 0;
+    double mu = 0.0;  /* min_c (u_c, v_c); 0 before the first step */
+    while (steps > 0 ? k < steps : (mu < 1.0 - tol && k < maxit)) {
+        memcpy(Vold, V, sizeof(double) * np);
+        for (int32_t c = 0; c < p; ++c) {
+            const double* v = Vold + (size_t)c * n;
+            double* u = V + (size_t)c * n;
+            orc_laplacian_apply(n, rp, col, w, v, t);
+            for (int32_t i = 0; i < n; ++i) u[i] = g * v[i] - t[i];
+        }
+        orc_orthonormalise(n, p, V);
+        ++k;
+        mu = 2.0;
+        for (int32_t c = 0; c < p; ++c) {
+            double d = orc_dot(n, V + (size_t)c * n, Vold + (size_t)c * n);
+            if (d < mu) mu = d;
+        }
+    }
+    *minutv = mu;
+    free(Vold); free(t);
+    return k;
+}
+
+typedef struct {
+    int32_t status;
+    int32_t nlevels;
+    int32_t p;
+    int32_t k[64];
+    double lambdas[ORC_MAXP];    /* Rayleigh quotients of the output columns */
+    double residuals[ORC_MAXP];  /* ||L x_c - lambda_c x_c|| */
+    double coarse[ORC_MAXP];     /* lambda_2 .. lambda_{p+1} of the coarsest level */
+    double* X;                   /* n0 x p, column-major */
+} orc_block_result;
+
+/* Several eigenpairs (Remark after Algorithm 4) on the hierarchy of
+ * Algorithm 1, Step 1: the coarsest block (orc_coarsest_block; the
+ * coarsest level must be dense, n_J <= dense_max, with p < n_J), then for
+ * j = J-1 .. 0 the columns are prolongated (x_v = x[agg_j(v)]) and refined
+ * by orc_block_pi, with the fixed schedule when fixed_k0 > 0.  The output
+ * columns are orthonormalised once more; lambdas are edge-form Rayleigh
+ * quotients and residuals ||L x - lambda x|| per column. */
+orc_block_result* orc_cmg_block(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
+                                const double* w, double tol, int32_t coarsest_n, int32_t dense_max,
+                                uint64_t seed, int32_t max_iters, int32_t fixed_k0,
+                                double fixed_beta, int32_t p)
+{
+    orc_block_result* out = (orc_block_result*)calloc(1, sizeof(orc_block_result));
+    orc_result* r = (orc_result*)calloc(1, sizeof(orc_result));
+    if (!out || !r) { free(out); free(r); return NULL; }
+    out->p = p;
+    if (p < 1 || p > ORC_MAXP) { out->status = ORC_E_ARG; free(r); return out; }
+    orc_build_hierarchy(r, n, nnz, rp, col, w, coarsest_n, seed, 0);
+    out->status = r->status;
+    out->nlevels = r->nlevels;
+    int32_t J = r->nlevels - 1;
+    if (out->status == ORC_OK && (r->lv[J].n > dense_max || p > r->lv[J].n - 1)) out->status = ORC_E_ARG;
+    double* cur = NULL;
+    if (out->status == ORC_OK) {
+        cur = (double*)malloc(sizeof(double) * (size_t)r->lv[J].n * p);
+        if (!cur || orc_coarsest_block(r->lv[J].n, r->lv[J].rp, r->lv[J].col, r->lv[J].w, seed, p, cur,
+                                       out->coarse) != ORC_OK)
+            out->status = ORC_E_OOM;
+        out->k[J] = -1;
+    }
+    for (int32_t t = J - 1; t >= 0 && out->status == ORC_OK; --t) {
+        orc_level* F = &r->lv[t];
+        const int32_t nc = r->lv[t + 1].n;
+        double* start = (double*)malloc(sizeof(double) * (size_t)F->n * p);
+        double* next = (double*)malloc(sizeof(double) * (size_t)F->n * p);
+        if (!start || !next) { free(start); free(next); out->status = ORC_E_OOM; break; }
+        for (int32_t c = 0; c < p; ++c)
+            for (int32_t v = 0; v < F->n; ++v)
+                start[(size_t)c * F->n + v] = cur[(size_t)c * nc + F->agg[v]];
+        const int32_t steps = fixed_k0 > 0 ? orc_fixed_steps(fixed_k0, fixed_beta, t, max_iters) : 0;
+        double mu;
+        out->k[t] = orc_block_pi(F->n, F->rp, F->col, F->w, F->g, p, start, tol, max_iters, steps, next, &mu);
+        if (fixed_k0 == 0 && out->k[t] >= max_iters) out->status = ORC_W_MAXIT;
+        free(start);
+        free(cur);
+        cur = next;
+    }
+    if (cur && (out->status == ORC_OK || out->status == ORC_W_MAXIT)) {
+        orc_orthonormalise(n, p, cur);
+        for (int32_t c = 0; c < p; ++c)
+            orc_rq_residual(n, rp, col, w, cur + (size_t)c * n, &out->lambdas[c], &out->residuals[c]);
+        out->X = cur;
+        cur = NULL;
+    }
+    free(cur);
+    orc_free(r);
+    return out;
+}
+
+void orc_block_free(orc_block_result* b)
+{
+    if (!b) return;
+    free(b->X);
+    free(b);
+}
+
+int32_t orc_block_status(const orc_block_result* b) { return b->status; }
+int32_t orc_block_nlevels(const orc_block_result* b) { return b->nlevels; }
+int32_t orc_block_k(const orc_block_result* b, int32_t j) { return b->k[j]; }
+double orc_block_lambda(const orc_block_result* b, int32_t c) { return b->lambdas[c]; }
+double orc_block_residual(const orc_block_result* b, int32_t c) { return b->residuals[c]; }
+double orc_block_coarse(const orc_block_result* b, int32_t c) { return b->coarse[c]; }
+void orc_block_copy_x(const orc_block_result* b, int32_t n, double* X)
+{
+    if (b->X) memcpy(X, b->X, sizeof(double) * (size_t)n * b->p);
 }
 
 /* ----------------------------------------------------- result accessors */

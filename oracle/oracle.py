@@ -88,6 +88,23 @@ def lib():
         L.orc_cmg_ex.restype = C.c_void_p
         L.orc_cmg_ex.argtypes = [C.c_int32, C.c_int64, _i32p, _i32p, _f64p, C.c_double, C.c_int32,
                                  C.c_int32, C.c_uint64, C.c_int32, C.c_int32, C.c_double, C.c_int32]
+        L.orc_cmg_block.restype = C.c_void_p
+        L.orc_cmg_block.argtypes = [C.c_int32, C.c_int64, _i32p, _i32p, _f64p, C.c_double, C.c_int32,
+                                    C.c_int32, C.c_uint64, C.c_int32, C.c_int32, C.c_double, C.c_int32]
+        L.orc_block_free.argtypes = [C.c_void_p]
+        for nm, rt in [("orc_block_status", C.c_int32), ("orc_block_nlevels", C.c_int32)]:
+            getattr(L, nm).restype = rt
+            getattr(L, nm).argtypes = [C.c_void_p]
+        for nm, rt in [("orc_block_k", C.c_int32), ("orc_block_lambda", C.c_double),
+                       ("orc_block_residual", C.c_double), ("orc_block_coarse", C.c_double)]:
+            getattr(L, nm).restype = rt
+            getattr(L, nm).argtypes = [C.c_void_p, C.c_int32]
+        L.orc_block_copy_x.argtypes = [C.c_void_p, C.c_int32, _f64p]
+        L.orc_coarsest_block.restype = C.c_int
+        L.orc_coarsest_block.argtypes = [C.c_int32, _i32p, _i32p, _f64p, C.c_uint64, C.c_int32, _f64p, _f64p]
+        L.orc_block_pi.restype = C.c_int32
+        L.orc_block_pi.argtypes = [C.c_int32, _i32p, _i32p, _f64p, C.c_double, C.c_int32, _f64p, C.c_double,
+                                   C.c_int32, C.c_int32, _f64p, C.POINTER(C.c_double)]
         L.orc_cmg.restype = C.c_void_p
         L.orc_cmg.argtypes = [C.c_int32, C.c_int64, _i32p, _i32p, _f64p, C.c_double, C.c_int32,
                               C.c_int32, C.c_uint64, C.c_int32]
@@ -356,3 +373,60 @@ def cmg(g, tol: float = 1e-8, coarsest_n: int = 25, dense_max: int = 128, seed: 
                       L.orc_res_coarse_lambda2(r), L.orc_res_coarse_mult(r), bool(L.orc_res_collapsed(r)))
     finally:
         L.orc_free(r)
+
+
+@dataclasses.dataclass
+class BlockResult:
+    status: str
+    k: list
+    lams: np.ndarray
+    residuals: np.ndarray
+    coarse: np.ndarray
+    X: np.ndarray  # n x p
+
+
+def coarsest_block(g, p: int, seed: int = 14120565):
+    rp, col, w = _csr_args(g)
+    V = np.zeros(g.n * p)
+    lams = np.zeros(p)
+    st = lib().orc_coarsest_block(g.n, rp, col, w, seed, p, V, lams)
+    if st != 0:
+        raise ValueError(STATUS[st])
+    return V.reshape(p, g.n).T.copy(), lams
+
+
+def block_pi(g, V0, tol: float = 1e-8, maxit: int = 100000, steps: int = 0, gval: float | None = None):
+    rp, col, w = _csr_args(g)
+    if gval is None:
+        gval = gershgorin(g)
+    p = V0.shape[1]
+    v0 = np.ascontiguousarray(V0.T, dtype=np.float64).reshape(-1)
+    V = np.zeros(g.n * p)
+    mu = C.c_double()
+    k = lib().orc_block_pi(g.n, rp, col, w, gval, p, v0, tol, maxit, steps, V, C.byref(mu))
+    return V.reshape(p, g.n).T.copy(), int(k), float(mu.value)
+
+
+def cmg_block(g, p: int, tol: float = 1e-8, coarsest_n: int = 25, dense_max: int = 128,
+              seed: int = 14120565, max_iters: int = 100000, fixed_k0: int = 0,
+              fixed_beta: float = 2.0) -> BlockResult:
+    """Several eigenpairs (Remark after Algorithm 4) on the oracle."""
+    L = lib()
+    rp, col, w = _csr_args(g)
+    r = L.orc_cmg_block(g.n, int(rp[-1]), rp, col, w, tol, coarsest_n, dense_max, seed, max_iters,
+                        int(fixed_k0), float(fixed_beta), int(p))
+    if not r:
+        raise MemoryError
+    try:
+        st = STATUS[L.orc_block_status(r)]
+        nl = L.orc_block_nlevels(r)
+        X = np.zeros(g.n * p)
+        if st in ("OK", "W_MAXIT"):
+            L.orc_block_copy_x(r, g.n, X)
+        return BlockResult(st, [L.orc_block_k(r, j) for j in range(nl)],
+                           np.array([L.orc_block_lambda(r, c) for c in range(p)]),
+                           np.array([L.orc_block_residual(r, c) for c in range(p)]),
+                           np.array([L.orc_block_coarse(r, c) for c in range(p)]),
+                           X.reshape(p, g.n).T.copy())
+    finally:
+        L.orc_block_free(r)

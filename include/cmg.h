@@ -221,6 +221,28 @@ cmg_status cmg_fiedler(cmg_handle h, double* lambda, void* x, cmg_memspace where
 cmg_status cmg_fiedler_batch(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
                              cmg_memspace where, cmg_stats* stats);
 
+/* Several eigenpairs at once (the Remark after Algorithm 4): the p
+ * eigenvectors of the coarsest level above the constant one (the dense
+ * solve's lowest eigenspaces, whole clusters, onto which p hashed-uniform
+ * starts are projected and orthonormalised) are prolongated level by level;
+ * on each level every vector is smoothed with B_g = gI - L and the block
+ * is orthonormalised after each step (orthogonal iteration), until every
+ * column passes Algorithm 3's test (or the fixed schedule's count, with
+ * fixed_k0 > 0).  The hierarchy is the handle's (cmg_setup).
+ *   p            1..4, and below the coarsest level's vertex count, which
+ *                must be solved densely (n_J <= dense_max); else CMG_E_ARG
+ *   lambdas[p]   edge-form Rayleigh quotients of the output columns (host)
+ *   X            n x p doubles, column-major (column c at X + c n), unit
+ *                columns orthogonal to each other and to the constant
+ *                vector, in memory space `where` (may be NULL)
+ *   residuals[p] ||L x_c - lambda_c x_c|| (host, may be NULL)
+ *   level_steps  steps per level, J + 1 entries (-1 on the coarsest; host,
+ *                may be NULL)
+ * FP64 throughout.  Returns CMG_OK, CMG_W_MAXIT (a level hit the cap), or
+ * CMG_E_DEVICE if the block lost rank. */
+cmg_status cmg_fiedler_block(cmg_handle h, int32_t p, double* lambdas, void* X, cmg_memspace where,
+                             double* residuals, int32_t* level_steps);
+
 /* Copy per-level information into out[0..cap-1]; *nlevels gets J+1. */
 cmg_status cmg_level_info(cmg_handle h, cmg_level_stats* out, int32_t cap, int32_t* nlevels);
 

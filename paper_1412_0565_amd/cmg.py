@@ -26,7 +26,7 @@ CMG_VAL_F64, CMG_VAL_F32 = 0, 1
 # functions declared in include/cmg.h
 EXPORTS = ["cmg_options_default", "cmg_setup", "cmg_fiedler", "cmg_fiedler_batch", "cmg_level_info",
            "cmg_level_copy", "cmg_set_stream", "cmg_footprint", "cmg_free", "cmg_status_string",
-           "cmg_last_error", "cmg_hash_probe", "cmg_fiedler_noalloc"]
+           "cmg_last_error", "cmg_hash_probe", "cmg_fiedler_noalloc", "cmg_fiedler_block"]
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 _FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
@@ -143,6 +143,9 @@ def lib():
                                           C.c_int, C.POINTER(cmg_options), C.POINTER(C.c_double), C.c_void_p,
                                           C.POINTER(cmg_stats)]
         L.cmg_fiedler_noalloc.restype = C.c_int
+        L.cmg_fiedler_block.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                        C.c_void_p]
+        L.cmg_fiedler_block.restype = C.c_int
         _lib = L
     return _lib
 
@@ -270,6 +273,22 @@ def cmg_fiedler_batch(hs, xs=None, stats=None):
     return list(lams), st
 
 
+def cmg_fiedler_block(h: int, p: int, X=None):
+    """Several eigenpairs on the handle's hierarchy.  X: float64 n x p
+    output, column-major (numpy array of shape (p, n), or a torch tensor
+    of p n entries), or None.  Returns (lambdas, residuals, level_steps,
+    status)."""
+    lams = np.zeros(p)
+    res = np.zeros(p)
+    nl = C.c_int32()
+    _check(lib().cmg_level_info(h, None, 0, C.byref(nl)), "cmg_level_info")
+    steps = np.zeros(nl.value, dtype=np.int32)
+    px, where = (None, CMG_MEM_HOST) if X is None else _ptr(X)
+    st = lib().cmg_fiedler_block(h, int(p), lams.ctypes.data, px, where, res.ctypes.data, steps.ctypes.data)
+    _check(st, "cmg_fiedler_block")
+    return lams, res, [int(k) for k in steps], st
+
+
 def cmg_level_info(h: int):
     nl = C.c_int32()
     _check(lib().cmg_level_info(h, None, 0, C.byref(nl)), "cmg_level_info")
@@ -350,6 +369,12 @@ class Fiedler:
             x = np.zeros(self.n)
         lam, status = cmg_fiedler(self.handle, x, st)
         return lam, x, st
+
+    def solve_block(self, p: int):
+        """p eigenpairs: (lambdas, X of shape (n, p), residuals, level_steps)."""
+        X = np.zeros((p, self.n))
+        lams, res, steps, _ = cmg_fiedler_block(self.handle, p, X)
+        return lams, X.T.copy(), res, steps
 
     def levels(self):
         return cmg_level_info(self.handle)

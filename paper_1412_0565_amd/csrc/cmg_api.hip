@@ -212,6 +212,13 @@ struct cmg_ctx {
     std::vector<hipEvent_t> chunk_ev;
     bool fixed = false;            // fixed smoothing schedule: every launch count known in advance
     bool noalloc = false;          // cmg_fiedler_noalloc: no events, no host-pinned or stream objects
+    // several eigenpairs (cmg_fiedler_block): buffers for blk_p columns
+    int blk_p = 0;
+    std::vector<BlkJob> blk_jobs;  // per level
+    BlkJob* d_blk_jobs = nullptr;
+    BlkCtl* d_blk_ctl = nullptr;
+    BlkOut* d_blk_out = nullptr;
+    double* d_blk_x = nullptr;
     hipGraphExec_t gexec = nullptr;  // captured refinement launches (cmg_options.graph)
 
     // Device memory of the handle (hierarchy, refinement state, job
@@ -1436,6 +1443,160 @@ cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where,
     return finalize(c, t0, !graph && !c->noalloc, lambda, stats);
 }
 
+// ---- several eigenpairs (Remark after Algorithm 4)
+
+cmg_status ensure_flags(cmg_ctx* c) {
+    if (c->h_flags) return CMG_OK;
+    CK(hipHostMalloc((void**)&c->h_flags, sizeof(int) * kChunkEvents, hipHostMallocDefault));
+    c->chunk_ev.resize(kChunkEvents);
+    for (auto& e : c->chunk_ev) CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return CMG_OK;
+}
+
+// Buffers and job table of the block refinement for p columns (once per p).
+cmg_status blk_plan(cmg_ctx* c, int p) {
+    if (c->blk_p == p) return CMG_OK;
+    const int J = (int)c->lv.size() - 1;
+    hipStream_t s = c->stream;
+    std::vector<BlkJob> jobs(J + 1);
+    int maxnb = 1;
+    ALLOC(c->d_blk_ctl, BlkCtl, J + 1);
+    ALLOC(c->d_blk_out, BlkOut, 1);
+    ALLOC(c->d_blk_x, double, (size_t)c->lv[0].n * p);
+    for (int j = 0; j <= J; ++j) {
+        const HostLevel& L = c->lv[j];
+        BlkJob b{};
+        b.n = L.n;
+        const int64_t nb = ((int64_t)L.n + L.nnz + kStepWork - 1) / kStepWork;
+        b.nb = (int)std::min<int64_t>(std::max<int64_t>(nb, 1), 65535);
+        maxnb = std::max(maxnb, b.nb);
+        b.rp = L.rp;
+        b.col = L.col;
+        b.w = L.w64;
+        b.g = L.g;
+        b.agg = L.agg;
+        ALLOC(b.W0, double, (size_t)L.n * p);
+        ALLOC(b.W1, double, (size_t)L.n * p);
+        b.ctl = c->d_blk_ctl + j;
+        int32_t* rpart = nullptr;
+        ALLOC(rpart, int32_t, b.nb + 1);
+        CK(launch_partition(L.n, L.nnz, L.rp, b.nb, rpart, s));
+        b.rpart = rpart;
+        b.out = c->d_blk_out;
+        b.tol = c->opt.tol;
+        b.seed = c->opt.seed;
+        b.maxit = c->opt.max_iters_per_level;
+        b.kfix = L.kfix;
+        jobs[j] = b;
+    }
+    double* part = nullptr;
+    ALLOC(part, double, (size_t)maxnb * blk_parts(p));
+    for (int j = 0; j <= J; ++j) {
+        jobs[j].part = part;
+        if (j < J) {
+            jobs[j].cW0 = jobs[j + 1].W0;
+            jobs[j].cW1 = jobs[j + 1].W1;
+            jobs[j].cctl = jobs[j + 1].ctl;
+        }
+    }
+    ALLOC(c->d_blk_jobs, BlkJob, J + 1);
+    CK(hipMemcpyAsync(c->d_blk_jobs, jobs.data(), sizeof(BlkJob) * (J + 1), hipMemcpyHostToDevice, s));
+    c->blk_jobs = jobs;
+    c->blk_p = p;
+    return CMG_OK;
+}
+
+// Steps of block level j: all at once on a fixed schedule, else in chunks
+// with one queued ahead while the host reads the done flag (as step mode).
+cmg_status blk_steps(cmg_ctx* c, int j, int p, hipStream_t s) {
+    const BlkJob& hj = c->blk_jobs[j];
+    const BlkJob* dj = c->d_blk_jobs + j;
+    if (hj.kfix > 0) {
+        for (int i = 0; i < hj.kfix; ++i) CK(launch_blk(kBlkStep, p, dj, hj, nullptr, nullptr, nullptr, nullptr, s));
+        return CMG_OK;
+    }
+    cmg_status st = ensure_flags(c);
+    if (st != CMG_OK) return st;
+    const int maxit = hj.maxit;
+    int launched = 0, chunks = 0;
+    auto enqueue = [&]() -> cmg_status {
+        const int q = std::min(kStepChunk, maxit - launched);
+        for (int i = 0; i < q; ++i) CK(launch_blk(kBlkStep, p, dj, hj, nullptr, nullptr, nullptr, nullptr, s));
+        launched += q;
+        CK(hipMemcpyAsync(c->h_flags + chunks % kChunkEvents, &hj.ctl->done, sizeof(int), hipMemcpyDeviceToHost,
+                          s));
+        CK(hipEventRecord(c->chunk_ev[chunks % kChunkEvents], s));
+        ++chunks;
+        return CMG_OK;
+    };
+    st = enqueue();
+    if (st != CMG_OK) return st;
+    if (launched < maxit) {
+        st = enqueue();
+        if (st != CMG_OK) return st;
+    }
+    for (int w = 0;; ++w) {
+        CK(hipEventSynchronize(c->chunk_ev[w % kChunkEvents]));
+        if (c->h_flags[w % kChunkEvents]) break;
+        if (w + 1 == chunks && launched >= maxit) break;
+        if (launched < maxit) {
+            st = enqueue();
+            if (st != CMG_OK) return st;
+        }
+    }
+    return CMG_OK;
+}
+
+cmg_status block_impl(cmg_ctx* c, int p, double* lambdas, void* X, cmg_memspace where, double* residuals,
+                      int32_t* level_steps) {
+    const int J = (int)c->lv.size() - 1;
+    if (!c->coarse_dense || p < 1 || p > kBlkMaxP || p > c->lv[J].n - 1) {
+        std::snprintf(g_last_error, sizeof(g_last_error),
+                      "cmg_fiedler_block: p = %d needs 1 <= p <= %d and p < the coarsest level's %d vertices, "
+                      "solved densely (n <= dense_max)",
+                      p, kBlkMaxP, c->lv[J].n);
+        return CMG_E_ARG;
+    }
+    hipStream_t s = c->stream;
+    if (!c->coarse_done) {
+        CK(launch_coarse_jobs(c->d_cjob, 1, s));
+        c->coarse_done = true;
+    }
+    cmg_status st = blk_plan(c, p);
+    if (st != CMG_OK) return st;
+    CK(launch_blk(kBlkCoarse, p, nullptr, c->blk_jobs[J], nullptr, c->d_V, c->d_ev, c->d_idx, s));
+    for (int j = J - 1; j >= 0; --j) {
+        CK(launch_blk(kBlkProlong, p, c->d_blk_jobs + j, c->blk_jobs[j], nullptr, nullptr, nullptr, nullptr, s));
+        st = blk_steps(c, j, p, s);
+        if (st != CMG_OK) return st;
+    }
+    CK(launch_blk(kBlkOut, p, c->d_blk_jobs, c->blk_jobs[0], c->d_blk_x, nullptr, nullptr, nullptr, s));
+    BlkOut out{};
+    std::vector<BlkCtl> ctl(J + 1);
+    CK(hipMemcpyAsync(&out, c->d_blk_out, sizeof(out), hipMemcpyDeviceToHost, s));
+    CK(hipMemcpyAsync(ctl.data(), c->d_blk_ctl, sizeof(BlkCtl) * (J + 1), hipMemcpyDeviceToHost, s));
+    if (X)
+        CK(hipMemcpyAsync(X, c->d_blk_x, sizeof(double) * (size_t)c->lv[0].n * p,
+                          where == CMG_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+    CK(hipStreamSynchronize(s));
+    cmg_status status = CMG_OK;
+    for (int j = 0; j < J; ++j) {
+        if (ctl[j].hit == 2) {
+            std::snprintf(g_last_error, sizeof(g_last_error),
+                          "cmg_fiedler_block: level %d: the block lost rank (Gram matrix not positive definite)", j);
+            return CMG_E_DEVICE;
+        }
+        if (ctl[j].hit == 1) status = CMG_W_MAXIT;
+    }
+    for (int q = 0; q < p; ++q) {
+        if (lambdas) lambdas[q] = out.lambda[q];
+        if (residuals) residuals[q] = out.residual[q];
+    }
+    if (level_steps)
+        for (int j = 0; j <= J; ++j) level_steps[j] = j == J ? -1 : ctl[j].k;
+    return status;
+}
+
 // Several graphs: every stage of all graphs in packed launches (one
 // workgroup per graph for the coarsest solve and the coarse levels; for
 // the grid levels, round r refines the r-th grid level, counted from the
@@ -1743,6 +1904,14 @@ cmg_status cmg_fiedler_batch(cmg_handle* hs, int32_t count, double* lambdas, voi
             if (hs[k] == hs[i]) return CMG_E_ARG;  // a handle's buffers serve one solve at a time
     }
     return batch_impl(hs, count, lambdas, xs, where, stats);
+}
+
+cmg_status cmg_fiedler_block(cmg_handle h, int32_t p, double* lambdas, void* X, cmg_memspace where,
+                             double* residuals, int32_t* level_steps) {
+    g_last_error[0] = 0;
+    if (!h) return CMG_E_ARG;
+    if (where != CMG_MEM_HOST && where != CMG_MEM_DEVICE) return CMG_E_ARG;
+    return block_impl(h, p, lambdas, X, where, residuals, level_steps);
 }
 
 cmg_status cmg_level_info(cmg_handle h, cmg_level_stats* out, int32_t cap, int32_t* nlevels) {

@@ -179,6 +179,49 @@ struct MeasureBuffers {
     hipStream_t stream;
 };
 void set_measure_buffers(const MeasureBuffers* b);
+// ---- block.hip: several eigenpairs (Remark after Algorithm 4), P <= kBlkMaxP
+constexpr int kBlkMaxP = 4;
+// Block state of one level (device written): V = (W[cur] - 1 mu^T) rinv.
+struct BlkCtl {
+    double mu[kBlkMaxP];
+    double rinv[kBlkMaxP * kBlkMaxP];  // R^{-1}, upper triangular, row-major P x P
+    double minutv;                     // smallest (u_c, v_c) of the last step
+    int32_t k, cur, done, hit;         // hit: 1 step cap, 2 Gram matrix not positive definite
+};
+struct BlkOut {
+    double lambda[kBlkMaxP], residual[kBlkMaxP], norm2[kBlkMaxP], coarse[kBlkMaxP];
+};
+// One level of the block refinement (P columns, n x P row-major blocks).
+struct BlkJob {
+    int32_t n;
+    int32_t nb;              // workgroups; rows rpart[b] .. rpart[b+1] for workgroup b
+    const int32_t* rp;
+    const int32_t* col;
+    const double* w;
+    double g;
+    const int32_t* agg;      // prolongation: vertex -> aggregate of the coarser level
+    const double* cW0;       // coarser level's blocks and state
+    const double* cW1;
+    const BlkCtl* cctl;
+    double* W0;
+    double* W1;
+    BlkCtl* ctl;
+    double* part;            // blk_parts(P) partial sums per workgroup
+    const int32_t* rpart;
+    BlkOut* out;
+    double tol;
+    uint64_t seed;
+    int32_t maxit, kfix;
+};
+constexpr int kBlkCoarse = 0, kBlkProlong = 1, kBlkStep = 2, kBlkOut = 3;
+int blk_parts(int p);
+// what: kBlkCoarse (one workgroup; V (n x n, eigenvector k in column k),
+// ev and the ascending order idx from the dense coarsest solve; hj by
+// value), kBlkProlong (prolongation + normalisation), kBlkStep (one step +
+// its check; does nothing once the level is done), kBlkOut (level 0: X
+// (n x P column-major), Rayleigh quotients and residuals).
+hipError_t launch_blk(int what, int p, const BlkJob* dj, const BlkJob& hj, double* X, const double* V,
+                      const double* ev, const int32_t* idx, hipStream_t s);
 // zero the barrier state and the slots (2 * nslots; at setup, and after an abort)
 hipError_t launch_reset_sync(GridSync* gs, GridSlot* slots, int nslots, GridSlot* bcast, hipStream_t s);
 

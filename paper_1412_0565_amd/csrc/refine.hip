@@ -369,6 +369,9 @@ __global__ void __launch_bounds__(256) k_coarse_jobs(const CoarseJob* __restrict
         }
         __syncthreads();
     }
+    // eigenvectors kept in LDS are left in Vg too (several-eigenpair starts read them)
+    if (n <= kDenseLds)
+        for (int t = tid; t < n * n; t += nt) Vg[t] = V[t];
     if (tid == 0) {
         int mult = 0;
         for (int r = 1; r < n; ++r)

@@ -1047,6 +1047,153 @@ void orc_block_copy_x(const orc_block_result* b, int32_t n, double* X)
     if (b->X) memcpy(X, b->X, sizeof(double) * (size_t)n * b->p);
 }
 
+/* ------------------------------------------- recursive spectral bisection */
+
+/* Induced subgraph of the vertices with sel[v] == 1: vertices relabelled
+ * 0..m-1 in ascending original index (glob[] maps back), edges to
+ * unselected vertices dropped, CSR order kept.  Returns m (-1 on
+ * allocation failure); the caller frees *prp, *pcol, *pw, *pglob. */
+int32_t orc_induced(int32_t n, const int32_t* rp, const int32_t* col, const double* w,
+                           const uint8_t* sel, int32_t** prp, int32_t** pcol, double** pw,
+                           int32_t** pglob)
+{
+    int32_t* loc = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!loc) return -1;
+    int32_t m = 0;
+    int64_t z = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        loc[v] = sel[v] ? m++ : -1;
+        if (sel[v])
+            for (int32_t e = rp[v]; e < rp[v + 1]; ++e) z += sel[col[e]] ? 1 : 0;
+    }
+    int32_t* srp = (int32_t*)malloc(sizeof(int32_t) * ((size_t)m + 1));
+    int32_t* scol = (int32_t*)malloc(sizeof(int32_t) * (size_t)(z > 0 ? z : 1));
+    double* sw = (double*)malloc(sizeof(double) * (size_t)(z > 0 ? z : 1));
+    int32_t* glob = (int32_t*)malloc(sizeof(int32_t) * ((size_t)m + 1));
+    if (!srp || !scol || !sw || !glob) {
+        free(loc); free(srp); free(scol); free(sw); free(glob);
+        return -1;
+    }
+    int64_t t = 0;
+    srp[0] = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (!sel[v]) continue;
+        glob[loc[v]] = v;
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
+            if (sel[col[e]]) {
+                scol[t] = loc[col[e]];
+                sw[t] = w[e];
+                ++t;
+            }
+        srp[loc[v] + 1] = (int32_t)t;
+    }
+    free(loc);
+    *prp = srp; *pcol = scol; *pw = sw; *pglob = glob;
+    return m;
+}
+
+/* Connected components: comp[v] = smallest vertex of v's component
+ * (breadth-first search from each unlabelled vertex in index order).
+ * Returns the number of components. */
+int32_t orc_components(int32_t n, const int32_t* rp, const int32_t* col, int32_t* comp)
+{
+    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    if (!queue) return -1;
+    for (int32_t v = 0; v < n; ++v) comp[v] = -1;
+    int32_t count = 0;
+    for (int32_t s = 0; s < n; ++s) {
+        if (comp[s] >= 0) continue;
+        ++count;
+        int32_t head = 0, tail = 0;
+        queue[tail++] = s;
+        comp[s] = s;
+        while (head < tail) {
+            int32_t v = queue[head++];
+            for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
+                if (comp[col[e]] < 0) {
+                    comp[col[e]] = s;
+                    queue[tail++] = col[e];
+                }
+        }
+    }
+    free(queue);
+    return count;
+}
+
+typedef struct {
+    double key;
+    int32_t v;
+} orc_split_item;
+
+static int orc_cmp_split(const void* a, const void* b)
+{
+    const orc_split_item* x = (const orc_split_item*)a;
+    const orc_split_item* y = (const orc_split_item*)b;
+    if (x->key < y->key) return -1;
+    if (x->key > y->key) return 1;
+    return (x->v > y->v) - (x->v < y->v);
+}
+
+/* Recursive spectral bisection (the graph-partitioning use of the Fiedler
+ * vector named in Section 1, with the repeated coarse solves the remark on
+ * the coarsest level anticipates): every part is split in two, `depth`
+ * times, giving part ids 0 .. 2^depth - 1 (part p splits into 2p, 2p + 1).
+ * READING (the paper gives no bisection rule): a part of fewer than 2
+ * vertices is not split (its children are 2p alone); a connected part is
+ * split at the median of its Fiedler vector (orc_cmg on the induced
+ * subgraph, default options): its vertices ordered by (x_i, index), the
+ * first floor(m/2) go to 2p; a disconnected part is ordered by (smallest
+ * vertex of the component, index) instead, so whole components stay
+ * together except the one the median falls in.  part[n] receives the ids;
+ * returns ORC_OK or the first failing status. */
+int orc_rsb(int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col, const double* w,
+            int32_t depth, int32_t* part)
+{
+    int st = orc_validate(n, nnz, rp, col, w);
+    if (st != ORC_OK) return st;
+    uint8_t* sel = (uint8_t*)malloc((size_t)n);
+    int32_t* next = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!sel || !next) { free(sel); free(next); return ORC_E_OOM; }
+    for (int32_t v = 0; v < n; ++v) part[v] = 0;
+    for (int32_t d = 0; d < depth && st == ORC_OK; ++d) {
+        const int32_t nparts = 1 << d;
+        for (int32_t p = 0; p < nparts && st == ORC_OK; ++p) {
+            for (int32_t v = 0; v < n; ++v) sel[v] = (uint8_t)(part[v] == p);
+            int32_t *srp = NULL, *scol = NULL, *glob = NULL;
+            double* sw = NULL;
+            int32_t m = orc_induced(n, rp, col, w, sel, &srp, &scol, &sw, &glob);
+            if (m < 0) { st = ORC_E_OOM; break; }
+            orc_split_item* it = (orc_split_item*)malloc(sizeof(orc_split_item) * ((size_t)m + 1));
+            int32_t* comp = (int32_t*)malloc(sizeof(int32_t) * ((size_t)m + 1));
+            if (!it || !comp) { st = ORC_E_OOM; }
+            if (st == ORC_OK && m >= 2) {
+                int32_t nc = orc_components(m, srp, scol, comp);
+                if (nc == 1) {
+                    orc_result* r = orc_cmg(m, srp[m], srp, scol, sw, 1e-8, 25, 128, 14120565ull, 100000);
+                    if (!r) st = ORC_E_OOM;
+                    else if (r->status != ORC_OK && r->status != ORC_W_MAXIT) st = r->status;
+                    else
+                        for (int32_t i = 0; i < m; ++i) { it[i].key = r->y[i]; it[i].v = i; }
+                    orc_free(r);
+                } else {
+                    for (int32_t i = 0; i < m; ++i) { it[i].key = (double)comp[i]; it[i].v = i; }
+                }
+                if (st == ORC_OK) {
+                    qsort(it, (size_t)m, sizeof(orc_split_item), orc_cmp_split);
+                    for (int32_t t = 0; t < m; ++t) next[glob[it[t].v]] = 2 * p + (t < m / 2 ? 0 : 1);
+                }
+            } else if (st == ORC_OK) {
+                for (int32_t i = 0; i < m; ++i) next[glob[i]] = 2 * p;
+            }
+            free(it); free(comp); free(srp); free(scol); free(sw); free(glob);
+        }
+        memcpy(part, next, sizeof(int32_t) * (size_t)n);
+    }
+    free(sel);
+    free(next);
+    return st;
+}
+
 /* ----------------------------------------------------- result accessors */
 
 int32_t orc_res_status(const orc_result* r) { return r->status; }

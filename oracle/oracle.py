@@ -105,6 +105,10 @@ def lib():
         L.orc_block_pi.restype = C.c_int32
         L.orc_block_pi.argtypes = [C.c_int32, _i32p, _i32p, _f64p, C.c_double, C.c_int32, _f64p, C.c_double,
                                    C.c_int32, C.c_int32, _f64p, C.POINTER(C.c_double)]
+        L.orc_components.restype = C.c_int32
+        L.orc_components.argtypes = [C.c_int32, _i32p, _i32p, _i32p]
+        L.orc_rsb.restype = C.c_int
+        L.orc_rsb.argtypes = [C.c_int32, C.c_int64, _i32p, _i32p, _f64p, C.c_int32, _i32p]
         L.orc_cmg.restype = C.c_void_p
         L.orc_cmg.argtypes = [C.c_int32, C.c_int64, _i32p, _i32p, _f64p, C.c_double, C.c_int32,
                               C.c_int32, C.c_uint64, C.c_int32]
@@ -430,3 +434,21 @@ def cmg_block(g, p: int, tol: float = 1e-8, coarsest_n: int = 25, dense_max: int
                            X.reshape(p, g.n).T.copy())
     finally:
         L.orc_block_free(r)
+
+
+def rsb(g, depth: int) -> np.ndarray:
+    """Recursive spectral bisection into 2^depth parts on the oracle."""
+    rp, col, w = _csr_args(g)
+    part = np.zeros(g.n, dtype=np.int32)
+    st = lib().orc_rsb(g.n, int(rp[-1]), rp, col, w, depth, part)
+    if st != 0:
+        raise ValueError(STATUS[st])
+    return part
+
+
+def components(g) -> np.ndarray:
+    """comp[v] = smallest vertex of v's connected component."""
+    rp, col, _ = _csr_args(g)
+    comp = np.zeros(g.n, dtype=np.int32)
+    lib().orc_components(g.n, rp, col, comp)
+    return comp

@@ -243,6 +243,27 @@ cmg_status cmg_fiedler_batch(cmg_handle* hs, int32_t count, double* lambdas, voi
 cmg_status cmg_fiedler_block(cmg_handle h, int32_t p, double* lambdas, void* X, cmg_memspace where,
                              double* residuals, int32_t* level_steps);
 
+/* Recursive spectral bisection (the graph-partitioning use of the Fiedler
+ * vector, Section 1; repeated solves as the remark on the coarsest level
+ * anticipates): every part is split in two, `depth` times, giving part ids
+ * 0 .. 2^depth - 1 (part p splits into 2p and 2p + 1).  Per depth all
+ * parts are handled at once: their induced subgraphs are compacted on the
+ * device, connected components labelled, and the connected parts of two
+ * vertices or more solved in one cmg_fiedler_batch (options `opt` apply to
+ * every solve); a connected part is split at the median of its Fiedler
+ * vector (ordered by (x_i, index); the first floor(m/2) go to 2p), a
+ * disconnected part by (smallest vertex of the component, index), a part
+ * of one vertex is not split.
+ *   n, nnz, row_ptr, col, w, wtype, where, opt   as cmg_setup
+ *   depth    0..16
+ *   part[n]  receives the part ids (int32, in `where`)
+ *   cut      receives the total weight of edges between parts (host, may
+ *            be NULL)
+ * Returns CMG_OK or the first failing status. */
+cmg_status cmg_bisect(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, const void* w,
+                      cmg_valtype wtype, cmg_memspace where, const cmg_options* opt, int32_t depth,
+                      int32_t* part, double* cut);
+
 /* Copy per-level information into out[0..cap-1]; *nlevels gets J+1. */
 cmg_status cmg_level_info(cmg_handle h, cmg_level_stats* out, int32_t cap, int32_t* nlevels);
 

@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 INC = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcmg.so")
-SOURCES = ["setup.hip", "coarsen_small.hip", "refine.hip", "block.hip", "cmg_api.hip"]
+SOURCES = ["setup.hip", "coarsen_small.hip", "refine.hip", "block.hip", "bisect.hip", "cmg_api.hip"]
 ARCH = "gfx950"
 
 

@@ -26,7 +26,7 @@ CMG_VAL_F64, CMG_VAL_F32 = 0, 1
 # functions declared in include/cmg.h
 EXPORTS = ["cmg_options_default", "cmg_setup", "cmg_fiedler", "cmg_fiedler_batch", "cmg_level_info",
            "cmg_level_copy", "cmg_set_stream", "cmg_footprint", "cmg_free", "cmg_status_string",
-           "cmg_last_error", "cmg_hash_probe", "cmg_fiedler_noalloc", "cmg_fiedler_block"]
+           "cmg_last_error", "cmg_hash_probe", "cmg_fiedler_noalloc", "cmg_fiedler_block", "cmg_bisect"]
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 _FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
@@ -146,6 +146,9 @@ def lib():
         L.cmg_fiedler_block.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
                                         C.c_void_p]
         L.cmg_fiedler_block.restype = C.c_int
+        L.cmg_bisect.argtypes = [C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                                 C.POINTER(cmg_options), C.c_int32, C.c_void_p, C.POINTER(C.c_double)]
+        L.cmg_bisect.restype = C.c_int
         _lib = L
     return _lib
 
@@ -287,6 +290,24 @@ def cmg_fiedler_block(h: int, p: int, X=None):
     st = lib().cmg_fiedler_block(h, int(p), lams.ctypes.data, px, where, res.ctypes.data, steps.ctypes.data)
     _check(st, "cmg_fiedler_block")
     return lams, res, [int(k) for k in steps], st
+
+
+def cmg_bisect(n: int, row_ptr, col, w, depth: int, part=None, opt: cmg_options | None = None):
+    """Recursive spectral bisection into 2^depth parts.  Arrays as
+    cmg_setup; part: int32 output of n entries in the same memory space
+    (a new numpy array if None).  Returns (part, cut)."""
+    prp, where = _ptr(row_ptr)
+    pcol, _ = _ptr(col)
+    pw, _ = _ptr(w)
+    if part is None:
+        part = np.zeros(int(n), dtype=np.int32)
+    pp, _ = _ptr(part)
+    wtype = CMG_VAL_F32 if str(w.dtype).split(".")[-1] == "float32" else CMG_VAL_F64
+    cut = C.c_double()
+    st = lib().cmg_bisect(int(n), int(col.shape[0]), prp, pcol, pw, wtype, where,
+                          C.byref(opt) if opt is not None else None, int(depth), pp, C.byref(cut))
+    _check(st, "cmg_bisect")
+    return part, cut.value
 
 
 def cmg_level_info(h: int):

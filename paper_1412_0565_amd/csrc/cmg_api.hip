@@ -1597,6 +1597,144 @@ cmg_status block_impl(cmg_ctx* c, int p, double* lambdas, void* X, cmg_memspace 
     return status;
 }
 
+// ---- recursive spectral bisection
+
+cmg_status bisect_impl(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, const void* w,
+                       cmg_valtype wtype, cmg_memspace where, const cmg_options& o, int32_t depth, int32_t* part_out,
+                       double* cut) {
+    cmg_ctx c;  // allocation helper: its direct allocations go back when it ends
+    c.opt = o;
+    c.stream = (hipStream_t)o.stream;
+    if (o.allocator) c.alloc = *o.allocator;
+    hipStream_t s = c.stream;
+    const hipMemcpyKind kind = where == CMG_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const int64_t nsc = sort_tmp_elems(n);
+    const int maxp = 1 << depth;
+    auto take = [&](size_t bytes) { return c.dalloc_direct(bytes); };
+    int32_t* rp = (int32_t*)take(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t* cl = (int32_t*)take(sizeof(int32_t) * (size_t)nnz);
+    double* wd = (double*)take(sizeof(double) * (size_t)nnz);
+    void* wtmp = wtype == CMG_VAL_F32 ? take(sizeof(float) * (size_t)nnz) : nullptr;
+    unsigned* vf = (unsigned*)take(sizeof(unsigned) * 4);
+    int32_t* part = (int32_t*)take(sizeof(int32_t) * (size_t)n);
+    int32_t* next = (int32_t*)take(sizeof(int32_t) * (size_t)n);
+    int32_t* perm = (int32_t*)take(sizeof(int32_t) * (size_t)n);
+    int32_t* pos = (int32_t*)take(sizeof(int32_t) * (size_t)n);
+    int32_t* deg = (int32_t*)take(sizeof(int32_t) * (size_t)n);
+    int32_t* eoff = (int32_t*)take(sizeof(int32_t) * (size_t)n);
+    int32_t* comp = (int32_t*)take(sizeof(int32_t) * (size_t)n);
+    int32_t* rpl = (int32_t*)take(sizeof(int32_t) * ((size_t)n + maxp));
+    int32_t* colk = (int32_t*)take(sizeof(int32_t) * (size_t)nnz);
+    double* wk = (double*)take(sizeof(double) * (size_t)nnz);
+    double* X = (double*)take(sizeof(double) * (size_t)n);
+    unsigned long long* k0 = (unsigned long long*)take(sizeof(unsigned long long) * (size_t)n);
+    unsigned long long* k1 = (unsigned long long*)take(sizeof(unsigned long long) * (size_t)n);
+    double* v0 = (double*)take(sizeof(double) * (size_t)n);
+    double* v1 = (double*)take(sizeof(double) * (size_t)n);
+    int32_t* scounts = (int32_t*)take(sizeof(int32_t) * (size_t)nsc);
+    long long* sscan = (long long*)take(sizeof(long long) * (size_t)(scan_tmp_elems(nsc) + 4));
+    long long* stmp = (long long*)take(sizeof(long long) * (size_t)(scan_tmp_elems(n) + 4));
+    int32_t* meta = (int32_t*)take(sizeof(int32_t) * 6 * (size_t)maxp);  // first, cnt, pnnz, pbase, ncomp, mode
+    int* chg = (int*)take(sizeof(int) * 4);
+    double* bsum = (double*)take(sizeof(double) * (size_t)rsb_cut_blocks(n));
+    if (!rp || !cl || !wd || (wtype == CMG_VAL_F32 && !wtmp) || !vf || !part || !next || !perm || !pos || !deg ||
+        !eoff || !comp || !rpl || !colk || !wk || !X || !k0 || !k1 || !v0 || !v1 || !scounts || !sscan || !stmp ||
+        !meta || !chg || !bsum)
+        return CMG_E_OOM;
+    int32_t *first = meta, *cnt = meta + maxp, *pnnz = meta + 2 * maxp, *pbase = meta + 3 * maxp,
+            *ncomp = meta + 4 * maxp, *mode = meta + 5 * maxp;
+    // the graph, checked as cmg_setup checks it
+    CK(hipMemcpyAsync(rp, row_ptr, sizeof(int32_t) * ((size_t)n + 1), kind, s));
+    CK(hipMemcpyAsync(cl, col, sizeof(int32_t) * (size_t)nnz, kind, s));
+    if (wtype == CMG_VAL_F32) {
+        CK(hipMemcpyAsync(wtmp, w, sizeof(float) * (size_t)nnz, kind, s));
+        CK(launch_convert_w(nnz, wtmp, 1, wd, s));
+    } else {
+        CK(hipMemcpyAsync(wd, w, sizeof(double) * (size_t)nnz, kind, s));
+    }
+    CK(launch_fill_u32(vf, 0u, 2, s));
+    CK(launch_validate(n, nnz, rp, cl, wd, 0, o.validate_full, vf, s));
+    unsigned vres[2] = {0u, 0u};
+    cmg_status st = d2h(&c, vres, vf, 2);
+    if (st != CMG_OK) return st;
+    if (vres[0] & (kBadGraph | kAsym)) return CMG_E_GRAPH;
+    if (vres[0] & kIsolated) return CMG_E_ISOLATED;
+    CK(launch_fill_u32((unsigned*)part, 0u, n, s));
+    std::vector<int32_t> hm(6 * (size_t)maxp);
+    int hchg = 0;
+    cmg_options so = o;  // options of every sub-solve
+    so.allocator = o.allocator;
+    for (int d = 0; d < depth; ++d) {
+        const int np = 1 << d;
+        // vertices grouped by part, ascending index inside a part
+        CK(launch_rsb_keys(n, part, k0, s));
+        int second = 0;
+        CK(launch_sort(k0, nullptr, k1, nullptr, n, 32, std::max(d, 1), scounts, sscan, &second, s));
+        const unsigned long long* ks = second ? k1 : k0;
+        CK(launch_fill_u32((unsigned*)meta, 0u, 6 * (int64_t)maxp, s));
+        CK(launch_rsb_perm(n, ks, perm, pos, first, comp, s));
+        // induced subgraphs: rows in position order, local columns
+        CK(launch_rsb_deg(n, rp, cl, part, perm, deg, s));
+        CK(launch_scan(deg, eoff, n, stmp, stmp + scan_tmp_elems(n), s));
+        CK(launch_rsb_fill(n, rp, cl, wd, part, perm, pos, first, eoff, rpl, colk, wk, cnt, pnnz, pbase, s));
+        CK(launch_rsb_components(n, rpl, colk, part, perm, first, eoff, comp, chg, &hchg, s));
+        CK(launch_rsb_roots(n, comp, part, perm, ncomp, s));
+        st = d2h(&c, hm.data(), meta, 5 * (size_t)maxp);
+        if (st != CMG_OK) return st;
+        // connected parts of two vertices or more: Fiedler vectors in one batch
+        std::vector<cmg_handle> hs;
+        std::vector<void*> xs;
+        for (int p = 0; p < np; ++p) {
+            const int m = hm[maxp + p], comps = hm[4 * maxp + p];
+            hm[5 * maxp + p] = m < 2 ? 0 : comps == 1 ? 1 : 2;
+        }
+        CK(hipMemcpyAsync(mode, hm.data() + 5 * maxp, sizeof(int32_t) * maxp, hipMemcpyHostToDevice, s));
+        st = CMG_OK;
+        for (int p = 0; p < np && st == CMG_OK; ++p) {
+            if (hm[5 * maxp + p] != 1) continue;
+            const int f = hm[p], m = hm[maxp + p], z = hm[2 * maxp + p], base = hm[3 * maxp + p];
+            cmg_handle h = nullptr;
+            st = cmg_setup(m, z, rpl + f + p, colk + base, wk + base, CMG_VAL_F64, CMG_MEM_DEVICE, &so, &h);
+            if (st == CMG_OK) {
+                hs.push_back(h);
+                xs.push_back(X + f);
+            }
+        }
+        if (st == CMG_OK && !hs.empty()) {
+            st = cmg_fiedler_batch(hs.data(), (int32_t)hs.size(), nullptr, xs.data(), CMG_MEM_DEVICE, nullptr);
+            if (st == CMG_W_MAXIT) st = CMG_OK;
+        }
+        for (cmg_handle h : hs) cmg_free(h);
+        if (st != CMG_OK) return st;
+        // split every part at its median: stable sort by key, then by part
+        CK(launch_rsb_split_keys(n, X, comp, part, perm, mode, k0, v0, s));
+        CK(launch_sort(k0, v0, k1, v1, n, 0, 64, scounts, sscan, &second, s));
+        const double* vs = second ? v1 : v0;
+        double* vo = second ? v0 : v1;
+        unsigned long long* kp = second ? k0 : k1;
+        unsigned long long* kq = second ? k1 : k0;
+        CK(launch_rsb_part_keys(n, vs, part, perm, kp, s));
+        CK(launch_sort(kp, (double*)vs, kq, vo, n, 32, std::max(d, 1), scounts, sscan, &second, s));
+        const double* fin = second ? vo : vs;
+        CK(launch_rsb_assign(n, fin, part, perm, first, cnt, mode, next, s));
+        std::swap(part, next);
+    }
+    CK(hipMemcpyAsync(part_out, part, sizeof(int32_t) * (size_t)n,
+                      where == CMG_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+    if (cut) {
+        const int nb = rsb_cut_blocks(n);
+        std::vector<double> hb(nb);
+        CK(launch_rsb_cut(n, rp, cl, wd, part, bsum, s));
+        st = d2h(&c, hb.data(), bsum, nb);
+        if (st != CMG_OK) return st;
+        double t = 0.0;
+        for (double x : hb) t += x;
+        *cut = 0.5 * t;
+    }
+    CK(hipStreamSynchronize(s));
+    return CMG_OK;
+}
+
 // Several graphs: every stage of all graphs in packed launches (one
 // workgroup per graph for the coarsest solve and the coarse levels; for
 // the grid levels, round r refines the r-th grid level, counted from the
@@ -1912,6 +2050,24 @@ cmg_status cmg_fiedler_block(cmg_handle h, int32_t p, double* lambdas, void* X, 
     if (!h) return CMG_E_ARG;
     if (where != CMG_MEM_HOST && where != CMG_MEM_DEVICE) return CMG_E_ARG;
     return block_impl(h, p, lambdas, X, where, residuals, level_steps);
+}
+
+cmg_status cmg_bisect(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, const void* w,
+                      cmg_valtype wtype, cmg_memspace where, const cmg_options* opt, int32_t depth, int32_t* part,
+                      double* cut) {
+    g_last_error[0] = 0;
+    if (n < 2 || nnz < 1 || nnz >= 2147483647LL || !row_ptr || !col || !w || !part) return CMG_E_ARG;
+    if (wtype != CMG_VAL_F64 && wtype != CMG_VAL_F32) return CMG_E_ARG;
+    if (where != CMG_MEM_HOST && where != CMG_MEM_DEVICE) return CMG_E_ARG;
+    if (depth < 0 || depth > 16) return CMG_E_ARG;
+    cmg_options o;
+    fill_defaults(&o);
+    if (opt) {
+        size_t sz = opt->struct_size ? std::min<size_t>(opt->struct_size, sizeof(o)) : sizeof(o);
+        std::memcpy(&o, opt, sz);
+        o.struct_size = sizeof(o);
+    }
+    return bisect_impl(n, nnz, row_ptr, col, w, wtype, where, o, depth, part, cut);
 }
 
 cmg_status cmg_level_info(cmg_handle h, cmg_level_stats* out, int32_t cap, int32_t* nlevels) {

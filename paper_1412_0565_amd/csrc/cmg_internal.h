@@ -222,6 +222,33 @@ int blk_parts(int p);
 // (n x P column-major), Rayleigh quotients and residuals).
 hipError_t launch_blk(int what, int p, const BlkJob* dj, const BlkJob& hj, double* X, const double* V,
                       const double* ev, const int32_t* idx, hipStream_t s);
+// ---- bisect.hip: recursive spectral bisection (one depth of all parts at once)
+hipError_t launch_rsb_keys(int n, const int32_t* part, unsigned long long* keys, hipStream_t s);
+hipError_t launch_rsb_perm(int n, const unsigned long long* keys, int32_t* perm, int32_t* pos, int32_t* first,
+                           int32_t* comp, hipStream_t s);
+hipError_t launch_rsb_deg(int n, const int32_t* rp, const int32_t* col, const int32_t* part, const int32_t* perm,
+                          int32_t* deg, hipStream_t s);
+hipError_t launch_rsb_fill(int n, const int32_t* rp, const int32_t* col, const double* w, const int32_t* part,
+                           const int32_t* perm, const int32_t* pos, const int32_t* first, const int32_t* eoff,
+                           int32_t* rpl, int32_t* colk, double* wk, int32_t* cnt, int32_t* pnnz, int32_t* pbase,
+                           hipStream_t s);
+// hook and jump until nothing changes (host-checked; changed/h_changed: one int each)
+hipError_t launch_rsb_components(int n, const int32_t* rpl, const int32_t* colk, const int32_t* part,
+                                 const int32_t* perm, const int32_t* first, const int32_t* eoff, int32_t* comp,
+                                 int* changed, int* h_changed, hipStream_t s);
+hipError_t launch_rsb_roots(int n, const int32_t* comp, const int32_t* part, const int32_t* perm, int32_t* ncomp,
+                            hipStream_t s);
+hipError_t launch_rsb_split_keys(int n, const double* x, const int32_t* comp, const int32_t* part,
+                                 const int32_t* perm, const int32_t* mode, unsigned long long* keys, double* vals,
+                                 hipStream_t s);
+hipError_t launch_rsb_part_keys(int n, const double* vals, const int32_t* part, const int32_t* perm,
+                                unsigned long long* keys, hipStream_t s);
+hipError_t launch_rsb_assign(int n, const double* vals, const int32_t* part, const int32_t* perm,
+                             const int32_t* first, const int32_t* cnt, const int32_t* mode, int32_t* next,
+                             hipStream_t s);
+hipError_t launch_rsb_cut(int n, const int32_t* rp, const int32_t* col, const double* w, const int32_t* part,
+                          double* bsum, hipStream_t s);
+int rsb_cut_blocks(int n);
 // zero the barrier state and the slots (2 * nslots; at setup, and after an abort)
 hipError_t launch_reset_sync(GridSync* gs, GridSlot* slots, int nslots, GridSlot* bcast, hipStream_t s);
 

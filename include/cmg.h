@@ -138,6 +138,11 @@ typedef struct {
                                     (each unmatched vertex, in the same visit order, is matched to
                                     its heaviest unmatched neighbour or stays alone; aggregates of
                                     one or two vertices, so n_{j+1} >= n_j / 2), for comparison. */
+    int32_t galerkin;            /* Galerkin product of the large levels: 0 (default) forms each
+                                    coarse row from its aggregate's member rows where no aggregate
+                                    has more than 256 entries, else sorts (key, weight) pairs; 1
+                                    always sorts.  Both sum in fine CSR order: coarse graphs are
+                                    bitwise equal. */
 } cmg_options;
 
 /* Per-level information (available after cmg_setup; PI fields after

@@ -60,6 +60,7 @@ class cmg_options(C.Structure):
         ("fixed_beta", C.c_double),
         ("graph", C.c_int32),
         ("coarsen", C.c_int32),
+        ("galerkin", C.c_int32),
     ]
 
 

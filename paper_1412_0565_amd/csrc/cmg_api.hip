@@ -476,11 +476,63 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
         ALLOC(L.agg, int32_t, L.n);
         CK(launch_hec_label(L.n, t.rootseed, t.rank, L.agg, s));
     }
-    // Galerkin product with the aggregate count left on the device: keys
+    // Galerkin product by aggregates when no aggregate's member rows hold
+    // more than kGalCap entries: the aggregate count and the largest
+    // aggregate are read back in one synchronisation, the coarse rows are
+    // formed in LDS in fine CSR order; else the radix-sort path below.
+    const int64_t ncmax = hem ? (int64_t)L.n : (int64_t)L.n / 2 + 1;
+    if (c->opt.galerkin == 0) {
+        int32_t* members = t.rootseed;
+        int32_t* mdeg = t.flags;
+        int32_t* mstart = t.pairseed;
+        int32_t* moff = t.rank;
+        int32_t* mpos = (int32_t*)t.slot;  // n ints in the n 8-byte slots
+        CK(launch_gal_members(L.n, L.agg, L.rp, t.k0, t.k1, bitlen((unsigned long long)ncmax), t.sort_counts,
+                              t.sort_scan, members, mdeg, mstart, mpos, s));
+        CK(launch_scan(mdeg, moff, L.n, t.scan_tmp, t.totals + 2, s));
+        CK(launch_fill_u32((unsigned*)(t.scal + 4), 0u, 2, s));
+        CK(launch_gal_agg_len((int)ncmax, t.totals, L.n, L.nnz, mstart, moff, t.scal + 4, s));
+        long long nc0 = 0;
+        unsigned long long emax = 0;
+        CK(hipMemcpyAsync(&nc0, t.totals, sizeof(long long), hipMemcpyDeviceToHost, s));
+        st = d2h(c, &emax, t.scal + 4, 1);
+        if (st != CMG_OK) return st;
+        if (nc0 < 2) {
+            c->dfree(L.agg);
+            L.agg = nullptr;
+            c->collapsed = 1;
+            *stop = true;
+            return CMG_OK;
+        }
+        if (emax <= (unsigned long long)kGalBigCap) {
+            const int nc = (int)nc0;
+            int32_t* rowlen = t.h;
+            int32_t* tcol = t.idx;
+            double* tw = t.v1;
+            CK(launch_gal_gather(nc, L.n, L.nnz, std::min(L.lanes, 8), mstart, mpos, moff, L.rp, L.col, L.w64,
+                                 L.agg, t.heads, t.v0, tcol, tw, rowlen, mdeg, (unsigned*)(t.scal + 5), s));
+            HostLevel C;
+            C.n = nc;
+            ALLOC(C.rp, int32_t, nc + 1);
+            CK(launch_scan(rowlen, C.rp, nc, t.scan_tmp, t.totals + 1, s));
+            long long zc = 0;
+            st = d2h(c, &zc, t.totals + 1, 1);
+            if (st != CMG_OK) return st;
+            CK(launch_fill_u32((unsigned*)(C.rp + nc), (unsigned)zc, 1, s));
+            C.nnz = zc;
+            ALLOC(C.col, int32_t, std::max<long long>(zc, 1));
+            ALLOC(C.w64, double, std::max<long long>(zc, 1));
+            if (zc > 0) CK(launch_gal_compact(nc, mstart, moff, C.rp, tcol, tw, C.col, C.w64, s));
+            C.lanes = pick_lanes(C.nnz / (double)C.n);
+            c->lv.push_back(C);
+            return CMG_OK;
+        }
+    }
+    // Radix-sort path, with the aggregate count left on the device: keys
     // a * mult + b with mult >= the count (HEC aggregates have two vertices
     // or more: n/2 + 1; HEM's one or two: n), sorted on enough bits that
     // the sentinel's low bits exceed every key
-    const int64_t mult = hem ? (int64_t)L.n : (int64_t)L.n / 2 + 1;
+    const int64_t mult = ncmax;
     const int bits = bitlen((unsigned long long)mult * (unsigned long long)mult);
     // packed words (key << pbits | fine position) when they fit 64 bits:
     // the sort then moves 8 bytes per entry instead of 16
@@ -1223,6 +1275,7 @@ void fill_defaults(cmg_options* o) {
     o->fixed_beta = 2.0;
     o->graph = 0;
     o->coarsen = 0;
+    o->galerkin = 0;
 }
 
 // Device results of the last solve -> host staging (asynchronous).
@@ -2005,7 +2058,7 @@ cmg_status cmg_setup(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
         o.fp64_final_sweeps < 0 || o.fp64_final_sweeps > 1 || o.coarsest_n > o.dense_max ||
         o.step_mode < -1 || o.step_mode > 1 || o.fixed_k0 < 0 ||
         (o.fixed_k0 > 0 && !(o.fixed_beta >= 1.0 && std::isfinite(o.fixed_beta))) || o.graph < 0 || o.graph > 1 ||
-        o.coarsen < 0 || o.coarsen > 1)
+        o.coarsen < 0 || o.coarsen > 1 || o.galerkin < 0 || o.galerkin > 1)
         return CMG_E_ARG;
     const double t0 = now_ms();
     cmg_ctx* c = new (std::nothrow) cmg_ctx;
@@ -2147,7 +2200,7 @@ cmg_status cmg_fiedler_noalloc(int32_t n, int64_t nnz, const int32_t* row_ptr, c
         o.max_iters_per_level < 1 || (o.precision != CMG_FP64 && o.precision != CMG_MIXED) ||
         o.fp64_final_sweeps < 0 || o.fp64_final_sweeps > 1 || o.coarsest_n > o.dense_max || o.fixed_k0 < 0 ||
         (o.fixed_k0 > 0 && !(o.fixed_beta >= 1.0 && std::isfinite(o.fixed_beta))) || o.coarsen < 0 ||
-        o.coarsen > 1)
+        o.coarsen > 1 || o.galerkin < 0 || o.galerkin > 1)
         return CMG_E_ARG;
     const size_t need = noalloc_need(n, nnz);
     if (need > kNoallocScratchBytes - kNoallocMeasureBytes) {

@@ -89,6 +89,34 @@ hipError_t launch_hec_attach(int n, const int32_t* h, const uint8_t* state, cons
                              int32_t* rootseed, int32_t* flags, hipStream_t s);
 hipError_t launch_hec_label(int n, const int32_t* rootseed, const int32_t* rank, int32_t* agg,
                             hipStream_t s);
+// Galerkin product by aggregates (levels whose aggregates have at most
+// kGalBigCap entries in their member rows): members sorted by aggregate
+// (ascending vertex inside one), their row lengths and each aggregate's
+// first member (mstart[nc] = n); moff = exclusive scan of mdeg; *emax
+// (zeroed by the caller) the most entries of one aggregate, for the
+// aggregate count *ncp (at most ncmax) read on the device; gather writes each
+// coarse row at moff[mstart[a]] of tcol/tw and its length; compact moves the
+// rows to the coarse CSR given its row pointers crp[nc + 1].
+constexpr int kGalLanes = 16;
+constexpr int kGalCap = 64;      // entries per aggregate on kGalLanes lanes
+constexpr int kGalBigCap = 512;  // ... on a wavefront; above this the level sorts
+hipError_t launch_gal_members(int n, const int32_t* agg, const int32_t* rp, unsigned long long* k0,
+                              unsigned long long* k1, int aggbits, int32_t* sort_counts, long long* sort_scan,
+                              int32_t* members, int32_t* mdeg, int32_t* mstart, int32_t* mpos, hipStream_t s);
+hipError_t launch_gal_agg_len(int ncmax, const long long* ncp, int n, int64_t nnz, const int32_t* mstart,
+                              const int32_t* moff, unsigned long long* emax, hipStream_t s);
+// (sb, sw: nnz staging of every entry's coarse column and weight in
+// aggregate-major order; big: nc ints listing the aggregates over kGalCap
+// entries, nbig their count)
+// (lanes: 1, 2, 4 or 8 per row when staging; mpos: position of each vertex
+// among the members)
+hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int lanes, const int32_t* mstart, const int32_t* mpos,
+                             const int32_t* moff, const int32_t* rp, const int32_t* col, const double* w,
+                             const int32_t* agg, int32_t* sb, double* sw, int32_t* tcol, double* tw, int32_t* rowlen,
+                             int32_t* big, unsigned* nbig, hipStream_t s);
+hipError_t launch_gal_compact(int nc, const int32_t* mstart, const int32_t* moff, const int32_t* crp,
+                              const int32_t* tcol, const double* tw, int32_t* col_out, double* w_out,
+                              hipStream_t s);
 // One round of heavy edge matching (two passes; opener[v] = -1 while v is
 // unmatched, else the vertex that opened its aggregate); alive[round] is
 // raised if any vertex was unmatched when the round began.

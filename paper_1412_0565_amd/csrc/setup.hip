@@ -363,6 +363,250 @@ __global__ void k_hem_flags(int n, const int32_t* __restrict__ opener, int32_t* 
     if (v < n) flags[v] = opener[v] == v ? 1 : 0;
 }
 
+// ------------------------------------------------- Galerkin by aggregates
+//
+// The coarse row of aggregate a collects, for every member vertex in
+// ascending index and every entry of its row in CSR order (that is, in fine
+// CSR order), the pair (b = agg(col), w); pairs with b = a are dropped and
+// equal b are summed in that order, the distinct b written in ascending
+// order.  This is the sorted-key Galerkin product without the sort: the
+// same sums in the same order, so coarse graphs are bitwise equal.  A group
+// group of lanes forms one coarse row in LDS; used on levels whose
+// aggregates have at most kGalBigCap entries (else the radix-sort path).
+
+// keys (agg << 32 | v) for the stable sort of vertices by aggregate
+__global__ void k_gal_member_keys(int n, const int32_t* __restrict__ agg, unsigned long long* __restrict__ keys) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) keys[v] = ((unsigned long long)(uint32_t)agg[v] << 32) | (uint32_t)v;
+}
+
+// members in aggregate order, their row lengths, each aggregate's first
+// member (mstart[nc] = n is written by the thread of the last member)
+__global__ void k_gal_members(int n, const unsigned long long* __restrict__ keys, const int32_t* __restrict__ rp,
+                              int32_t* __restrict__ members, int32_t* __restrict__ mdeg,
+                              int32_t* __restrict__ mstart, int32_t* __restrict__ mpos) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int v = (int)(keys[k] & 0xffffffffull);
+    const int a = (int)(keys[k] >> 32);
+    members[k] = v;
+    mpos[v] = k;
+    mdeg[k] = rp[v + 1] - rp[v];
+    if (k == 0 || (int)(keys[k - 1] >> 32) != a) mstart[a] = k;
+    if (k == n - 1) mstart[a + 1] = n;
+}
+
+// the largest number of entries of an aggregate's member rows (the
+// aggregate count read from the device)
+__global__ void k_gal_agg_len(int ncmax, const long long* __restrict__ ncp, int n, int64_t nnz,
+                              const int32_t* __restrict__ mstart, const int32_t* __restrict__ moff,
+                              unsigned long long* __restrict__ emax) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nc = (int)*ncp;
+    int e = 0;
+    if (a < nc && a < ncmax) {
+        const int k0 = mstart[a], k1 = mstart[a + 1];
+        const int64_t end = k1 >= n ? nnz : (int64_t)moff[k1];
+        e = (int)(end - moff[k0]);
+    }
+    for (int o = 32; o > 0; o >>= 1) e = max(e, __shfl_xor(e, o, kWave));
+    __shared__ int wm[kBlk / 64];
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < kBlk / 64; ++q) e = max(e, wm[q]);
+        if (e > 0) atomicMax(emax, (unsigned long long)e);
+    }
+}
+
+// every entry's (coarse column, weight) at its place in aggregate-major
+// order (member k's row starts at moff[k]); rows read in fine order, G
+// lanes per row
+template <int G>
+__global__ void k_gal_stage(int n, const int32_t* __restrict__ mpos, const int32_t* __restrict__ moff,
+                            const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            const double* __restrict__ w, const int32_t* __restrict__ agg, int32_t* __restrict__ sb,
+                            double* __restrict__ sw) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = (int)(tid / G), lane = (int)(tid & (G - 1));
+    if (v >= n) return;
+    const int r0 = rp[v], r1 = rp[v + 1];
+    const int o = moff[mpos[v]] - r0;
+    for (int e = r0 + lane; e < r1; e += G) {
+        sb[o + e] = agg[col[e]];
+        sw[o + e] = w[e];
+    }
+}
+
+// pass 1: the coarse row of an aggregate (entries staged in aggregate-major
+// order, E of them) formed by a group of G lanes in LDS and written at the
+// aggregate's entry offset in tcol/tw.  Heads are the first occurrences of
+// each coarse column (the aggregate's own dropped); a head's rank among the
+// heads orders the columns, its sum runs over the later equal entries in
+// order.  A group walks its aggregates with the next one's entries loaded
+// into registers while the current one is formed.
+
+__device__ __forceinline__ int64_t gal_entries(int a, int n, int64_t nnz, const int32_t* __restrict__ mstart,
+                                               const int32_t* __restrict__ moff, int64_t* o0) {
+    const int k1 = mstart[a + 1];
+    *o0 = moff[mstart[a]];
+    return (k1 >= n ? nnz : (int64_t)moff[k1]) - *o0;
+}
+
+// A group's lanes share LDS within one wavefront, whose LDS operations
+// complete in program order: keeping the compiler from moving LDS accesses
+// across this point is all the ordering needed.
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// one aggregate's entries, lane-strided, in registers (R = CAP / G)
+template <int G, int R>
+struct GalRegs {
+    int32_t b[R];
+    double w[R];
+    int E, a;
+    int64_t o0;
+    __device__ __forceinline__ void load(int a_, int n, int64_t nnz, const int32_t* __restrict__ mstart,
+                                         const int32_t* __restrict__ moff, const int32_t* __restrict__ gb,
+                                         const double* __restrict__ gw, int lane, int cap) {
+        a = a_;
+        E = (int)gal_entries(a, n, nnz, mstart, moff, &o0);
+        if (E > cap) return;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int t = lane + r * G;
+            if (t < E) {
+                b[r] = gb[o0 + t];
+                w[r] = gw[o0 + t];
+            }
+        }
+    }
+    __device__ __forceinline__ void to_lds(int32_t* b_, double* w_, int lane) const {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int t = lane + r * G;
+            if (t < E) {
+                b_[t] = b[r];
+                w_[t] = w[r];
+            }
+        }
+    }
+};
+
+template <int G>
+__device__ __forceinline__ int gal_form(int a, int E, int64_t o0, int lane, const int32_t* b_, const double* w_,
+                                        uint8_t* h_, int32_t* __restrict__ tcol, double* __restrict__ tw) {
+    for (int t = lane; t < E; t += G) {
+        const int b = b_[t];
+        bool head = b != a;
+        for (int u = 0; u < t && head; ++u) head = b_[u] != b;
+        h_[t] = head ? 1 : 0;
+    }
+    wave_sync_lds();
+    int cnt = 0;
+    for (int t = lane; t < E; t += G) {
+        if (!h_[t]) continue;
+        const int b = b_[t];
+        int rank = 0;
+        double sum = 0.0;
+        for (int u = 0; u < E; ++u) {
+            rank += (h_[u] && b_[u] < b) ? 1 : 0;
+            if (u >= t && b_[u] == b) sum += w_[u];  // in fine CSR order
+        }
+        tcol[o0 + rank] = b;
+        tw[o0 + rank] = sum;
+        ++cnt;
+    }
+    for (int o = G >> 1; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, kWave);
+    return cnt;
+}
+
+// aggregates of at most kGalCap entries, kGalLanes lanes each, striding over
+// the aggregates; larger ones go to a list for k_gal_big
+__global__ void __launch_bounds__(kBlk) k_gal_gather(int nc, int n, int64_t nnz, const int32_t* __restrict__ mstart,
+                                                     const int32_t* __restrict__ moff,
+                                                     const int32_t* __restrict__ gb, const double* __restrict__ gw,
+                                                     int32_t* __restrict__ tcol, double* __restrict__ tw,
+                                                     int32_t* __restrict__ rowlen, int32_t* __restrict__ big,
+                                                     unsigned* __restrict__ nbig) {
+    constexpr int G = kGalLanes, R = kGalCap / kGalLanes;
+    __shared__ int32_t sb[kBlk / G][kGalCap];
+    __shared__ double sw[kBlk / G][kGalCap];
+    __shared__ uint8_t sh[kBlk / G][kGalCap];
+    const int grp = threadIdx.x / G, lane = threadIdx.x & (G - 1);
+    const int stride = gridDim.x * (kBlk / G);
+    int a = blockIdx.x * (kBlk / G) + grp;
+    GalRegs<G, R> cur;
+    if (a < nc) cur.load(a, n, nnz, mstart, moff, gb, gw, lane, kGalCap);
+    for (; a < nc; a += stride) {
+        wave_sync_lds();  // the previous aggregate's LDS reads are done
+        if (cur.E <= kGalCap) cur.to_lds(sb[grp], sw[grp], lane);
+        const int a2 = a + stride;
+        GalRegs<G, R> nxt;
+        nxt.E = 0;
+        if (a2 < nc) nxt.load(a2, n, nnz, mstart, moff, gb, gw, lane, kGalCap);
+        if (cur.E > kGalCap) {
+            if (lane == 0) big[atomicAdd(nbig, 1u)] = a;
+        } else {
+            wave_sync_lds();
+            const int cnt = gal_form<G>(a, cur.E, cur.o0, lane, sb[grp], sw[grp], sh[grp], tcol, tw);
+            if (lane == 0) rowlen[a] = cnt;
+        }
+        cur = nxt;
+    }
+}
+
+// the listed aggregates (at most kGalBigCap entries), a wavefront each,
+// wavefronts striding over the list
+__global__ void __launch_bounds__(kBlk) k_gal_big(int n, int64_t nnz, const int32_t* __restrict__ mstart,
+                                                  const int32_t* __restrict__ moff, const int32_t* __restrict__ gb,
+                                                  const double* __restrict__ gw, const int32_t* __restrict__ big,
+                                                  const unsigned* __restrict__ nbig, int32_t* __restrict__ tcol,
+                                                  double* __restrict__ tw, int32_t* __restrict__ rowlen) {
+    constexpr int R = kGalBigCap / kWave;
+    __shared__ int32_t sb[kBlk / kWave][kGalBigCap];
+    __shared__ double sw[kBlk / kWave][kGalBigCap];
+    __shared__ uint8_t sh[kBlk / kWave][kGalBigCap];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int count = (int)*nbig;
+    const int stride = gridDim.x * (kBlk / kWave);
+    int q = blockIdx.x * (kBlk / kWave) + wv;
+    GalRegs<kWave, R> cur;
+    if (q < count) cur.load(big[q], n, nnz, mstart, moff, gb, gw, lane, kGalBigCap);
+    for (; q < count; q += stride) {
+        wave_sync_lds();
+        cur.to_lds(sb[wv], sw[wv], lane);
+        GalRegs<kWave, R> nxt;
+        nxt.E = 0;
+        if (q + stride < count) nxt.load(big[q + stride], n, nnz, mstart, moff, gb, gw, lane, kGalBigCap);
+        wave_sync_lds();
+        const int cnt = gal_form<kWave>(cur.a, cur.E, cur.o0, lane, sb[wv], sw[wv], sh[wv], tcol, tw);
+        if (lane == 0) rowlen[cur.a] = cnt;
+        cur = nxt;
+    }
+}
+
+// pass 2: the rows into the coarse CSR (row pointers from the scan of
+// rowlen), kGalCompactLanes lanes per row
+constexpr int kGalCompactLanes = 16;
+__global__ void k_gal_compact(int nc, const int32_t* __restrict__ mstart, const int32_t* __restrict__ moff,
+                              const int32_t* __restrict__ crp, const int32_t* __restrict__ tcol,
+                              const double* __restrict__ tw, int32_t* __restrict__ col_out,
+                              double* __restrict__ w_out) {
+    constexpr int G = kGalCompactLanes;
+    const int a = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G);
+    const int lane = threadIdx.x & (G - 1);
+    if (a >= nc) return;
+    const int base = moff[mstart[a]];
+    const int o = crp[a], len = crp[a + 1] - o;
+    for (int t = lane; t < len; t += G) {
+        col_out[o + t] = tcol[base + t];
+        w_out[o + t] = tw[base + t];
+    }
+}
+
 // ------------------------------------------------------------------ scan
 
 constexpr int kScanItems = 8;
@@ -854,6 +1098,54 @@ hipError_t launch_hem_round(int n, const int32_t* rp, const int32_t* col, const 
     hipLaunchKernelGGL(k_hem_scan, dim3(nb), dim3(kBlk), 0, s, n, rp, col, seed, level, opener, live, mkey, alive,
                        round);
     hipLaunchKernelGGL(k_hem_match, dim3(nb), dim3(kBlk), 0, s, n, rp, col, w, seed, level, live, mkey, opener);
+    return hipGetLastError();
+}
+
+hipError_t launch_gal_members(int n, const int32_t* agg, const int32_t* rp, unsigned long long* k0,
+                              unsigned long long* k1, int aggbits, int32_t* sort_counts, long long* sort_scan,
+                              int32_t* members, int32_t* mdeg, int32_t* mstart, int32_t* mpos, hipStream_t s) {
+    hipLaunchKernelGGL(k_gal_member_keys, dim3(nblocks(n, kBlk)), dim3(kBlk), 0, s, n, agg, k0);
+    int second = 0;
+    hipError_t e = launch_sort(k0, nullptr, k1, nullptr, n, 32, aggbits, sort_counts, sort_scan, &second, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gal_members, dim3(nblocks(n, kBlk)), dim3(kBlk), 0, s, n, second ? k1 : k0, rp, members,
+                       mdeg, mstart, mpos);
+    return hipGetLastError();
+}
+
+hipError_t launch_gal_agg_len(int ncmax, const long long* ncp, int n, int64_t nnz, const int32_t* mstart,
+                              const int32_t* moff, unsigned long long* emax, hipStream_t s) {
+    hipLaunchKernelGGL(k_gal_agg_len, dim3(nblocks(ncmax, kBlk)), dim3(kBlk), 0, s, ncmax, ncp, n, nnz, mstart, moff,
+                       emax);
+    return hipGetLastError();
+}
+
+hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int lanes, const int32_t* mstart, const int32_t* mpos,
+                             const int32_t* moff, const int32_t* rp, const int32_t* col, const double* w,
+                             const int32_t* agg, int32_t* sb, double* sw, int32_t* tcol, double* tw, int32_t* rowlen,
+                             int32_t* big, unsigned* nbig, hipStream_t s) {
+    const unsigned sb_blocks = nblocks((int64_t)n * lanes, kBlk);
+    switch (lanes) {
+        case 1: hipLaunchKernelGGL(k_gal_stage<1>, dim3(sb_blocks), dim3(kBlk), 0, s, n, mpos, moff, rp, col, w, agg, sb, sw); break;
+        case 2: hipLaunchKernelGGL(k_gal_stage<2>, dim3(sb_blocks), dim3(kBlk), 0, s, n, mpos, moff, rp, col, w, agg, sb, sw); break;
+        case 4: hipLaunchKernelGGL(k_gal_stage<4>, dim3(sb_blocks), dim3(kBlk), 0, s, n, mpos, moff, rp, col, w, agg, sb, sw); break;
+        case 8: hipLaunchKernelGGL(k_gal_stage<8>, dim3(sb_blocks), dim3(kBlk), 0, s, n, mpos, moff, rp, col, w, agg, sb, sw); break;
+        default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlk), 0, s, nbig, 0u, (int64_t)1);
+    const unsigned gb_blocks = std::min<unsigned>(nblocks(nc, kBlk / kGalLanes), 256u * 8u);
+    hipLaunchKernelGGL(k_gal_gather, dim3(gb_blocks), dim3(kBlk), 0, s, nc, n, nnz, mstart, moff,
+                       (const int32_t*)sb, (const double*)sw, tcol, tw, rowlen, big, nbig);
+    hipLaunchKernelGGL(k_gal_big, dim3(1024), dim3(kBlk), 0, s, n, nnz, mstart, moff, (const int32_t*)sb,
+                       (const double*)sw, (const int32_t*)big, (const unsigned*)nbig, tcol, tw, rowlen);
+    return hipGetLastError();
+}
+
+hipError_t launch_gal_compact(int nc, const int32_t* mstart, const int32_t* moff, const int32_t* crp,
+                              const int32_t* tcol, const double* tw, int32_t* col_out, double* w_out,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_gal_compact, dim3(nblocks((int64_t)nc * kGalCompactLanes, kBlk)), dim3(kBlk), 0, s, nc, mstart,
+                       moff, crp, tcol, tw, col_out, w_out);
     return hipGetLastError();
 }
 

@@ -514,3 +514,23 @@ def test_block_register_rows_and_csr_agree_with_oracle(name):
         elif name in ("rgg20k", "grid128", "grid3d_20"):
             assert any(l.block_regs > 0 for l in levels if l.in_block)
         assert_fp64_parity(g, lam, x, st, levels, arrays, ref)
+
+
+@pytest.mark.parametrize("name", ["grid128", "rgg60k", "cl30k", "grid3d_20", "real_rgg"])
+def test_galerkin_gather_and_sort_agree(name):
+    # coarse rows formed per aggregate (default where aggregates are small)
+    # and by the radix sort (galerkin=1) sum in the same fine CSR order:
+    # both hierarchies bitwise equal to the oracle's, real weights included
+    if name == "real_rgg":
+        g = G.rgg(40000, 10.0, seed=12, int_weights=False)
+        rng = np.random.default_rng(3)
+        r = rng.random(g.m) + 0.1
+        u, v, _ = g.edges()
+        g = G.from_edges(g.n, u, v, r)
+    else:
+        g = _named(name)
+    ref = oracle_of(g)
+    for mode in (0, 1):
+        lam, x, st, levels, arrays = run_gpu(g, galerkin=mode)
+        # g = 2 max degree sums real weights in another order than the oracle
+        assert_fp64_parity(g, lam, x, st, levels, arrays, ref, exact_g=name != "real_rgg")

@@ -766,12 +766,13 @@ constexpr int kChunkEvents = 16;
 
 // Default workgroup count: about 2k rows+entries per workgroup (short
 // per-group latency chains on mid-size levels), a multiple of 8, at most
-// 3 per CU for levels whose step fits the 256 MB last-level cache (there
-// the cost of the grid barrier, which grows with the workgroup count,
-// outweighs more waves) and at most what can be co-resident.
+// 3 per CU (on levels whose step fits the 256 MB last-level cache the cost
+// of the grid barrier, which grows with the workgroup count, outweighs
+// more waves; on the streaming levels of a 256^3 grid 3 per CU also beat 4:
+// level 0 2.46 against 3.04 ms for 5 steps) and at most what can be
+// co-resident.
 int default_grid(const HostLevel& L, int j, int ncu) {
-    int cap = grid_cap(L, j, L.lanes);
-    if (step_bytes(L) <= ((int64_t)256 << 20)) cap = std::min(cap, 3 * ncu);
+    int cap = std::min(grid_cap(L, j, L.lanes), 3 * ncu);
     // about 2k rows + entries per workgroup; on mid-size levels (up to 4M
     // rows + entries) no more than sqrt(work)/4.5 workgroups, since there the
     // barrier's cost, which grows with the count, outweighs the step's work

@@ -116,14 +116,16 @@ def launch_bytes(levels, j=0):
 
 
 def serve_leg(args):
-    """Served stream: requests drawn from a seeded pool of graphs (sizes
-    log-uniform over 1k-1M vertices; 2D grids, RGGs, Chung-Lu; integer
-    weights), Poisson arrivals at 0.7x the closed-loop throughput of the
-    plain FP64 one-at-a-time path.  The same stream is replayed through the
-    server twice: plain FP64 with batches of one, and mixed precision with
+    """Served stream shaped like the paper-derived serving workload: requests
+    drawn from a seeded pool of graphs (sizes log-uniform over 1k-1M
+    vertices; 2D grids, RGGs, Chung-Lu; integer weights), Poisson arrivals
+    at 0.7x the closed-loop throughput of the plain FP64 one-at-a-time path.
+    The same stream is replayed through the server twice: plain FP64 with
+    batches of one in arrival order, and mixed precision with cost-aware
     continuous batching (up to 64 graphs per packed launch).  Hierarchies
     stay resident (LRU) under an HBM budget small enough for admission to
-    bind."""
+    bind.  A no-repeat variant sends every pool graph once (every request
+    builds its hierarchy)."""
     import numpy as np
 
     from paper_1412_0565_amd import cmg
@@ -149,22 +151,28 @@ def serve_leg(args):
     qps = 0.7 * x_fp64
     budget = int(args.serve_budget_gb * (1 << 30))
     backend = CmgBackend()
-    res = {"pool": len(pool), "requests": args.serve_requests, "qps": round(qps, 2),
-           "closed_loop_fp64_solves_per_s": round(x_fp64, 2), "budget_bytes": budget}
-    for label, prec, maxb in [("fp64_sequential", 0, 1), ("mixed_batched", 1, 64)]:
+    res = {"pool": len(pool), "requests": args.serve_requests,
+           "requests_note": f"{args.serve_requests} requests per path (the serving workload names 10,000; "
+                            f"reduced to keep the run to minutes)",
+           "qps": round(qps, 2), "closed_loop_fp64_solves_per_s": round(x_fp64, 2), "budget_bytes": budget}
+    legs = [("fp64_sequential", 0, 1, "fifo", list(picks)), ("mixed_batched", 1, 64, "cost", list(picks)),
+            ("mixed_batched_no_repeat", 1, 64, "cost", list(range(min(args.serve_norepeat, len(pool)))))]
+    for label, prec, maxb, policy, order in legs:
         stream = [Request(i, pool[int(p)][0], pool[int(p)][1].n, pool[int(p)][1].row_ptr, pool[int(p)][1].col,
-                          pool[int(p)][1].w, precision=prec) for i, p in enumerate(picks)]
-        srv = Server(backend, budget_bytes=budget, max_batch=maxb)
+                          pool[int(p)][1].w, precision=prec) for i, p in enumerate(order)]
+        srv = Server(backend, budget_bytes=budget, max_batch=maxb, policy=policy)
         log(f"[serve] {label}: {len(stream)} requests at {qps:.1f}/s")
         try:
             replay(srv, stream, qps=qps, seed=7,
-                   progress=lambda d, tot: log(f"[serve] {label}: {d}/{tot} completed"))
+                   progress=lambda d, tot: log(f"[serve] {label}: {d}/{tot} completed"), every=100)
         finally:
             srv.close()
         summ = latency_summary(stream)
+        summ["requests"] = len(stream)
         summ["mean_batch"] = round(float(np.mean(srv.batches)), 2) if srv.batches else 0.0
         summ["max_batch"] = int(max(srv.batches)) if srv.batches else 0
         summ["peak_reserved_bytes"] = int(srv.peak)
+        summ["evictions"] = int(srv.evictions)
         summ["failed"] = sum(r.status != "done" for r in stream)
         for r in stream:
             if r.status != "done":
@@ -172,6 +180,93 @@ def serve_leg(args):
         res[label] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
         log(f"[serve] {label}: {res[label]}")
     return res
+
+
+def extras_leg(args, g, g_dev, opts):
+    """The next rows built beside the hot path, on the same workload:
+    Algorithm 4's fixed schedule replayed from a captured HIP graph, heavy
+    edge matching against HEC, several eigenpairs, recursive bisection."""
+    import numpy as np
+    import torch
+
+    from paper_1412_0565_amd import cmg
+    from paper_1412_0565_amd import graphs as G
+
+    x = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    out = {}
+
+    def resident_rate(opt, reps=10):
+        h = cmg.cmg_setup(g.n, *g_dev, opt)
+        try:
+            for _ in range(2):
+                cmg.cmg_fiedler(h, x)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                lam, _ = cmg.cmg_fiedler(h, x)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t) / reps
+            st = cmg.cmg_stats()
+            st.struct_size = C.sizeof(cmg.cmg_stats)
+            cmg.cmg_fiedler(h, x, st)
+            levels = cmg.cmg_level_info(h)
+            return el, lam, st, levels, st.setup_ms
+        finally:
+            cmg.cmg_free(h)
+
+    # fixed schedule k_j = ceil(3 * 1.6^j), graph replay
+    el, lam, st, levels, _ = resident_rate(opts(precision=cmg.CMG_FP64, fixed_k0=3, fixed_beta=1.6, graph=1))
+    out["fixed_schedule"] = {"k0": 3, "beta": 1.6, "steps": [L.k for L in levels],
+                             "resident_solves_per_s": round(1.0 / el, 2), "lambda": lam,
+                             "residual": st.residual, "graph_replay": True}
+    log(f"[extras] fixed schedule: {1.0 / el:.2f} resident solves/s lambda {lam:.12e} residual {st.residual:.3e}")
+    # coarsening ablation: HEC against heavy edge matching
+    abl = {}
+    for label, cz in [("hec", 0), ("hem", 1)]:
+        t = time.perf_counter()
+        h = cmg.cmg_setup(g.n, *g_dev, opts(precision=cmg.CMG_FP64, coarsen=cz))
+        torch.cuda.synchronize()
+        setup_ms = 1e3 * (time.perf_counter() - t)
+        try:
+            st = cmg.cmg_stats()
+            st.struct_size = C.sizeof(cmg.cmg_stats)
+            t = time.perf_counter()
+            lam, _ = cmg.cmg_fiedler(h, x, st)
+            solve_ms = 1e3 * (time.perf_counter() - t)
+            levels = cmg.cmg_level_info(h)
+        finally:
+            cmg.cmg_free(h)
+        abl[label] = {"levels": len(levels), "sizes": [L.n for L in levels][:6], "setup_ms": round(setup_ms, 2),
+                      "solve_ms": round(solve_ms, 2), "lambda": lam, "residual": st.residual}
+        log(f"[extras] {label}: {len(levels)} levels setup {setup_ms:.1f} ms solve {solve_ms:.1f} ms "
+            f"lambda {lam:.10e} residual {st.residual:.3e}")
+    out["coarsening_ablation"] = abl
+    # several eigenpairs
+    h = cmg.cmg_setup(g.n, *g_dev, opts(precision=cmg.CMG_FP64))
+    try:
+        X = torch.zeros(4 * g.n, dtype=torch.float64, device="cuda")
+        cmg.cmg_fiedler_block(h, 4, X)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lams, res, steps, _ = cmg.cmg_fiedler_block(h, 4, X)
+        torch.cuda.synchronize()
+        out["block_p4"] = {"ms": round(1e3 * (time.perf_counter() - t), 2), "lambdas": [float(v) for v in lams],
+                           "residuals": [float(v) for v in res], "steps": steps}
+        log(f"[extras] block p=4: {out['block_p4']['ms']} ms lambdas {lams}")
+        del X
+    finally:
+        cmg.cmg_free(h)
+    # recursive spectral bisection, 16 parts
+    part = torch.zeros(g.n, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, cut = cmg.cmg_bisect(g.n, *g_dev, 4, part=part, opt=opts(precision=cmg.CMG_FP64))
+    torch.cuda.synchronize()
+    sizes = torch.bincount(part.long(), minlength=16).cpu().numpy()
+    out["bisection_16"] = {"ms": round(1e3 * (time.perf_counter() - t), 1), "cut": cut,
+                           "part_sizes_min_max": [int(sizes.min()), int(sizes.max())]}
+    log(f"[extras] bisection into 16: {out['bisection_16']}")
+    return out
 
 
 def main():
@@ -185,9 +280,11 @@ def main():
                     help="oracle solves for the CPU baseline (0: about 10-30 s of work for the workload)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-pool", type=int, default=12)
-    ap.add_argument("--serve-requests", type=int, default=120)
-    ap.add_argument("--serve-budget-gb", type=float, default=4.0)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--serve-pool", type=int, default=100)
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-norepeat", type=int, default=100)
+    ap.add_argument("--serve-budget-gb", type=float, default=2.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="finish with one device-to-device copy of this many MiB (the reference kernel that "
                          "scales the HBM byte counters)")
@@ -320,6 +417,7 @@ def main():
                "lambda": r.lam, "lambda_rel_diff_gpu": abs(r.lam - lams[-1]) / abs(r.lam)}
         log(f"[bench] cpu oracle: {reps} solves in {el_cpu:.2f}s")
 
+    extras = None if args.no_extras else extras_leg(args, g, g_dev, opts)
     serve = None if args.no_serve else serve_leg(args)
 
     out = {
@@ -346,6 +444,7 @@ def main():
         "residual": st.residual,
         "footprint_bytes": fp,
         "mixed": mixed,
+        "extras": extras,
         "serve": serve,
     }
     if args.copy_mib > 0:

@@ -4,14 +4,26 @@ Requests (a graph and its id) arrive at any time.  The server
 
 * admits a request when its device-memory footprint fits the budget next to
   everything already resident or in flight (admission by HBM footprint);
-* builds its hierarchy (``cmg_setup``) on a setup worker with its own HIP
-  stream, overlapping the solves of earlier requests;
-* solves every request whose hierarchy is ready in the next packed batch
-  (``cmg_fiedler_batch``), so requests that arrive while a batch is on the
-  GPU join the following one (continuous batching, not a queue);
+* builds its hierarchy (``cmg_setup``) on a setup thread while the solve
+  thread solves earlier requests.  Both issue their work to one HIP stream:
+  a solve's grid levels wait at grid barriers for all their workgroups, and
+  setup kernels from a second stream could hold compute units long enough
+  to exhaust the barrier's bounded wait.  The host-side work of the two
+  threads overlaps; the device runs their kernels in issue order;
+* solves the ready requests in packed batches (``cmg_fiedler_batch``), so
+  requests that arrive while a batch is on the GPU join a following one
+  (continuous batching, not a queue).  A batch returns when its longest
+  solve ends, so batches are formed by expected cost: the cheapest ready
+  request first (shortest job first, with requests that waited longer than
+  ``max_wait_s`` taken first), then others of at most ``cost_ratio`` times
+  its cost.  The cost of a graph is its last measured solve time, or an
+  estimate from its size before the first;
 * keeps hierarchies resident, keyed by graph id, and evicts the least
   recently used ones that are not in use when memory is needed, so a repeat
   graph skips the setup phase;
+* honours a per-request deadline (``timeout_s``) and ``cancel``: a request
+  that expires or is cancelled before its batch starts is dropped with
+  status "timeout" or "cancelled"; one already on the GPU completes;
 * records arrival, admission, setup, and completion times per request.
 
 The solve results equal those of a solo ``cmg_fiedler`` bit for bit: the
@@ -49,7 +61,12 @@ class Request:
     status: str = "queued"
     error: str = ""
     resident_hit: bool = False
+    timeout_s: float | None = None  # deadline after arrival; None: none
+    cancelled: bool = False
     event: threading.Event = dataclasses.field(default_factory=threading.Event)
+
+    def expired(self, now: float) -> bool:
+        return self.timeout_s is not None and now - self.t_arrive > self.timeout_s
 
     @property
     def latency(self) -> float:
@@ -106,12 +123,25 @@ class CmgBackend:
         self.cmg.cmg_free(h)
 
 
+def estimate_cost(n: int, nnz: int) -> float:
+    """Seconds a first solve of an unseen graph is expected to take: a
+    launch floor plus streaming its levels a few hundred times (an upper
+    estimate; measured times replace it)."""
+    return 2e-3 + 400 * 16.0 * nnz / 2e12
+
+
 class Server:
-    def __init__(self, backend, budget_bytes: int, max_batch: int = 64, resident_cap: int | None = None):
+    def __init__(self, backend, budget_bytes: int, max_batch: int = 64, resident_cap: int | None = None,
+                 cost_ratio: float = 2.0, max_wait_s: float = 0.5, policy: str = "cost"):
         self.backend = backend
         self.budget = int(budget_bytes)
         self.max_batch = max_batch
         self.resident_cap = resident_cap
+        self.cost_ratio = cost_ratio
+        self.max_wait_s = max_wait_s
+        self.policy = policy                   # "cost" (cost-aware batches) or "fifo" (arrival order)
+        self.cost = {}                         # graph_id -> last measured solve seconds
+        self.evictions = 0
         self.lock = threading.Condition()
         self.pending = collections.deque()     # arrived, not admitted
         self.setup_q = collections.deque()     # admitted, waiting for setup
@@ -137,6 +167,13 @@ class Server:
             self.lock.notify_all()
         return req
 
+    def cancel(self, req: Request) -> None:
+        """Drop `req` unless its batch has started (then it completes)."""
+        with self.lock:
+            req.cancelled = True
+            self._drop_stale(time.perf_counter())
+            self.lock.notify_all()
+
     def close(self):
         with self.lock:
             self.stop = True
@@ -148,6 +185,65 @@ class Server:
         self.resident.clear()
 
     # ---------------------------------------------------------- internals
+    def _finish(self, req: Request, status: str, error: str = "") -> None:
+        req.status = status
+        req.error = error
+        req.t_done = time.perf_counter()
+        req.event.set()
+        self.done.append(req)
+
+    def _drop_stale(self, now: float) -> None:
+        """Cancelled or expired requests leave the pending and ready queues
+        (caller holds the lock); a ready one gives back its residency use."""
+        for q in (self.pending, self.ready):
+            keep = collections.deque()
+            for req in q:
+                if req.cancelled or req.expired(now):
+                    if q is self.ready:
+                        ent = self.resident.get(req.graph_id)
+                        if ent is not None:
+                            ent[2] -= 1
+                    self._finish(req, "cancelled" if req.cancelled else "timeout")
+                else:
+                    keep.append(req)
+            q.clear()
+            q.extend(keep)
+
+    def _req_cost(self, req: Request) -> float:
+        c = self.cost.get(req.graph_id)
+        return c if c is not None else estimate_cost(req.n, int(req.col.shape[0]))
+
+    def _pick_batch(self, now: float):
+        """Cost-aware batch (caller holds the lock): the cheapest ready
+        request, or the longest-waiting one past max_wait_s, then other
+        ready requests of at most cost_ratio times its cost, one per
+        hierarchy, up to max_batch."""
+        ready = list(self.ready)
+        if self.policy == "fifo":  # arrival order, one solve per hierarchy
+            batch, seen = [], set()
+            for r in ready:
+                if len(batch) >= self.max_batch:
+                    break
+                if r.graph_id not in seen:
+                    seen.add(r.graph_id)
+                    batch.append(r)
+            return batch
+        late = [r for r in ready if now - r.t_arrive > self.max_wait_s]
+        if late:
+            first = min(late, key=lambda r: r.t_arrive)
+        else:
+            first = min(ready, key=lambda r: (self._req_cost(r), r.t_arrive))
+        limit = self.cost_ratio * self._req_cost(first)
+        batch, seen = [first], {first.graph_id}
+        for r in sorted(ready, key=lambda r: (self._req_cost(r), r.t_arrive)):
+            if len(batch) >= self.max_batch:
+                break
+            if r is first or r.graph_id in seen or self._req_cost(r) > limit:
+                continue
+            seen.add(r.graph_id)
+            batch.append(r)
+        return batch
+
     def _evict_for(self, need: int) -> bool:
         """Free least recently used idle hierarchies until `need` fits."""
         while self.used + self.reserved + need > self.budget:
@@ -161,10 +257,12 @@ class Server:
             h, b, _ = self.resident.pop(victim)
             self.backend.free(h)
             self.used -= b
+            self.evictions += 1
         return True
 
     def _admit(self):
         """Admission by footprint, in arrival order (caller holds the lock)."""
+        self._drop_stale(time.perf_counter())
         while self.pending:
             req = self.pending[0]
             if req.graph_id in self.resident:
@@ -204,6 +302,12 @@ class Server:
                 if self.stop and not self.setup_q:
                     return
                 req = self.setup_q.popleft()
+                if req.cancelled or req.expired(time.perf_counter()):
+                    self.reserved -= req._reserved
+                    self._finish(req, "cancelled" if req.cancelled else "timeout")
+                    self._admit()
+                    self.lock.notify_all()
+                    continue
             try:
                 h, nbytes = self.backend.setup(req)
                 err = None
@@ -238,22 +342,16 @@ class Server:
                     self.lock.wait()
                 if self.stop and not self.ready and not self.setup_q and not self.pending:
                     return
+                self._drop_stale(time.perf_counter())
                 if not self.ready:
                     self.lock.wait(0.01)
                     continue
-                batch = []
-                seen = set()
-                for req in list(self.ready):
-                    if len(batch) >= self.max_batch:
-                        break
-                    if req.graph_id in seen:  # one solve per hierarchy per batch
-                        continue
-                    seen.add(req.graph_id)
-                    batch.append(req)
+                batch = self._pick_batch(time.perf_counter())
                 for req in batch:
                     self.ready.remove(req)
                     req.status = "solving"
                 handles = [self.resident[r.graph_id][0] for r in batch]
+            t0 = time.perf_counter()
             try:
                 lams, xs = self.backend.solve(handles, [r.n for r in batch])
                 err = None
@@ -262,6 +360,11 @@ class Server:
             now = time.perf_counter()
             with self.lock:
                 self.batches.append(len(batch))
+                if err is None and len(batch) == 1:  # a solo solve measures the graph's cost
+                    self.cost[batch[0].graph_id] = now - t0
+                elif err is None:
+                    for r in batch:  # a batch bounds each member's cost from above
+                        self.cost.setdefault(r.graph_id, now - t0)
                 for req, lam, x in zip(batch, lams, xs):
                     req.lam, req.x = lam, x
                     req.t_done = now
@@ -284,6 +387,7 @@ class Server:
                 self.resident.pop(gid)
                 self.backend.free(h)
                 self.used -= b
+                self.evictions += 1
                 return True
         return False
 
@@ -292,6 +396,7 @@ def latency_summary(reqs) -> dict:
     lat = np.array([r.latency for r in reqs if r.status == "done"])
     if lat.size == 0:
         return {"completed": 0}
+    small = [r.latency for r in reqs if r.status == "done" and r.n <= 100_000]
     t0 = min(r.t_arrive for r in reqs)
     t1 = max(r.t_done for r in reqs)
     return {
@@ -301,6 +406,7 @@ def latency_summary(reqs) -> dict:
         "mean_ms": float(lat.mean() * 1e3),
         "solves_per_s": float(lat.size / (t1 - t0)),
         "resident_hit_rate": float(np.mean([r.resident_hit for r in reqs if r.status == "done"])),
+        "p99_small_ms": float(np.percentile(small, 99) * 1e3) if small else None,  # graphs <= 100k vertices
     }
 
 

@@ -134,3 +134,63 @@ def test_replay_poisson_and_summary():
     s = latency_summary(stream)
     assert s["completed"] == 40 and s["p99_ms"] >= s["p50_ms"] > 0
     assert 0.5 < s["resident_hit_rate"] <= 1.0
+
+
+def test_cancel_and_timeout_drop_requests_before_their_batch():
+    be = FakeBackend(setup_s=0.001, solve_s=0.2)
+    srv = Server(be, budget_bytes=1 << 30, max_batch=1)
+    try:
+        first = srv.submit(_req(0, "busy"))           # occupies the GPU for 0.2 s
+        time.sleep(0.05)
+        gone = srv.submit(_req(1, "gone"))
+        late = _req(2, "late")
+        late.timeout_s = 0.05
+        srv.submit(late)
+        kept = srv.submit(_req(3, "kept"))
+        srv.cancel(gone)
+        for r in (first, gone, late, kept):
+            assert r.event.wait(5)
+    finally:
+        srv.close()
+    assert first.status == "done" and kept.status == "done"
+    assert gone.status == "cancelled" and late.status == "timeout"
+    assert be.live == {} or all(v in ("busy", "kept") for v in be.live.values())
+
+
+def test_batches_group_requests_of_similar_cost():
+    be = FakeBackend(setup_s=0.001, solve_s=0.05)
+    srv = Server(be, budget_bytes=1 << 30, max_batch=8, cost_ratio=2.0, max_wait_s=10.0)
+    try:
+        # measured costs: two cheap graphs and one expensive one
+        srv.cost.update({"cheap1": 0.001, "cheap2": 0.0015, "dear": 0.2})
+        blocker = srv.submit(_req(0, "blocker"))
+        time.sleep(0.01)
+        reqs = [srv.submit(_req(i + 1, g)) for i, g in enumerate(["dear", "cheap1", "cheap2"])]
+        for r in [blocker] + reqs:
+            assert r.event.wait(5)
+    finally:
+        srv.close()
+    # the cheap pair shared a batch and it ran before the expensive one
+    cheap = [r for r in reqs if r.graph_id.startswith("cheap")]
+    dear = [r for r in reqs if r.graph_id == "dear"][0]
+    assert cheap[0].t_done == cheap[1].t_done
+    assert cheap[0].t_done < dear.t_done
+    assert 2 in srv.batches
+
+
+def test_long_waiting_request_is_not_starved():
+    be = FakeBackend(setup_s=0.001, solve_s=0.02)
+    srv = Server(be, budget_bytes=1 << 30, max_batch=1, max_wait_s=0.05)
+    try:
+        srv.cost["dear"] = 1.0
+        dear = srv.submit(_req(0, "dear"))
+        cheap = []
+        for i in range(20):  # a steady supply of cheaper work
+            srv.cost[f"c{i}"] = 0.001
+            cheap.append(srv.submit(_req(i + 1, f"c{i}")))
+            time.sleep(0.01)
+        for r in [dear] + cheap:
+            assert r.event.wait(5)
+    finally:
+        srv.close()
+    assert dear.t_done < cheap[-1].t_done

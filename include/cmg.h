@@ -143,6 +143,11 @@ typedef struct {
                                     has more than 256 entries, else sorts (key, weight) pairs; 1
                                     always sorts.  Both sum in fine CSR order: coarse graphs are
                                     bitwise equal. */
+    int32_t test_abort_level;    /* tests of the barrier fallback only (default -1): the first
+                                    attempt of every solve raises the grid barrier's abort flag
+                                    before refining this level, as if its bounded wait had been
+                                    given up; every kernel then exits and the solve is re-run
+                                    with the persistent levels one launch per step. */
 } cmg_options;
 
 /* Per-level information (available after cmg_setup; PI fields after
@@ -181,6 +186,8 @@ typedef struct {
     int32_t finest_k;       /* PI steps on level 0 */
     double finest_bytes;    /* algorithmic bytes of level-0 PI: k_0 * bytes_per_iter(0) */
     int32_t status;         /* status of the last call */
+    int32_t fallback;       /* 1 if a grid barrier's wait was given up and the refinement was
+                               re-run with the persistent levels one launch per step */
 } cmg_stats;
 
 /* Fill `o` with defaults: tol 1e-8, coarsest_n 25, dense_max 128,
@@ -211,10 +218,15 @@ cmg_status cmg_setup(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
  * barriers, so all of them must be resident together (the library sizes
  * each launch to the co-resident count it measured on the idle device).  Kernels that other
  * streams keep launching on the same device can hold compute units long
- * enough that a barrier's bounded wait (2 s) ends: the call then returns
- * CMG_E_DEVICE (cmg_last_error() names the level) and the handle stays
- * usable.  Callers that overlap work should keep other kernels off the
- * device while a solve runs, e.g. by issuing both on one stream. */
+ * enough that a barrier's bounded wait (2 s) ends: every kernel of the
+ * solve then exits and the refinement is re-run with the persistent
+ * levels that traverse rows one launch per step, which needs no waits
+ * between workgroups (stats->fallback = 1; the result matches the
+ * oracle to the same tolerances).  Levels on the merge path and the
+ * finishing pass have no such form: if their wait is given up, the call
+ * returns CMG_E_DEVICE (cmg_last_error() names the level) and the handle
+ * stays usable.  Callers that overlap work should keep other kernels off
+ * the device while a solve runs, e.g. by issuing both on one stream. */
 cmg_status cmg_fiedler(cmg_handle h, double* lambda, void* x, cmg_memspace where,
                        cmg_stats* stats);
 

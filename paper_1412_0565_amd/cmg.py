@@ -61,6 +61,7 @@ class cmg_options(C.Structure):
         ("graph", C.c_int32),
         ("coarsen", C.c_int32),
         ("galerkin", C.c_int32),
+        ("test_abort_level", C.c_int32),
     ]
 
 
@@ -101,6 +102,7 @@ class cmg_stats(C.Structure):
         ("finest_k", C.c_int32),
         ("finest_bytes", C.c_double),
         ("status", C.c_int32),
+        ("fallback", C.c_int32),
     ]
 
 

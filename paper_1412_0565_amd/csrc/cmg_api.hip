@@ -61,6 +61,8 @@ struct HostLevel {
     int kfix = 0;              // fixed schedule: PI steps of this level (0: stopping test)
     int fgrid = 0;             // level 0 in step mode: finishing pass grid
     int32_t* fpart = nullptr;  // ... and its row split
+    int fbgrid = 0;            // persistent level: workgroups of its step-mode fallback
+    int32_t* fbpart = nullptr; // ... and their row split
     int k = 0;
     double margin = 0.0;
     double pi_ms = 0.0;
@@ -206,6 +208,8 @@ struct cmg_ctx {
     std::vector<hipEvent_t> events;
     // levels refined with one launch per step
     StepJob* d_step = nullptr;  // [J+1]
+    StepJob* d_step_fb = nullptr;  // [J+1]: step-mode fallback of the persistent levels
+    int fallbacks = 0;          // solves re-run one launch per step after a barrier wait was given up
     StepCtl* d_ctl = nullptr;
     double* d_part = nullptr;   // 4 partial sums per workgroup
     int* h_flags = nullptr;     // pinned: done flag after each chunk of steps
@@ -1035,16 +1039,22 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         }
         ALLOC(L.part, int32_t, L.grid + 1);
         CK(launch_partition(L.n, L.nnz, L.rp, L.grid, L.part, c->stream));
+        // a persistent rows-traversal level can be re-run one launch per step
+        // (no inter-workgroup waits) if a barrier wait is given up
+        L.fbgrid = 0;
+        if (!c->noalloc && !L.in_block && j <= top && L.variant != 2 && !L.step) {
+            const int64_t nb = ((int64_t)L.n + L.nnz + kStepWork - 1) / kStepWork;
+            L.fbgrid = (int)std::min<int64_t>(std::max<int64_t>(nb, 8), 65535);
+            ALLOC(L.fbpart, int32_t, L.fbgrid + 1);
+            CK(launch_partition(L.n, L.nnz, L.rp, L.fbgrid, L.fbpart, c->stream));
+            max_step_grid = std::max(max_step_grid, L.fbgrid);
+        }
     }
     if (max_step_grid > 0) {
         ALLOC(c->d_ctl, StepCtl, 1);
         ALLOC(c->d_part, double, 4 * (size_t)max_step_grid);
         ALLOC(c->d_step, StepJob, J + 1);
-        if (!c->h_flags) {
-            CK(hipHostMalloc((void**)&c->h_flags, sizeof(int) * kChunkEvents, hipHostMallocDefault));
-            c->chunk_ev.resize(kChunkEvents);
-            for (auto& e : c->chunk_ev) CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        }
+        ALLOC(c->d_step_fb, StepJob, J + 1);
     }
     std::vector<LevelDev> ld(J + 1);
     for (int j = 0; j <= J; ++j) ld[j] = level_dev(c->lv[j]);
@@ -1116,6 +1126,13 @@ cmg_status build_refine_plan(cmg_ctx* c) {
             sj[j] = t;
         }
         CK(hipMemcpyAsync(c->d_step, sj.data(), sizeof(StepJob) * (J + 1), hipMemcpyHostToDevice, c->stream));
+        // the fallback table: the same jobs on the step-mode row splits
+        for (int j = 0; j <= J; ++j)
+            if (c->lv[j].fbgrid > 0) {
+                sj[j].L.grid = c->lv[j].fbgrid;
+                sj[j].L.part = c->lv[j].fbpart;
+            }
+        CK(hipMemcpyAsync(c->d_step_fb, sj.data(), sizeof(StepJob) * (J + 1), hipMemcpyHostToDevice, c->stream));
     }
     c->top = top;
     // single-workgroup levels: maximal runs of levels on the same kernel,
@@ -1277,6 +1294,7 @@ void fill_defaults(cmg_options* o) {
     o->graph = 0;
     o->coarsen = 0;
     o->galerkin = 0;
+    o->test_abort_level = -1;
 }
 
 // Device results of the last solve -> host staging (asynchronous).
@@ -1371,21 +1389,27 @@ cmg_status finalize(cmg_ctx* c, double t0, bool timed, double* lambda, cmg_stats
 // on the device, so steps go out in chunks of kStepChunk with one chunk
 // queued behind the one whose done flag the host waits for.  Steps
 // launched after the stopping test passed return at once.
-cmg_status run_step_level(cmg_ctx* c, int j, hipStream_t s) {
+cmg_status ensure_flags(cmg_ctx* c);
+
+cmg_status run_step_level(cmg_ctx* c, int j, hipStream_t s, bool fallback = false) {
     const HostLevel& L = c->lv[j];
-    const StepJob* job = c->d_step + j;
+    const bool fb = fallback && !L.step;
+    const StepJob* job = (fb ? c->d_step_fb : c->d_step) + j;
+    const int grid = fb ? L.fbgrid : L.grid;
     const int kind = job_kind(L.variant, L.lanes, L.fp32);
     const int maxit = c->opt.max_iters_per_level;
-    CK(launch_step_begin(job, L.grid, kind, s));
+    CK(launch_step_begin(job, grid, kind, s));
     if (L.kfix > 0) {  // fixed schedule: the step count is known, no host checks
-        for (int i = 0; i < L.kfix; ++i) CK(launch_step_pi(job, L.grid, kind, s));
+        for (int i = 0; i < L.kfix; ++i) CK(launch_step_pi(job, grid, kind, s));
         return CMG_OK;
     }
+    cmg_status fst = ensure_flags(c);
+    if (fst != CMG_OK) return fst;
     int launched = 0, chunks = 0;
     const int chunk = kStepChunk;
     auto enqueue = [&]() -> cmg_status {
         const int q = std::min(chunk, maxit - launched);
-        for (int i = 0; i < q; ++i) CK(launch_step_pi(job, L.grid, kind, s));
+        for (int i = 0; i < q; ++i) CK(launch_step_pi(job, grid, kind, s));
         launched += q;
         CK(hipMemcpyAsync(c->h_flags + chunks % kChunkEvents, &c->d_ctl->done, sizeof(int), hipMemcpyDeviceToHost, s));
         CK(hipEventRecord(c->chunk_ev[chunks % kChunkEvents], s));
@@ -1416,17 +1440,19 @@ cmg_status run_step_level(cmg_ctx* c, int j, hipStream_t s) {
 // The launches of a solve after the coarsest solve: the single-workgroup
 // runs, the grid levels coarse to fine, the finishing pass.  timed: events
 // around each grid level (not inside a captured graph).
-cmg_status enqueue_refine(cmg_ctx* c, hipStream_t s, bool timed) {
+cmg_status enqueue_refine(cmg_ctx* c, hipStream_t s, bool timed, bool fallback = false) {
     const int J = (int)c->lv.size() - 1;
     for (size_t r = 0; r < c->h_bruns.size(); ++r) CK(launch_block_jobs(c->d_bruns + r, 1, c->brun_kind[r], s));
-    // grid levels: one persistent launch per level
+    // grid levels: one persistent launch per level (one launch per step in
+    // step mode, and on the fallback after a barrier wait was given up)
     for (int j = std::min(c->top, c->block_lo - 1); j >= 0; --j) {
         const HostLevel& L = c->lv[j];
         if (timed) CK(hipEventRecord(c->events[2 * j], s));
-        if (L.step) {
-            cmg_status st = run_step_level(c, j, s);
+        if (L.step || (fallback && L.fbgrid > 0)) {
+            cmg_status st = run_step_level(c, j, s, fallback);
             if (st != CMG_OK) return st;
         } else {
+            if (!fallback && j == c->opt.test_abort_level) CK(launch_raise_abort(c->d_sync, s));
             CK(launch_refine_jobs(c->d_jobs + j, 1, L.grid, job_kind(L.variant, L.lanes, L.fp32), s));
         }
         if (timed) CK(hipEventRecord(c->events[2 * j + 1], s));
@@ -1494,7 +1520,26 @@ cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where,
     cmg_status st = enqueue_readback(c, x, where, s);
     if (st != CMG_OK) return st;
     CK(hipStreamSynchronize(s));
-    return finalize(c, t0, !graph && !c->noalloc, lambda, stats);
+    bool fell_back = false;
+    if (c->h_gs.abort && c->d_step_fb) {
+        // a grid barrier's bounded wait was given up (workgroups of a
+        // persistent level not all resident, e.g. kernels of other streams
+        // holding compute units): every launch has exited; re-run the
+        // refinement with the persistent rows-traversal levels one launch
+        // per step, which needs no inter-workgroup waits
+        CK(launch_reset_sync(c->d_sync, c->d_slots, c->nslots, c->d_bcast, s));
+        st = enqueue_refine(c, s, !c->noalloc, true);
+        if (st != CMG_OK) return st;
+        st = enqueue_readback(c, x, where, s);
+        if (st != CMG_OK) return st;
+        CK(hipStreamSynchronize(s));
+        ++c->fallbacks;
+        fell_back = true;
+    }
+    st = finalize(c, t0, !graph && !c->noalloc, lambda, stats);
+    if (stats && stats->struct_size >= offsetof(cmg_stats, fallback) + sizeof(int32_t))
+        stats->fallback = fell_back ? 1 : 0;
+    return st;
 }
 
 // ---- several eigenpairs (Remark after Algorithm 4)

@@ -277,6 +277,8 @@ hipError_t launch_rsb_assign(int n, const double* vals, const int32_t* part, con
 hipError_t launch_rsb_cut(int n, const int32_t* rp, const int32_t* col, const double* w, const int32_t* part,
                           double* bsum, hipStream_t s);
 int rsb_cut_blocks(int n);
+// raise the abort flag of a graph's barrier state (tests of the fallback)
+hipError_t launch_raise_abort(GridSync* gs, hipStream_t s);
 // zero the barrier state and the slots (2 * nslots; at setup, and after an abort)
 hipError_t launch_reset_sync(GridSync* gs, GridSlot* slots, int nslots, GridSlot* bcast, hipStream_t s);
 

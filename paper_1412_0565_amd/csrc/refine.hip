@@ -1604,6 +1604,10 @@ __device__ __forceinline__ GridCtx make_ctx(const GridJob& J) {
 }
 
 // nslots: the slot array holds two banks of nslots
+__global__ void k_raise_abort(GridSync* gs) {
+    if (threadIdx.x == 0) atomicOr(&gs->abort, 1u);
+}
+
 __global__ void k_reset_sync(GridSync* gs, GridSlot* slots, int nslots, GridSlot* bcast) {
     nslots *= 2;
     for (int b = threadIdx.x; b < nslots; b += blockDim.x) {
@@ -2117,6 +2121,11 @@ hipError_t launch_step_pi(const StepJob* job, int nblocks, int kind, hipStream_t
 
 hipError_t launch_reset_sync(GridSync* gs, GridSlot* slots, int nslots, GridSlot* bcast, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(256), 0, s, gs, slots, nslots, bcast);
+    return hipGetLastError();
+}
+
+hipError_t launch_raise_abort(GridSync* gs, hipStream_t s) {
+    hipLaunchKernelGGL(k_raise_abort, dim3(1), dim3(64), 0, s, gs);
     return hipGetLastError();
 }
 

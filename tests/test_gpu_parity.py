@@ -534,3 +534,28 @@ def test_galerkin_gather_and_sort_agree(name):
         lam, x, st, levels, arrays = run_gpu(g, galerkin=mode)
         # g = 2 max degree sums real weights in another order than the oracle
         assert_fp64_parity(g, lam, x, st, levels, arrays, ref, exact_g=name != "real_rgg")
+
+
+@pytest.mark.parametrize("name,level", [("grid128", 0), ("rgg60k", 0), ("rgg60k", 1), ("grid3d_20", 0)])
+def test_barrier_fallback_matches_oracle(name, level):
+    # the first attempt raises the barrier's abort flag from the host before
+    # the level's persistent launch (every kernel then exits normally); the
+    # call re-runs the persistent levels one launch per step and returns the
+    # oracle's result, step counts included
+    g = _named(name)
+    ref = oracle_of(g)
+    lam, x, st, levels, arrays = run_gpu(g, test_abort_level=level)
+    say(f"[fallback] {name} level {level}: fallback={st.fallback} k {[l.k for l in levels]}")
+    assert not levels[level].in_block and not levels[level].step
+    assert st.fallback == 1
+    assert_fp64_parity(g, lam, x, st, levels, arrays, ref)
+    lam2, x2, st2, _, _ = run_gpu(g, want_levels=False)
+    assert st2.fallback == 0
+
+
+def test_barrier_fallback_mixed():
+    g = _named("rgg60k")
+    ref = oracle_of(g)
+    lam, x, st, levels, _ = run_gpu(g, want_levels=False, test_abort_level=0, precision=1, mixed_min_nnz=1)
+    assert st.fallback == 1
+    assert abs(lam - ref.lam) <= MIXED_LAM_RTOL * ref.lam

@@ -15,12 +15,25 @@
 #include <tuple>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "cmg.h"
 #include "cmg_internal.h"
 
 using namespace cmg;
 
 namespace {
+
+// roctx range around a phase (named in rocprofv3 --marker-trace output);
+// a no-op without a tool attached
+struct Range {
+    explicit Range(const char* fmt, int a = 0) {
+        char buf[64];
+        std::snprintf(buf, sizeof(buf), fmt, a);
+        roctxRangePushA(buf);
+    }
+    ~Range() { roctxRangePop(); }
+};
 
 double now_ms() {
     using namespace std::chrono;
@@ -430,6 +443,7 @@ cmg_status finish_rowinfo(cmg_ctx* c, SetupTmp& t) {
 // One HEC + Galerkin step from level j; appends level j+1 unless HEC
 // collapses (fewer than 2 aggregates).
 cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
+    Range range("cmg coarsen level %d", j);
     HostLevel& L = c->lv[j];
     hipStream_t s = c->stream;
     const uint64_t seed = c->opt.seed;
@@ -596,6 +610,7 @@ bool chain_level(const HostLevel& L) { return L.n <= kChainMaxN && L.nnz <= kCha
 // if the hierarchy is complete, else the index of a level left to the grid
 // kernels (a coarse row too long for the single-workgroup Galerkin step).
 cmg_status coarsen_chain(cmg_ctx* c, SetupTmp& t, int j0, int* next) {
+    Range range("cmg coarsen levels from %d in one workgroup", j0);
     HostLevel L = c->lv[j0];
     hipStream_t s = c->stream;
     const int max_levels = 61 - j0;  // coarsening stops at level index 60
@@ -923,6 +938,7 @@ int fixed_steps(int k0, double beta, int j, int cap) {
 }
 
 cmg_status build_refine_plan(cmg_ctx* c) {
+    Range range("cmg refinement plan");
     const int J = (int)c->lv.size() - 1;
     const cmg_options& o = c->opt;
     HostLevel& CJ = c->lv[J];
@@ -1185,6 +1201,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
 
 cmg_status setup_impl(cmg_ctx* c, int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
                       const void* w, cmg_valtype wtype, cmg_memspace where) {
+    Range range("cmg_setup");
     hipStream_t s = c->stream;
     // first arena chunk: level 0's CSR copy, vectors and refinement state
     // plus the coarser levels (together about half of level 0)
@@ -1447,6 +1464,7 @@ cmg_status enqueue_refine(cmg_ctx* c, hipStream_t s, bool timed, bool fallback =
     // step mode, and on the fallback after a barrier wait was given up)
     for (int j = std::min(c->top, c->block_lo - 1); j >= 0; --j) {
         const HostLevel& L = c->lv[j];
+        Range range("cmg refine level %d", j);
         if (timed) CK(hipEventRecord(c->events[2 * j], s));
         if (L.step || (fallback && L.fbgrid > 0)) {
             cmg_status st = run_step_level(c, j, s, fallback);
@@ -1500,6 +1518,7 @@ cmg_status capture_refine(cmg_ctx* c) {
 }
 
 cmg_status fiedler_impl(cmg_ctx* c, double* lambda, void* x, cmg_memspace where, cmg_stats* stats) {
+    Range range("cmg_fiedler");
     const double t0 = now_ms();
     hipStream_t s = c->stream;
     if (c->d_cjob && !c->coarse_done) {

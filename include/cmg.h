@@ -140,14 +140,21 @@ typedef struct {
                                     one or two vertices, so n_{j+1} >= n_j / 2), for comparison. */
     int32_t galerkin;            /* Galerkin product of the large levels: 0 (default) forms each
                                     coarse row from its aggregate's member rows where no aggregate
-                                    has more than 256 entries, else sorts (key, weight) pairs; 1
-                                    always sorts.  Both sum in fine CSR order: coarse graphs are
-                                    bitwise equal. */
+                                    has more than 1024 entries (in registers, or by a wavefront's
+                                    sort in LDS for rows with many distinct columns), else sorts
+                                    (key, weight) pairs over the level; 1 always sorts; 2 forms
+                                    every row by the wavefront's sort (to test that former).  All
+                                    sum in fine CSR order: coarse graphs are bitwise equal. */
     int32_t test_abort_level;    /* tests of the barrier fallback only (default -1): the first
                                     attempt of every solve raises the grid barrier's abort flag
                                     before refining this level, as if its bounded wait had been
                                     given up; every kernel then exits and the solve is re-run
                                     with the persistent levels one launch per step. */
+    int32_t weight_storage;      /* 0 (default): the grid and step kernels read no weights on a
+                                    level whose weights are all 1 and an FP32 copy on an FP64
+                                    level whose weights are all exact in FP32 (the same values:
+                                    results are bitwise those of FP64 storage); 1: always the
+                                    iterates' precision. */
 } cmg_options;
 
 /* Per-level information (available after cmg_setup; PI fields after
@@ -169,6 +176,9 @@ typedef struct {
     int32_t block_waves;   /* in_block: wavefronts running the PI steps (0: all) */
     int32_t block_regs;    /* in_block: rows per lane group held in registers (0: CSR reads) */
     int32_t step;          /* 1 if refined with one launch per PI step (no grid barrier) */
+    int32_t weights;       /* edge weights as the level's PI steps read them: 0 FP64, 1 FP32
+                              (mixed-precision level, or an exact FP32 copy beside FP64
+                              iterates), 2 none (every weight is 1) */
 } cmg_level_stats;
 
 typedef struct {

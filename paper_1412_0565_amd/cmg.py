@@ -62,6 +62,7 @@ class cmg_options(C.Structure):
         ("coarsen", C.c_int32),
         ("galerkin", C.c_int32),
         ("test_abort_level", C.c_int32),
+        ("weight_storage", C.c_int32),
     ]
 
 
@@ -83,6 +84,7 @@ class cmg_level_stats(C.Structure):
         ("block_waves", C.c_int32),
         ("block_regs", C.c_int32),
         ("step", C.c_int32),
+        ("weights", C.c_int32),
     ]
 
 

@@ -63,6 +63,8 @@ struct HostLevel {
     int32_t* agg = nullptr;
     double g = 0.0, wmax = 0.0;
     int w32exact = 0;
+    int wunit = 0;  // every weight is 1 (checked on the input level)
+    int wk = kWNative;  // weight storage read by the grid and step kernels
     int64_t maxlen = 0;
     int fp32 = 0, in_block = 0, lanes = 8, grid = 0, variant = 1;
     int stage = 1;  // grid levels: a workgroup's rows may be staged in LDS
@@ -495,18 +497,17 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
         CK(launch_hec_label(L.n, t.rootseed, t.rank, L.agg, s));
     }
     // Galerkin product by aggregates when no aggregate's member rows hold
-    // more than kGalCap entries: the aggregate count and the largest
+    // more than kGalWaveCap entries: the aggregate count and the largest
     // aggregate are read back in one synchronisation, the coarse rows are
-    // formed in LDS in fine CSR order; else the radix-sort path below.
+    // formed in fine CSR order; else the radix-sort path below.
     const int64_t ncmax = hem ? (int64_t)L.n : (int64_t)L.n / 2 + 1;
-    if (c->opt.galerkin == 0) {
+    if (c->opt.galerkin != 1) {
         int32_t* members = t.rootseed;
         int32_t* mdeg = t.flags;
         int32_t* mstart = t.pairseed;
         int32_t* moff = t.rank;
-        int32_t* mpos = (int32_t*)t.slot;  // n ints in the n 8-byte slots
         CK(launch_gal_members(L.n, L.agg, L.rp, t.k0, t.k1, bitlen((unsigned long long)ncmax), t.sort_counts,
-                              t.sort_scan, members, mdeg, mstart, mpos, s));
+                              t.sort_scan, members, mdeg, mstart, s));
         CK(launch_scan(mdeg, moff, L.n, t.scan_tmp, t.totals + 2, s));
         CK(launch_fill_u32((unsigned*)(t.scal + 4), 0u, 2, s));
         CK(launch_gal_agg_len((int)ncmax, t.totals, L.n, L.nnz, mstart, moff, t.scal + 4, s));
@@ -522,13 +523,20 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
             *stop = true;
             return CMG_OK;
         }
-        if (emax <= (unsigned long long)kGalBigCap) {
+        if (emax <= (unsigned long long)kGalWaveCap) {
             const int nc = (int)nc0;
             int32_t* rowlen = t.h;
             int32_t* tcol = t.idx;
             double* tw = t.v1;
-            CK(launch_gal_gather(nc, L.n, L.nnz, std::min(L.lanes, 8), mstart, mpos, moff, L.rp, L.col, L.w64,
-                                 L.agg, t.heads, t.v0, tcol, tw, rowlen, mdeg, (unsigned*)(t.scal + 5), s));
+            // a lane per aggregate with 16 register slots where fine rows are
+            // short (coarse rows rarely exceed 16 columns), else 32; on levels
+            // with few aggregates (a lane's walk would be one long chain of
+            // loads on a mostly idle device) every row by the wave sort
+            const int slots = (c->opt.galerkin == 2 || nc < kGalLaneMinRows) ? 0
+                              : L.nnz <= 7 * (int64_t)L.n                    ? 16
+                                                                             : 32;
+            CK(launch_gal_gather(nc, L.n, L.nnz, slots, members, mstart, moff, L.rp, L.col, L.w64, L.agg, tcol, tw,
+                                 rowlen, t.heads, (unsigned*)(t.scal + 5), s));
             HostLevel C;
             C.n = nc;
             ALLOC(C.rp, int32_t, nc + 1);
@@ -724,6 +732,7 @@ LevelDev level_dev(const HostLevel& L) {
     d.bslots = L.bslots;
     d.stage = L.stage;
     d.kfix = L.kfix;
+    d.wk = L.wk;
     return d;
 }
 
@@ -759,7 +768,7 @@ bool block_level(const HostLevel& L, int block_rows) {
 // Largest co-resident workgroup count of the level's kernels (a multiple
 // of 8, at least 8); level 0 also runs the finishing kernel on its grid.
 int grid_cap(const HostLevel& L, int j, int lanes) {
-    const int kind = job_kind(L.variant, lanes, L.fp32);
+    const int kind = job_kind(L.variant, lanes, L.fp32, L.wk);
     int cap = refine_jobs_max_blocks(kind);
     if (j == 0) cap = std::min(cap, finish_jobs_max_blocks(kind));
     return std::max(8, (cap / 8) * 8);
@@ -890,7 +899,7 @@ cmg_status tune_level(cmg_ctx* c, int j, int maxgrid) {
         g.uniform = 1;
         g.tag = j;
         CK(hipMemcpyAsync(dj, &g, sizeof(GridJob), hipMemcpyHostToDevice, s));
-        const int kind = job_kind(T.variant, T.lanes, T.fp32);
+        const int kind = job_kind(T.variant, T.lanes, T.fp32, T.wk);
         float ms_min = 0.f;
         for (int rep = 0; rep < 2; ++rep) {
             CK(hipEventRecord(e0, s));
@@ -1025,13 +1034,21 @@ cmg_status build_refine_plan(cmg_ctx* c) {
             L.wmax < 16777216.0 && !(j == J && c->coarse_dense))
             L.fp32 = 1;
         L.variant = choose_variant(L, o.spmv_variant);
+        // weights as the grid and step kernels read them: none where all are
+        // 1, an FP32 copy beside FP64 iterates where every weight is exact in
+        // FP32 (the same values, a third fewer bytes per entry)
+        L.wk = kWNative;
+        if (o.weight_storage == 0 && !L.in_block && j <= top && !(j == J && c->coarse_dense)) {
+            if (L.wunit) L.wk = kWUnit;
+            else if (!L.fp32 && L.w32exact) L.wk = kWF32;
+        }
         const size_t vb = L.fp32 ? 4 : 8;
         if (!(j == J && c->coarse_dense)) {  // else allocated above
             L.buf0 = c->dalloc(vb * (size_t)L.n);
             L.buf1 = c->dalloc(vb * (size_t)L.n);
             if (!L.buf0 || !L.buf1) return CMG_E_OOM;
         }
-        if (L.fp32) {
+        if (L.fp32 || L.wk == kWF32) {
             ALLOC(L.w32, float, std::max<int64_t>(L.nnz, 1));
             CK(launch_to_f32(L.nnz, L.w64, L.w32, c->stream));
         }
@@ -1244,6 +1261,7 @@ cmg_status setup_impl(cmg_ctx* c, int32_t n, int64_t nnz, const int32_t* row_ptr
     if (flags & (kBadGraph | kAsym)) return CMG_E_GRAPH;
     if (flags & kIsolated) return CMG_E_ISOLATED;
     c->int_weights = (flags & kWideWeight) == 0;
+    L0.wunit = (flags & kNonUnit) == 0;
     L0.lanes = pick_lanes(nnz / (double)n);
     c->lv.push_back(L0);
     SetupTmp t;
@@ -1413,7 +1431,7 @@ cmg_status run_step_level(cmg_ctx* c, int j, hipStream_t s, bool fallback = fals
     const bool fb = fallback && !L.step;
     const StepJob* job = (fb ? c->d_step_fb : c->d_step) + j;
     const int grid = fb ? L.fbgrid : L.grid;
-    const int kind = job_kind(L.variant, L.lanes, L.fp32);
+    const int kind = job_kind(L.variant, L.lanes, L.fp32, L.wk);
     const int maxit = c->opt.max_iters_per_level;
     CK(launch_step_begin(job, grid, kind, s));
     if (L.kfix > 0) {  // fixed schedule: the step count is known, no host checks
@@ -1471,12 +1489,12 @@ cmg_status enqueue_refine(cmg_ctx* c, hipStream_t s, bool timed, bool fallback =
             if (st != CMG_OK) return st;
         } else {
             if (!fallback && j == c->opt.test_abort_level) CK(launch_raise_abort(c->d_sync, s));
-            CK(launch_refine_jobs(c->d_jobs + j, 1, L.grid, job_kind(L.variant, L.lanes, L.fp32), s));
+            CK(launch_refine_jobs(c->d_jobs + j, 1, L.grid, job_kind(L.variant, L.lanes, L.fp32, L.wk), s));
         }
         if (timed) CK(hipEventRecord(c->events[2 * j + 1], s));
     }
     const HostLevel& L0 = c->lv[0];
-    CK(launch_finish_jobs(c->d_jobs + J + 1, 1, L0.step ? L0.fgrid : L0.grid, job_kind(L0.variant, L0.lanes, L0.fp32),
+    CK(launch_finish_jobs(c->d_jobs + J + 1, 1, L0.step ? L0.fgrid : L0.grid, job_kind(L0.variant, L0.lanes, L0.fp32, L0.wk),
                           s));
     return CMG_OK;
 }
@@ -1901,7 +1919,7 @@ cmg_status batch_impl(cmg_handle* hs, int32_t count, double* lambdas, void** xs,
         for (int jk = 0; jk < kJobKinds; ++jk) {
             std::vector<GridJob> sel;
             for (const GridJob& g : round)
-                if (job_kind(g.L.variant, g.L.lanes, g.L.fp32) == jk) sel.push_back(g);
+                if (job_kind(g.L.variant, g.L.lanes, g.L.fp32, g.L.wk) == jk) sel.push_back(g);
             const int cap = kind ? finish_jobs_max_blocks(jk) : refine_jobs_max_blocks(jk);
             size_t i = 0;
             while (i < sel.size()) {
@@ -2123,7 +2141,8 @@ cmg_status cmg_setup(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32
         o.fp64_final_sweeps < 0 || o.fp64_final_sweeps > 1 || o.coarsest_n > o.dense_max ||
         o.step_mode < -1 || o.step_mode > 1 || o.fixed_k0 < 0 ||
         (o.fixed_k0 > 0 && !(o.fixed_beta >= 1.0 && std::isfinite(o.fixed_beta))) || o.graph < 0 || o.graph > 1 ||
-        o.coarsen < 0 || o.coarsen > 1 || o.galerkin < 0 || o.galerkin > 1)
+        o.coarsen < 0 || o.coarsen > 1 || o.galerkin < 0 || o.galerkin > 2 || o.weight_storage < 0 ||
+        o.weight_storage > 1)
         return CMG_E_ARG;
     const double t0 = now_ms();
     cmg_ctx* c = new (std::nothrow) cmg_ctx;
@@ -2208,8 +2227,11 @@ cmg_status cmg_level_info(cmg_handle h, cmg_level_stats* out, int32_t cap, int32
         li.lanes = L.lanes;
         li.grid = L.grid;
         li.pi_ms = L.pi_ms;
-        double sv = L.fp32 ? 4 : 8;
-        li.bytes_per_iter = 4.0 * (L.n + 1) + (double)L.nnz * (4 + sv) + 2 * sv * L.n;
+        const double sx = L.fp32 ? 4 : 8;
+        const int wkr = L.wk == kWUnit ? 2 : (L.fp32 || L.wk == kWF32) ? 1 : 0;
+        const double sw = wkr == 2 ? 0 : wkr == 1 ? 4 : 8;
+        li.bytes_per_iter = 4.0 * (L.n + 1) + (double)L.nnz * (4 + sw) + 2 * sx * L.n;
+        li.weights = wkr;
         li.block_waves = L.bwaves;
         li.block_regs = L.bregs;
         li.step = L.step;
@@ -2265,7 +2287,7 @@ cmg_status cmg_fiedler_noalloc(int32_t n, int64_t nnz, const int32_t* row_ptr, c
         o.max_iters_per_level < 1 || (o.precision != CMG_FP64 && o.precision != CMG_MIXED) ||
         o.fp64_final_sweeps < 0 || o.fp64_final_sweeps > 1 || o.coarsest_n > o.dense_max || o.fixed_k0 < 0 ||
         (o.fixed_k0 > 0 && !(o.fixed_beta >= 1.0 && std::isfinite(o.fixed_beta))) || o.coarsen < 0 ||
-        o.coarsen > 1 || o.galerkin < 0 || o.galerkin > 1)
+        o.coarsen > 1 || o.galerkin < 0 || o.galerkin > 2 || o.weight_storage < 0 || o.weight_storage > 1)
         return CMG_E_ARG;
     const size_t need = noalloc_need(n, nnz);
     if (need > kNoallocScratchBytes - kNoallocMeasureBytes) {

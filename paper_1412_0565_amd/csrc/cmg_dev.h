@@ -155,6 +155,11 @@ __device__ __forceinline__ void block_sum1(double (&v)[NV], double* red, int& pa
 // --------------------------------------------------------------- levels
 
 // One level of the hierarchy as the refinement kernels see it.
+// storage of a level's edge weights in the grid and step kernels
+constexpr int kWNative = 0;  // the iterates' type (FP64, or FP32 on mixed-precision levels)
+constexpr int kWF32 = 1;     // an FP32 copy beside FP64 iterates (every weight exact in FP32)
+constexpr int kWUnit = 2;    // every weight is 1: none is read
+
 struct LevelDev {
     int32_t n;
     int32_t lanes;       // lanes per row for the row-group SpMV
@@ -178,6 +183,7 @@ struct LevelDev {
     int32_t bslots;      // register rows: entry slots per lane and row (E of the layout)
     int32_t stage;       // grid levels: 1 if a workgroup's rows may be staged in LDS
     int32_t kfix;        // > 0: fixed schedule, exactly this many PI steps and no stopping test
+    int32_t wk;          // weight storage of the grid and step kernels (kWNative, kWF32, kWUnit)
 };
 
 // State a refinement launch leaves for the next level (device written).

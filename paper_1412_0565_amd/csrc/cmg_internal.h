@@ -16,6 +16,8 @@ constexpr unsigned kAsym = 4u;
 // Not an error: some weight is not an integer below 2^20.  Without it every
 // sum of weights of the hierarchy is an integer below 2^51, exact in any order.
 constexpr unsigned kWideWeight = 8u;
+// Not an error: some weight is not 1.
+constexpr unsigned kNonUnit = 16u;
 
 // ---- coarsen_small.hip: the setup of small levels in one workgroup
 constexpr int kChainThreads = 1024;
@@ -64,7 +66,7 @@ struct ChainJob {
 hipError_t launch_coarsen_chain(const ChainJob& job, hipStream_t s);
 
 // ---- setup.hip
-// flags[0]: kBadGraph | kIsolated | kAsym | kWideWeight; flags[1]: longest
+// flags[0]: kBadGraph | kIsolated | kAsym | kWideWeight | kNonUnit; flags[1]: longest
 // row if it exceeds 64 entries, else left as it was (both zeroed by the caller)
 hipError_t launch_validate(int n, int64_t nnz, const int32_t* rp, const int32_t* col, const void* w,
                            int wf32, int full, unsigned* flags, hipStream_t s);
@@ -90,30 +92,26 @@ hipError_t launch_hec_attach(int n, const int32_t* h, const uint8_t* state, cons
 hipError_t launch_hec_label(int n, const int32_t* rootseed, const int32_t* rank, int32_t* agg,
                             hipStream_t s);
 // Galerkin product by aggregates (levels whose aggregates have at most
-// kGalBigCap entries in their member rows): members sorted by aggregate
+// kGalWaveCap entries in their member rows): members sorted by aggregate
 // (ascending vertex inside one), their row lengths and each aggregate's
 // first member (mstart[nc] = n); moff = exclusive scan of mdeg; *emax
 // (zeroed by the caller) the most entries of one aggregate, for the
 // aggregate count *ncp (at most ncmax) read on the device; gather writes each
 // coarse row at moff[mstart[a]] of tcol/tw and its length; compact moves the
 // rows to the coarse CSR given its row pointers crp[nc + 1].
-constexpr int kGalLanes = 16;
-constexpr int kGalCap = 64;      // entries per aggregate on kGalLanes lanes
-constexpr int kGalBigCap = 512;  // ... on a wavefront; above this the level sorts
+constexpr int kGalWaveCap = 1024;       // entries per aggregate; above this the level sorts
+constexpr int kGalLaneMinRows = 65536;  // fewer coarse rows: all formed by wavefronts
 hipError_t launch_gal_members(int n, const int32_t* agg, const int32_t* rp, unsigned long long* k0,
                               unsigned long long* k1, int aggbits, int32_t* sort_counts, long long* sort_scan,
-                              int32_t* members, int32_t* mdeg, int32_t* mstart, int32_t* mpos, hipStream_t s);
+                              int32_t* members, int32_t* mdeg, int32_t* mstart, hipStream_t s);
 hipError_t launch_gal_agg_len(int ncmax, const long long* ncp, int n, int64_t nnz, const int32_t* mstart,
                               const int32_t* moff, unsigned long long* emax, hipStream_t s);
-// (sb, sw: nnz staging of every entry's coarse column and weight in
-// aggregate-major order; big: nc ints listing the aggregates over kGalCap
-// entries, nbig their count)
-// (lanes: 1, 2, 4 or 8 per row when staging; mpos: position of each vertex
-// among the members)
-hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int lanes, const int32_t* mstart, const int32_t* mpos,
+// (slots: 16 or 32 distinct columns a lane keeps in registers, 0 for none;
+// big: nc ints listing the aggregates with more, nbig their count)
+hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int slots, const int32_t* members, const int32_t* mstart,
                              const int32_t* moff, const int32_t* rp, const int32_t* col, const double* w,
-                             const int32_t* agg, int32_t* sb, double* sw, int32_t* tcol, double* tw, int32_t* rowlen,
-                             int32_t* big, unsigned* nbig, hipStream_t s);
+                             const int32_t* agg, int32_t* tcol, double* tw, int32_t* rowlen, int32_t* big,
+                             unsigned* nbig, hipStream_t s);
 hipError_t launch_gal_compact(int nc, const int32_t* mstart, const int32_t* moff, const int32_t* crp,
                               const int32_t* tcol, const double* tw, int32_t* col_out, double* w_out,
                               hipStream_t s);
@@ -190,8 +188,10 @@ hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, int kind, hipStrea
 // Job kernels are specialised by traversal (merge path or G lanes per
 // row) and precision: kind = 2 * t + fp32, t = 0 for the merge path, else
 // 1 + log2(G); finishing kernels depend on the traversal only.
-constexpr int kJobKinds = 16;
-int job_kind(int variant, int lanes, int fp32);
+constexpr int kJobKinds = 48;
+// 16 wk + 2 t + fp32: traversal t (0 merge path, else 1 + log2(lanes)),
+// FP32 iterates, weight storage wk
+int job_kind(int variant, int lanes, int fp32, int wk);
 // co-resident workgroups of a job kernel kind (measured once per process)
 int refine_jobs_max_blocks(int kind);
 int finish_jobs_max_blocks(int kind);

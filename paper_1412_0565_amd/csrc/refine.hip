@@ -1065,15 +1065,60 @@ __device__ __forceinline__ bool job_allreduce(double (&v)[NV], GridCtx& c, doubl
 }
 
 // ---- per-row operations fed by the two traversal drivers
+//
+// Edge weights are read through WRead<W>: W = double or float (an FP32
+// copy, used only where every weight of the level is exact in FP32), or
+// WUnit where every weight is 1 and nothing is read.  The value is the
+// same double in all three, so results do not depend on the storage.
+struct WUnit {};
+template <typename W>
+struct WRead {
+    const W* __restrict__ p;
+    __device__ __forceinline__ double operator[](int e) const { return (double)p[e]; }
+};
+template <>
+struct WRead<WUnit> {
+    const void* p;
+    __device__ __forceinline__ double operator[](int) const { return 1.0; }
+};
+// storage type of kind WK for iterates of type T
+template <typename T, int WK>
+struct WStore {
+    using type = T;
+};
+template <typename T>
+struct WStore<T, kWF32> {
+    using type = float;
+};
+template <typename T>
+struct WStore<T, kWUnit> {
+    using type = WUnit;
+};
+// the level's weights of kind WK for iterates of type T
+template <typename T, int WK>
+__device__ __forceinline__ WRead<typename WStore<T, WK>::type> weights_of(const LevelDev& L) {
+    WRead<typename WStore<T, WK>::type> r;
+    if constexpr (WK == kWUnit) r.p = nullptr;
+    else if constexpr (WK == kWF32 || sizeof(T) == 4) r.p = L.w32;
+    else r.p = L.w64;
+    return r;
+}
+// the finishing pass reads FP64 weights, or the exact FP32 copy, or none
+template <int WK>
+using FinW = WRead<typename WStore<double, WK>::type>;
+template <int WK>
+__device__ __forceinline__ FinW<WK> fin_weights(const LevelDev& L) {
+    return weights_of<double, WK>(L);
+}
 
 // One PI step: y_i = s (g (w_i - mu) + sum_k a_ik (w_k - w_i)), stored as
 // T; acc += {y, y^2, y v, v} with v = (w_i - mu) s.
 // Rows and entries are numbered from the arrays the traversal reads (the
 // level's, or a workgroup's LDS stage); vector index = row + roff.
-template <typename T>
+template <typename T, int WK>
 struct PiOp {
     const int32_t* __restrict__ col;
-    const T* __restrict__ wv;
+    WRead<typename WStore<T, WK>::type> wv;
     const T* __restrict__ win;
     T* __restrict__ wout;
     int roff;
@@ -1081,11 +1126,11 @@ struct PiOp {
     double acc[4];
     __device__ __forceinline__ double xi(int i) const { return (double)win[roff + i]; }
     __device__ __forceinline__ double entry(int e, double x) const {
-        return (double)wv[e] * ((double)win[col[e]] - x);
+        return wv[e] * ((double)win[col[e]] - x);
     }
     // entry() on a column and weight read earlier (merge path LDS stage)
     __device__ __forceinline__ int colof(int e) const { return col[e]; }
-    __device__ __forceinline__ double wof(int e) const { return (double)wv[e]; }
+    __device__ __forceinline__ double wof(int e) const { return wv[e]; }
     __device__ __forceinline__ double entry_cw(int c, double wt, double x) const {
         return wt * ((double)win[c] - x);
     }
@@ -1102,9 +1147,10 @@ struct PiOp {
 };
 
 // FP64 recomputation of a step from a (possibly FP32) iterate.
+template <int WK>
 struct RedoOp {
     const int32_t* __restrict__ col;
-    const double* __restrict__ w;
+    FinW<WK> w;
     const void* src;
     int f32;
     double* __restrict__ dst;
@@ -1128,9 +1174,10 @@ struct RedoOp {
 };
 
 // Sums of u = (src - mu) s and the edge form sum_k a_ik ((src_k - src_i) s)^2.
+template <int WK>
 struct EdgeOp {
     const int32_t* __restrict__ col;
-    const double* __restrict__ w;
+    FinW<WK> w;
     const void* src;
     int f32;
     double mu, s;
@@ -1155,9 +1202,10 @@ struct EdgeOp {
 };
 
 // Output y = (u - mean)/nrm and residual terms (L y - lambda y)_i.
+template <int WK>
 struct ResidualOp {
     const int32_t* __restrict__ col;
-    const double* __restrict__ w;
+    FinW<WK> w;
     const void* src;
     int f32;
     double mu, s, mean_u, nrm, lam;
@@ -1399,7 +1447,7 @@ struct StageLds {
 
 // ---- refinement of one level by a job's workgroups
 
-template <typename T, int TRAV>
+template <typename T, int TRAV, int WK>
 __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeShared* sh, StageLds* stg) {
     const LevelDev& L = J.L;
     const double tol = J.tol;
@@ -1410,9 +1458,11 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     T* b1 = (T*)L.buf1;
     const double n = (double)L.n;
     // traversal arrays of the PI steps: the level's, or the LDS stage
+    // (weights staged in their storage type; none where all are 1)
+    using WT = typename WStore<T, WK>::type;
     const int32_t* trp = L.rp;
     const int32_t* tcol = L.col;
-    const T* tw = (const T*)(sizeof(T) == 4 ? (const void*)L.w32 : (const void*)L.w64);
+    auto tw = weights_of<T, WK>(L);
     int tlo = r0, thi = r1, roff = 0;
     if constexpr (TRAV > 0 && sizeof(T) == 8) {
         const int a0 = L.rp[r0], a1 = L.rp[r1];
@@ -1421,12 +1471,12 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
             for (int i = threadIdx.x; i <= r1 - r0; i += blockDim.x) stg->rp[i] = L.rp[r0 + i] - a0;
             for (int e = threadIdx.x; e < a1 - a0; e += blockDim.x) {
                 stg->col[e] = L.col[a0 + e];
-                stg->w[e] = L.w64[a0 + e];
+                if constexpr (WK != kWUnit) ((WT*)stg->w)[e] = tw.p[a0 + e];
             }
             __syncthreads();
             trp = stg->rp;
             tcol = stg->col;
-            tw = (const T*)stg->w;
+            if constexpr (WK != kWUnit) tw.p = (const WT*)stg->w;
             tlo = 0;
             thi = r1 - r0;
             roff = r0;
@@ -1460,7 +1510,7 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     double s = 1.0 / sqrt(ss[0]);
     int cur = 0, k = 0, hit = 0;
     double utv = 0.0, pmu = mu, ps = s;
-    PiOp<T> op;
+    PiOp<T, WK> op;
     op.col = tcol;
     op.wv = tw;
     op.roff = roff;
@@ -1514,7 +1564,7 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
 // rounding.  Then the output y = deflated, normalised iterate, the
 // edge-form Rayleigh quotient r = sum_edges w (y_i - y_k)^2 and the
 // residual ||L y - r y||, all in FP64.
-template <int TRAV>
+template <int TRAV, int WK>
 __device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeShared* sh) {
     const LevelDev& L = J.L;
     const int r0 = L.part[c.lb], r1 = L.part[c.lb + 1];
@@ -1524,9 +1574,9 @@ __device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     int f32 = L.fp32;
     double mu = st.mu, s = st.s;
     if (J.redo && st.k > 0) {
-        RedoOp op;
+        RedoOp<WK> op;
         op.col = L.col;
-        op.w = L.w64;
+        op.w = fin_weights<WK>(L);
         op.src = st.fin ? L.buf0 : L.buf1;
         op.f32 = f32;
         op.dst = J.fa;
@@ -1541,9 +1591,9 @@ __device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeSha
         src = J.fa;
         f32 = 0;
     }
-    EdgeOp eo;
+    EdgeOp<WK> eo;
     eo.col = L.col;
-    eo.w = L.w64;
+    eo.w = fin_weights<WK>(L);
     eo.src = src;
     eo.f32 = f32;
     eo.mu = mu;
@@ -1555,9 +1605,9 @@ __device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     const double nrm2 = eo.acc[1] - eo.acc[0] * mean_u;
     const double nrm = sqrt(nrm2);
     const double lam = 0.5 * eo.acc[2] / nrm2;
-    ResidualOp ro;
+    ResidualOp<WK> ro;
     ro.col = L.col;
-    ro.w = L.w64;
+    ro.w = fin_weights<WK>(L);
     ro.src = src;
     ro.f32 = f32;
     ro.mu = mu;
@@ -1645,7 +1695,7 @@ __device__ void residency_count(const GridJob& J) {
 // One launch refines one level of each job (one graph per job).  Kernels
 // are specialised by traversal (merge path, or G lanes per row) and
 // storage precision to keep registers low; a packed launch holds one kind.
-template <int TRAV, typename T>
+template <int TRAV, typename T, int WK>
 __device__ __forceinline__ void refine_entry(const GridJob* __restrict__ jobs, int njobs, double* red,
                                              MergeShared* sh, StageLds* stg) {
     const GridJob J = jobs[find_job(jobs, njobs)];
@@ -1655,22 +1705,22 @@ __device__ __forceinline__ void refine_entry(const GridJob* __restrict__ jobs, i
     }
     GridCtx c = make_ctx(J);
     if (c.vb < 0 || c.vb >= c.nb) return;
-    refine_level<T, TRAV>(J, c, red, sh, stg);
+    refine_level<T, TRAV, WK>(J, c, red, sh, stg);
 }
 
 // At most 128 VGPRs: two workgroups of 512 threads per CU.
-template <typename T>
+template <typename T, int WK>
 __global__ void __launch_bounds__(kGridBlock) __attribute__((amdgpu_waves_per_eu(4)))
 k_refine_merge(const GridJob* __restrict__ jobs, int njobs) {
     __shared__ double red[16 * 5 + 8];
     __shared__ MergeShared msh;
-    refine_entry<0, T>(jobs, njobs, red, &msh, nullptr);
+    refine_entry<0, T, WK>(jobs, njobs, red, &msh, nullptr);
 }
 
 // G lanes per row.  Held to 8 waves per SIMD (at most 64 VGPRs and about
 // 80 SGPRs): with more SGPRs the device keeps only 3 workgroups of 512
 // threads per CU resident although the occupancy query reports 4.
-template <int G, typename T>
+template <int G, typename T, int WK>
 __global__ void __launch_bounds__(kGridBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_refine_rows(const GridJob* __restrict__ jobs, int njobs) {
     __shared__ double red[16 * 5 + 8];
@@ -1679,11 +1729,11 @@ k_refine_rows(const GridJob* __restrict__ jobs, int njobs) {
         __shared__ StageLds st;
         stg = &st;
     }
-    refine_entry<G, T>(jobs, njobs, red, nullptr, stg);
+    refine_entry<G, T, WK>(jobs, njobs, red, nullptr, stg);
 }
 
 // One launch finishes the finest level of each job.
-template <int TRAV>
+template <int TRAV, int WK>
 __global__ void __launch_bounds__(kGridBlock) k_finish_jobs(const GridJob* __restrict__ jobs, int njobs) {
     __shared__ double red[16 * 5 + 8];
     MergeShared* sh = nullptr;
@@ -1698,7 +1748,7 @@ __global__ void __launch_bounds__(kGridBlock) k_finish_jobs(const GridJob* __res
     }
     GridCtx c = make_ctx(J);
     if (c.vb < 0 || c.vb >= c.nb) return;
-    finish_level<TRAV>(J, c, red, sh);
+    finish_level<TRAV, WK>(J, c, red, sh);
 }
 
 // ------------------------------------------ large levels: a launch per step
@@ -1807,7 +1857,7 @@ __global__ void __launch_bounds__(kCheckThreads) k_step_norm(const StepJob* __re
 }
 
 // one power-iteration step: buf[cur] -> buf[cur ^ 1], posts {y, y^2, y v, v}
-template <int G, typename T>
+template <int G, typename T, int WK>
 __global__ void __launch_bounds__(kStepBlock) k_step_spmv(const StepJob* __restrict__ jp) {
     __shared__ double red[16 * 5 + 8];
     const StepJob J = *jp;
@@ -1815,9 +1865,9 @@ __global__ void __launch_bounds__(kStepBlock) k_step_spmv(const StepJob* __restr
     if (c.done) return;
     const LevelDev& L = J.L;
     const int r0 = L.part[blockIdx.x], r1 = L.part[blockIdx.x + 1];
-    PiOp<T> op;
+    PiOp<T, WK> op;
     op.col = L.col;
-    op.wv = (const T*)(sizeof(T) == 4 ? (const void*)L.w32 : (const void*)L.w64);
+    op.wv = weights_of<T, WK>(L);
     op.roff = 0;
     op.g = L.g;
     op.win = (const T*)(c.cur ? L.buf1 : L.buf0);
@@ -1940,37 +1990,55 @@ hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, int kind, hipStrea
 }
 
 namespace {
-// kind = 2 * t + fp32 with t = 0 (merge path) or 1 + log2(G)
-template <int TRAV>
-const void* refine_kernel_t(int fp32) {
-    if constexpr (TRAV == 0)
-        return fp32 ? (const void*)k_refine_merge<float> : (const void*)k_refine_merge<double>;
-    else
-        return fp32 ? (const void*)k_refine_rows<TRAV, float> : (const void*)k_refine_rows<TRAV, double>;
-}
-const void* refine_kernel(int kind) {
-    const int fp32 = kind & 1;
-    switch (kind >> 1) {
-        case 0: return refine_kernel_t<0>(fp32);
-        case 1: return refine_kernel_t<1>(fp32);
-        case 2: return refine_kernel_t<2>(fp32);
-        case 3: return refine_kernel_t<4>(fp32);
-        case 4: return refine_kernel_t<8>(fp32);
-        case 5: return refine_kernel_t<16>(fp32);
-        case 6: return refine_kernel_t<32>(fp32);
-        default: return refine_kernel_t<64>(fp32);
+// kind = 16 wk + 2 t + fp32 with t = 0 (merge path) or 1 + log2(G) and wk
+// the weight storage (FP32 iterates have no kWF32 form)
+template <int TRAV, int WK>
+const void* refine_kernel_w(int fp32) {
+    if constexpr (TRAV == 0) {
+        if constexpr (WK == kWF32) return (const void*)k_refine_merge<double, kWF32>;
+        else return fp32 ? (const void*)k_refine_merge<float, WK> : (const void*)k_refine_merge<double, WK>;
+    } else if constexpr (WK == kWF32) {
+        return (const void*)k_refine_rows<TRAV, double, kWF32>;
+    } else {
+        return fp32 ? (const void*)k_refine_rows<TRAV, float, WK> : (const void*)k_refine_rows<TRAV, double, WK>;
     }
 }
+template <int TRAV>
+const void* refine_kernel_t(int fp32, int wk) {
+    return wk == kWUnit ? refine_kernel_w<TRAV, kWUnit>(fp32)
+           : wk == kWF32 ? refine_kernel_w<TRAV, kWF32>(fp32)
+                         : refine_kernel_w<TRAV, kWNative>(fp32);
+}
+const void* refine_kernel(int kind) {
+    const int fp32 = kind & 1, wk = kind >> 4;
+    switch ((kind >> 1) & 7) {
+        case 0: return refine_kernel_t<0>(fp32, wk);
+        case 1: return refine_kernel_t<1>(fp32, wk);
+        case 2: return refine_kernel_t<2>(fp32, wk);
+        case 3: return refine_kernel_t<4>(fp32, wk);
+        case 4: return refine_kernel_t<8>(fp32, wk);
+        case 5: return refine_kernel_t<16>(fp32, wk);
+        case 6: return refine_kernel_t<32>(fp32, wk);
+        default: return refine_kernel_t<64>(fp32, wk);
+    }
+}
+template <int TRAV>
+const void* finish_kernel_t(int wk) {
+    return wk == kWUnit ? (const void*)k_finish_jobs<TRAV, kWUnit>
+           : wk == kWF32 ? (const void*)k_finish_jobs<TRAV, kWF32>
+                         : (const void*)k_finish_jobs<TRAV, kWNative>;
+}
 const void* finish_kernel(int kind) {
-    switch (kind >> 1) {
-        case 0: return (const void*)k_finish_jobs<0>;
-        case 1: return (const void*)k_finish_jobs<1>;
-        case 2: return (const void*)k_finish_jobs<2>;
-        case 3: return (const void*)k_finish_jobs<4>;
-        case 4: return (const void*)k_finish_jobs<8>;
-        case 5: return (const void*)k_finish_jobs<16>;
-        case 6: return (const void*)k_finish_jobs<32>;
-        default: return (const void*)k_finish_jobs<64>;
+    const int wk = kind >> 4;
+    switch ((kind >> 1) & 7) {
+        case 0: return finish_kernel_t<0>(wk);
+        case 1: return finish_kernel_t<1>(wk);
+        case 2: return finish_kernel_t<2>(wk);
+        case 3: return finish_kernel_t<4>(wk);
+        case 4: return finish_kernel_t<8>(wk);
+        case 5: return finish_kernel_t<16>(wk);
+        case 6: return finish_kernel_t<32>(wk);
+        default: return finish_kernel_t<64>(wk);
     }
 }
 // Workgroups of kernel `k` that can be resident at once.  The occupancy
@@ -2037,30 +2105,41 @@ int max_blocks_ptr(const void* k) {
 
 void set_measure_buffers(const MeasureBuffers* b) { t_meas = b ? *b : MeasureBuffers{nullptr, nullptr, nullptr}; }
 
-int job_kind(int variant, int lanes, int fp32) {
+int job_kind(int variant, int lanes, int fp32, int wk) {
     int t = 0;
     if (variant != 2) {
         t = 1;
         for (int g = lanes; g > 1 && t < 7; g >>= 1) ++t;
     }
-    return 2 * t + (fp32 ? 1 : 0);
+    // FP32 iterates read FP32 weights (their native storage)
+    if (fp32 && wk == kWF32) wk = kWNative;
+    return 16 * wk + 2 * t + (fp32 ? 1 : 0);
 }
 
 namespace {
 std::mutex g_cap_mutex;
-int g_refine_cap[kJobKinds] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
-int g_finish_cap[kJobKinds] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+int g_refine_cap[kJobKinds];
+int g_finish_cap[kJobKinds];
+bool g_caps_init = false;
 }  // namespace
 
 // Measured once per kernel and process (the first call launches it).
+void caps_init() {
+    if (g_caps_init) return;
+    for (int k = 0; k < kJobKinds; ++k) g_refine_cap[k] = g_finish_cap[k] = -1;
+    g_caps_init = true;
+}
+
 int refine_jobs_max_blocks(int kind) {
     std::lock_guard<std::mutex> lock(g_cap_mutex);
+    caps_init();
     if (g_refine_cap[kind] < 0) g_refine_cap[kind] = max_blocks_ptr(refine_kernel(kind));
     return g_refine_cap[kind];
 }
 
 int finish_jobs_max_blocks(int kind) {
     std::lock_guard<std::mutex> lock(g_cap_mutex);
+    caps_init();
     if (g_finish_cap[kind] < 0) g_finish_cap[kind] = max_blocks_ptr(finish_kernel(kind));
     return g_finish_cap[kind];
 }
@@ -2096,23 +2175,33 @@ hipError_t launch_step_begin(const StepJob* job, int nblocks, int kind, hipStrea
 }
 
 namespace {
+template <int G, int WK>
+void step_spmv_w(const StepJob* job, int nblocks, int fp32, hipStream_t s) {
+    if constexpr (WK == kWF32) {
+        hipLaunchKernelGGL((k_step_spmv<G, double, kWF32>), dim3(nblocks), dim3(kStepBlock), 0, s, job);
+    } else {
+        if (fp32) hipLaunchKernelGGL((k_step_spmv<G, float, WK>), dim3(nblocks), dim3(kStepBlock), 0, s, job);
+        else hipLaunchKernelGGL((k_step_spmv<G, double, WK>), dim3(nblocks), dim3(kStepBlock), 0, s, job);
+    }
+}
 template <int G>
-void step_spmv_g(const StepJob* job, int nblocks, int fp32, hipStream_t s) {
-    if (fp32) hipLaunchKernelGGL((k_step_spmv<G, float>), dim3(nblocks), dim3(kStepBlock), 0, s, job);
-    else hipLaunchKernelGGL((k_step_spmv<G, double>), dim3(nblocks), dim3(kStepBlock), 0, s, job);
+void step_spmv_g(const StepJob* job, int nblocks, int fp32, int wk, hipStream_t s) {
+    if (wk == kWUnit) step_spmv_w<G, kWUnit>(job, nblocks, fp32, s);
+    else if (wk == kWF32) step_spmv_w<G, kWF32>(job, nblocks, fp32, s);
+    else step_spmv_w<G, kWNative>(job, nblocks, fp32, s);
 }
 }  // namespace
 
 hipError_t launch_step_pi(const StepJob* job, int nblocks, int kind, hipStream_t s) {
-    const int fp32 = kind & 1;
-    switch (kind >> 1) {
-        case 1: step_spmv_g<1>(job, nblocks, fp32, s); break;
-        case 2: step_spmv_g<2>(job, nblocks, fp32, s); break;
-        case 3: step_spmv_g<4>(job, nblocks, fp32, s); break;
-        case 4: step_spmv_g<8>(job, nblocks, fp32, s); break;
-        case 5: step_spmv_g<16>(job, nblocks, fp32, s); break;
-        case 6: step_spmv_g<32>(job, nblocks, fp32, s); break;
-        case 7: step_spmv_g<64>(job, nblocks, fp32, s); break;
+    const int fp32 = kind & 1, wk = kind >> 4;
+    switch ((kind >> 1) & 7) {
+        case 1: step_spmv_g<1>(job, nblocks, fp32, wk, s); break;
+        case 2: step_spmv_g<2>(job, nblocks, fp32, wk, s); break;
+        case 3: step_spmv_g<4>(job, nblocks, fp32, wk, s); break;
+        case 4: step_spmv_g<8>(job, nblocks, fp32, wk, s); break;
+        case 5: step_spmv_g<16>(job, nblocks, fp32, wk, s); break;
+        case 6: step_spmv_g<32>(job, nblocks, fp32, wk, s); break;
+        case 7: step_spmv_g<64>(job, nblocks, fp32, wk, s); break;
         default: return hipErrorInvalidValue;  // the merge path has no step form
     }
     hipLaunchKernelGGL(k_step_check, dim3(1), dim3(kCheckThreads), 0, s, job, nblocks);

@@ -59,6 +59,7 @@ __global__ void k_validate(int n, int64_t nnz, const int32_t* __restrict__ rp,
                 bool bad = c < 0 || c >= n || c == i || c <= prev;
                 if (!(x > 0.0) || !isfinite(x)) bad = true;
                 if (!bad && (x != floor(x) || x >= 1048576.0)) f |= kWideWeight;
+                if (x != 1.0) f |= kNonUnit;
                 if (bad) {
                     f |= kBadGraph;
                 } else if (full && rp[c] >= 0 && rp[c] <= rp[c + 1] && (int64_t)rp[c + 1] <= nnz) {
@@ -370,9 +371,16 @@ __global__ void k_hem_flags(int n, const int32_t* __restrict__ opener, int32_t* 
 // CSR order), the pair (b = agg(col), w); pairs with b = a are dropped and
 // equal b are summed in that order, the distinct b written in ascending
 // order.  This is the sorted-key Galerkin product without the sort: the
-// same sums in the same order, so coarse graphs are bitwise equal.  A group
-// group of lanes forms one coarse row in LDS; used on levels whose
-// aggregates have at most kGalBigCap entries (else the radix-sort path).
+// same sums in the same order, so coarse graphs are bitwise equal.  Used on
+// levels whose aggregates have at most kGalWaveCap entries (else the
+// radix-sort path).
+//
+// Pass 1 forms each row where its columns fit: one lane per aggregate
+// walks the member rows and keeps the distinct columns, sorted, with their
+// running sums in registers (one add per entry, in fine order).  Aggregates with more than S distinct columns
+// are listed for pass 1b: a wavefront per aggregate sorts the entries'
+// keys (b, position) in LDS, so equal b stay in fine order, and the first
+// lane of each run of equal b adds the run in that order.
 
 // keys (agg << 32 | v) for the stable sort of vertices by aggregate
 __global__ void k_gal_member_keys(int n, const int32_t* __restrict__ agg, unsigned long long* __restrict__ keys) {
@@ -384,30 +392,38 @@ __global__ void k_gal_member_keys(int n, const int32_t* __restrict__ agg, unsign
 // member (mstart[nc] = n is written by the thread of the last member)
 __global__ void k_gal_members(int n, const unsigned long long* __restrict__ keys, const int32_t* __restrict__ rp,
                               int32_t* __restrict__ members, int32_t* __restrict__ mdeg,
-                              int32_t* __restrict__ mstart, int32_t* __restrict__ mpos) {
+                              int32_t* __restrict__ mstart) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int v = (int)(keys[k] & 0xffffffffull);
     const int a = (int)(keys[k] >> 32);
     members[k] = v;
-    mpos[v] = k;
     mdeg[k] = rp[v + 1] - rp[v];
     if (k == 0 || (int)(keys[k - 1] >> 32) != a) mstart[a] = k;
     if (k == n - 1) mstart[a + 1] = n;
 }
 
+// entries of aggregate a's member rows and the offset of the first
+__device__ __forceinline__ int64_t gal_entries(int a, int n, int64_t nnz, const int32_t* __restrict__ mstart,
+                                               const int32_t* __restrict__ moff, int64_t* o0) {
+    const int k1 = mstart[a + 1];
+    *o0 = moff[mstart[a]];
+    return (k1 >= n ? nnz : (int64_t)moff[k1]) - *o0;
+}
+
+constexpr int kGalLenBlocks = 1024;
+
 // the largest number of entries of an aggregate's member rows (the
-// aggregate count read from the device)
+// aggregate count read from the device); a fixed grid striding over the
+// aggregates so that only kGalLenBlocks atomics reach the one word
 __global__ void k_gal_agg_len(int ncmax, const long long* __restrict__ ncp, int n, int64_t nnz,
                               const int32_t* __restrict__ mstart, const int32_t* __restrict__ moff,
                               unsigned long long* __restrict__ emax) {
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nc = (int)*ncp;
+    const int nc = (int)min((long long)ncmax, *ncp);
     int e = 0;
-    if (a < nc && a < ncmax) {
-        const int k0 = mstart[a], k1 = mstart[a + 1];
-        const int64_t end = k1 >= n ? nnz : (int64_t)moff[k1];
-        e = (int)(end - moff[k0]);
+    for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < nc; a += gridDim.x * blockDim.x) {
+        int64_t o0;
+        e = max(e, (int)gal_entries(a, n, nnz, mstart, moff, &o0));
     }
     for (int o = 32; o > 0; o >>= 1) e = max(e, __shfl_xor(e, o, kWave));
     __shared__ int wm[kBlk / 64];
@@ -419,172 +435,218 @@ __global__ void k_gal_agg_len(int ncmax, const long long* __restrict__ ncp, int 
     }
 }
 
-// every entry's (coarse column, weight) at its place in aggregate-major
-// order (member k's row starts at moff[k]); rows read in fine order, G
-// lanes per row
-template <int G>
-__global__ void k_gal_stage(int n, const int32_t* __restrict__ mpos, const int32_t* __restrict__ moff,
-                            const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                            const double* __restrict__ w, const int32_t* __restrict__ agg, int32_t* __restrict__ sb,
-                            double* __restrict__ sw) {
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = (int)(tid / G), lane = (int)(tid & (G - 1));
-    if (v >= n) return;
-    const int r0 = rp[v], r1 = rp[v + 1];
-    const int o = moff[mpos[v]] - r0;
-    for (int e = r0 + lane; e < r1; e += G) {
-        sb[o + e] = agg[col[e]];
-        sw[o + e] = w[e];
+// pass 1: a lane per aggregate, S register slots
+template <int S>
+__global__ void __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) k_gal_lane(int nc, const int32_t* __restrict__ members,
+                                                   const int32_t* __restrict__ mstart,
+                                                   const int32_t* __restrict__ moff, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col, const double* __restrict__ w,
+                                                   const int32_t* __restrict__ agg, int32_t* __restrict__ tcol,
+                                                   double* __restrict__ tw, int32_t* __restrict__ rowlen,
+                                                   int32_t* __restrict__ big, unsigned* __restrict__ nbig) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= nc) return;
+    const int k0 = mstart[a], k1 = mstart[a + 1];
+    int rb[S];
+    double rw[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        rb[q] = 0x7fffffff;
+        rw[q] = 0.0;
     }
+    int len = 0;
+    bool over = false;
+    // entries in batches of kGalBatch: their columns and weights, then the
+    // columns' aggregates, are loaded together before any is added
+    constexpr int kGalBatch = S <= 16 ? 8 : 4;
+    for (int k = k0; k < k1 && !over; ++k) {
+        const int v = members[k];
+        const int e1 = rp[v + 1];
+        for (int e = rp[v]; e < e1 && !over; e += kGalBatch) {
+            int cb[kGalBatch];
+            double xb[kGalBatch];
+#pragma unroll
+            for (int i = 0; i < kGalBatch; ++i) {
+                if (e + i < e1) {
+                    cb[i] = col[e + i];
+                    xb[i] = w[e + i];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kGalBatch; ++i)
+                if (e + i < e1) cb[i] = agg[cb[i]];
+#pragma unroll
+            for (int i = 0; i < kGalBatch; ++i) {
+                const int b = cb[i];
+                const double x = xb[i];
+                if (e + i >= e1 || over || b == a) continue;
+                bool found = false;
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    if (rb[q] == b) {
+                        rw[q] += x;
+                        found = true;
+                    }
+                }
+                if (found) continue;
+                if (len == S) {
+                    over = true;
+                    continue;
+                }
+                // insert b at its place: the slots stay sorted ascending
+                // (unused ones hold INT_MAX), those above it move up one
+#pragma unroll
+                for (int q = S - 1; q >= 0; --q) {
+                    const int prev = q > 0 ? rb[q - 1] : INT_MIN;
+                    const double prevw = q > 0 ? rw[q - 1] : 0.0;
+                    if (rb[q] > b) {
+                        if (prev > b) {
+                            rb[q] = prev;
+                            rw[q] = prevw;
+                        } else {
+                            rb[q] = b;
+                            rw[q] = x;
+                        }
+                    }
+                }
+                ++len;
+            }
+        }
+    }
+    if (over) {
+        big[atomicAdd(nbig, 1u)] = a;
+        return;
+    }
+    const int64_t base = moff[k0];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        if (q < len) {
+            tcol[base + q] = rb[q];
+            tw[base + q] = rw[q];
+        }
+    }
+    rowlen[a] = len;
 }
 
-// pass 1: the coarse row of an aggregate (entries staged in aggregate-major
-// order, E of them) formed by a group of G lanes in LDS and written at the
-// aggregate's entry offset in tcol/tw.  Heads are the first occurrences of
-// each coarse column (the aggregate's own dropped); a head's rank among the
-// heads orders the columns, its sum runs over the later equal entries in
-// order.  A group walks its aggregates with the next one's entries loaded
-// into registers while the current one is formed.
+constexpr int kGalWaveMembers = 256;
 
-__device__ __forceinline__ int64_t gal_entries(int a, int n, int64_t nnz, const int32_t* __restrict__ mstart,
-                                               const int32_t* __restrict__ moff, int64_t* o0) {
-    const int k1 = mstart[a + 1];
-    *o0 = moff[mstart[a]];
-    return (k1 >= n ? nnz : (int64_t)moff[k1]) - *o0;
+// every aggregate listed for pass 1b
+__global__ void k_gal_all(int nc, int32_t* __restrict__ big, unsigned* __restrict__ nbig) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < nc) big[a] = a;
+    if (a == 0) *nbig = (unsigned)nc;
 }
 
-// A group's lanes share LDS within one wavefront, whose LDS operations
-// complete in program order: keeping the compiler from moving LDS accesses
-// across this point is all the ordering needed.
+// A wavefront's LDS operations complete in program order: keeping the
+// compiler from moving LDS accesses across this point is all the ordering
+// the lanes of one wavefront need.
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_wave_barrier();
     asm volatile("" ::: "memory");
 }
 
-// one aggregate's entries, lane-strided, in registers (R = CAP / G)
-template <int G, int R>
-struct GalRegs {
-    int32_t b[R];
-    double w[R];
-    int E, a;
-    int64_t o0;
-    __device__ __forceinline__ void load(int a_, int n, int64_t nnz, const int32_t* __restrict__ mstart,
-                                         const int32_t* __restrict__ moff, const int32_t* __restrict__ gb,
-                                         const double* __restrict__ gw, int lane, int cap) {
-        a = a_;
-        E = (int)gal_entries(a, n, nnz, mstart, moff, &o0);
-        if (E > cap) return;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int t = lane + r * G;
-            if (t < E) {
-                b[r] = gb[o0 + t];
-                w[r] = gw[o0 + t];
-            }
-        }
-    }
-    __device__ __forceinline__ void to_lds(int32_t* b_, double* w_, int lane) const {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int t = lane + r * G;
-            if (t < E) {
-                b_[t] = b[r];
-                w_[t] = w[r];
-            }
-        }
-    }
-};
-
-template <int G>
-__device__ __forceinline__ int gal_form(int a, int E, int64_t o0, int lane, const int32_t* b_, const double* w_,
-                                        uint8_t* h_, int32_t* __restrict__ tcol, double* __restrict__ tw) {
-    for (int t = lane; t < E; t += G) {
-        const int b = b_[t];
-        bool head = b != a;
-        for (int u = 0; u < t && head; ++u) head = b_[u] != b;
-        h_[t] = head ? 1 : 0;
-    }
-    wave_sync_lds();
-    int cnt = 0;
-    for (int t = lane; t < E; t += G) {
-        if (!h_[t]) continue;
-        const int b = b_[t];
-        int rank = 0;
-        double sum = 0.0;
-        for (int u = 0; u < E; ++u) {
-            rank += (h_[u] && b_[u] < b) ? 1 : 0;
-            if (u >= t && b_[u] == b) sum += w_[u];  // in fine CSR order
-        }
-        tcol[o0 + rank] = b;
-        tw[o0 + rank] = sum;
-        ++cnt;
-    }
-    for (int o = G >> 1; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, kWave);
-    return cnt;
-}
-
-// aggregates of at most kGalCap entries, kGalLanes lanes each, striding over
-// the aggregates; larger ones go to a list for k_gal_big
-__global__ void __launch_bounds__(kBlk) k_gal_gather(int nc, int n, int64_t nnz, const int32_t* __restrict__ mstart,
-                                                     const int32_t* __restrict__ moff,
-                                                     const int32_t* __restrict__ gb, const double* __restrict__ gw,
-                                                     int32_t* __restrict__ tcol, double* __restrict__ tw,
-                                                     int32_t* __restrict__ rowlen, int32_t* __restrict__ big,
-                                                     unsigned* __restrict__ nbig) {
-    constexpr int G = kGalLanes, R = kGalCap / kGalLanes;
-    __shared__ int32_t sb[kBlk / G][kGalCap];
-    __shared__ double sw[kBlk / G][kGalCap];
-    __shared__ uint8_t sh[kBlk / G][kGalCap];
-    const int grp = threadIdx.x / G, lane = threadIdx.x & (G - 1);
-    const int stride = gridDim.x * (kBlk / G);
-    int a = blockIdx.x * (kBlk / G) + grp;
-    GalRegs<G, R> cur;
-    if (a < nc) cur.load(a, n, nnz, mstart, moff, gb, gw, lane, kGalCap);
-    for (; a < nc; a += stride) {
-        wave_sync_lds();  // the previous aggregate's LDS reads are done
-        if (cur.E <= kGalCap) cur.to_lds(sb[grp], sw[grp], lane);
-        const int a2 = a + stride;
-        GalRegs<G, R> nxt;
-        nxt.E = 0;
-        if (a2 < nc) nxt.load(a2, n, nnz, mstart, moff, gb, gw, lane, kGalCap);
-        if (cur.E > kGalCap) {
-            if (lane == 0) big[atomicAdd(nbig, 1u)] = a;
-        } else {
-            wave_sync_lds();
-            const int cnt = gal_form<G>(a, cur.E, cur.o0, lane, sb[grp], sw[grp], sh[grp], tcol, tw);
-            if (lane == 0) rowlen[a] = cnt;
-        }
-        cur = nxt;
-    }
-}
-
-// the listed aggregates (at most kGalBigCap entries), a wavefront each,
-// wavefronts striding over the list
-__global__ void __launch_bounds__(kBlk) k_gal_big(int n, int64_t nnz, const int32_t* __restrict__ mstart,
-                                                  const int32_t* __restrict__ moff, const int32_t* __restrict__ gb,
-                                                  const double* __restrict__ gw, const int32_t* __restrict__ big,
-                                                  const unsigned* __restrict__ nbig, int32_t* __restrict__ tcol,
-                                                  double* __restrict__ tw, int32_t* __restrict__ rowlen) {
-    constexpr int R = kGalBigCap / kWave;
-    __shared__ int32_t sb[kBlk / kWave][kGalBigCap];
-    __shared__ double sw[kBlk / kWave][kGalBigCap];
-    __shared__ uint8_t sh[kBlk / kWave][kGalBigCap];
+// pass 1b: the listed aggregates (at most kGalWaveCap entries), a wavefront
+// each, wavefronts striding over the list
+__global__ void __launch_bounds__(kBlk) k_gal_wave(int n, int64_t nnz, const int32_t* __restrict__ members,
+                                                   const int32_t* __restrict__ mstart,
+                                                   const int32_t* __restrict__ moff, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col, const double* __restrict__ w,
+                                                   const int32_t* __restrict__ agg,
+                                                   const int32_t* __restrict__ big,
+                                                   const unsigned* __restrict__ nbig, int32_t* __restrict__ tcol,
+                                                   double* __restrict__ tw, int32_t* __restrict__ rowlen) {
+    constexpr unsigned long long kNone = ~0ull;
+    __shared__ unsigned long long skey[kBlk / kWave][kGalWaveCap];
+    __shared__ double sw[kBlk / kWave][kGalWaveCap];
+    __shared__ int smrow[kBlk / kWave][kGalWaveMembers];
+    __shared__ int smpos[kBlk / kWave][kGalWaveMembers];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    unsigned long long* key = skey[wv];
+    double* wt = sw[wv];
+    int* mrow = smrow[wv];
+    int* mposn = smpos[wv];
     const int count = (int)*nbig;
-    const int stride = gridDim.x * (kBlk / kWave);
-    int q = blockIdx.x * (kBlk / kWave) + wv;
-    GalRegs<kWave, R> cur;
-    if (q < count) cur.load(big[q], n, nnz, mstart, moff, gb, gw, lane, kGalBigCap);
-    for (; q < count; q += stride) {
+    for (int q = blockIdx.x * (kBlk / kWave) + wv; q < count; q += gridDim.x * (kBlk / kWave)) {
+        const int a = big[q];
+        int64_t o0;
+        const int E = (int)gal_entries(a, n, nnz, mstart, moff, &o0);
+        int P = kWave;
+        while (P < E) P <<= 1;
+        wave_sync_lds();  // the previous aggregate's LDS reads are done
+        // keys (b << 32 | position) in fine order; the own aggregate and
+        // the padding sort last as kNone.  With at most kGalWaveMembers
+        // members, their row starts and positions go to LDS and every lane
+        // loads entries t = lane, lane + 64, ... (its member found by binary
+        // search); else member after member.
+        const int k0 = mstart[a], k1 = mstart[a + 1];
+        const int cnt = k1 - k0;
+        if (cnt <= kGalWaveMembers) {
+            for (int i = lane; i < cnt; i += kWave) {
+                mrow[i] = rp[members[k0 + i]];
+                mposn[i] = (int)(moff[k0 + i] - o0);
+            }
+            wave_sync_lds();
+            for (int t = lane; t < E; t += kWave) {
+                int lo = 0, hi = cnt - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (mposn[mid] <= t) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int e = mrow[lo] + (t - mposn[lo]);
+                const int b = agg[col[e]];
+                key[t] = b == a ? kNone : (((unsigned long long)(uint32_t)b << 32) | (uint32_t)t);
+                wt[t] = w[e];
+            }
+        } else {
+            for (int k = k0; k < k1; ++k) {
+                const int v = members[k];
+                const int r0 = rp[v], len = rp[v + 1] - r0;
+                const int pos = (int)(moff[k] - o0);
+                for (int i = lane; i < len; i += kWave) {
+                    const int b = agg[col[r0 + i]];
+                    key[pos + i] = b == a ? kNone : (((unsigned long long)(uint32_t)b << 32) | (uint32_t)(pos + i));
+                    wt[pos + i] = w[r0 + i];
+                }
+            }
+        }
+        for (int i = E + lane; i < P; i += kWave) key[i] = kNone;
         wave_sync_lds();
-        cur.to_lds(sb[wv], sw[wv], lane);
-        GalRegs<kWave, R> nxt;
-        nxt.E = 0;
-        if (q + stride < count) nxt.load(big[q + stride], n, nnz, mstart, moff, gb, gw, lane, kGalBigCap);
-        wave_sync_lds();
-        const int cnt = gal_form<kWave>(cur.a, cur.E, cur.o0, lane, sb[wv], sw[wv], sh[wv], tcol, tw);
-        if (lane == 0) rowlen[cur.a] = cnt;
-        cur = nxt;
+        // bitonic sort of P keys, ascending
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int p = lane; p < (P >> 1); p += kWave) {
+                    const int lo = ((p / j) * 2 * j) + (p % j), hi = lo + j;
+                    const unsigned long long x = key[lo], y = key[hi];
+                    const bool up = (lo & k) == 0;
+                    if ((x > y) == up) {
+                        key[lo] = y;
+                        key[hi] = x;
+                    }
+                }
+                wave_sync_lds();
+            }
+        }
+        // heads of the runs of equal b, ranked in sorted order; each head
+        // adds its run in position (fine) order
+        int before = 0;
+        for (int p0 = 0; p0 < P; p0 += kWave) {
+            const int p = p0 + lane;
+            const unsigned long long kp = key[p];
+            const bool head = kp != kNone && (p == 0 || (key[p - 1] >> 32) != (kp >> 32));
+            const unsigned long long hm = __ballot(head);
+            const int rank = before + __popcll(hm & ((1ull << lane) - 1ull));
+            if (head) {
+                const uint32_t b = (uint32_t)(kp >> 32);
+                double sum = 0.0;
+                for (int r = p; r < P && key[r] != kNone && (uint32_t)(key[r] >> 32) == b; ++r)
+                    sum += wt[key[r] & 0xffffffffull];
+                tcol[o0 + rank] = (int32_t)b;
+                tw[o0 + rank] = sum;
+            }
+            before += __popcll(hm);
+        }
+        if (lane == 0) rowlen[a] = before;
     }
 }
 
@@ -1103,41 +1165,43 @@ hipError_t launch_hem_round(int n, const int32_t* rp, const int32_t* col, const 
 
 hipError_t launch_gal_members(int n, const int32_t* agg, const int32_t* rp, unsigned long long* k0,
                               unsigned long long* k1, int aggbits, int32_t* sort_counts, long long* sort_scan,
-                              int32_t* members, int32_t* mdeg, int32_t* mstart, int32_t* mpos, hipStream_t s) {
+                              int32_t* members, int32_t* mdeg, int32_t* mstart, hipStream_t s) {
     hipLaunchKernelGGL(k_gal_member_keys, dim3(nblocks(n, kBlk)), dim3(kBlk), 0, s, n, agg, k0);
     int second = 0;
     hipError_t e = launch_sort(k0, nullptr, k1, nullptr, n, 32, aggbits, sort_counts, sort_scan, &second, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gal_members, dim3(nblocks(n, kBlk)), dim3(kBlk), 0, s, n, second ? k1 : k0, rp, members,
-                       mdeg, mstart, mpos);
+                       mdeg, mstart);
     return hipGetLastError();
 }
 
 hipError_t launch_gal_agg_len(int ncmax, const long long* ncp, int n, int64_t nnz, const int32_t* mstart,
                               const int32_t* moff, unsigned long long* emax, hipStream_t s) {
-    hipLaunchKernelGGL(k_gal_agg_len, dim3(nblocks(ncmax, kBlk)), dim3(kBlk), 0, s, ncmax, ncp, n, nnz, mstart, moff,
-                       emax);
+    const unsigned nb = std::min<unsigned>(nblocks(ncmax, kBlk), (unsigned)kGalLenBlocks);
+    hipLaunchKernelGGL(k_gal_agg_len, dim3(nb), dim3(kBlk), 0, s, ncmax, ncp, n, nnz, mstart, moff, emax);
     return hipGetLastError();
 }
 
-hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int lanes, const int32_t* mstart, const int32_t* mpos,
+hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int slots, const int32_t* members, const int32_t* mstart,
                              const int32_t* moff, const int32_t* rp, const int32_t* col, const double* w,
-                             const int32_t* agg, int32_t* sb, double* sw, int32_t* tcol, double* tw, int32_t* rowlen,
-                             int32_t* big, unsigned* nbig, hipStream_t s) {
-    const unsigned sb_blocks = nblocks((int64_t)n * lanes, kBlk);
-    switch (lanes) {
-        case 1: hipLaunchKernelGGL(k_gal_stage<1>, dim3(sb_blocks), dim3(kBlk), 0, s, n, mpos, moff, rp, col, w, agg, sb, sw); break;
-        case 2: hipLaunchKernelGGL(k_gal_stage<2>, dim3(sb_blocks), dim3(kBlk), 0, s, n, mpos, moff, rp, col, w, agg, sb, sw); break;
-        case 4: hipLaunchKernelGGL(k_gal_stage<4>, dim3(sb_blocks), dim3(kBlk), 0, s, n, mpos, moff, rp, col, w, agg, sb, sw); break;
-        case 8: hipLaunchKernelGGL(k_gal_stage<8>, dim3(sb_blocks), dim3(kBlk), 0, s, n, mpos, moff, rp, col, w, agg, sb, sw); break;
+                             const int32_t* agg, int32_t* tcol, double* tw, int32_t* rowlen, int32_t* big,
+                             unsigned* nbig, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlk), 0, s, nbig, 0u, (int64_t)1);
+    const unsigned nb = nblocks(nc, kBlk);
+    switch (slots) {
+        case 16:
+            hipLaunchKernelGGL(k_gal_lane<16>, dim3(nb), dim3(kBlk), 0, s, nc, members, mstart, moff, rp, col, w,
+                               agg, tcol, tw, rowlen, big, nbig);
+            break;
+        case 32:
+            hipLaunchKernelGGL(k_gal_lane<32>, dim3(nb), dim3(kBlk), 0, s, nc, members, mstart, moff, rp, col, w,
+                               agg, tcol, tw, rowlen, big, nbig);
+            break;
+        case 0: hipLaunchKernelGGL(k_gal_all, dim3(nb), dim3(kBlk), 0, s, nc, big, nbig); break;
         default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlk), 0, s, nbig, 0u, (int64_t)1);
-    const unsigned gb_blocks = std::min<unsigned>(nblocks(nc, kBlk / kGalLanes), 256u * 8u);
-    hipLaunchKernelGGL(k_gal_gather, dim3(gb_blocks), dim3(kBlk), 0, s, nc, n, nnz, mstart, moff,
-                       (const int32_t*)sb, (const double*)sw, tcol, tw, rowlen, big, nbig);
-    hipLaunchKernelGGL(k_gal_big, dim3(1024), dim3(kBlk), 0, s, n, nnz, mstart, moff, (const int32_t*)sb,
-                       (const double*)sw, (const int32_t*)big, (const unsigned*)nbig, tcol, tw, rowlen);
+    hipLaunchKernelGGL(k_gal_wave, dim3(1024), dim3(kBlk), 0, s, n, nnz, members, mstart, moff, rp, col, w, agg,
+                       (const int32_t*)big, (const unsigned*)nbig, tcol, tw, rowlen);
     return hipGetLastError();
 }
 

@@ -518,9 +518,11 @@ def test_block_register_rows_and_csr_agree_with_oracle(name):
 
 @pytest.mark.parametrize("name", ["grid128", "rgg60k", "cl30k", "grid3d_20", "real_rgg"])
 def test_galerkin_gather_and_sort_agree(name):
-    # coarse rows formed per aggregate (default where aggregates are small)
-    # and by the radix sort (galerkin=1) sum in the same fine CSR order:
-    # both hierarchies bitwise equal to the oracle's, real weights included
+    # coarse rows formed per aggregate (default where aggregates are small:
+    # in registers, the rows with many columns by a wavefront's sort), every
+    # row by the wavefront's sort (galerkin=2) and by the radix sort over the
+    # level (galerkin=1) sum in the same fine CSR order: all hierarchies
+    # bitwise equal to the oracle's, real weights included
     if name == "real_rgg":
         g = G.rgg(40000, 10.0, seed=12, int_weights=False)
         rng = np.random.default_rng(3)
@@ -530,7 +532,7 @@ def test_galerkin_gather_and_sort_agree(name):
     else:
         g = _named(name)
     ref = oracle_of(g)
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         lam, x, st, levels, arrays = run_gpu(g, galerkin=mode)
         # g = 2 max degree sums real weights in another order than the oracle
         assert_fp64_parity(g, lam, x, st, levels, arrays, ref, exact_g=name != "real_rgg")
@@ -559,3 +561,36 @@ def test_barrier_fallback_mixed():
     lam, x, st, levels, _ = run_gpu(g, want_levels=False, test_abort_level=0, precision=1, mixed_min_nnz=1)
     assert st.fallback == 1
     assert abs(lam - ref.lam) <= MIXED_LAM_RTOL * ref.lam
+
+
+@pytest.mark.parametrize("name", ["grid128", "grid3d_20", "rgg60k", "grid_aniso", "cl30k"])
+@pytest.mark.parametrize("mode", ["grid", "step", "mixed"])
+def test_narrow_weight_storage_is_bitwise_fp64_storage(name, mode):
+    # the grid and step kernels read no weights where all are 1 and an FP32
+    # copy where all are exact in FP32: the values are the same doubles, so
+    # step counts, lambda and the vector equal FP64 storage bit for bit,
+    # and both match the oracle
+    g = _named(name)
+    ref = oracle_of(g)
+    kw = {"block_rows": 1}
+    if mode == "step":
+        kw["step_mode"] = 1
+    if mode == "mixed":
+        kw.update(precision=1, mixed_min_nnz=1)
+    runs = {}
+    for ws in (0, 1):
+        lam, x, st, levels, _ = run_gpu(g, want_levels=False, weight_storage=ws, **kw)
+        runs[ws] = (lam, x, [l.k for l in levels], [l.weights for l in levels])
+    say(f"[weights] {name} {mode}: storage {runs[0][3]} vs {runs[1][3]} k {runs[0][2]}")
+    assert runs[0][2] == runs[1][2]
+    assert runs[0][0] == runs[1][0]
+    assert np.array_equal(runs[0][1], runs[1][1])
+    unit = bool(np.all(g.w == 1.0))
+    if mode != "mixed":
+        assert all(w == 0 for w in runs[1][3])
+        assert (runs[0][3][0] == 2) == unit, runs[0][3]
+        if mode == "grid" and name in ("rgg60k", "grid_aniso"):
+            assert runs[0][3][0] == 1, runs[0][3]
+        assert [l.k for l in ref.levels] == runs[0][2]
+    lam_ref = ref.lam
+    assert abs(runs[0][0] - lam_ref) <= (1e-5 if mode == "mixed" else 1e-9) * abs(lam_ref)

@@ -78,6 +78,8 @@ struct HostLevel {
     int32_t* fpart = nullptr;  // ... and its row split
     int fbgrid = 0;            // persistent level: workgroups of its step-mode fallback
     int32_t* fbpart = nullptr; // ... and their row split
+    int lmin = 0x7fffffff;     // rows traversal: rows with more entries are long
+    int32_t* lrows = nullptr;  // ... their count and the list (nullptr: none)
     int k = 0;
     double margin = 0.0;
     double pi_ms = 0.0;
@@ -733,15 +735,22 @@ LevelDev level_dev(const HostLevel& L) {
     d.stage = L.stage;
     d.kfix = L.kfix;
     d.wk = L.wk;
+    d.lmin = L.lrows ? L.lmin : 0x7fffffff;
+    d.lrows = L.lrows;
     return d;
 }
 
-// SpMV traversal of a grid level: rows per lane group unless the longest
-// row dwarfs the mean (skewed degrees), then the merge path.
+// SpMV traversal of a grid level: rows per lane group (rows far longer than
+// the lanes' share summed by whole workgroups), unless the longest row
+// dwarfs the mean (skewed degrees) on a level of short rows, then the merge
+// path: there many rows of a few hundred entries would each hold a small
+// lane group (measured on 4M-vertex Chung-Lu graphs: merge path faster at
+// 8 lanes per row, rows traversal at 64).
 int choose_variant(const HostLevel& L, int requested) {
     if (requested == 1 || requested == 2) return requested;
     const double avg = L.nnz / (double)std::max(L.n, 1);
-    return (L.maxlen > 256 && L.maxlen > 32.0 * avg) ? 2 : 1;
+    const bool skewed = L.maxlen > 256 && L.maxlen > 32.0 * avg;
+    return (skewed && pick_lanes(avg) < 32) ? 2 : 1;
 }
 
 size_t align8h(size_t b) { return (b + 7) & ~(size_t)7; }
@@ -787,6 +796,9 @@ int64_t step_bytes(const HostLevel& L) {
 // us of fixed launches and host checks, which only levels with many steps
 // recover; in a cascadic cycle those are the coarser ones.
 constexpr int64_t kStepModeBytes = (int64_t)16 << 20;
+// rows traversal: rows longer than max(kLongRowMin, 32 lanes) are long
+// (summed by a whole workgroup)
+constexpr int kLongRowMin = 256;
 constexpr int kStepModeDepth = 2;
 constexpr int64_t kStepWork = 4096;
 constexpr int kStepChunk = 8;
@@ -1027,6 +1039,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         c->coarse_done = true;
     }
     int max_step_grid = 0;
+    int32_t* lt_flags = nullptr;  // long-row list scratch (freed once the plan is built)
     for (int j = 0; j <= J; ++j) {
         HostLevel& L = c->lv[j];
         L.fp32 = 0;
@@ -1059,6 +1072,25 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         if (o.autotune && !L.in_block && !L.step && j <= top) {
             cmg_status st = tune_level(c, j, maxgrid);
             if (st != CMG_OK) return st;
+        }
+        // hub rows of a rows-traversal level are summed by whole workgroups
+        L.lrows = nullptr;
+        L.lmin = std::max(kLongRowMin, 32 * L.lanes);
+        if (!L.in_block && j <= top && L.variant == 1 && L.maxlen > L.lmin) {
+            // flags and positions (n0 ints each, n0 rounded up to even), scan
+            // scratch and the total, for any level
+            const int64_t n0e = ((int64_t)c->lv[0].n + 1) & ~(int64_t)1;
+            if (!lt_flags) {
+                const size_t nb = sizeof(int32_t) * 2 * (size_t)n0e +
+                                  sizeof(long long) * (size_t)(scan_tmp_elems(c->lv[0].n) + 8);
+                lt_flags = (int32_t*)c->dalloc_direct(nb);
+                if (!lt_flags) return CMG_E_OOM;
+            }
+            int32_t* lt_pos = lt_flags + n0e;
+            long long* lt_scan = (long long*)(lt_pos + n0e);
+            long long* lt_total = lt_scan + scan_tmp_elems(c->lv[0].n) + 4;
+            ALLOC(L.lrows, int32_t, 1 + L.nnz / ((int64_t)L.lmin + 1));
+            CK(launch_long_rows(L.n, L.rp, L.lmin, lt_flags, lt_pos, lt_scan, lt_total, L.lrows, c->stream));
         }
         if (L.step) {
             if (j == 0) {  // the finishing pass keeps a co-resident grid
@@ -1213,6 +1245,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         for (auto& e : c->events) CK(hipEventCreate(&e));
     }
     CK(hipStreamSynchronize(c->stream));
+    if (lt_flags) c->dfree_direct(lt_flags);
     return CMG_OK;
 }
 

@@ -184,6 +184,8 @@ struct LevelDev {
     int32_t stage;       // grid levels: 1 if a workgroup's rows may be staged in LDS
     int32_t kfix;        // > 0: fixed schedule, exactly this many PI steps and no stopping test
     int32_t wk;          // weight storage of the grid and step kernels (kWNative, kWF32, kWUnit)
+    int32_t lmin;        // rows traversal: rows with more entries are long (INT_MAX: none)
+    const int32_t* lrows;// ... their count, then the long rows in ascending order (nullptr: none)
 };
 
 // State a refinement launch leaves for the next level (device written).

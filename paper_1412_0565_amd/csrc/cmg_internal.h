@@ -167,6 +167,11 @@ hipError_t launch_gal_reduce(int64_t m, const unsigned long long* keys, const do
 int64_t gal_part_elems(int64_t m);
 hipError_t launch_partition(int n, int64_t nnz, const int32_t* rp, int nb, int32_t* part,
                             hipStream_t s);
+// Rows with more than lmin entries: out[0] = count, out[1..] = the rows in
+// ascending order (out holds 1 + nnz / (lmin + 1) ints; flags, pos: n ints;
+// scan_tmp: scan_tmp_elems(n) + 4; total: one long long).
+hipError_t launch_long_rows(int n, const int32_t* rp, int lmin, int32_t* flags, int32_t* pos, long long* scan_tmp,
+                            long long* total, int32_t* out, hipStream_t s);
 hipError_t launch_hash_probe(uint64_t seed, int level, int count, unsigned long long* out,
                              hipStream_t s);
 hipError_t launch_fill_u32(unsigned* p, unsigned v, int64_t m, hipStream_t s);

@@ -1233,16 +1233,38 @@ struct ResidualOp {
 // Each lane group takes two rows at a time (rows i and i + ngroups) so the
 // loads of both are in flight together; the rows are still emitted in the
 // order i, i + ngroups, i + 2 ngroups, ... of a one-row loop.
+//
+// Rows with more than lmin entries (the hubs of a skewed degree
+// distribution; lrows lists them in ascending order after their count) are
+// left out of the groups' loop and summed afterwards by the whole
+// workgroup, one after the other in ascending order, so a hub row no longer
+// holds one lane group while the others idle.  `red` is block_sum scratch;
+// rows r of the traversal are rows r + loff of the list (an LDS stage).
+
+__device__ __forceinline__ int lower_bound_i32(const int32_t* __restrict__ a, int n, int v) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
 
 template <int G, class Op>
-__device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r0, int r1, Op& op) {
+__device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r0, int r1, Op& op,
+                                           const int32_t* __restrict__ lrows = nullptr, int lmin = 0x7fffffff,
+                                           double* red = nullptr, int loff = 0) {
     const int lane = threadIdx.x & (G - 1);
     const int ngroups = blockDim.x / G;
     int i = r0 + (int)(threadIdx.x / G);
     for (; i + ngroups < r1; i += 2 * ngroups) {
         const int i2 = i + ngroups;
-        const int a1 = rp[i], b1 = rp[i + 1];
-        const int a2 = rp[i2], b2 = rp[i2 + 1];
+        const int a1 = rp[i], a2 = rp[i2];
+        int b1 = rp[i + 1], b2 = rp[i2 + 1];
+        const bool l1 = b1 - a1 > lmin, l2 = b2 - a2 > lmin;
+        if (l1) b1 = a1;
+        if (l2) b2 = a2;
         const double x1 = op.xi(i), x2 = op.xi(i2);
         double t1 = 0.0, t2 = 0.0;
         int e1 = a1 + lane, e2 = a2 + lane;
@@ -1259,17 +1281,33 @@ __device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r
         t1 = group_sum_t<G>(t1);
         t2 = group_sum_t<G>(t2);
         if (lane == 0) {
-            op.row(i, x1, t1);
-            op.row(i2, x2, t2);
+            if (!l1) op.row(i, x1, t1);
+            if (!l2) op.row(i2, x2, t2);
         }
     }
     if (i < r1) {
         const int a = rp[i], b = rp[i + 1];
-        const double x = op.xi(i);
-        double t = 0.0;
-        for (int e = a + lane; e < b; e += G) t += op.entry(e, x);
-        t = group_sum_t<G>(t);
-        if (lane == 0) op.row(i, x, t);
+        if (b - a <= lmin) {
+            const double x = op.xi(i);
+            double t = 0.0;
+            for (int e = a + lane; e < b; e += G) t += op.entry(e, x);
+            t = group_sum_t<G>(t);
+            if (lane == 0) op.row(i, x, t);
+        }
+    }
+    if (lrows != nullptr) {
+        const int cnt = lrows[0];
+        const int32_t* lr = lrows + 1;
+        const int q1 = lower_bound_i32(lr, cnt, r1 + loff);
+        for (int q = lower_bound_i32(lr, cnt, r0 + loff); q < q1; ++q) {
+            const int r = lr[q] - loff;
+            const int a = rp[r], b = rp[r + 1];
+            const double x = op.xi(r);
+            double t[1] = {0.0};
+            for (int e = a + (int)threadIdx.x; e < b; e += (int)blockDim.x) t[0] += op.entry(e, x);
+            block_sum<1>(t, red);
+            if (threadIdx.x == 0) op.row(r, x, t[0]);
+        }
     }
 }
 
@@ -1419,11 +1457,11 @@ __device__ __forceinline__ void drive_merge(const int32_t* __restrict__ rp, int 
 
 // TRAV = 0: merge path; TRAV = G > 0: G lanes per row.
 template <int TRAV, class Op>
-__device__ __forceinline__ void drive(const LevelDev& L, int r0, int r1, Op& op, MergeShared* sh) {
+__device__ __forceinline__ void drive(const LevelDev& L, int r0, int r1, Op& op, MergeShared* sh, double* red) {
     if constexpr (TRAV == 0) {
         drive_merge(L.rp, r0, r1, op, *sh);
     } else {
-        drive_rows<TRAV>(L.rp, r0, r1, op);
+        drive_rows<TRAV>(L.rp, r0, r1, op, L.lrows, L.lmin, red);
     }
 }
 
@@ -1522,7 +1560,7 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
         op.s = s;
         op.acc[0] = op.acc[1] = op.acc[2] = op.acc[3] = 0.0;
         if constexpr (TRAV == 0) drive_merge(L.rp, r0, r1, op, *sh);
-        else drive_rows<TRAV>(trp, tlo, thi, op);
+        else drive_rows<TRAV>(trp, tlo, thi, op, L.lrows, L.lmin, red, roff);
         if (!job_allreduce<4>(op.acc, c, red)) return;
         const double mu2 = op.acc[0] / n;
         const double s2 = 1.0 / sqrt(op.acc[1] - op.acc[0] * mu2);
@@ -1584,7 +1622,7 @@ __device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeSha
         op.s = st.s_prev;
         op.g = L.g;
         op.acc[0] = op.acc[1] = 0.0;
-        drive<TRAV>(L, r0, r1, op, sh);
+        drive<TRAV>(L, r0, r1, op, sh, red);
         if (!job_allreduce<2>(op.acc, c, red)) return;
         mu = op.acc[0] / n;
         s = 1.0 / sqrt(op.acc[1] - op.acc[0] * mu);
@@ -1599,7 +1637,7 @@ __device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     eo.mu = mu;
     eo.s = s;
     eo.acc[0] = eo.acc[1] = eo.acc[2] = 0.0;
-    drive<TRAV>(L, r0, r1, eo, sh);
+    drive<TRAV>(L, r0, r1, eo, sh, red);
     if (!job_allreduce<3>(eo.acc, c, red)) return;
     const double mean_u = eo.acc[0] / n;
     const double nrm2 = eo.acc[1] - eo.acc[0] * mean_u;
@@ -1617,7 +1655,7 @@ __device__ void finish_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     ro.lam = lam;
     ro.yout = J.yout;
     ro.acc[0] = 0.0;
-    drive<TRAV>(L, r0, r1, ro, sh);
+    drive<TRAV>(L, r0, r1, ro, sh, red);
     if (!job_allreduce<1>(ro.acc, c, red)) return;
     if (c.vb == 0 && threadIdx.x == 0) {
         J.fo->lambda = lam;
@@ -1875,7 +1913,7 @@ __global__ void __launch_bounds__(kStepBlock) k_step_spmv(const StepJob* __restr
     op.mu = c.mu;
     op.s = c.s;
     op.acc[0] = op.acc[1] = op.acc[2] = op.acc[3] = 0.0;
-    drive_rows<G>(L.rp, r0, r1, op);
+    drive_rows<G>(L.rp, r0, r1, op, L.lrows, L.lmin, red);
     post_part<4>(op.acc, red, J.part);
 }
 

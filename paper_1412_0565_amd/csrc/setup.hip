@@ -1031,6 +1031,22 @@ __global__ void k_sort_scatter(const unsigned long long* __restrict__ kin,
     }
 }
 
+// ------------------------------------------------------------- long rows
+
+// rows with more than lmin entries flagged, then listed in ascending order
+// after their count (out[0] = count, out[1 + k] = k-th long row)
+__global__ void k_long_flags(int n, const int32_t* __restrict__ rp, int lmin, int32_t* __restrict__ flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flags[i] = rp[i + 1] - rp[i] > lmin ? 1 : 0;
+}
+
+__global__ void k_long_fill(int n, const int32_t* __restrict__ flags, const int32_t* __restrict__ pos,
+                            const long long* __restrict__ total, int32_t* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flags[i]) out[1 + pos[i]] = i;
+    if (i == 0) out[0] = (int32_t)*total;
+}
+
 // ------------------------------------------------------------- partition
 
 // Row range of each workgroup: boundaries on the merge path of (rows, nnz)
@@ -1320,6 +1336,16 @@ hipError_t launch_gal_reduce(int64_t m, const unsigned long long* keys, const do
                        heads, idx, mult, 1.0 / (double)mult, nc, zc, rp_out, col_out, w_out, part);
     if (part != nullptr && nb > 1)
         hipLaunchKernelGGL(k_gal_fix, dim3(nblocks(nb, kBlk)), dim3(kBlk), 0, s, m, nb, heads, idx, part, w_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_long_rows(int n, const int32_t* rp, int lmin, int32_t* flags, int32_t* pos, long long* scan_tmp,
+                            long long* total, int32_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_long_flags, dim3(nblocks(n, kBlk)), dim3(kBlk), 0, s, n, rp, lmin, flags);
+    hipError_t e = launch_scan(flags, pos, n, scan_tmp, total, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_long_fill, dim3(nblocks(n, kBlk)), dim3(kBlk), 0, s, n, (const int32_t*)flags,
+                       (const int32_t*)pos, (const long long*)total, out);
     return hipGetLastError();
 }
 

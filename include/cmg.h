@@ -35,7 +35,10 @@
  *  - Errors: only status codes cross the ABI.  On failure of cmg_setup,
  *    *out is set to NULL and everything allocated is released.
  *    CMG_W_MAXIT is a warning: the result is still written.
- *  - Synchronisation: every call returns after its work has completed.
+ *  - Synchronisation: every call returns after its work has completed,
+ *    also with device arrays (the step counts, statistics and the barrier
+ *    fallback decision are read on the host before returning).  To queue
+ *    several solves, pass them to cmg_fiedler_batch, which shares launches.
  *  - Threads: one handle is used by one thread at a time; distinct handles
  *    are independent.  Calls on one device share no mutable state except
  *    the allocator the caller supplies.

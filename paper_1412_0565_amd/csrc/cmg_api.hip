@@ -418,7 +418,7 @@ void free_tmp(cmg_ctx* c, SetupTmp& t) {
 cmg_status level_rowinfo(cmg_ctx* c, SetupTmp& t, int j) {
     HostLevel& L = c->lv[j];
     if (j >= kMaxLevels) return CMG_E_DEVICE;
-    CK(launch_rowinfo(L.n, L.lanes, L.rp, L.col, L.w64, t.h, t.bmax, t.ri + 4 * j, c->stream));
+    CK(launch_rowinfo(L.n, L.lanes, L.rp, L.col, L.w64, L.wunit, t.h, t.bmax, t.ri + 4 * j, c->stream));
     t.ri_pending.push_back(j);
     return CMG_OK;
 }
@@ -537,8 +537,8 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
             const int slots = (c->opt.galerkin == 2 || nc < kGalLaneMinRows) ? 0
                               : L.nnz <= 7 * (int64_t)L.n                    ? 16
                                                                              : 32;
-            CK(launch_gal_gather(nc, L.n, L.nnz, slots, members, mstart, moff, L.rp, L.col, L.w64, L.agg, tcol, tw,
-                                 rowlen, t.heads, (unsigned*)(t.scal + 5), s));
+            CK(launch_gal_gather(nc, L.n, L.nnz, slots, L.wunit, members, mstart, moff, L.rp, L.col, L.w64, L.agg,
+                                 tcol, tw, rowlen, t.heads, (unsigned*)(t.scal + 5), s));
             HostLevel C;
             C.n = nc;
             ALLOC(C.rp, int32_t, nc + 1);

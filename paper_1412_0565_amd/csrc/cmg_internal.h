@@ -78,7 +78,8 @@ hipError_t launch_to_f32(int64_t nnz, const double* w64, float* w32, hipStream_t
 // bits of the longest row length (as a double).
 // bmax: scratch of 4 * kRowinfoMaxBlocks doubles.
 constexpr int kRowinfoMaxBlocks = 1024;
-hipError_t launch_rowinfo(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w,
+// (unit: every weight is 1; w is then not read)
+hipError_t launch_rowinfo(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w, int unit,
                           int32_t* h, double* bmax, unsigned long long* out, hipStream_t s);
 hipError_t launch_hec_init(int n, const int32_t* h, uint64_t seed, int level, uint8_t* live,
                            uint8_t* state, int32_t* pairseed, unsigned long long* slot, hipStream_t s);
@@ -108,10 +109,10 @@ hipError_t launch_gal_agg_len(int ncmax, const long long* ncp, int n, int64_t nn
                               const int32_t* moff, unsigned long long* emax, hipStream_t s);
 // (slots: 16 or 32 distinct columns a lane keeps in registers, 0 for none;
 // big: nc ints listing the aggregates with more, nbig their count)
-hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int slots, const int32_t* members, const int32_t* mstart,
-                             const int32_t* moff, const int32_t* rp, const int32_t* col, const double* w,
-                             const int32_t* agg, int32_t* tcol, double* tw, int32_t* rowlen, int32_t* big,
-                             unsigned* nbig, hipStream_t s);
+hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int slots, int unit, const int32_t* members,
+                             const int32_t* mstart, const int32_t* moff, const int32_t* rp, const int32_t* col,
+                             const double* w, const int32_t* agg, int32_t* tcol, double* tw, int32_t* rowlen,
+                             int32_t* big, unsigned* nbig, hipStream_t s);
 hipError_t launch_gal_compact(int nc, const int32_t* mstart, const int32_t* moff, const int32_t* crp,
                               const int32_t* tcol, const double* tw, int32_t* col_out, double* w_out,
                               hipStream_t s);

@@ -173,6 +173,31 @@ __global__ void k_rowinfo(int n, const int32_t* __restrict__ rp, const int32_t* 
     }
 }
 
+// The same for a level whose weights are all 1: the heaviest neighbour is
+// the lowest column (the row's first entry), the weighted degree the row
+// length; the weights are not read.
+__global__ void k_rowinfo_unit(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                               int32_t* __restrict__ h, double* __restrict__ bmax) {
+    double lmax = 0.0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const int a = rp[v], b = rp[v + 1];
+        h[v] = col[a];
+        lmax = fmax(lmax, (double)(b - a));
+    }
+    __shared__ double sm[kBlk / kWave];
+    for (int o = 32; o > 0; o >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, o, kWave));
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = lmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double d = 0.0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) d = fmax(d, sm[q]);
+        bmax[4 * blockIdx.x] = 2.0 * d;
+        bmax[4 * blockIdx.x + 1] = 1.0;
+        bmax[4 * blockIdx.x + 2] = 0.0;
+        bmax[4 * blockIdx.x + 3] = d;
+    }
+}
+
 // one block: maxima over the per-block values; results as double bit
 // patterns in out[0] (g), out[1] (largest weight), out[2] (largest FP32
 // rounding error of a weight: 0 if all weights are exact in FP32)
@@ -435,8 +460,9 @@ __global__ void k_gal_agg_len(int ncmax, const long long* __restrict__ ncp, int 
     }
 }
 
-// pass 1: a lane per aggregate, S register slots
-template <int S>
+// pass 1: a lane per aggregate, S register slots (UNIT: every weight is 1
+// and the weights are not read)
+template <int S, bool UNIT>
 __global__ void __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) k_gal_lane(int nc, const int32_t* __restrict__ members,
                                                    const int32_t* __restrict__ mstart,
                                                    const int32_t* __restrict__ moff, const int32_t* __restrict__ rp,
@@ -469,7 +495,7 @@ __global__ void __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) 
             for (int i = 0; i < kGalBatch; ++i) {
                 if (e + i < e1) {
                     cb[i] = col[e + i];
-                    xb[i] = w[e + i];
+                    xb[i] = UNIT ? 1.0 : w[e + i];
                 }
             }
 #pragma unroll
@@ -1120,8 +1146,14 @@ hipError_t launch_to_f32(int64_t nnz, const double* w64, float* w32, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_rowinfo(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w,
+hipError_t launch_rowinfo(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w, int unit,
                           int32_t* h, double* bmax, unsigned long long* out, hipStream_t s) {
+    if (unit) {
+        const unsigned nb = (unsigned)std::min<int64_t>(nblocks(n, kBlk), kRowinfoMaxBlocks);
+        hipLaunchKernelGGL(k_rowinfo_unit, dim3(nb), dim3(kBlk), 0, s, n, rp, col, h, bmax);
+        hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(kBlk), 0, s, bmax, (int)nb, out);
+        return hipGetLastError();
+    }
     int gpb = kBlk / lanes;
     unsigned nb = (unsigned)std::min<int64_t>(nblocks(n, gpb), kRowinfoMaxBlocks);
     switch (lanes) {
@@ -1198,20 +1230,28 @@ hipError_t launch_gal_agg_len(int ncmax, const long long* ncp, int n, int64_t nn
     return hipGetLastError();
 }
 
-hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int slots, const int32_t* members, const int32_t* mstart,
-                             const int32_t* moff, const int32_t* rp, const int32_t* col, const double* w,
-                             const int32_t* agg, int32_t* tcol, double* tw, int32_t* rowlen, int32_t* big,
-                             unsigned* nbig, hipStream_t s) {
+hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int slots, int unit, const int32_t* members,
+                             const int32_t* mstart, const int32_t* moff, const int32_t* rp, const int32_t* col,
+                             const double* w, const int32_t* agg, int32_t* tcol, double* tw, int32_t* rowlen,
+                             int32_t* big, unsigned* nbig, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlk), 0, s, nbig, 0u, (int64_t)1);
     const unsigned nb = nblocks(nc, kBlk);
     switch (slots) {
         case 16:
-            hipLaunchKernelGGL(k_gal_lane<16>, dim3(nb), dim3(kBlk), 0, s, nc, members, mstart, moff, rp, col, w,
-                               agg, tcol, tw, rowlen, big, nbig);
+            if (unit)
+                hipLaunchKernelGGL((k_gal_lane<16, true>), dim3(nb), dim3(kBlk), 0, s, nc, members, mstart, moff, rp,
+                                   col, w, agg, tcol, tw, rowlen, big, nbig);
+            else
+                hipLaunchKernelGGL((k_gal_lane<16, false>), dim3(nb), dim3(kBlk), 0, s, nc, members, mstart, moff, rp,
+                                   col, w, agg, tcol, tw, rowlen, big, nbig);
             break;
         case 32:
-            hipLaunchKernelGGL(k_gal_lane<32>, dim3(nb), dim3(kBlk), 0, s, nc, members, mstart, moff, rp, col, w,
-                               agg, tcol, tw, rowlen, big, nbig);
+            if (unit)
+                hipLaunchKernelGGL((k_gal_lane<32, true>), dim3(nb), dim3(kBlk), 0, s, nc, members, mstart, moff, rp,
+                                   col, w, agg, tcol, tw, rowlen, big, nbig);
+            else
+                hipLaunchKernelGGL((k_gal_lane<32, false>), dim3(nb), dim3(kBlk), 0, s, nc, members, mstart, moff, rp,
+                                   col, w, agg, tcol, tw, rowlen, big, nbig);
             break;
         case 0: hipLaunchKernelGGL(k_gal_all, dim3(nb), dim3(kBlk), 0, s, nc, big, nbig); break;
         default: return hipErrorInvalidValue;

@@ -36,10 +36,12 @@ __device__ __forceinline__ void st_agent(double* p, double v) {
 }
 
 // Workgroup b runs on XCD b % 8; give each XCD a contiguous range of row
-// blocks so neighbouring rows (and their x gathers) share one L2.
+// blocks so neighbouring rows (and their x gathers) share one L2.  XCD x
+// runs the blocks x, x + 8, ... of [0, nb): nb / 8 of them, one more for the
+// first nb % 8 XCDs.
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
-    if (nb % 8) return b;
-    return (b & 7) * (nb >> 3) + (b >> 3);
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
 }
 
 // ~2 s at the 100 MHz constant clock: a safety bound, never reached when
@@ -1800,11 +1802,11 @@ __global__ void __launch_bounds__(kGridBlock) k_finish_jobs(const GridJob* __res
 constexpr int kCheckThreads = 1024;
 
 template <int NV>
-__device__ __forceinline__ void post_part(double (&v)[NV], double* red, double* part) {
+__device__ __forceinline__ void post_part(double (&v)[NV], double* red, double* part, int slot) {
     block_sum<NV>(v, red);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) part[4 * (size_t)blockIdx.x + q] = v[q];
+        for (int q = 0; q < NV; ++q) part[4 * (size_t)slot + q] = v[q];
     }
 }
 
@@ -1826,7 +1828,8 @@ __global__ void __launch_bounds__(kStepBlock) k_step_prolong(const StepJob* __re
     __shared__ double red[16 * 5 + 8];
     const StepJob J = *jp;
     const LevelDev& L = J.L;
-    const int r0 = L.part[blockIdx.x], r1 = L.part[blockIdx.x + 1];
+    const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);  // row block, posted in row order
+    const int r0 = L.part[lb], r1 = L.part[lb + 1];
     T* b0 = (T*)L.buf0;
     double sum[1] = {0.0};
     if (J.uniform) {
@@ -1844,7 +1847,7 @@ __global__ void __launch_bounds__(kStepBlock) k_step_prolong(const StepJob* __re
             sum[0] += (double)v;
         }
     }
-    post_part<1>(sum, red, J.part);
+    post_part<1>(sum, red, J.part, lb);
 }
 
 // mean of the start vector
@@ -1862,7 +1865,8 @@ __global__ void __launch_bounds__(kStepBlock) k_step_sumsq(const StepJob* __rest
     __shared__ double red[16 * 5 + 8];
     const StepJob J = *jp;
     const LevelDev& L = J.L;
-    const int r0 = L.part[blockIdx.x], r1 = L.part[blockIdx.x + 1];
+    const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);  // row block, posted in row order
+    const int r0 = L.part[lb], r1 = L.part[lb + 1];
     const T* b0 = (const T*)L.buf0;
     const double mu = J.ctl->mu;
     double ss[1] = {0.0};
@@ -1870,7 +1874,7 @@ __global__ void __launch_bounds__(kStepBlock) k_step_sumsq(const StepJob* __rest
         const double d = (double)b0[i] - mu;
         ss[0] += d * d;
     }
-    post_part<1>(ss, red, J.part);
+    post_part<1>(ss, red, J.part, lb);
 }
 
 // normalisation of the start vector; arms the step loop
@@ -1902,7 +1906,8 @@ __global__ void __launch_bounds__(kStepBlock) k_step_spmv(const StepJob* __restr
     const StepCtl c = *J.ctl;
     if (c.done) return;
     const LevelDev& L = J.L;
-    const int r0 = L.part[blockIdx.x], r1 = L.part[blockIdx.x + 1];
+    const int lb = xcd_remap((int)blockIdx.x, (int)gridDim.x);  // row block, posted in row order
+    const int r0 = L.part[lb], r1 = L.part[lb + 1];
     PiOp<T, WK> op;
     op.col = L.col;
     op.wv = weights_of<T, WK>(L);
@@ -1914,7 +1919,7 @@ __global__ void __launch_bounds__(kStepBlock) k_step_spmv(const StepJob* __restr
     op.s = c.s;
     op.acc[0] = op.acc[1] = op.acc[2] = op.acc[3] = 0.0;
     drive_rows<G>(L.rp, r0, r1, op, L.lrows, L.lmin, red);
-    post_part<4>(op.acc, red, J.part);
+    post_part<4>(op.acc, red, J.part, lb);
 }
 
 // sums of the step, stopping test, state for the next step; writes the

@@ -72,24 +72,12 @@ def solve_once(cmg, g_dev, n, opt, x):
     return lam, st, levels
 
 
-def kernel_source_hash():
-    """Hash of the HIP sources; HBM counter figures taken on other sources
-    no longer describe the kernel."""
-    import hashlib
-
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_1412_0565_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(workload, level0):
     """HBM bytes per level-0 refinement launch from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel), or None if
     there is none for this workload and these kernel sources."""
+    from paper_1412_0565_amd.profsum import kernel_source_hash
+
     path = os.path.join(ROOT, "profiles", f"{workload}_level0_refine_hbm_counters.md")
     try:
         kv = {}
@@ -395,8 +383,9 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_source": traffic_src,
-                "kernel": (f"k_refine_rows<{levels[0].lanes},double>" if levels[0].variant != 2 else
-                           "k_refine_merge<double>") + f" on level 0 (prolongation, deflation, {ks[-1]} PI steps)",
+                "kernel": (f"k_refine_rows<{levels[0].lanes}, double, {levels[0].weights}>" if levels[0].variant != 2
+                           else f"k_refine_merge<double, {levels[0].weights}>")
+                          + f" on level 0 (prolongation, deflation, {ks[-1]} PI steps)",
                 "bytes_per_launch": int(bytes_launch), "avg_launch_ms": round(pi_ms, 4),
                 "pi_steps_per_launch": ks[-1], "hbm_levels": hbm_levels}
 

@@ -1,20 +1,40 @@
 """Summaries of rocprofv3 output for the refinement roofline.
 
     python -m paper_1412_0565_amd.profsum trace <kernel_trace.csv> <kernel_stats.csv>
-    python -m paper_1412_0565_amd.profsum counters <fetch counter_collection.csv> <write counter_collection.csv>
+    python -m paper_1412_0565_amd.profsum counters <fetch counter_collection.csv> <write counter_collection.csv> \
+        <copy bytes> [bench JSON line of the same run]
 
 `trace` prints the busiest kernels and the duration of the finest-level
 refinement launches: in every solve the last k_refine_rows/k_refine_merge
 dispatch before the k_finish_jobs dispatch refines level 0.  `counters` prints FETCH_SIZE
 and WRITE_SIZE (KiB per dispatch) of those launches, each divided by what
 the same counter reads per byte of the reference device copy that ends
-the run (bench.py --copy-mib), i.e. HBM bytes per level-0 launch.
+the run (bench.py --copy-mib), i.e. HBM bytes per level-0 launch.  Given
+the JSON line the counted bench run printed, it also records the
+algorithmic bytes of the launch, level 0's step count and the hash of the
+kernel sources, which bench.py checks before it reports the traffic.
 """
 from __future__ import annotations
 
 import csv
+import hashlib
+import json
+import os
 import statistics
 import sys
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources: counter figures taken on other sources no
+    longer describe the kernel."""
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
 
 
 def _level0_dispatch_ids(rows, name_key, id_key):
@@ -81,7 +101,7 @@ def _elementwise_counted(per):
     return last["v"] * 1024.0
 
 
-def counters(fetch_csv, write_csv, copy_bytes):
+def counters(fetch_csv, write_csv, copy_bytes, bench_json=None):
     out = {}
     for label, path, counter in [("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")]:
         per = _counter_rows(path, counter)
@@ -101,6 +121,14 @@ def counters(fetch_csv, write_csv, copy_bytes):
                  f"- WRITE_SIZE factor of the elementwise reference: {w['ew_factor']:.4f}",
                  f"- HBM bytes per launch with the elementwise factors: "
                  f"{f['raw_mean'] / f['ew_factor'] + w['raw_mean'] / w['ew_factor']:.0f}"]
+    if bench_json is not None:
+        line = [ln for ln in open(bench_json) if ln.lstrip().startswith("{")][-1]
+        b = json.loads(line)
+        alg = int(b["roofline"]["bytes_per_launch"])
+        extra += [f"- algorithmic bytes per launch: {alg}",
+                  f"- traffic / algorithmic: {(f['bytes'] + w['bytes']) / alg:.3f}",
+                  f"- kernel sources: `{kernel_source_hash()}`",
+                  f"- level-0 k: {b['config']['pi_steps'][0]}"]
     return "\n".join([
         f"- reference copy bytes: {copy_bytes}",
         f"- FETCH_SIZE of the copy: {f['copy_counted']:.0f} bytes (factor {f['factor']:.4f})",
@@ -118,7 +146,8 @@ if __name__ == "__main__":
     if len(sys.argv) >= 4 and sys.argv[1] == "trace":
         print(trace(sys.argv[2], sys.argv[3]))
     elif len(sys.argv) >= 5 and sys.argv[1] == "counters":
-        print(counters(sys.argv[2], sys.argv[3], int(sys.argv[4]) if len(sys.argv) > 4 else 1 << 30))
+        print(counters(sys.argv[2], sys.argv[3], int(sys.argv[4]) if len(sys.argv) > 4 else 1 << 30,
+                       sys.argv[5] if len(sys.argv) > 5 else None))
     else:
         print(__doc__)
         sys.exit(2)

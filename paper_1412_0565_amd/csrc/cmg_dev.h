@@ -70,6 +70,31 @@ __device__ __forceinline__ double pair_sum_rows(double v) {
     }
 }
 
+// Explicit address spaces.  A pointer read from a descriptor in memory is
+// generic to the compiler, and generic (flat) loads make every use of a
+// loaded value wait for all outstanding memory operations, so loads that
+// could be in flight together are serialised.  gld/gst read and write
+// through a global-memory view (loads waited on one by one), sld/sst
+// through an LDS view, for pointers known to be of that kind.
+#define CMG_AS_GLOBAL __attribute__((address_space(1)))
+#define CMG_AS_LDS __attribute__((address_space(3)))
+template <typename T, typename I>
+__device__ __forceinline__ T gld(const T* p, I i) {
+    return ((const CMG_AS_GLOBAL T*)p)[i];
+}
+template <typename T, typename I>
+__device__ __forceinline__ void gst(T* p, I i, T v) {
+    ((CMG_AS_GLOBAL T*)p)[i] = v;
+}
+template <typename T, typename I>
+__device__ __forceinline__ T sld(const T* p, I i) {
+    return ((const CMG_AS_LDS T*)p)[i];
+}
+template <typename T, typename I>
+__device__ __forceinline__ void sst(T* p, I i, T v) {
+    ((CMG_AS_LDS T*)p)[i] = v;
+}
+
 // Value of a lane, identical in every lane (needs that lane active).
 __device__ __forceinline__ double read_lane(double v, int lane) {
     const long long b = __double_as_longlong(v);

@@ -21,7 +21,7 @@ namespace cmg {
 namespace {
 
 __device__ __forceinline__ double ld_any(const void* p, int fp32, int64_t i) {
-    return fp32 ? (double)((const float*)p)[i] : ((const double*)p)[i];
+    return fp32 ? (double)gld((const float*)p, i) : gld((const double*)p, i);
 }
 
 __device__ __forceinline__ double ld_agent(const double* p) {
@@ -400,6 +400,18 @@ __global__ void __launch_bounds__(256) k_coarse_jobs(const CoarseJob* __restrict
 
 __device__ __forceinline__ size_t align8(size_t b) { return (b + 7) & ~(size_t)7; }
 
+// a load or store through the LDS view (LDS) or the global view
+template <bool LDS, typename T>
+__device__ __forceinline__ T ldx(const T* p, int i) {
+    if constexpr (LDS) return sld(p, i);
+    else return gld(p, i);
+}
+template <bool LDS, typename T>
+__device__ __forceinline__ void stx(T* p, int i, T v) {
+    if constexpr (LDS) sst(p, i, v);
+    else gst(p, i, v);
+}
+
 // Bytes of the LDS image of a level: two vectors, weights (FP32 when that
 // is exact), row pointers, columns (uint16 when n <= 65536).
 __device__ __forceinline__ size_t staged_bytes(const LevelDev& L, int w32, int col16) {
@@ -505,15 +517,15 @@ __device__ __forceinline__ void step_sum4(double (&v)[4], double* red, int& pari
 
 // One PI step of a small level, rows shared by `nthr` threads in G-lane
 // groups.  Pointers are either all LDS (staged modes) or all global.
-template <int G, bool W32, bool C16>
+template <int G, bool W32, bool C16, bool LDS>
 __device__ __forceinline__ void pi_small(int n, int nthr, const int32_t* rp, const void* colp,
                                          const void* wp, double g, const double* win, double* wout,
                                          double mu, double s, double (&acc)[4]) {
     const int lane = threadIdx.x & (G - 1);
     const int ngroups = nthr / G;
     for (int i = (int)(threadIdx.x / G); i < n; i += ngroups) {
-        const int a = rp[i], b = rp[i + 1];
-        const double wi = win[i];
+        const int a = ldx<LDS>(rp, i), b = ldx<LDS>(rp, i + 1);
+        const double wi = ldx<LDS>(win, i);
         double t = 0.0;
         int e = a + lane;
         // four entries per trip: their column and value loads, then their
@@ -524,24 +536,30 @@ __device__ __forceinline__ void pi_small(int n, int nthr, const int32_t* rp, con
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int f = e + q * G;
-                c[q] = C16 ? (int)((const uint16_t*)colp)[f] : ((const int32_t*)colp)[f];
-                wt[q] = W32 ? (double)((const float*)wp)[f] : ((const double*)wp)[f];
+                if constexpr (C16) c[q] = (int)ldx<LDS>((const uint16_t*)colp, f);
+                else c[q] = ldx<LDS>((const int32_t*)colp, f);
+                if constexpr (W32) wt[q] = (double)ldx<LDS>((const float*)wp, f);
+                else wt[q] = ldx<LDS>((const double*)wp, f);
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) x[q] = win[c[q]];
+            for (int q = 0; q < 4; ++q) x[q] = ldx<LDS>(win, c[q]);
 #pragma unroll
             for (int q = 0; q < 4; ++q) t += wt[q] * (x[q] - wi);
         }
         for (; e < b; e += G) {
-            const int c = C16 ? (int)((const uint16_t*)colp)[e] : ((const int32_t*)colp)[e];
-            const double wt = W32 ? (double)((const float*)wp)[e] : ((const double*)wp)[e];
-            t += wt * (win[c] - wi);
+            int c;
+            double wt;
+            if constexpr (C16) c = (int)ldx<LDS>((const uint16_t*)colp, e);
+            else c = ldx<LDS>((const int32_t*)colp, e);
+            if constexpr (W32) wt = (double)ldx<LDS>((const float*)wp, e);
+            else wt = ldx<LDS>((const double*)wp, e);
+            t += wt * (ldx<LDS>(win, c) - wi);
         }
         t = group_sum_t<G>(t);
         if (lane == 0) {
             const double x = (wi - mu) * s;
             const double y = s * (g * (wi - mu) + t);
-            wout[i] = y;
+            stx<LDS>(wout, i, y);
             acc[0] += y;
             acc[1] += y * y;
             acc[2] += y * x;
@@ -589,8 +607,8 @@ struct RegRows {
             row[r] = i < n ? i : -1;
             int a = 0, b = 0;
             if (i < n) {
-                a = L.rp[i];
-                b = L.rp[i + 1];
+                a = gld(L.rp, i);
+                b = gld(L.rp, i + 1);
                 if (b - a > G * E) *bad = 1;
             }
             const uint32_t self = i < n ? (uint32_t)i : 0u;
@@ -600,8 +618,8 @@ struct RegRows {
                 uint32_t cv = self;
                 float wv = 0.0f;
                 if (e < b) {
-                    cv = (uint32_t)L.col[e];
-                    wv = (float)L.w64[e];
+                    cv = (uint32_t)gld(L.col, e);
+                    wv = (float)gld(L.w64, e);
                 }
                 if (m & 1) c2[r][m >> 1] |= cv << 16;
                 else c2[r][m >> 1] = cv;
@@ -615,7 +633,7 @@ struct RegRows {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int i = row[r];
-            const double wi = win[i < 0 ? 0 : i];
+            const double wi = sld(win, i < 0 ? 0 : i);
             if constexpr (R * E > 32) {
                 // decode the columns and widen the weights every step:
                 // hoisted out of the step loop they would not fit
@@ -626,7 +644,7 @@ struct RegRows {
             }
             double x[E];
 #pragma unroll
-            for (int m = 0; m < E; ++m) x[m] = win[(m & 1) ? (c2[r][m >> 1] >> 16) : (c2[r][m >> 1] & 0xffffu)];
+            for (int m = 0; m < E; ++m) x[m] = sld(win, (int)((m & 1) ? (c2[r][m >> 1] >> 16) : (c2[r][m >> 1] & 0xffffu)));
             double t = 0.0;
 #pragma unroll
             for (int m = 0; m < E; ++m) t += (double)w[r][m] * (x[m] - wi);
@@ -634,7 +652,7 @@ struct RegRows {
             if (lane == 0 && i >= 0) {
                 const double xv = (wi - mu) * s;
                 const double y = s * (g * (wi - mu) + t);
-                wout[i] = y;
+                sst(wout, i, y);
                 acc[0] += y;
                 acc[1] += y * y;
                 acc[2] += y * xv;
@@ -651,6 +669,7 @@ template <int MODE, bool W32, bool C16>
 __device__ void small_level(const LevelDev& L, const SmallIn& in, double* lds, double* red, int& parity,
                             int* stop_flag, int nw_run, LevelState& out) {
     constexpr bool WAVE = (MODE == 0);
+    constexpr bool LDS = (MODE != 2);
     const int n = L.n;
     const int nthr = WAVE ? 64 : (int)blockDim.x;
     double* b0;
@@ -679,13 +698,13 @@ __device__ void small_level(const LevelDev& L, const SmallIn& in, double* lds, d
     if (in.uniform) {
         for (int i = threadIdx.x; i < n; i += nthr) {
             const double v = hashed_uniform(in.seed, i) - 0.5;
-            b0[i] = v;
+            stx<LDS>(b0, i, v);
             sum[0] += v;
         }
     } else {
         for (int i = threadIdx.x; i < n; i += nthr) {
-            const double v = (ld_any(in.cbuf, in.cfp32, L.agg[i]) - in.cm) * in.cs;
-            b0[i] = v;
+            const double v = (ld_any(in.cbuf, in.cfp32, gld(L.agg, i)) - in.cm) * in.cs;
+            stx<LDS>(b0, i, v);
             sum[0] += v;
         }
     }
@@ -693,7 +712,7 @@ __device__ void small_level(const LevelDev& L, const SmallIn& in, double* lds, d
     double mu = sum[0] / (double)n;
     double ss[1] = {0.0};
     for (int i = threadIdx.x; i < n; i += nthr) {
-        const double d = b0[i] - mu;
+        const double d = ldx<LDS>(b0, i) - mu;
         ss[0] += d * d;
     }
     small_sum<1, WAVE>(ss, red, parity);
@@ -712,13 +731,13 @@ __device__ void small_level(const LevelDev& L, const SmallIn& in, double* lds, d
             double* wout = cur ? b0 : b1;
             double acc[4] = {0.0, 0.0, 0.0, 0.0};
             switch (L.lanes) {
-                case 1: pi_small<1, W32, C16>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
-                case 2: pi_small<2, W32, C16>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
-                case 4: pi_small<4, W32, C16>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
-                case 8: pi_small<8, W32, C16>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
-                case 16: pi_small<16, W32, C16>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
-                case 32: pi_small<32, W32, C16>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
-                default: pi_small<64, W32, C16>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+                case 1: pi_small<1, W32, C16, LDS>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+                case 2: pi_small<2, W32, C16, LDS>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+                case 4: pi_small<4, W32, C16, LDS>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+                case 8: pi_small<8, W32, C16, LDS>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+                case 16: pi_small<16, W32, C16, LDS>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+                case 32: pi_small<32, W32, C16, LDS>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
+                default: pi_small<64, W32, C16, LDS>(n, nact, rp, colp, wp, L.g, win, wout, mu, s, acc); break;
             }
             step_sum4<WAVE>(acc, red, parity, nw);
             const double mu2 = acc[0] / (double)n;
@@ -757,8 +776,8 @@ __device__ void small_level(const LevelDev& L, const SmallIn& in, double* lds, d
         double* g0 = (double*)L.buf0;
         double* g1 = (double*)L.buf1;
         for (int i = threadIdx.x; i < n; i += nact) {
-            g0[i] = src[i];
-            g1[i] = prv[i];
+            gst(g0, i, sld(src, i));
+            gst(g1, i, sld(prv, i));
         }
         fin = 0;
     }
@@ -824,12 +843,14 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
             int32_t* rdst = (int32_t*)p;
             p += align8(4 * ((size_t)n + 1));
             void* cdst = p;
-            for (int i = threadIdx.x; i <= n; i += blockDim.x) rdst[i] = L.rp[i];
+            for (int i = threadIdx.x; i <= n; i += blockDim.x) sst(rdst, i, gld(L.rp, i));
             for (int e = threadIdx.x; e < (int)L.nnz; e += blockDim.x) {
-                if (c16) ((uint16_t*)cdst)[e] = (uint16_t)L.col[e];
-                else ((int32_t*)cdst)[e] = L.col[e];
-                if (w32) ((float*)wdst)[e] = (float)L.w64[e];
-                else ((double*)wdst)[e] = L.w64[e];
+                const int cv = gld(L.col, e);
+                const double wv = gld(L.w64, e);
+                if (c16) sst((uint16_t*)cdst, e, (uint16_t)cv);
+                else sst((int32_t*)cdst, e, (int32_t)cv);
+                if (w32) sst((float*)wdst, e, (float)wv);
+                else sst((double*)wdst, e, wv);
             }
             __syncthreads();
         }
@@ -895,13 +916,13 @@ __device__ void reg_level(const LevelDev& L, const SmallIn& in, double* b0, doub
     if (in.uniform) {
         for (int i = threadIdx.x; i < n; i += nthr) {
             const double v = hashed_uniform(in.seed, i) - 0.5;
-            b0[i] = v;
+            sst(b0, i, v);
             sum[0] += v;
         }
     } else {
         for (int i = threadIdx.x; i < n; i += nthr) {
-            const double v = (ld_any(in.cbuf, in.cfp32, L.agg[i]) - in.cm) * in.cs;
-            b0[i] = v;
+            const double v = (ld_any(in.cbuf, in.cfp32, gld(L.agg, i)) - in.cm) * in.cs;
+            sst(b0, i, v);
             sum[0] += v;
         }
     }
@@ -910,7 +931,7 @@ __device__ void reg_level(const LevelDev& L, const SmallIn& in, double* b0, doub
     double mu = sum[0] / (double)n;
     double ss[1] = {0.0};
     for (int i = threadIdx.x; i < n; i += nthr) {
-        const double d = b0[i] - mu;
+        const double d = sld(b0, i) - mu;
         ss[0] += d * d;
     }
     if (wave) small_sum<1, true>(ss, red, parity);
@@ -961,8 +982,8 @@ __device__ void reg_level(const LevelDev& L, const SmallIn& in, double* b0, doub
     double* g0 = (double*)L.buf0;
     double* g1 = (double*)L.buf1;
     for (int i = threadIdx.x; i < n; i += nact) {
-        g0[i] = src[i];
-        g1[i] = prv[i];
+        gst(g0, i, sld(src, i));
+        gst(g1, i, sld(prv, i));
     }
     if (wave) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     out.mu = mu;
@@ -1073,13 +1094,16 @@ __device__ __forceinline__ bool job_allreduce(double (&v)[NV], GridCtx& c, doubl
 // WUnit where every weight is 1 and nothing is read.  The value is the
 // same double in all three, so results do not depend on the storage.
 struct WUnit {};
-template <typename W>
+template <typename W, bool LDS = false>
 struct WRead {
     const W* __restrict__ p;
-    __device__ __forceinline__ double operator[](int e) const { return (double)p[e]; }
+    __device__ __forceinline__ double operator[](int e) const {
+        if constexpr (LDS) return (double)sld(p, e);
+        else return (double)gld(p, e);
+    }
 };
-template <>
-struct WRead<WUnit> {
+template <bool LDS>
+struct WRead<WUnit, LDS> {
     const void* p;
     __device__ __forceinline__ double operator[](int) const { return 1.0; }
 };
@@ -1116,30 +1140,34 @@ __device__ __forceinline__ FinW<WK> fin_weights(const LevelDev& L) {
 // One PI step: y_i = s (g (w_i - mu) + sum_k a_ik (w_k - w_i)), stored as
 // T; acc += {y, y^2, y v, v} with v = (w_i - mu) s.
 // Rows and entries are numbered from the arrays the traversal reads (the
-// level's, or a workgroup's LDS stage); vector index = row + roff.
-template <typename T, int WK>
+// level's, or with STG a workgroup's LDS stage); vector index = row + roff.
+template <typename T, int WK, bool STG = false>
 struct PiOp {
     const int32_t* __restrict__ col;
-    WRead<typename WStore<T, WK>::type> wv;
+    WRead<typename WStore<T, WK>::type, STG> wv;
     const T* __restrict__ win;
     T* __restrict__ wout;
     int roff;
     double mu, s, g;
     double acc[4];
-    __device__ __forceinline__ double xi(int i) const { return (double)win[roff + i]; }
-    __device__ __forceinline__ double entry(int e, double x) const {
-        return wv[e] * ((double)win[col[e]] - x);
+    __device__ __forceinline__ double xi(int i) const { return (double)gld(win, roff + i); }
+    __device__ __forceinline__ int vidx(int i) const { return roff + i; }
+    // an entry's term split into its loads (column and weight, then the
+    // gathered vector value) and its arithmetic, so a traversal can issue
+    // the loads of several entries before it adds their terms in order
+    __device__ __forceinline__ int colof(int e) const {
+        if constexpr (STG) return sld(col, e);
+        else return gld(col, e);
     }
-    // entry() on a column and weight read earlier (merge path LDS stage)
-    __device__ __forceinline__ int colof(int e) const { return col[e]; }
     __device__ __forceinline__ double wof(int e) const { return wv[e]; }
-    __device__ __forceinline__ double entry_cw(int c, double wt, double x) const {
-        return wt * ((double)win[c] - x);
-    }
+    __device__ __forceinline__ double xk(int c) const { return (double)gld(win, c); }
+    __device__ __forceinline__ double term(double xc, double wt, double x) const { return wt * (xc - x); }
+    __device__ __forceinline__ double entry(int e, double x) const { return term(xk(colof(e)), wof(e), x); }
+    __device__ __forceinline__ double entry_cw(int c, double wt, double x) const { return term(xk(c), wt, x); }
     __device__ __forceinline__ void row(int i, double x, double t) {
         const double v = (x - mu) * s;
         const T ys = (T)(s * (g * (x - mu) + t));
-        wout[roff + i] = ys;
+        gst(wout, roff + i, ys);
         const double yd = (double)ys;
         acc[0] += yd;
         acc[1] += yd * yd;
@@ -1159,17 +1187,16 @@ struct RedoOp {
     double mu, s, g;
     double acc[2];
     __device__ __forceinline__ double xi(int i) const { return ld_any(src, f32, i); }
-    __device__ __forceinline__ double entry(int e, double x) const {
-        return w[e] * (ld_any(src, f32, col[e]) - x);
-    }
-    __device__ __forceinline__ int colof(int e) const { return col[e]; }
+    __device__ __forceinline__ int vidx(int i) const { return i; }
+    __device__ __forceinline__ int colof(int e) const { return gld(col, e); }
     __device__ __forceinline__ double wof(int e) const { return w[e]; }
-    __device__ __forceinline__ double entry_cw(int c, double wt, double x) const {
-        return wt * (ld_any(src, f32, c) - x);
-    }
+    __device__ __forceinline__ double xk(int c) const { return ld_any(src, f32, c); }
+    __device__ __forceinline__ double term(double xc, double wt, double x) const { return wt * (xc - x); }
+    __device__ __forceinline__ double entry(int e, double x) const { return term(xk(colof(e)), wof(e), x); }
+    __device__ __forceinline__ double entry_cw(int c, double wt, double x) const { return term(xk(c), wt, x); }
     __device__ __forceinline__ void row(int i, double x, double t) {
         const double y = s * (g * (x - mu) + t);
-        dst[i] = y;
+        gst(dst, i, y);
         acc[0] += y;
         acc[1] += y * y;
     }
@@ -1185,16 +1212,16 @@ struct EdgeOp {
     double mu, s;
     double acc[3];
     __device__ __forceinline__ double xi(int i) const { return ld_any(src, f32, i); }
-    __device__ __forceinline__ double entry(int e, double x) const {
-        const double d = (ld_any(src, f32, col[e]) - x) * s;
-        return w[e] * d * d;
-    }
-    __device__ __forceinline__ int colof(int e) const { return col[e]; }
+    __device__ __forceinline__ int vidx(int i) const { return i; }
+    __device__ __forceinline__ int colof(int e) const { return gld(col, e); }
     __device__ __forceinline__ double wof(int e) const { return w[e]; }
-    __device__ __forceinline__ double entry_cw(int c, double wt, double x) const {
-        const double d = (ld_any(src, f32, c) - x) * s;
+    __device__ __forceinline__ double xk(int c) const { return ld_any(src, f32, c); }
+    __device__ __forceinline__ double term(double xc, double wt, double x) const {
+        const double d = (xc - x) * s;
         return wt * d * d;
     }
+    __device__ __forceinline__ double entry(int e, double x) const { return term(xk(colof(e)), wof(e), x); }
+    __device__ __forceinline__ double entry_cw(int c, double wt, double x) const { return term(xk(c), wt, x); }
     __device__ __forceinline__ void row(int i, double x, double t) {
         const double u = (x - mu) * s;
         acc[0] += u;
@@ -1214,19 +1241,18 @@ struct ResidualOp {
     double* __restrict__ yout;
     double acc[1];
     __device__ __forceinline__ double xi(int i) const { return ld_any(src, f32, i); }
-    __device__ __forceinline__ double entry(int e, double x) const {
-        return w[e] * (x - ld_any(src, f32, col[e]));
-    }
-    __device__ __forceinline__ int colof(int e) const { return col[e]; }
+    __device__ __forceinline__ int vidx(int i) const { return i; }
+    __device__ __forceinline__ int colof(int e) const { return gld(col, e); }
     __device__ __forceinline__ double wof(int e) const { return w[e]; }
-    __device__ __forceinline__ double entry_cw(int c, double wt, double x) const {
-        return wt * (x - ld_any(src, f32, c));
-    }
+    __device__ __forceinline__ double xk(int c) const { return ld_any(src, f32, c); }
+    __device__ __forceinline__ double term(double xc, double wt, double x) const { return wt * (x - xc); }
+    __device__ __forceinline__ double entry(int e, double x) const { return term(xk(colof(e)), wof(e), x); }
+    __device__ __forceinline__ double entry_cw(int c, double wt, double x) const { return term(xk(c), wt, x); }
     __device__ __forceinline__ void row(int i, double x, double t) {
         const double yi = ((x - mu) * s - mean_u) / nrm;
         const double r = t * s / nrm - lam * yi;
         acc[0] += r * r;
-        yout[i] = yi;
+        gst(yout, i, yi);
     }
 };
 
@@ -1247,13 +1273,61 @@ __device__ __forceinline__ int lower_bound_i32(const int32_t* __restrict__ a, in
     int lo = 0, hi = n;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (a[mid] < v) lo = mid + 1;
+        if (gld(a, mid) < v) lo = mid + 1;
         else hi = mid;
     }
     return lo;
 }
 
-template <int G, class Op>
+// The first kRowBatch entries of each lane in a row are loaded before any
+// of them is added: all column and weight loads of both rows are issued,
+// then all their vector gathers, then the terms are added in entry order
+// (so the sums are those of the plain loop), and a row with more entries
+// finishes in the loop.  Without the batch a lane waits for a column and
+// then its gather once per entry.  The loads are unconditional, so no
+// loaded value passes through a branch (which would make the compiler wait
+// for it early): a slot past the row's end reads the entry before the row
+// end (a valid index whenever the level has entries; the term is then
+// dropped) and gathers the row's own vector value.
+constexpr int kRowBatch = 2;
+
+template <int U, int G, class Op>
+__device__ __forceinline__ void rows_batch(const Op& op, int lane, int self1, int a1, int b1, double x1, double& t1,
+                                           int self2, int a2, int b2, double x2, double& t2) {
+    int c1[U], c2[U];
+    double w1[U], w2[U], y1[U], y2[U];
+    const int z1 = max(b1 - 1, 0), z2 = max(b2 - 1, 0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int e1 = a1 + lane + u * G, e2 = a2 + lane + u * G;
+        const int q1 = e1 < b1 ? e1 : z1, q2 = e2 < b2 ? e2 : z2;
+        c1[u] = op.colof(q1);
+        w1[u] = op.wof(q1);
+        c2[u] = op.colof(q2);
+        w2[u] = op.wof(q2);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        y1[u] = op.xk(a1 + lane + u * G < b1 ? c1[u] : self1);
+        y2[u] = op.xk(a2 + lane + u * G < b2 ? c2[u] : self2);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const double v1 = op.term(y1[u], w1[u], x1);
+        const double v2 = op.term(y2[u], w2[u], x2);
+        t1 = a1 + lane + u * G < b1 ? t1 + v1 : t1;
+        t2 = a2 + lane + u * G < b2 ? t2 + v2 : t2;
+    }
+}
+
+// SRP: the row pointers are an LDS stage (else global memory).
+template <bool SRP>
+__device__ __forceinline__ int ld_rp(const int32_t* rp, int i) {
+    if constexpr (SRP) return sld(rp, i);
+    else return gld(rp, i);
+}
+
+template <int G, bool SRP = false, class Op>
 __device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r0, int r1, Op& op,
                                            const int32_t* __restrict__ lrows = nullptr, int lmin = 0x7fffffff,
                                            double* red = nullptr, int loff = 0) {
@@ -1262,14 +1336,15 @@ __device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r
     int i = r0 + (int)(threadIdx.x / G);
     for (; i + ngroups < r1; i += 2 * ngroups) {
         const int i2 = i + ngroups;
-        const int a1 = rp[i], a2 = rp[i2];
-        int b1 = rp[i + 1], b2 = rp[i2 + 1];
+        const int a1 = ld_rp<SRP>(rp, i), a2 = ld_rp<SRP>(rp, i2);
+        int b1 = ld_rp<SRP>(rp, i + 1), b2 = ld_rp<SRP>(rp, i2 + 1);
         const bool l1 = b1 - a1 > lmin, l2 = b2 - a2 > lmin;
         if (l1) b1 = a1;
         if (l2) b2 = a2;
         const double x1 = op.xi(i), x2 = op.xi(i2);
         double t1 = 0.0, t2 = 0.0;
-        int e1 = a1 + lane, e2 = a2 + lane;
+        rows_batch<kRowBatch, G>(op, lane, op.vidx(i), a1, b1, x1, t1, op.vidx(i2), a2, b2, x2, t2);
+        int e1 = a1 + lane + kRowBatch * G, e2 = a2 + lane + kRowBatch * G;
         while (e1 < b1 || e2 < b2) {
             if (e1 < b1) {
                 t1 += op.entry(e1, x1);
@@ -1288,7 +1363,7 @@ __device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r
         }
     }
     if (i < r1) {
-        const int a = rp[i], b = rp[i + 1];
+        const int a = ld_rp<SRP>(rp, i), b = ld_rp<SRP>(rp, i + 1);
         if (b - a <= lmin) {
             const double x = op.xi(i);
             double t = 0.0;
@@ -1298,12 +1373,12 @@ __device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r
         }
     }
     if (lrows != nullptr) {
-        const int cnt = lrows[0];
+        const int cnt = gld(lrows, 0);
         const int32_t* lr = lrows + 1;
         const int q1 = lower_bound_i32(lr, cnt, r1 + loff);
         for (int q = lower_bound_i32(lr, cnt, r0 + loff); q < q1; ++q) {
-            const int r = lr[q] - loff;
-            const int a = rp[r], b = rp[r + 1];
+            const int r = gld(lr, q) - loff;
+            const int a = ld_rp<SRP>(rp, r), b = ld_rp<SRP>(rp, r + 1);
             const double x = op.xi(r);
             double t[1] = {0.0};
             for (int e = a + (int)threadIdx.x; e < b; e += (int)blockDim.x) t[0] += op.entry(e, x);
@@ -1350,9 +1425,9 @@ __device__ __forceinline__ void drive_merge(const int32_t* __restrict__ rp, int 
                                             MergeShared& sh) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
-    const int e0 = rp[r0];
+    const int e0 = gld(rp, r0);
     const int nrows = r1 - r0;
-    const int nent = rp[r1] - e0;
+    const int nent = gld(rp, r1) - e0;
     const int total = nrows + nent;
     int carry_row = -1;
     double carry_val = 0.0;
@@ -1360,7 +1435,7 @@ __device__ __forceinline__ void drive_merge(const int32_t* __restrict__ rp, int 
     for (int d0 = 0; d0 < total; d0 += kMergeChunk) {
         const int dl_end = min(kMergeChunk, total - d0);
         const int W = min(kMergeChunk + 1, nrows - ia);  // rows whose ends can lie in this chunk
-        for (int q = tid; q <= W; q += blockDim.x) sh.win[q] = rp[r0 + ia + q] - e0;
+        for (int q = tid; q <= W; q += blockDim.x) sh.win[q] = gld(rp, r0 + ia + q) - e0;
         // the chunk's entries start where the previous chunk's ended and
         // are at most kMergeChunk (those past its end serve the next one)
         const int ns = min(kMergeChunk, nent - js);
@@ -1500,26 +1575,28 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     // traversal arrays of the PI steps: the level's, or the LDS stage
     // (weights staged in their storage type; none where all are 1)
     using WT = typename WStore<T, WK>::type;
-    const int32_t* trp = L.rp;
-    const int32_t* tcol = L.col;
-    auto tw = weights_of<T, WK>(L);
-    int tlo = r0, thi = r1, roff = 0;
+    PiOp<T, WK> op;
+    op.col = L.col;
+    op.wv = weights_of<T, WK>(L);
+    op.roff = 0;
+    op.g = L.g;
+    PiOp<T, WK, true> ops;
+    bool staged = false;
     if constexpr (TRAV > 0 && sizeof(T) == 8) {
-        const int a0 = L.rp[r0], a1 = L.rp[r1];
+        const int a0 = gld(L.rp, r0), a1 = gld(L.rp, r1);
         // the same in every thread of the workgroup
         if (stg != nullptr && L.stage && r1 - r0 <= kStageRows && a1 - a0 <= kStageEnts) {
-            for (int i = threadIdx.x; i <= r1 - r0; i += blockDim.x) stg->rp[i] = L.rp[r0 + i] - a0;
+            for (int i = threadIdx.x; i <= r1 - r0; i += blockDim.x) stg->rp[i] = gld(L.rp, r0 + i) - a0;
             for (int e = threadIdx.x; e < a1 - a0; e += blockDim.x) {
-                stg->col[e] = L.col[a0 + e];
-                if constexpr (WK != kWUnit) ((WT*)stg->w)[e] = tw.p[a0 + e];
+                stg->col[e] = gld(L.col, a0 + e);
+                if constexpr (WK != kWUnit) ((WT*)stg->w)[e] = gld(op.wv.p, a0 + e);
             }
             __syncthreads();
-            trp = stg->rp;
-            tcol = stg->col;
-            if constexpr (WK != kWUnit) tw.p = (const WT*)stg->w;
-            tlo = 0;
-            thi = r1 - r0;
-            roff = r0;
+            ops.col = stg->col;
+            if constexpr (WK != kWUnit) ops.wv.p = (const WT*)stg->w;
+            ops.roff = r0;
+            ops.g = L.g;
+            staged = true;
         }
     }
     // prolongation from level j+1 (or the hashed uniform start)
@@ -1527,15 +1604,15 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     if (J.uniform) {
         for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
             const T v = (T)(hashed_uniform(seed, i) - 0.5);
-            b0[i] = v;
+            gst(b0, i, v);
             sum[0] += (double)v;
         }
     } else {
         const LevelState cst = *J.stc;
         const void* cb = cst.fin ? J.C.buf1 : J.C.buf0;
         for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-            const T v = (T)((ld_any(cb, J.C.fp32, L.agg[i]) - cst.mu) * cst.s);
-            b0[i] = v;
+            const T v = (T)((ld_any(cb, J.C.fp32, gld(L.agg, i)) - cst.mu) * cst.s);
+            gst(b0, i, v);
             sum[0] += (double)v;
         }
     }
@@ -1543,30 +1620,40 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     double mu = sum[0] / n;
     double ss[1] = {0.0};
     for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-        const double d = (double)b0[i] - mu;
+        const double d = (double)gld(b0, i) - mu;
         ss[0] += d * d;
     }
     if (!job_allreduce<1>(ss, c, red)) return;
     double s = 1.0 / sqrt(ss[0]);
     int cur = 0, k = 0, hit = 0;
     double utv = 0.0, pmu = mu, ps = s;
-    PiOp<T, WK> op;
-    op.col = tcol;
-    op.wv = tw;
-    op.roff = roff;
-    op.g = L.g;
     while (true) {
-        op.win = cur ? b1 : b0;
-        op.wout = cur ? b0 : b1;
-        op.mu = mu;
-        op.s = s;
-        op.acc[0] = op.acc[1] = op.acc[2] = op.acc[3] = 0.0;
-        if constexpr (TRAV == 0) drive_merge(L.rp, r0, r1, op, *sh);
-        else drive_rows<TRAV>(trp, tlo, thi, op, L.lrows, L.lmin, red, roff);
-        if (!job_allreduce<4>(op.acc, c, red)) return;
-        const double mu2 = op.acc[0] / n;
-        const double s2 = 1.0 / sqrt(op.acc[1] - op.acc[0] * mu2);
-        utv = s2 * (op.acc[2] - mu2 * op.acc[3]);
+        double acc[4];
+        if (TRAV > 0 && staged) {
+            ops.win = cur ? b1 : b0;
+            ops.wout = cur ? b0 : b1;
+            ops.mu = mu;
+            ops.s = s;
+            ops.acc[0] = ops.acc[1] = ops.acc[2] = ops.acc[3] = 0.0;
+            if constexpr (TRAV > 0 && sizeof(T) == 8)
+                drive_rows<TRAV, true>(stg->rp, 0, r1 - r0, ops, L.lrows, L.lmin, red, r0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = ops.acc[q];
+        } else {
+            op.win = cur ? b1 : b0;
+            op.wout = cur ? b0 : b1;
+            op.mu = mu;
+            op.s = s;
+            op.acc[0] = op.acc[1] = op.acc[2] = op.acc[3] = 0.0;
+            if constexpr (TRAV == 0) drive_merge(L.rp, r0, r1, op, *sh);
+            else drive_rows<TRAV>(L.rp, r0, r1, op, L.lrows, L.lmin, red);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = op.acc[q];
+        }
+        if (!job_allreduce<4>(acc, c, red)) return;
+        const double mu2 = acc[0] / n;
+        const double s2 = 1.0 / sqrt(acc[1] - acc[0] * mu2);
+        utv = s2 * (acc[2] - mu2 * acc[3]);
         ++k;
         cur ^= 1;
         pmu = mu;
@@ -1757,11 +1844,10 @@ k_refine_merge(const GridJob* __restrict__ jobs, int njobs) {
     refine_entry<0, T, WK>(jobs, njobs, red, &msh, nullptr);
 }
 
-// G lanes per row.  Held to 8 waves per SIMD (at most 64 VGPRs and about
-// 80 SGPRs): with more SGPRs the device keeps only 3 workgroups of 512
-// threads per CU resident although the occupancy query reports 4.
+// G lanes per row.  Held to 6 waves per SIMD (at most 80 VGPRs): grids
+// run at most 3 workgroups of 512 threads per CU.
 template <int G, typename T, int WK>
-__global__ void __launch_bounds__(kGridBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+__global__ void __launch_bounds__(kGridBlock) __attribute__((amdgpu_waves_per_eu(6, 6)))
 k_refine_rows(const GridJob* __restrict__ jobs, int njobs) {
     __shared__ double red[16 * 5 + 8];
     StageLds* stg = nullptr;
@@ -1835,15 +1921,15 @@ __global__ void __launch_bounds__(kStepBlock) k_step_prolong(const StepJob* __re
     if (J.uniform) {
         for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
             const T v = (T)(hashed_uniform(J.seed, i) - 0.5);
-            b0[i] = v;
+            gst(b0, i, v);
             sum[0] += (double)v;
         }
     } else {
         const LevelState cst = *J.stc;
         const void* cb = cst.fin ? J.C.buf1 : J.C.buf0;
         for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-            const T v = (T)((ld_any(cb, J.C.fp32, L.agg[i]) - cst.mu) * cst.s);
-            b0[i] = v;
+            const T v = (T)((ld_any(cb, J.C.fp32, gld(L.agg, i)) - cst.mu) * cst.s);
+            gst(b0, i, v);
             sum[0] += (double)v;
         }
     }
@@ -1871,7 +1957,7 @@ __global__ void __launch_bounds__(kStepBlock) k_step_sumsq(const StepJob* __rest
     const double mu = J.ctl->mu;
     double ss[1] = {0.0};
     for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-        const double d = (double)b0[i] - mu;
+        const double d = (double)gld(b0, i) - mu;
         ss[0] += d * d;
     }
     post_part<1>(ss, red, J.part, lb);

@@ -444,6 +444,39 @@ cmg_status finish_rowinfo(cmg_ctx* c, SetupTmp& t) {
     return CMG_OK;
 }
 
+// HEC greedy rounds launched before the first host check of a level (the
+// 3D-grid and geometric levels measured need 4 to 6; unused rounds return
+// at once)
+constexpr int kHecRoundsAhead = 6;
+
+// More HEC rounds, two per host check, until none leaves a live candidate
+// edge; *launched counts the rounds launched on the level so far.
+cmg_status hec_finish(cmg_ctx* c, SetupTmp& t, int j, int* launched) {
+    const HostLevel& L = c->lv[j];
+    unsigned long long* hflags = t.scal + 6;
+    for (;;) {
+        unsigned long long more = 0;
+        cmg_status st = d2h(c, &more, hflags + ((*launched - 1) & 1), 1);
+        if (st != CMG_OK) return st;
+        if (more == 0) return CMG_OK;
+        if (*launched > 100000) return CMG_E_DEVICE;
+        for (int r = 0; r < 2; ++r)
+            CK(launch_hec_round(L.n, t.h, c->opt.seed, j, t.live, t.state, t.pairseed, t.slot, hflags, *launched + r,
+                                c->stream));
+        *launched += 2;
+        c->hec_rounds += 2;
+    }
+}
+
+// aggregates of the HEC matching: attach, number the opening vertices, label
+hipError_t hec_aggregates(cmg_ctx* c, SetupTmp& t, const HostLevel& L) {
+    hipStream_t s = c->stream;
+    hipError_t e = launch_hec_attach(L.n, t.h, t.state, t.pairseed, t.rootseed, t.flags, s);
+    if (e == hipSuccess) e = launch_scan(t.flags, t.rank, L.n, t.scan_tmp, t.totals, s);  // totals[0]: aggregates
+    if (e == hipSuccess) e = launch_hec_label(L.n, t.rootseed, t.rank, L.agg, s);
+    return e;
+}
+
 // One HEC + Galerkin step from level j; appends level j+1 unless HEC
 // collapses (fewer than 2 aggregates).
 cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
@@ -455,6 +488,8 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
     cmg_status st = level_rowinfo(c, t, j);
     if (st != CMG_OK) return st;
     const bool hem = c->opt.coarsen == 1;
+    unsigned long long* hflags = t.scal + 6;  // HEC round flags
+    int hec_launched = 0;
     if (hem) {
         // heavy edge matching: rounds in batches between host checks; the
         // flag of a batch's last round tells whether any vertex was still
@@ -478,25 +513,19 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
         ALLOC(L.agg, int32_t, L.n);
         CK(launch_hec_label(L.n, t.pairseed, t.rank, L.agg, s));
     } else {
-        CK(launch_hec_init(L.n, t.h, seed, j, t.live, t.state, t.pairseed, t.slot, s));
-        // greedy rounds in batches between host checks; a round after the last
-        // live candidate edge changes nothing
-        for (int batch = 4, total = 0;; batch = 2) {
-            for (int r = 0; r < batch; ++r) {
-                CK(launch_hec_round(L.n, t.h, seed, j, t.live, t.state, t.pairseed, t.slot, t.scal + 2, s));
-            }
-            total += batch;
-            c->hec_rounds += batch;
-            unsigned long long live = 0;
-            st = d2h(c, &live, t.scal + 2, 1);
+        CK(launch_hec_init(L.n, t.h, seed, j, t.live, t.state, t.pairseed, t.slot, hflags, s));
+        // greedy rounds launched ahead without a host check; whether they
+        // were enough is read with the next synchronisation below
+        for (int r = 0; r < kHecRoundsAhead; ++r)
+            CK(launch_hec_round(L.n, t.h, seed, j, t.live, t.state, t.pairseed, t.slot, hflags, hec_launched + r, s));
+        hec_launched += kHecRoundsAhead;
+        c->hec_rounds += kHecRoundsAhead;
+        if (c->opt.galerkin == 1) {
+            st = hec_finish(c, t, j, &hec_launched);
             if (st != CMG_OK) return st;
-            if (live == 0) break;
-            if (total > 100000) return CMG_E_DEVICE;
         }
-        CK(launch_hec_attach(L.n, t.h, t.state, t.pairseed, t.rootseed, t.flags, s));
-        CK(launch_scan(t.flags, t.rank, L.n, t.scan_tmp, t.totals, s));  // totals[0]: aggregates
         ALLOC(L.agg, int32_t, L.n);
-        CK(launch_hec_label(L.n, t.rootseed, t.rank, L.agg, s));
+        CK(hec_aggregates(c, t, L));
     }
     // Galerkin product by aggregates when no aggregate's member rows hold
     // more than kGalWaveCap entries: the aggregate count and the largest
@@ -508,16 +537,35 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
         int32_t* mdeg = t.flags;
         int32_t* mstart = t.pairseed;
         int32_t* moff = t.rank;
-        CK(launch_gal_members(L.n, L.agg, L.rp, t.k0, t.k1, bitlen((unsigned long long)ncmax), t.sort_counts,
-                              t.sort_scan, members, mdeg, mstart, s));
-        CK(launch_scan(mdeg, moff, L.n, t.scan_tmp, t.totals + 2, s));
-        CK(launch_fill_u32((unsigned*)(t.scal + 4), 0u, 2, s));
-        CK(launch_gal_agg_len((int)ncmax, t.totals, L.n, L.nnz, mstart, moff, t.scal + 4, s));
         long long nc0 = 0;
         unsigned long long emax = 0;
-        CK(hipMemcpyAsync(&nc0, t.totals, sizeof(long long), hipMemcpyDeviceToHost, s));
-        st = d2h(c, &emax, t.scal + 4, 1);
-        if (st != CMG_OK) return st;
+        for (;;) {
+            CK(launch_gal_members(L.n, L.agg, L.rp, t.k0, t.k1, bitlen((unsigned long long)ncmax), t.sort_counts,
+                                  t.sort_scan, members, mdeg, mstart, s));
+            CK(launch_scan(mdeg, moff, L.n, t.scan_tmp, t.totals + 2, s));
+            CK(launch_fill_u32((unsigned*)(t.scal + 4), 0u, 2, s));
+            CK(launch_gal_agg_len((int)ncmax, t.totals, L.n, L.nnz, mstart, moff, t.scal + 4, s));
+            unsigned long long more = 0;
+            CK(hipMemcpyAsync(&nc0, t.totals, sizeof(long long), hipMemcpyDeviceToHost, s));
+            if (!hem) CK(hipMemcpyAsync(&more, hflags + ((hec_launched - 1) & 1), sizeof(more), hipMemcpyDeviceToHost, s));
+            st = d2h(c, &emax, t.scal + 4, 1);
+            if (st != CMG_OK) return st;
+            if (more == 0) break;
+            // the rounds launched ahead left live candidate edges.  The
+            // member lists reused the matching's pair array, so the matching
+            // is formed again from the start (the rounds are deterministic)
+            // with two more rounds, then finished, and the aggregates and
+            // their members formed again.
+            CK(launch_hec_init(L.n, t.h, seed, j, t.live, t.state, t.pairseed, t.slot, hflags, s));
+            const int redo = hec_launched + 2;
+            for (int r = 0; r < redo; ++r)
+                CK(launch_hec_round(L.n, t.h, seed, j, t.live, t.state, t.pairseed, t.slot, hflags, r, s));
+            c->hec_rounds += 2;
+            hec_launched = redo;
+            st = hec_finish(c, t, j, &hec_launched);
+            if (st != CMG_OK) return st;
+            CK(hec_aggregates(c, t, L));
+        }
         if (nc0 < 2) {
             c->dfree(L.agg);
             L.agg = nullptr;

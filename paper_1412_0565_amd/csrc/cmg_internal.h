@@ -81,13 +81,15 @@ constexpr int kRowinfoMaxBlocks = 1024;
 // (unit: every weight is 1; w is then not read)
 hipError_t launch_rowinfo(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w, int unit,
                           int32_t* h, double* bmax, unsigned long long* out, hipStream_t s);
+// flags: two words; after round r, flags[r & 1] is 1 if a candidate edge
+// survived it, else 0 (a round after one that left none does nothing)
 hipError_t launch_hec_init(int n, const int32_t* h, uint64_t seed, int level, uint8_t* live,
-                           uint8_t* state, int32_t* pairseed, unsigned long long* slot, hipStream_t s);
-// One greedy round; *any_live ends as 1 if a candidate edge survives it,
-// else 0.
+                           uint8_t* state, int32_t* pairseed, unsigned long long* slot,
+                           unsigned long long* flags, hipStream_t s);
+// greedy round `round` (0, 1, ... in launch order)
 hipError_t launch_hec_round(int n, const int32_t* h, uint64_t seed, int level, uint8_t* live,
                             uint8_t* state, int32_t* pairseed, unsigned long long* slot,
-                            unsigned long long* any_live, hipStream_t s);
+                            unsigned long long* flags, int round, hipStream_t s);
 hipError_t launch_hec_attach(int n, const int32_t* h, const uint8_t* state, const int32_t* pairseed,
                              int32_t* rootseed, int32_t* flags, hipStream_t s);
 hipError_t launch_hec_label(int n, const int32_t* rootseed, const int32_t* rank, int32_t* agg,

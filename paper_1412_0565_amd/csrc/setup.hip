@@ -224,10 +224,20 @@ constexpr uint8_t kSeed = 1;     // opened an aggregate (visited vertex)
 constexpr uint8_t kPartner = 2;  // heaviest neighbour of a seed
 constexpr unsigned long long kNoKey = 0xFFFFFFFFFFFFFFFFull;
 
+// Rounds are launched ahead of the host's check and disable themselves:
+// round r runs only if round r - 1 left a live candidate edge
+// (flags[(r - 1) & 1]; k_hec_init sets flags[1] for round 0), and k_hec_kill
+// of round r raises flags[r & 1] after k_hec_post of round r cleared it.  A
+// round after the last live edge changes nothing either way.
 __global__ void k_hec_init(int n, const int32_t* __restrict__ h, uint64_t seed, int level,
                            uint8_t* __restrict__ live, uint8_t* __restrict__ state,
-                           int32_t* __restrict__ pairseed, unsigned long long* __restrict__ slot) {
+                           int32_t* __restrict__ pairseed, unsigned long long* __restrict__ slot,
+                           unsigned long long* __restrict__ flags) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v == 0) {
+        flags[0] = 0ull;
+        flags[1] = 1ull;
+    }
     if (v >= n) return;
     pairseed[v] = v;
     uint64_t kv = hec_key(seed, level, v);
@@ -242,9 +252,10 @@ __global__ void k_hec_init(int n, const int32_t* __restrict__ h, uint64_t seed, 
 // cleared here.
 __global__ void k_hec_post(int n, const int32_t* __restrict__ h, uint64_t seed, int level,
                            const uint8_t* __restrict__ live, unsigned long long* slot,
-                           unsigned long long* any_live) {
+                           unsigned long long* flags, int round) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v == 0) *any_live = 0ull;
+    if (v == 0) flags[round & 1] = 0ull;
+    if (flags[(round - 1) & 1] == 0ull) return;
     if (v >= n || !live[v]) return;
     unsigned long long k = hec_key(seed, level, v);
     atomicMin(&slot[v], k);
@@ -256,7 +267,9 @@ __global__ void k_hec_post(int n, const int32_t* __restrict__ h, uint64_t seed, 
 __global__ void k_hec_accept(int n, const int32_t* __restrict__ h, uint64_t seed, int level,
                              uint8_t* __restrict__ live, uint8_t* __restrict__ state,
                              int32_t* __restrict__ pairseed,
-                             const unsigned long long* __restrict__ slot) {
+                             const unsigned long long* __restrict__ slot,
+                             const unsigned long long* __restrict__ flags, int round) {
+    if (flags[(round - 1) & 1] == 0ull) return;
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n || !live[v]) return;
     unsigned long long k = hec_key(seed, level, v);
@@ -275,7 +288,8 @@ __global__ void k_hec_accept(int n, const int32_t* __restrict__ h, uint64_t seed
 // writers store the same value).
 __global__ void k_hec_kill(int n, const int32_t* __restrict__ h, uint8_t* __restrict__ live,
                            const uint8_t* __restrict__ state, unsigned long long* slot,
-                           unsigned long long* any_live) {
+                           unsigned long long* flags, int round) {
+    if (flags[(round - 1) & 1] == 0ull) return;
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     int alive = 0;
     if (v < n && live[v]) {
@@ -288,7 +302,7 @@ __global__ void k_hec_kill(int n, const int32_t* __restrict__ h, uint8_t* __rest
             alive = 1;
         }
     }
-    if (__syncthreads_or(alive) && threadIdx.x == 0) *any_live = 1ull;
+    if (__syncthreads_or(alive) && threadIdx.x == 0) flags[round & 1] = 1ull;
 }
 
 // Unmatched vertices follow h to a matched vertex (keys decrease along the
@@ -1171,20 +1185,21 @@ hipError_t launch_rowinfo(int n, int lanes, const int32_t* rp, const int32_t* co
 }
 
 hipError_t launch_hec_init(int n, const int32_t* h, uint64_t seed, int level, uint8_t* live,
-                           uint8_t* state, int32_t* pairseed, unsigned long long* slot, hipStream_t s) {
+                           uint8_t* state, int32_t* pairseed, unsigned long long* slot,
+                           unsigned long long* flags, hipStream_t s) {
     hipLaunchKernelGGL(k_hec_init, dim3(nblocks(n, kBlk)), dim3(kBlk), 0, s, n, h, seed, level, live,
-                       state, pairseed, slot);
+                       state, pairseed, slot, flags);
     return hipGetLastError();
 }
 
 hipError_t launch_hec_round(int n, const int32_t* h, uint64_t seed, int level, uint8_t* live,
                             uint8_t* state, int32_t* pairseed, unsigned long long* slot,
-                            unsigned long long* any_live, hipStream_t s) {
+                            unsigned long long* flags, int round, hipStream_t s) {
     unsigned nb = nblocks(n, kBlk);
-    hipLaunchKernelGGL(k_hec_post, dim3(nb), dim3(kBlk), 0, s, n, h, seed, level, live, slot, any_live);
+    hipLaunchKernelGGL(k_hec_post, dim3(nb), dim3(kBlk), 0, s, n, h, seed, level, live, slot, flags, round);
     hipLaunchKernelGGL(k_hec_accept, dim3(nb), dim3(kBlk), 0, s, n, h, seed, level, live, state,
-                       pairseed, slot);
-    hipLaunchKernelGGL(k_hec_kill, dim3(nb), dim3(kBlk), 0, s, n, h, live, state, slot, any_live);
+                       pairseed, slot, flags, round);
+    hipLaunchKernelGGL(k_hec_kill, dim3(nb), dim3(kBlk), 0, s, n, h, live, state, slot, flags, round);
     return hipGetLastError();
 }
 

@@ -74,6 +74,27 @@ def test_fp64_parity(name):
     assert float(np.dot(x, ref.y)) > 0
 
 
+def test_hec_rounds_beyond_those_launched_ahead():
+    """A path visited in ascending HEC key order with weights rising along
+    it: each vertex's heaviest neighbour is the next one and every edge is a
+    candidate, and a greedy round matches the first pair of the chain and
+    kills the edge after it, so level 0 needs n / 2 rounds.  The rounds the
+    setup launches before its first host check fall short; the matching is
+    then finished and the aggregates formed again.  n is above the size the
+    single-workgroup setup takes, so level 0 runs on the grid kernels."""
+    from oracle import oracle as O
+
+    n = 10000
+    key = np.array([O.hec_key(14120565, 0, v) for v in range(n)], dtype=np.uint64)
+    p = np.argsort(key, kind="stable")
+    g = G.from_edges(n, p[:-1], p[1:], w=np.arange(1, n, dtype=float))
+    say(f"[parity] key-ordered path n={g.n}")
+    ref = oracle_of(g)
+    lam, x, st, levels, arrays = run_gpu(g)
+    assert st.hec_rounds >= n // 2
+    assert_fp64_parity(g, lam, x, st, levels, arrays, ref)
+
+
 def test_coarsest_fallback_start():
     # The ramp is orthogonal to the lambda_2 eigenspace of this graph (its
     # label reversal is an automorphism that fixes the eigenspace), so the

@@ -198,6 +198,7 @@ struct cmg_ctx {
     // every input weight an integer below 2^20: Galerkin sums are exact in
     // any order, and runs of a long coarse entry are summed in pieces
     bool int_weights = false;
+    bool gal_int32 = false;  // integer weights summing below 2^32 (set on level 0)
     unsigned maxlen0 = 0;  // longest input row if over 64 entries (else 0)
     std::vector<BlockJob> h_bruns;
     std::vector<int> brun_kind;   // kernel of each run (launch_block_jobs kind)
@@ -444,6 +445,9 @@ cmg_status finish_rowinfo(cmg_ctx* c, SetupTmp& t) {
     return CMG_OK;
 }
 
+// longest input row for which member lists are built by counting
+constexpr unsigned kCountMembersMaxRow = 1024;
+
 // HEC greedy rounds launched before the first host check of a level (the
 // 3D-grid and geometric levels measured need 4 to 6; unused rounds return
 // at once)
@@ -540,16 +544,33 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
         long long nc0 = 0;
         unsigned long long emax = 0;
         for (;;) {
-            CK(launch_gal_members(L.n, L.agg, L.rp, t.k0, t.k1, bitlen((unsigned long long)ncmax), t.sort_counts,
-                                  t.sort_scan, members, mdeg, mstart, s));
+            // counted lists where the input has no long rows: an
+            // aggregate's members (at most one plus the vertices naming the
+            // same heaviest neighbour) then contend for its counter only a
+            // few at a time; power-law hubs keep the radix sort
+            if (c->int_weights && !hem && c->maxlen0 <= kCountMembersMaxRow)
+                CK(launch_gal_members_count(L.n, (int)ncmax, L.agg, L.rp, t.idx, t.scan_tmp, t.totals + 3, members,
+                                            mdeg, mstart, s));
+            else
+                CK(launch_gal_members(L.n, L.agg, L.rp, t.k0, t.k1, bitlen((unsigned long long)ncmax),
+                                      t.sort_counts, t.sort_scan, members, mdeg, mstart, s));
             CK(launch_scan(mdeg, moff, L.n, t.scan_tmp, t.totals + 2, s));
             CK(launch_fill_u32((unsigned*)(t.scal + 4), 0u, 2, s));
             CK(launch_gal_agg_len((int)ncmax, t.totals, L.n, L.nnz, mstart, moff, t.scal + 4, s));
-            unsigned long long more = 0;
+            unsigned long long more = 0, wmax0 = 0;
             CK(hipMemcpyAsync(&nc0, t.totals, sizeof(long long), hipMemcpyDeviceToHost, s));
+            if (j == 0) CK(hipMemcpyAsync(&wmax0, t.ri + 1, sizeof(wmax0), hipMemcpyDeviceToHost, s));
             if (!hem) CK(hipMemcpyAsync(&more, hflags + ((hec_launched - 1) & 1), sizeof(more), hipMemcpyDeviceToHost, s));
             st = d2h(c, &emax, t.scal + 4, 1);
             if (st != CMG_OK) return st;
+            if (j == 0) {
+                // every coarse weight is a sum of input weights: with
+                // integer weights whose total (at most nnz times the
+                // largest) stays below 2^32, 32-bit integer sums are exact
+                double wm = 0.0;
+                std::memcpy(&wm, &wmax0, sizeof(wm));
+                c->gal_int32 = c->int_weights && (double)L.nnz * wm < 4294967295.0;
+            }
             if (more == 0) break;
             // the rounds launched ahead left live candidate edges.  The
             // member lists reused the matching's pair array, so the matching
@@ -585,7 +606,8 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
             const int slots = (c->opt.galerkin == 2 || nc < kGalLaneMinRows) ? 0
                               : L.nnz <= 7 * (int64_t)L.n                    ? 16
                                                                              : 32;
-            CK(launch_gal_gather(nc, L.n, L.nnz, slots, L.wunit, members, mstart, moff, L.rp, L.col, L.w64, L.agg,
+            CK(launch_gal_gather(nc, L.n, L.nnz, slots, L.wunit, c->gal_int32, members, mstart, moff, L.rp, L.col,
+                                 L.w64, L.agg,
                                  tcol, tw, rowlen, t.heads, (unsigned*)(t.scal + 5), s));
             HostLevel C;
             C.n = nc;

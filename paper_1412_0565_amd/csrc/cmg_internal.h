@@ -107,11 +107,17 @@ constexpr int kGalLaneMinRows = 65536;  // fewer coarse rows: all formed by wave
 hipError_t launch_gal_members(int n, const int32_t* agg, const int32_t* rp, unsigned long long* k0,
                               unsigned long long* k1, int aggbits, int32_t* sort_counts, long long* sort_scan,
                               int32_t* members, int32_t* mdeg, int32_t* mstart, hipStream_t s);
+// the same lists in any order within an aggregate (integer weights below
+// 2^20 only); cnt: ncmax + 1 ints of scratch; mstart: ncmax + 1 entries
+hipError_t launch_gal_members_count(int n, int ncmax, const int32_t* agg, const int32_t* rp, int32_t* cnt,
+                                    long long* scan_tmp, long long* total, int32_t* members, int32_t* mdeg,
+                                    int32_t* mstart, hipStream_t s);
 hipError_t launch_gal_agg_len(int ncmax, const long long* ncp, int n, int64_t nnz, const int32_t* mstart,
                               const int32_t* moff, unsigned long long* emax, hipStream_t s);
 // (slots: 16 or 32 distinct columns a lane keeps in registers, 0 for none;
-// big: nc ints listing the aggregates with more, nbig their count)
-hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int slots, int unit, const int32_t* members,
+// int32sum: all weights are integers summing below 2^32, kept as 32-bit
+// integer sums; big: nc ints listing the aggregates with more, nbig their count)
+hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int slots, int unit, int int32sum, const int32_t* members,
                              const int32_t* mstart, const int32_t* moff, const int32_t* rp, const int32_t* col,
                              const double* w, const int32_t* agg, int32_t* tcol, double* tw, int32_t* rowlen,
                              int32_t* big, unsigned* nbig, hipStream_t s);

@@ -17,6 +17,8 @@
 //   * an unmatched vertex ends in the aggregate reached by following h until
 //     a matched vertex (keys strictly decrease along that chain).
 // Aggregates are numbered by ascending index of their opening vertex.
+#include <type_traits>
+
 #include "cmg_internal.h"
 
 namespace cmg {
@@ -442,6 +444,29 @@ __global__ void k_gal_members(int n, const unsigned long long* __restrict__ keys
     if (k == n - 1) mstart[a + 1] = n;
 }
 
+// Member lists by counting, for graphs whose weights are all integers
+// below 2^20: every Galerkin sum is then an integer far below 2^53, exact
+// in any order, so the members of an aggregate may be listed in any order
+// (the coarse graph does not change).  Each aggregate's members are
+// counted, the counts scanned into first-member offsets, and every vertex
+// placed at the next free slot of its aggregate (counting down); mdeg is
+// the degree of each listed member.
+__global__ void k_mem_count(int n, const int32_t* __restrict__ agg, int32_t* __restrict__ cnt) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) atomicAdd(&cnt[agg[v]], 1);
+}
+
+__global__ void k_mem_place(int n, const int32_t* __restrict__ agg, const int32_t* __restrict__ rp,
+                            const int32_t* __restrict__ mstart, int32_t* __restrict__ cnt,
+                            int32_t* __restrict__ members, int32_t* __restrict__ mdeg) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int a = agg[v];
+    const int k = mstart[a] + atomicSub(&cnt[a], 1) - 1;
+    members[k] = v;
+    mdeg[k] = rp[v + 1] - rp[v];
+}
+
 // entries of aggregate a's member rows and the offset of the first
 __device__ __forceinline__ int64_t gal_entries(int a, int n, int64_t nnz, const int32_t* __restrict__ mstart,
                                                const int32_t* __restrict__ moff, int64_t* o0) {
@@ -475,8 +500,10 @@ __global__ void k_gal_agg_len(int ncmax, const long long* __restrict__ ncp, int 
 }
 
 // pass 1: a lane per aggregate, S register slots (UNIT: every weight is 1
-// and the weights are not read)
-template <int S, bool UNIT>
+// and the weights are not read; INT: every weight is an integer and all of
+// them together sum below 2^32, so the sums are kept as 32-bit integers,
+// exact and equal to the FP64 sums, with half the register traffic)
+template <int S, bool UNIT, bool INT>
 __global__ void __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) k_gal_lane(int nc, const int32_t* __restrict__ members,
                                                    const int32_t* __restrict__ mstart,
                                                    const int32_t* __restrict__ moff, const int32_t* __restrict__ rp,
@@ -487,12 +514,13 @@ __global__ void __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) 
     const int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= nc) return;
     const int k0 = mstart[a], k1 = mstart[a + 1];
+    using Acc = typename std::conditional<INT, uint32_t, double>::type;
     int rb[S];
-    double rw[S];
+    Acc rw[S];
 #pragma unroll
     for (int q = 0; q < S; ++q) {
         rb[q] = 0x7fffffff;
-        rw[q] = 0.0;
+        rw[q] = (Acc)0;
     }
     int len = 0;
     bool over = false;
@@ -504,12 +532,12 @@ __global__ void __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) 
         const int e1 = rp[v + 1];
         for (int e = rp[v]; e < e1 && !over; e += kGalBatch) {
             int cb[kGalBatch];
-            double xb[kGalBatch];
+            Acc xb[kGalBatch];
 #pragma unroll
             for (int i = 0; i < kGalBatch; ++i) {
                 if (e + i < e1) {
                     cb[i] = col[e + i];
-                    xb[i] = UNIT ? 1.0 : w[e + i];
+                    xb[i] = UNIT ? (Acc)1 : (Acc)w[e + i];
                 }
             }
 #pragma unroll
@@ -518,7 +546,7 @@ __global__ void __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) 
 #pragma unroll
             for (int i = 0; i < kGalBatch; ++i) {
                 const int b = cb[i];
-                const double x = xb[i];
+                const Acc x = xb[i];
                 if (e + i >= e1 || over || b == a) continue;
                 bool found = false;
 #pragma unroll
@@ -538,7 +566,7 @@ __global__ void __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) 
 #pragma unroll
                 for (int q = S - 1; q >= 0; --q) {
                     const int prev = q > 0 ? rb[q - 1] : INT_MIN;
-                    const double prevw = q > 0 ? rw[q - 1] : 0.0;
+                    const Acc prevw = q > 0 ? rw[q - 1] : (Acc)0;
                     if (rb[q] > b) {
                         if (prev > b) {
                             rb[q] = prev;
@@ -562,7 +590,7 @@ __global__ void __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) 
     for (int q = 0; q < S; ++q) {
         if (q < len) {
             tcol[base + q] = rb[q];
-            tw[base + q] = rw[q];
+            tw[base + q] = (double)rw[q];
         }
     }
     rowlen[a] = len;
@@ -1238,6 +1266,18 @@ hipError_t launch_gal_members(int n, const int32_t* agg, const int32_t* rp, unsi
     return hipGetLastError();
 }
 
+hipError_t launch_gal_members_count(int n, int ncmax, const int32_t* agg, const int32_t* rp, int32_t* cnt,
+                                    long long* scan_tmp, long long* total, int32_t* members, int32_t* mdeg,
+                                    int32_t* mstart, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(nblocks(ncmax + 1, kBlk)), dim3(kBlk), 0, s, (unsigned*)cnt, 0u,
+                       (int64_t)ncmax + 1);
+    hipLaunchKernelGGL(k_mem_count, dim3(nblocks(n, kBlk)), dim3(kBlk), 0, s, n, agg, cnt);
+    hipError_t e = launch_scan(cnt, mstart, (int64_t)ncmax + 1, scan_tmp, total, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mem_place, dim3(nblocks(n, kBlk)), dim3(kBlk), 0, s, n, agg, rp, mstart, cnt, members, mdeg);
+    return hipGetLastError();
+}
+
 hipError_t launch_gal_agg_len(int ncmax, const long long* ncp, int n, int64_t nnz, const int32_t* mstart,
                               const int32_t* moff, unsigned long long* emax, hipStream_t s) {
     const unsigned nb = std::min<unsigned>(nblocks(ncmax, kBlk), (unsigned)kGalLenBlocks);
@@ -1245,32 +1285,30 @@ hipError_t launch_gal_agg_len(int ncmax, const long long* ncp, int n, int64_t nn
     return hipGetLastError();
 }
 
-hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int slots, int unit, const int32_t* members,
+hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int slots, int unit, int int32sum, const int32_t* members,
                              const int32_t* mstart, const int32_t* moff, const int32_t* rp, const int32_t* col,
                              const double* w, const int32_t* agg, int32_t* tcol, double* tw, int32_t* rowlen,
                              int32_t* big, unsigned* nbig, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlk), 0, s, nbig, 0u, (int64_t)1);
     const unsigned nb = nblocks(nc, kBlk);
+#define CMG_GAL_LANE(S, U, I)                                                                                     \
+    hipLaunchKernelGGL((k_gal_lane<S, U, I>), dim3(nb), dim3(kBlk), 0, s, nc, members, mstart, moff, rp, col, w, agg, \
+                       tcol, tw, rowlen, big, nbig)
     switch (slots) {
         case 16:
-            if (unit)
-                hipLaunchKernelGGL((k_gal_lane<16, true>), dim3(nb), dim3(kBlk), 0, s, nc, members, mstart, moff, rp,
-                                   col, w, agg, tcol, tw, rowlen, big, nbig);
-            else
-                hipLaunchKernelGGL((k_gal_lane<16, false>), dim3(nb), dim3(kBlk), 0, s, nc, members, mstart, moff, rp,
-                                   col, w, agg, tcol, tw, rowlen, big, nbig);
+            if (unit) CMG_GAL_LANE(16, true, true);
+            else if (int32sum) CMG_GAL_LANE(16, false, true);
+            else CMG_GAL_LANE(16, false, false);
             break;
         case 32:
-            if (unit)
-                hipLaunchKernelGGL((k_gal_lane<32, true>), dim3(nb), dim3(kBlk), 0, s, nc, members, mstart, moff, rp,
-                                   col, w, agg, tcol, tw, rowlen, big, nbig);
-            else
-                hipLaunchKernelGGL((k_gal_lane<32, false>), dim3(nb), dim3(kBlk), 0, s, nc, members, mstart, moff, rp,
-                                   col, w, agg, tcol, tw, rowlen, big, nbig);
+            if (unit) CMG_GAL_LANE(32, true, true);
+            else if (int32sum) CMG_GAL_LANE(32, false, true);
+            else CMG_GAL_LANE(32, false, false);
             break;
         case 0: hipLaunchKernelGGL(k_gal_all, dim3(nb), dim3(kBlk), 0, s, nc, big, nbig); break;
         default: return hipErrorInvalidValue;
     }
+#undef CMG_GAL_LANE
     hipLaunchKernelGGL(k_gal_wave, dim3(1024), dim3(kBlk), 0, s, n, nnz, members, mstart, moff, rp, col, w, agg,
                        (const int32_t*)big, (const unsigned*)nbig, tcol, tw, rowlen);
     return hipGetLastError();

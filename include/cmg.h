@@ -115,7 +115,7 @@ typedef struct {
     int32_t grid_stage;          /* FP64 levels refined by the whole grid with lanes per row:
                                     1 (default) copies each workgroup's rows, columns and
                                     weights to LDS once per level when they fit (at most 1024
-                                    rows and 2560 entries) and runs the PI steps from there;
+                                    rows and 3840 entries) and runs the PI steps from there;
                                     0 always reads them from global memory.  Results are
                                     bitwise equal. */
     int32_t step_mode;           /* grid levels traversed by rows: 0 (default) refines the levels

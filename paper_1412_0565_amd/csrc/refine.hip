@@ -1553,7 +1553,7 @@ __device__ __forceinline__ void drive(const LevelDev& L, int r0, int r1, Op& op,
 // are visited in the same order, so the sums are bit for bit those of the
 // global traversal.
 constexpr int kStageRows = 1024;
-constexpr int kStageEnts = 2560;
+constexpr int kStageEnts = 3840;
 struct StageLds {
     int32_t rp[kStageRows + 1];  // row pointers relative to the first entry
     int32_t col[kStageEnts];

@@ -419,7 +419,7 @@ void free_tmp(cmg_ctx* c, SetupTmp& t) {
 cmg_status level_rowinfo(cmg_ctx* c, SetupTmp& t, int j) {
     HostLevel& L = c->lv[j];
     if (j >= kMaxLevels) return CMG_E_DEVICE;
-    CK(launch_rowinfo(L.n, L.lanes, L.rp, L.col, L.w64, L.wunit, t.h, t.bmax, t.ri + 4 * j, c->stream));
+    CK(launch_rowinfo(L.n, L.lanes, L.rp, L.col, L.w64, L.wunit, t.h, t.bmax, t.ri + 4 * j, t.vflags, c->stream));
     t.ri_pending.push_back(j);
     return CMG_OK;
 }
@@ -460,8 +460,11 @@ cmg_status hec_finish(cmg_ctx* c, SetupTmp& t, int j, int* launched) {
     unsigned long long* hflags = t.scal + 6;
     for (;;) {
         unsigned long long more = 0;
+        unsigned iso = 0;
+        CK(hipMemcpyAsync(&iso, t.vflags, sizeof(iso), hipMemcpyDeviceToHost, c->stream));
         cmg_status st = d2h(c, &more, hflags + ((*launched - 1) & 1), 1);
         if (st != CMG_OK) return st;
+        if (iso) return CMG_E_ISOLATED;
         if (more == 0) return CMG_OK;
         if (*launched > 100000) return CMG_E_DEVICE;
         for (int r = 0; r < 2; ++r)
@@ -489,6 +492,7 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
     hipStream_t s = c->stream;
     const uint64_t seed = c->opt.seed;
     *stop = false;
+    CK(launch_fill_u32(t.vflags, 0u, 1, s));  // raised by the row pass if a vertex has no neighbour
     cmg_status st = level_rowinfo(c, t, j);
     if (st != CMG_OK) return st;
     const bool hem = c->opt.coarsen == 1;
@@ -507,9 +511,11 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
                 CK(launch_hem_round(L.n, L.rp, L.col, L.w64, seed, j, t.pairseed, t.live, t.slot, t.alive, round,
                                     s));
             c->hec_rounds += batch;
-            unsigned last = 0;
+            unsigned last = 0, iso = 0;
+            CK(hipMemcpyAsync(&iso, t.vflags, sizeof(iso), hipMemcpyDeviceToHost, s));
             st = d2h(c, &last, t.alive + round - 1, 1);
             if (st != CMG_OK) return st;
+            if (iso) return CMG_E_ISOLATED;
             if (last == 0) break;
         }
         CK(launch_hem_flags(L.n, t.pairseed, t.flags, s));
@@ -558,11 +564,14 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
             CK(launch_fill_u32((unsigned*)(t.scal + 4), 0u, 2, s));
             CK(launch_gal_agg_len((int)ncmax, t.totals, L.n, L.nnz, mstart, moff, t.scal + 4, s));
             unsigned long long more = 0, wmax0 = 0;
+            unsigned iso = 0;
+            CK(hipMemcpyAsync(&iso, t.vflags, sizeof(iso), hipMemcpyDeviceToHost, s));
             CK(hipMemcpyAsync(&nc0, t.totals, sizeof(long long), hipMemcpyDeviceToHost, s));
             if (j == 0) CK(hipMemcpyAsync(&wmax0, t.ri + 1, sizeof(wmax0), hipMemcpyDeviceToHost, s));
             if (!hem) CK(hipMemcpyAsync(&more, hflags + ((hec_launched - 1) & 1), sizeof(more), hipMemcpyDeviceToHost, s));
             st = d2h(c, &emax, t.scal + 4, 1);
             if (st != CMG_OK) return st;
+            if (iso) return CMG_E_ISOLATED;  // a component of the graph became one aggregate
             if (j == 0) {
                 // every coarse weight is a sum of input weights: with
                 // integer weights whose total (at most nnz times the
@@ -753,6 +762,7 @@ cmg_status coarsen_chain(cmg_ctx* c, SetupTmp& t, int j0, int* next) {
     const int32_t* out = (const int32_t*)(hb.data() + sizeof(ChainHdr) * max_levels);
     const int K = out[0], reason = out[2];
     if (K < 1 || K > max_levels) return CMG_E_DEVICE;
+    if (reason == 6) return CMG_E_ISOLATED;  // a component of the graph became one aggregate
     for (int k = 0; k < K; ++k) {
         const ChainHdr& h = hdr[k];
         if (k > 0) {

@@ -79,8 +79,10 @@ hipError_t launch_to_f32(int64_t nnz, const double* w64, float* w32, hipStream_t
 // bmax: scratch of 4 * kRowinfoMaxBlocks doubles.
 constexpr int kRowinfoMaxBlocks = 1024;
 // (unit: every weight is 1; w is then not read)
+// *iso is raised if some vertex of the level has no neighbour (it is then
+// its own h)
 hipError_t launch_rowinfo(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w, int unit,
-                          int32_t* h, double* bmax, unsigned long long* out, hipStream_t s);
+                          int32_t* h, double* bmax, unsigned long long* out, unsigned* iso, hipStream_t s);
 // flags: two words; after round r, flags[r & 1] is 1 if a candidate edge
 // survived it, else 0 (a round after one that left none does nothing)
 hipError_t launch_hec_init(int n, const int32_t* h, uint64_t seed, int level, uint8_t* live,

@@ -100,7 +100,10 @@ __global__ void __launch_bounds__(kChainThreads) k_coarsen_chain(ChainJob J) {
     __shared__ long long sh[17];
     __shared__ double sm[4 * 16];
     __shared__ int s_bad;
+    __shared__ int s_iso;
     const int tid = threadIdx.x, T = blockDim.x;
+    if (tid == 0) s_iso = 0;
+    __syncthreads();
     int n = J.n0;
     int64_t nnz = J.nnz0;
     const int32_t* rp = J.rp0;
@@ -128,6 +131,12 @@ __global__ void __launch_bounds__(kChainThreads) k_coarsen_chain(ChainJob J) {
                     bc = c;
                 }
             }
+            // a vertex with no neighbour (a component that became one
+            // aggregate) names itself and stops the chain below
+            if (b == a) {
+                bc = v;
+                s_iso = 1;
+            }
             J.h[v] = bc;
             m4[0] = fmax(m4[0], 2.0 * d);
             m4[1] = fmax(m4[1], bw);
@@ -147,6 +156,12 @@ __global__ void __launch_bounds__(kChainThreads) k_coarsen_chain(ChainJob J) {
         K = k + 1;
         if (n <= J.coarsest_n || k + 1 >= J.max_levels) {
             stop_reason = (n <= J.coarsest_n) ? 1 : 5;
+            if (tid == 0) J.hdr[k] = hd;
+            break;
+        }
+        if (s_iso) {
+            // HEC needs every vertex to have a neighbour (CMG_E_ISOLATED)
+            stop_reason = 6;
             if (tid == 0) J.hdr[k] = hd;
             break;
         }

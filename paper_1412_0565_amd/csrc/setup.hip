@@ -103,11 +103,16 @@ __global__ void k_to_f32(int64_t nnz, const double* __restrict__ in, float* __re
 
 // One G-lane group per row: heaviest neighbour (max weight, lowest column
 // on ties: the first minimum of the column of L), weighted degree for the
-// Gershgorin shift g = 2 max_v d_v, largest weight.
+// Gershgorin shift g = 2 max_v d_v, largest weight.  A vertex with no
+// neighbour (on a coarse level, a component that became one aggregate)
+// raises *iso and names itself as its heaviest neighbour, so the HEC
+// kernels that run before the host reads the flag touch only valid
+// indices: it is never a candidate, and its aggregate is discarded with
+// the level when the setup returns CMG_E_ISOLATED.
 template <int G>
 __global__ void k_rowinfo(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                           const double* __restrict__ w, int32_t* __restrict__ h,
-                          double* __restrict__ bmax) {
+                          double* __restrict__ bmax, unsigned* __restrict__ iso) {
     const int lane = threadIdx.x & (G - 1);
     const int gpb = blockDim.x / G;
     int row = blockIdx.x * gpb + threadIdx.x / G;
@@ -140,7 +145,8 @@ __global__ void k_rowinfo(int n, const int32_t* __restrict__ rp, const int32_t* 
         }
         d = group_sum_t<G>(d);
         if (lane == 0) {
-            h[row] = bc;
+            h[row] = b > a ? bc : row;
+            if (b == a) atomicOr(iso, 1u);
             dmax = fmax(dmax, 2.0 * d);
             wm = fmax(wm, bw);
         }
@@ -179,11 +185,12 @@ __global__ void k_rowinfo(int n, const int32_t* __restrict__ rp, const int32_t* 
 // the lowest column (the row's first entry), the weighted degree the row
 // length; the weights are not read.
 __global__ void k_rowinfo_unit(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                               int32_t* __restrict__ h, double* __restrict__ bmax) {
+                               int32_t* __restrict__ h, double* __restrict__ bmax, unsigned* __restrict__ iso) {
     double lmax = 0.0;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const int a = rp[v], b = rp[v + 1];
-        h[v] = col[a];
+        h[v] = b > a ? col[a] : v;
+        if (b == a) atomicOr(iso, 1u);
         lmax = fmax(lmax, (double)(b - a));
     }
     __shared__ double sm[kBlk / kWave];
@@ -315,7 +322,7 @@ __global__ void k_hec_attach(int n, const int32_t* __restrict__ h, const uint8_t
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     int r = v;
-    for (int guard = 0; guard < n && state[r] == 0; ++guard) r = h[r];
+    for (int guard = 0; guard < n && state[r] == 0 && h[r] != r; ++guard) r = h[r];
     rootseed[v] = pairseed[r];
     flags[v] = (state[v] == kSeed) ? 1 : 0;
 }
@@ -1189,10 +1196,10 @@ hipError_t launch_to_f32(int64_t nnz, const double* w64, float* w32, hipStream_t
 }
 
 hipError_t launch_rowinfo(int n, int lanes, const int32_t* rp, const int32_t* col, const double* w, int unit,
-                          int32_t* h, double* bmax, unsigned long long* out, hipStream_t s) {
+                          int32_t* h, double* bmax, unsigned long long* out, unsigned* iso, hipStream_t s) {
     if (unit) {
         const unsigned nb = (unsigned)std::min<int64_t>(nblocks(n, kBlk), kRowinfoMaxBlocks);
-        hipLaunchKernelGGL(k_rowinfo_unit, dim3(nb), dim3(kBlk), 0, s, n, rp, col, h, bmax);
+        hipLaunchKernelGGL(k_rowinfo_unit, dim3(nb), dim3(kBlk), 0, s, n, rp, col, h, bmax, iso);
         hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(kBlk), 0, s, bmax, (int)nb, out);
         return hipGetLastError();
     }
@@ -1201,7 +1208,7 @@ hipError_t launch_rowinfo(int n, int lanes, const int32_t* rp, const int32_t* co
     switch (lanes) {
 #define CMG_RI(G)                                                                                  \
     case G:                                                                                        \
-        hipLaunchKernelGGL(k_rowinfo<G>, dim3(nb), dim3(kBlk), 0, s, n, rp, col, w, h, bmax);       \
+        hipLaunchKernelGGL(k_rowinfo<G>, dim3(nb), dim3(kBlk), 0, s, n, rp, col, w, h, bmax, iso);  \
         break;
         CMG_RI(1) CMG_RI(2) CMG_RI(4) CMG_RI(8) CMG_RI(16) CMG_RI(32) CMG_RI(64)
 #undef CMG_RI

@@ -309,6 +309,37 @@ def test_invalid_graphs(case):
     assert ei.value.status == exp
 
 
+def _grid_plus_edge(side):
+    """A side x side grid with a separate two-vertex component: level 0 is
+    valid, but the pair becomes one aggregate, a vertex with no neighbour
+    on level 1."""
+    g = G.grid2d(side, side)
+    e = g.edges()
+    n = g.n + 2
+    return G.from_edges(n, np.concatenate([e[0], [g.n]]), np.concatenate([e[1], [g.n + 1]]))
+
+
+@pytest.mark.parametrize("side", [40, 200])
+def test_component_collapsing_to_an_isolated_coarse_vertex(side):
+    """The oracle rejects the graph when HEC meets the vertex without a
+    neighbour on level 1 (Algorithm 2 takes a heaviest neighbour); the GPU
+    returns the same status, from the single-workgroup setup (side 40,
+    level 1 of 534 vertices) and from the grid kernels (side 200, level 1 of
+    over 13k vertices), after HEC ran on that level with the vertex naming
+    itself."""
+    from paper_1412_0565_amd import cmg
+
+    g = _grid_plus_edge(side)
+    assert oracle_of(g).status == "E_ISOLATED"
+    say(f"[parity] grid {side}x{side} + edge: expecting CMG_E_ISOLATED")
+    with pytest.raises(cmg.CmgError) as ei:
+        cmg.cmg_setup(g.n, g.row_ptr, g.col, g.w, cmg.cmg_options_default())
+    assert ei.value.status == cmg.CMG_E_ISOLATED
+    # the library stays usable
+    lam, x, st, levels, arrays = run_gpu(G.grid2d(30, 30))
+    assert_fp64_parity(G.grid2d(30, 30), lam, x, st, levels, arrays, oracle_of(G.grid2d(30, 30)))
+
+
 @pytest.mark.parametrize("case", ["valid", "unsorted", "duplicate", "range", "selfloop", "zero", "asym"])
 def test_invalid_entry_deep_in_a_long_row(case):
     """Faults past the first lanes of the row check: the hub row of a

@@ -531,6 +531,23 @@ def test_validate_statuses(orc):
     assert r.status == "E_ISOLATED"
 
 
+def test_component_collapsing_to_one_aggregate_is_rejected(orc):
+    # A separate pair of vertices is one aggregate on level 1, a coarse
+    # vertex with no neighbour: Algorithm 2 has no heaviest neighbour for it
+    # and the setup stops with E_ISOLATED; two separate paths small enough
+    # to be the coarsest level are solved densely (lambda_2 = 0).
+    g = G.grid2d(40, 40)
+    e = g.edges()
+    gg = G.from_edges(g.n + 2, np.concatenate([e[0], [g.n]]), np.concatenate([e[1], [g.n + 1]]))
+    assert orc.validate(gg) == "OK"
+    assert orc.cmg(gg).status == "E_ISOLATED"
+    two = G.from_edges(20, np.concatenate([np.arange(9), np.arange(10, 19)]),
+                       np.concatenate([np.arange(1, 10), np.arange(11, 20)]))
+    r = orc.cmg(two)
+    assert r.status == "OK" and len(r.levels) == 1
+    assert abs(r.lam) <= 1e-12
+
+
 def test_cmg_small_is_dense_only(orc):
     for n in (2, 9, 25):
         r = orc.cmg(G.complete(n))

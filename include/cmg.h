@@ -60,7 +60,9 @@ typedef enum {
     CMG_E_ARG = 1,      /* bad argument (NULL pointer, n < 2, sizes out of range, bad option) */
     CMG_E_GRAPH = 2,    /* bad index, unsorted/duplicate column, self-loop, w <= 0 or non-finite,
                            asymmetric (only detected with validate_full) */
-    CMG_E_ISOLATED = 3, /* a vertex without neighbours */
+    CMG_E_ISOLATED = 3, /* a vertex without neighbours: in the input, or on a level HEC
+                           coarsens (a component of a disconnected graph that became one
+                           aggregate; Algorithm 2 needs a heaviest neighbour) */
     CMG_E_OOM = 4,      /* an allocation failed */
     CMG_E_DEVICE = 5,   /* a HIP runtime error or a device-side failure */
     CMG_W_MAXIT = 6     /* warning: a level hit max_iters_per_level; result still valid */

@@ -112,8 +112,9 @@ typedef struct {
                                     rounding) between processes.  0 (default): fixed rules. */
     int32_t block_regs;          /* levels refined inside one workgroup: 0 (default) holds each
                                     level's rows in registers for all its PI steps where a
-                                    layout fits (rows of at most 64 entries); -1 always reads
-                                    the CSR arrays.  Both give the same lambda to rounding. */
+                                    layout fits (rows of at most 128 entries, those beyond
+                                    the layout's slots in an LDS list); -1 always reads the
+                                    CSR arrays.  Both give the same lambda to rounding. */
     int32_t grid_stage;          /* FP64 levels refined by the whole grid with lanes per row:
                                     1 (default) copies each workgroup's rows, columns and
                                     weights to LDS once per level when they fit (at most 1024
@@ -184,6 +185,9 @@ typedef struct {
     int32_t weights;       /* edge weights as the level's PI steps read them: 0 FP64, 1 FP32
                               (mixed-precision level, or an exact FP32 copy beside FP64
                               iterates), 2 none (every weight is 1) */
+    int32_t block_slots;   /* in_block with register rows: entry slots per lane and row; the
+                              entries of rows longer than lanes x block_slots (at most twice
+                              that) are read from a list in LDS */
 } cmg_level_stats;
 
 typedef struct {

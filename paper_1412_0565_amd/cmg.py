@@ -85,6 +85,7 @@ class cmg_level_stats(C.Structure):
         ("block_regs", C.c_int32),
         ("step", C.c_int32),
         ("weights", C.c_int32),
+        ("block_slots", C.c_int32),
     ]
 
 

@@ -129,36 +129,51 @@ int bitlen(unsigned long long x) {
 
 // Register-row layout of a single-workgroup level (kernels of
 // kBlockRegsThreads threads): W wavefronts run the steps; layout l gives G
-// lanes per row and E entry slots per lane and row (rows of up to G E
-// entries); R rows per lane group; one wavefront only with G = R = 1;
-// weights exact in FP32.  The layout of least modelled step time wins:
-// a cost per wave count (barrier and cross-wave sums; none for one wave),
-// the latency of R E gathers, and their LDS bandwidth (W R E 64 gathers of
-// 8 bytes).  Fitted to MI355X measurements: 0.41 us per step for 62 rows
-// on one wave (E = 8), 0.64 us for 171 rows on 4 waves, 0.92 us for 400
-// rows of 12 to 16 entries on 4 to 8 waves, 1.46 us for 1536 rows on
-// 8 waves (R = 4, E = 8).
+// lanes per row and E entry slots per lane and row; R rows per lane group;
+// one wavefront only with G = R = 1; weights exact in FP32.  Rows of up to
+// 2 G E entries are allowed: the entries beyond G E go to an LDS list
+// after the two vectors, which must hold n (maxlen - G E) of them (or nnz,
+// if fewer).  The layout of least modelled step time wins: a cost per wave
+// count (barrier and cross-wave sums; none for one wave), the latency of
+// R E gathers, their LDS bandwidth (W R E 64 gathers of 8 bytes), and two
+// dependent LDS reads per trip over a long row's list (two entries a
+// trip).  Fitted to MI355X measurements: 0.41 us per step for 62 rows on
+// one wave (E = 8), 0.64 us for 171 rows on 4 waves, 0.92 us for 400 rows
+// of 12 to 16 entries on 4 to 8 waves, 1.46 us for 1536 rows on 8 waves
+// (R = 4, E = 8), 2.19 us for 262 rows of up to 34 entries on 8 waves
+// (G = 4, R = 4, E = 16); with the list, 1.34 us for those rows (G = 2,
+// R = 2, E = 16, one trip), 2.49 us for 895 rows of up to 35 entries
+// (G = 2, R = 4, E = 16, one trip), 1.86 us for 1536 rows of up to 11
+// entries (G = 1, R = 4, E = 8, two trips) and 1.29 us for 511 rows of up
+// to 12 (G = 1, R = 2, E = 8, two trips; 1.04 us with E = 16).
 struct BlockPlan {
     int waves = 0, lanes = 1, regs = 0, slots = 0, layout = -1;
 };
 
-BlockPlan plan_block_regs(const HostLevel& L) {
+BlockPlan plan_block_regs(const HostLevel& L, int lds_budget) {
     static const double wave_cost[9] = {0, 0.31, 0.45, 0, 0.52, 0, 0, 0, 0.70};
-    const double slot_cost = 0.0125, lds_cost = 0.0012, lane_sum_cost = 0.02;
+    const double slot_cost = 0.0125, lds_cost = 0.0012, lane_sum_cost = 0.02, list_trip_cost = 0.25;
     BlockPlan best;
     double best_cost = 0.0;
     if (L.n < 1 || L.n > 65536 || !L.w32exact) return best;
     for (int W : {1, 2, 4, 8}) {
         for (int l = 0; l < kRegLayouts; ++l) {
             const int G = kRegLayoutG[l], E = kRegLayoutE[l];
-            if (L.maxlen > (int64_t)G * E) continue;
+            const int64_t over = std::max<int64_t>(L.maxlen - (int64_t)G * E, 0);
+            if (over > (int64_t)G * E) continue;
+            if (over > 0) {
+                const int64_t list = std::min<int64_t>((int64_t)L.n * over, L.nnz);
+                if (16 * (int64_t)L.n + 8 * list > (int64_t)lds_budget) continue;
+            }
             const int groups = 64 * W / G;
             const int need = (L.n + groups - 1) / groups;
             const int R = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 0;
             if (R == 0) continue;
             if (W == 1 && (G != 1 || R != 1)) continue;
+            const int64_t trips = (over + 2 * G - 1) / (2 * G);
             const double cost = wave_cost[W] + R * E * slot_cost + W * R * E * lds_cost +
-                                R * (bitlen((unsigned)G) - 1) * lane_sum_cost;
+                                R * (bitlen((unsigned)G) - 1) * lane_sum_cost +
+                                (trips > 0 ? lane_sum_cost + trips * list_trip_cost : 0.0);
             if (best.regs == 0 || cost < best_cost) {
                 best.waves = W;
                 best.lanes = G;
@@ -1079,7 +1094,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         L.stage = o.grid_stage != 0 ? 1 : 0;
         L.bwaves = L.bregs = L.bslots = 0;
         if (!L.in_block) continue;
-        const BlockPlan p = o.block_regs < 0 ? BlockPlan{} : plan_block_regs(L);
+        const BlockPlan p = o.block_regs < 0 ? BlockPlan{} : plan_block_regs(L, refine_block_lds_budget());
         if (p.regs > 0) {
             L.bwaves = p.waves;
             L.lanes = p.lanes;
@@ -1491,8 +1506,9 @@ cmg_status finalize(cmg_ctx* c, double t0, bool timed, double* lambda, cmg_stats
                                   j, L.lanes, L.bregs, L.bslots, L.bwaves);
                 else
                     std::snprintf(g_last_error, sizeof(g_last_error),
-                                  "level %d: a row longer than its register layout (%d slots of %d lanes)", j,
-                                  L.bslots, L.lanes);
+                                  "level %d: the entries of rows longer than the register layout (%d slots of %d "
+                                  "lanes) do not fit the LDS left",
+                                  j, L.bslots, L.lanes);
                 return CMG_E_DEVICE;
             }
         }
@@ -2347,6 +2363,7 @@ cmg_status cmg_level_info(cmg_handle h, cmg_level_stats* out, int32_t cap, int32
         li.weights = wkr;
         li.block_waves = L.bwaves;
         li.block_regs = L.bregs;
+        li.block_slots = L.bslots;
         li.step = L.step;
         out[j] = li;
     }

@@ -587,18 +587,27 @@ struct SmallIn {
 // one round of independent gathers from the LDS vector.  Unused slots point
 // at the row's own vertex with weight 0 and add an exact zero, which keeps
 // the sums bit for bit those of the CSR traversal with the same G.
+// A row longer than G E keeps its further entries (column, FP32 weight)
+// in an LDS list; the lanes take them as slots E, E + 1, ... of the same
+// stride, so each lane still sums its entries in CSR order.
 template <int G, int R, int E>
 struct RegRows {
     uint32_t c2[R][E / 2];
     float w[R][E];
     int row[R];
+    int ooff[R], ocnt[R];  // the row's entries beyond G E: LDS list offset and count
+    const uint64_t* ovl;
     int n;
     double g;
 
-    __device__ __forceinline__ void load(const LevelDev& L, int nact, int* bad) {
+    // ov: LDS list of ovcap entries, filled from *ofill (zero before the
+    // first call of the level); a list that would overflow sets *bad
+    __device__ __forceinline__ void load(const LevelDev& L, int nact, int* bad, uint64_t* ov, int ovcap, int* ofill) {
         n = L.n;
         g = L.g;
+        ovl = ov;
         const int lane = (int)threadIdx.x & (G - 1);
+        const int lead = ((int)threadIdx.x & (kWave - 1)) & ~(G - 1);
         const int ngroups = nact / G;
         const int grp = (int)threadIdx.x / G;
 #pragma unroll
@@ -609,7 +618,23 @@ struct RegRows {
             if (i < n) {
                 a = gld(L.rp, i);
                 b = gld(L.rp, i + 1);
-                if (b - a > G * E) *bad = 1;
+            }
+            // the same count in every lane of the group; its first lane
+            // takes the list space for all of them
+            int extra = max(b - a - G * E, 0);
+            int off = 0;
+            if (extra > 0 && lane == 0) off = atomicAdd(ofill, extra);
+            off = __shfl(off, lead, kWave);
+            if (extra > 0 && (off < 0 || off > ovcap - extra)) {
+                if (lane == 0) *bad = 1;
+                extra = 0;
+            }
+            ooff[r] = off;
+            ocnt[r] = extra;
+            for (int q = lane; q < extra; q += G) {
+                const int e = a + G * E + q;
+                const uint64_t wb = __float_as_uint((float)gld(L.w64, e));
+                sst(ov, off + q, (uint64_t)(uint32_t)gld(L.col, e) | (wb << 32));
             }
             const uint32_t self = i < n ? (uint32_t)i : 0u;
 #pragma unroll
@@ -626,6 +651,11 @@ struct RegRows {
                 w[r][m] = wv;
             }
         }
+        // the list entries are read back by the lanes of the group that
+        // wrote them, in the same wavefront
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 
     __device__ __forceinline__ void step(const double* win, double* wout, double mu, double s, double (&acc)[4]) {
@@ -648,6 +678,15 @@ struct RegRows {
             double t = 0.0;
 #pragma unroll
             for (int m = 0; m < E; ++m) t += (double)w[r][m] * (x[m] - wi);
+            // entries beyond G E, two per trip; the second of a trip past
+            // the row's end is its own vertex with weight 0 (an exact zero)
+            for (int q = lane; q < ocnt[r]; q += 2 * G) {
+                const uint64_t p0 = sld(ovl, ooff[r] + q);
+                const uint64_t p1 = q + G < ocnt[r] ? sld(ovl, ooff[r] + q + G) : (uint64_t)(uint32_t)i;
+                const double x0 = sld(win, (int)(uint32_t)p0), x1 = sld(win, (int)(uint32_t)p1);
+                t += (double)__uint_as_float((uint32_t)(p0 >> 32)) * (x0 - wi);
+                t += (double)__uint_as_float((uint32_t)(p1 >> 32)) * (x1 - wi);
+            }
             t = group_sum_t<G>(t);
             if (lane == 0 && i >= 0) {
                 const double xv = (wi - mu) * s;
@@ -902,13 +941,14 @@ __global__ void __launch_bounds__(kBlockKernelThreads)
     }
 }
 
-// One level on register rows with both vectors in LDS.  nw == 1: on
-// wavefront 0 alone with no workgroup barrier (the caller keeps the other
-// waves out); else the first nw waves run the steps and the others keep the
-// barrier count as in the CSR traversal.
+// One level on register rows with both vectors in LDS (and the entries of
+// rows longer than the layout in the LDS list ov of ovcap entries, filled
+// from *ofill).  nw == 1: on wavefront 0 alone with no workgroup barrier
+// (the caller keeps the other waves out); else the first nw waves run the
+// steps and the others keep the barrier count as in the CSR traversal.
 template <int G, int R, int E>
-__device__ void reg_level(const LevelDev& L, const SmallIn& in, double* b0, double* b1, double* red, int& parity,
-                          int* stop_flag, int* bad, int nw, LevelState& out) {
+__device__ void reg_level(const LevelDev& L, const SmallIn& in, double* b0, double* b1, uint64_t* ov, int ovcap,
+                          int* ofill, double* red, int& parity, int* stop_flag, int* bad, int nw, LevelState& out) {
     const bool wave = (nw == 1);
     const int n = L.n;
     const int nthr = wave ? 64 : (int)blockDim.x;
@@ -950,7 +990,7 @@ __device__ void reg_level(const LevelDev& L, const SmallIn& in, double* b0, doub
         return;  // the state is kept by thread 0
     }
     RegRows<G, R, E> rows;
-    rows.load(L, nact, bad);
+    rows.load(L, nact, bad, ov, ovcap, ofill);
     while (true) {
         const double* win = cur ? b1 : b0;
         double* wout = cur ? b0 : b1;
@@ -1002,8 +1042,10 @@ __device__ void reg_level(const LevelDev& L, const SmallIn& in, double* b0, doub
 // Levels jhi down to jlo refined inside one workgroup on register rows of
 // G lanes per row, R rows per lane group and E slots per lane and row
 // (every level of the job has that layout and LevelDev::bwaves waves;
-// FP32-exact weights).  A level whose layout does not fit is skipped with err = 2 in
-// its state.
+// FP32-exact weights; rows longer than G E keep the rest in the LDS left
+// after the two vectors).  A level whose layout does not fit is skipped
+// with err = 2 in its state; err = 1 if the entries beyond the layout do
+// not fit the LDS left.
 template <int G, int R, int E>
 __global__ void __launch_bounds__(kBlockRegsThreads)
     k_block_regs(const BlockJob* __restrict__ jobs, int lds_budget) {
@@ -1013,6 +1055,7 @@ __global__ void __launch_bounds__(kBlockRegsThreads)
     __shared__ int s_cfin;
     __shared__ int s_stop[2];
     __shared__ int s_bad;
+    __shared__ int s_ofill;
     const BlockJob Jb = jobs[blockIdx.x];
     const LevelDev* __restrict__ lv = Jb.lv;
     int parity = 0;
@@ -1031,7 +1074,13 @@ __global__ void __launch_bounds__(kBlockRegsThreads)
         const bool fits = L.lanes == G && L.bregs == R && L.bslots == E && L.w32exact && n >= 1 && n <= 65536 &&
                           16 * (size_t)n <= (size_t)lds_budget && n <= R * (64 * nw / G) &&
                           (nw > 1 || (G == 1 && R == 1));
-        if (threadIdx.x == 0) s_bad = 0;
+        if (threadIdx.x == 0) {
+            s_bad = 0;
+            s_ofill = 0;
+        }
+        // list of the entries beyond the layout: the LDS left after the vectors
+        uint64_t* ov = (uint64_t*)(lds + 2 * (size_t)n);
+        const int ovcap = fits ? (int)(((size_t)lds_budget - 16 * (size_t)n) / 8) : 0;
         SmallIn in;
         in.uniform = (Jb.uniform && j == Jb.jhi) ? 1 : 0;
         if (!in.uniform) {
@@ -1051,9 +1100,10 @@ __global__ void __launch_bounds__(kBlockRegsThreads)
         if (!fits) {
             o.err = 2;
         } else if (nw == 1) {
-            if (threadIdx.x < 64) reg_level<G, R, E>(L, in, lds, lds + n, red, parity, s_stop, &s_bad, 1, o);
+            if (threadIdx.x < 64)
+                reg_level<G, R, E>(L, in, lds, lds + n, ov, ovcap, &s_ofill, red, parity, s_stop, &s_bad, 1, o);
         } else {
-            reg_level<G, R, E>(L, in, lds, lds + n, red, parity, s_stop, &s_bad, nw, o);
+            reg_level<G, R, E>(L, in, lds, lds + n, ov, ovcap, &s_ofill, red, parity, s_stop, &s_bad, nw, o);
         }
         if (threadIdx.x == 0) {
             o.ticks = wall_clock64() - t_start;

@@ -61,7 +61,7 @@ int main(void) {
   F(cmg_options, fixed_k0) F(cmg_options, fixed_beta) F(cmg_options, graph) F(cmg_options, coarsen) F(cmg_options, galerkin)
   F(cmg_options, test_abort_level) F(cmg_options, weight_storage) F(cmg_stats, fallback) F(cmg_level_stats, weights)
   F(cmg_stats, lambda) F(cmg_stats, residual) F(cmg_stats, finest_bytes) F(cmg_stats, status)
-  F(cmg_level_stats, nnz) F(cmg_level_stats, pi_ms) F(cmg_level_stats, bytes_per_iter)
+  F(cmg_level_stats, nnz) F(cmg_level_stats, pi_ms) F(cmg_level_stats, bytes_per_iter) F(cmg_level_stats, block_slots)
   return 0;
 }
 """)

@@ -553,18 +553,27 @@ def test_grid_stage_is_bitwise_equal_to_global_reads(name):
 def test_block_register_rows_and_csr_agree_with_oracle(name):
     """Single-workgroup levels on register rows (default) and on the CSR
     traversal (block_regs=-1): both bit-exact in hierarchy and step counts
-    against the oracle.  Graphs with short rows use register rows; a hub
-    row longer than any layout keeps its level on the CSR kernel."""
+    against the oracle.  Graphs with short rows use register rows; rows up
+    to twice a layout's slots keep the rest in an LDS list (a level of
+    grid128, cl30k and er500 each); a hub row longer than that keeps its
+    level on the CSR kernel."""
     g = _named(name)
     ref = oracle_of(g)
     for regs in (0, -1):
         lam, x, st, levels, arrays = run_gpu(g, block_regs=regs)
-        lay = [(j, l.lanes, l.block_waves, l.block_regs) for j, l in enumerate(levels) if l.in_block]
-        say(f"[parity] {name} block_regs={regs} block levels (j, lanes, waves, rows per group) {lay}")
+        lay = [(j, l.lanes, l.block_waves, l.block_regs, l.block_slots,
+                int(np.diff(ref.levels[j].row_ptr).max())) for j, l in enumerate(levels) if l.in_block]
+        say(f"[parity] {name} block_regs={regs} block levels "
+            f"(j, lanes, waves, rows per group, slots, longest row) {lay}")
         if regs < 0:
             assert all(l.block_regs == 0 for l in levels)
-        elif name in ("rgg20k", "grid128", "grid3d_20"):
-            assert any(l.block_regs > 0 for l in levels if l.in_block)
+        else:
+            if name in ("rgg20k", "grid128", "grid3d_20"):
+                assert any(l.block_regs > 0 for l in levels if l.in_block)
+            if name in ("grid128", "cl30k", "er500"):
+                # a level whose longest row exceeds lanes x slots
+                assert any(r > 0 and ml > ln * sl for _, ln, _, r, sl, ml in lay)
+            assert all(ml <= 2 * ln * sl for _, ln, _, r, sl, ml in lay if r > 0)
         assert_fp64_parity(g, lam, x, st, levels, arrays, ref)
 
 

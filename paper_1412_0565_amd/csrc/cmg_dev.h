@@ -211,6 +211,9 @@ struct LevelDev {
     int32_t wk;          // weight storage of the grid and step kernels (kWNative, kWF32, kWUnit)
     int32_t lmin;        // rows traversal: rows with more entries are long (INT_MAX: none)
     const int32_t* lrows;// ... their count, then the long rows in ascending order (nullptr: none)
+    int32_t ileave;      // rows traversal of the persistent grid kernel: 1 if each workgroup's PI
+                         // steps take row chunks interleaved over its XCD's workgroups (the
+                         // long rows stay with its own part); never staged in LDS
 };
 
 // State a refinement launch leaves for the next level (device written).

@@ -310,6 +310,7 @@ constexpr int kGridBlock = 512;
 constexpr int kBlockKernelThreads = 1024;
 constexpr int kBlockRegsThreads = 512;   // 256 VGPRs per lane for register rows
 constexpr int kBlockLdsMax = 144 * 1024;  // LDS image budget of the single-workgroup kernel
+constexpr int kGridStageRows = 1024;       // most rows of a grid workgroup's LDS stage
 int refine_block_lds_budget();
 
 }  // namespace cmg

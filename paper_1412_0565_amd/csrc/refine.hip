@@ -1377,6 +1377,25 @@ __device__ __forceinline__ int ld_rp(const int32_t* rp, int i) {
     else return gld(rp, i);
 }
 
+// the long rows of [r0, r1) (listed in lrows), each summed by the whole
+// workgroup
+template <bool SRP = false, typename Op>
+__device__ __forceinline__ void drive_long_rows(const int32_t* __restrict__ rp, int r0, int r1, Op& op,
+                                                const int32_t* __restrict__ lrows, double* red, int loff = 0) {
+    const int cnt = gld(lrows, 0);
+    const int32_t* lr = lrows + 1;
+    const int q1 = lower_bound_i32(lr, cnt, r1 + loff);
+    for (int q = lower_bound_i32(lr, cnt, r0 + loff); q < q1; ++q) {
+        const int r = gld(lr, q) - loff;
+        const int a = ld_rp<SRP>(rp, r), b = ld_rp<SRP>(rp, r + 1);
+        const double x = op.xi(r);
+        double t[1] = {0.0};
+        for (int e = a + (int)threadIdx.x; e < b; e += (int)blockDim.x) t[0] += op.entry(e, x);
+        block_sum<1>(t, red);
+        if (threadIdx.x == 0) op.row(r, x, t[0]);
+    }
+}
+
 template <int G, bool SRP = false, class Op>
 __device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r0, int r1, Op& op,
                                            const int32_t* __restrict__ lrows = nullptr, int lmin = 0x7fffffff,
@@ -1422,20 +1441,7 @@ __device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r
             if (lane == 0) op.row(i, x, t);
         }
     }
-    if (lrows != nullptr) {
-        const int cnt = gld(lrows, 0);
-        const int32_t* lr = lrows + 1;
-        const int q1 = lower_bound_i32(lr, cnt, r1 + loff);
-        for (int q = lower_bound_i32(lr, cnt, r0 + loff); q < q1; ++q) {
-            const int r = gld(lr, q) - loff;
-            const int a = ld_rp<SRP>(rp, r), b = ld_rp<SRP>(rp, r + 1);
-            const double x = op.xi(r);
-            double t[1] = {0.0};
-            for (int e = a + (int)threadIdx.x; e < b; e += (int)blockDim.x) t[0] += op.entry(e, x);
-            block_sum<1>(t, red);
-            if (threadIdx.x == 0) op.row(r, x, t[0]);
-        }
-    }
+    if (lrows != nullptr) drive_long_rows<SRP>(rp, r0, r1, op, lrows, red, loff);
 }
 
 // ---- traversal driver 2: merge path
@@ -1602,7 +1608,7 @@ __device__ __forceinline__ void drive(const LevelDev& L, int r0, int r1, Op& op,
 // same traversal; only the vector gathers go to memory.  Rows and entries
 // are visited in the same order, so the sums are bit for bit those of the
 // global traversal.
-constexpr int kStageRows = 1024;
+constexpr int kStageRows = kGridStageRows;
 constexpr int kStageEnts = 3840;
 struct StageLds {
     int32_t rp[kStageRows + 1];  // row pointers relative to the first entry
@@ -1635,7 +1641,7 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
     if constexpr (TRAV > 0 && sizeof(T) == 8) {
         const int a0 = gld(L.rp, r0), a1 = gld(L.rp, r1);
         // the same in every thread of the workgroup
-        if (stg != nullptr && L.stage && r1 - r0 <= kStageRows && a1 - a0 <= kStageEnts) {
+        if (stg != nullptr && L.stage && !L.ileave && r1 - r0 <= kStageRows && a1 - a0 <= kStageEnts) {
             for (int i = threadIdx.x; i <= r1 - r0; i += blockDim.x) stg->rp[i] = gld(L.rp, r0 + i) - a0;
             for (int e = threadIdx.x; e < a1 - a0; e += blockDim.x) {
                 stg->col[e] = gld(L.col, a0 + e);
@@ -1648,6 +1654,18 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
             ops.g = L.g;
             staged = true;
         }
+    }
+    // interleaved steps: this workgroup's XCD holds parts xl0 .. xl0 + np - 1
+    // (the grouping of xcd_remap); their rows [x0, x1) go in chunks of four
+    // passes, chunk q to the workgroup at position q mod np
+    int x0 = r0, x1 = r1, xp = 0, np = 1;
+    if (TRAV > 0 && L.ileave) {
+        const int q = c.nb >> 3, rr = c.nb & 7, x = c.vb & 7;
+        const int xl0 = x * q + min(x, rr);
+        np = q + (x < rr ? 1 : 0);
+        xp = c.vb >> 3;
+        x0 = gld(L.part, xl0);
+        x1 = gld(L.part, xl0 + np);
     }
     // prolongation from level j+1 (or the hashed uniform start)
     double sum[1] = {0.0};
@@ -1695,8 +1713,16 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
             op.mu = mu;
             op.s = s;
             op.acc[0] = op.acc[1] = op.acc[2] = op.acc[3] = 0.0;
-            if constexpr (TRAV == 0) drive_merge(L.rp, r0, r1, op, *sh);
-            else drive_rows<TRAV>(L.rp, r0, r1, op, L.lrows, L.lmin, red);
+            if constexpr (TRAV == 0) {
+                drive_merge(L.rp, r0, r1, op, *sh);
+            } else if (L.ileave) {
+                const int cw = 4 * ((int)blockDim.x / TRAV);
+                for (int a = x0 + xp * cw; a < x1; a += np * cw)
+                    drive_rows<TRAV>(L.rp, a, min(a + cw, x1), op, nullptr, L.lmin, red);
+                if (L.lrows != nullptr) drive_long_rows(L.rp, r0, r1, op, L.lrows, red);
+            } else {
+                drive_rows<TRAV>(L.rp, r0, r1, op, L.lrows, L.lmin, red);
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q] = op.acc[q];
         }

@@ -9,10 +9,12 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <new>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include <rocprofiler-sdk-roctx/roctx.h>
@@ -364,6 +366,7 @@ struct SetupTmp {
     unsigned long long* ri = nullptr;    // row information of level j at ri[4j .. 4j+3]
     double* gpart = nullptr;             // Galerkin pieces of runs that cross workgroups
     unsigned* alive = nullptr;           // HEM: one flag per round
+    unsigned long long* rb = nullptr;    // words gathered for one host read
     void* block = nullptr;               // the one allocation all of the above point into
     std::vector<int> ri_pending;         // levels whose row information is still on the device
 };
@@ -409,6 +412,7 @@ void carve_tmp(Carver& cv, SetupTmp& t, int32_t n, int64_t nnz) {
     t.ri = cv.take<unsigned long long>(4 * kMaxLevels);
     t.gpart = cv.take<double>(gal_part_elems(nnz));
     t.alive = cv.take<unsigned>(kHemMaxRounds);
+    t.rb = cv.take<unsigned long long>(kPackWordsMax);
 }
 
 cmg_status alloc_tmp(cmg_ctx* c, SetupTmp& t, int32_t n, int64_t nnz) {
@@ -463,6 +467,22 @@ cmg_status finish_rowinfo(cmg_ctx* c, SetupTmp& t) {
 // longest input row for which member lists are built by counting
 constexpr unsigned kCountMembersMaxRow = 1024;
 
+// Device words (4 or 8 bytes each) read back with one copy: a launch
+// gathers them into the setup scratch, so a host decision waits for one
+// transfer instead of one per value.
+cmg_status read_words(cmg_ctx* c, SetupTmp& t, std::initializer_list<std::pair<const void*, int>> src,
+                      unsigned long long* out) {
+    PackWords p{};
+    for (const auto& e : src) {
+        if (p.n == kPackWordsMax) return CMG_E_ARG;
+        p.src[p.n] = e.first;
+        p.bytes[p.n] = e.second;
+        ++p.n;
+    }
+    CK(launch_pack_words(p, t.rb, c->stream));
+    return d2h(c, out, t.rb, (size_t)p.n);
+}
+
 // HEC greedy rounds launched before the first host check of a level (the
 // 3D-grid and geometric levels measured need 4 to 6; unused rounds return
 // at once)
@@ -474,11 +494,10 @@ cmg_status hec_finish(cmg_ctx* c, SetupTmp& t, int j, int* launched) {
     const HostLevel& L = c->lv[j];
     unsigned long long* hflags = t.scal + 6;
     for (;;) {
-        unsigned long long more = 0;
-        unsigned iso = 0;
-        CK(hipMemcpyAsync(&iso, t.vflags, sizeof(iso), hipMemcpyDeviceToHost, c->stream));
-        cmg_status st = d2h(c, &more, hflags + ((*launched - 1) & 1), 1);
+        unsigned long long w[2];
+        cmg_status st = read_words(c, t, {{t.vflags, 4}, {hflags + ((*launched - 1) & 1), 8}}, w);
         if (st != CMG_OK) return st;
+        const unsigned long long iso = w[0], more = w[1];
         if (iso) return CMG_E_ISOLATED;
         if (more == 0) return CMG_OK;
         if (*launched > 100000) return CMG_E_DEVICE;
@@ -526,10 +545,10 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
                 CK(launch_hem_round(L.n, L.rp, L.col, L.w64, seed, j, t.pairseed, t.live, t.slot, t.alive, round,
                                     s));
             c->hec_rounds += batch;
-            unsigned last = 0, iso = 0;
-            CK(hipMemcpyAsync(&iso, t.vflags, sizeof(iso), hipMemcpyDeviceToHost, s));
-            st = d2h(c, &last, t.alive + round - 1, 1);
+            unsigned long long w[2];
+            st = read_words(c, t, {{t.vflags, 4}, {t.alive + round - 1, 4}}, w);
             if (st != CMG_OK) return st;
+            const unsigned long long iso = w[0], last = w[1];
             if (iso) return CMG_E_ISOLATED;
             if (last == 0) break;
         }
@@ -578,14 +597,18 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
             CK(launch_scan(mdeg, moff, L.n, t.scan_tmp, t.totals + 2, s));
             CK(launch_fill_u32((unsigned*)(t.scal + 4), 0u, 2, s));
             CK(launch_gal_agg_len((int)ncmax, t.totals, L.n, L.nnz, mstart, moff, t.scal + 4, s));
-            unsigned long long more = 0, wmax0 = 0;
-            unsigned iso = 0;
-            CK(hipMemcpyAsync(&iso, t.vflags, sizeof(iso), hipMemcpyDeviceToHost, s));
-            CK(hipMemcpyAsync(&nc0, t.totals, sizeof(long long), hipMemcpyDeviceToHost, s));
-            if (j == 0) CK(hipMemcpyAsync(&wmax0, t.ri + 1, sizeof(wmax0), hipMemcpyDeviceToHost, s));
-            if (!hem) CK(hipMemcpyAsync(&more, hflags + ((hec_launched - 1) & 1), sizeof(more), hipMemcpyDeviceToHost, s));
-            st = d2h(c, &emax, t.scal + 4, 1);
+            // flag of a coarse vertex without neighbours, aggregate count,
+            // largest input weight (level 0), live candidates after the
+            // rounds launched (HEC), entries of the largest aggregate
+            unsigned long long w[5];
+            st = read_words(c, t,
+                            {{t.vflags, 4}, {t.totals, 8}, {t.ri + 1, 8}, {hflags + ((hec_launched - 1) & 1), 8},
+                             {t.scal + 4, 8}},
+                            w);
             if (st != CMG_OK) return st;
+            const unsigned long long iso = w[0], wmax0 = j == 0 ? w[2] : 0ull, more = hem ? 0ull : w[3];
+            nc0 = (long long)w[1];
+            emax = w[4];
             if (iso) return CMG_E_ISOLATED;  // a component of the graph became one aggregate
             if (j == 0) {
                 // every coarse weight is a sum of input weights: with
@@ -644,7 +667,9 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
             C.nnz = zc;
             ALLOC(C.col, int32_t, std::max<long long>(zc, 1));
             ALLOC(C.w64, double, std::max<long long>(zc, 1));
-            if (zc > 0) CK(launch_gal_compact(nc, mstart, moff, C.rp, tcol, tw, C.col, C.w64, s));
+            if (zc > 0)
+                CK(launch_gal_compact(nc, mstart, moff, C.rp, tcol, tw, t.heads, (const unsigned*)(t.scal + 5), C.col,
+                                      C.w64, s));
             C.lanes = pick_lanes(C.nnz / (double)C.n);
             c->lv.push_back(C);
             return CMG_OK;
@@ -677,12 +702,11 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
     CK(launch_count_below(ks, L.nnz, packed ? (sent << pshift) : kGalSentinel, t.scal + 3, s));
     CK(launch_gal_heads(L.nnz, t.scal + 3, ks, pshift, t.heads, s));
     CK(launch_scan(t.heads, t.idx, L.nnz, t.scan_tmp, t.totals + 1, s));  // totals[1]: coarse entries
-    long long tot[2] = {0, 0};
-    unsigned long long nvalid = 0;
-    CK(hipMemcpyAsync(tot, t.totals, sizeof(tot), hipMemcpyDeviceToHost, s));
-    st = d2h(c, &nvalid, t.scal + 3, 1);
+    unsigned long long w[3];
+    st = read_words(c, t, {{t.totals, 8}, {t.totals + 1, 8}, {t.scal + 3, 8}}, w);
     if (st != CMG_OK) return st;
-    const long long nc = tot[0], zc = tot[1];
+    const long long nc = (long long)w[0], zc = (long long)w[1];
+    const unsigned long long nvalid = w[2];
     if (nc < 2) {
         c->dfree(L.agg);
         L.agg = nullptr;

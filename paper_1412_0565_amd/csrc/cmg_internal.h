@@ -123,9 +123,18 @@ hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int slots, int unit, in
                              const int32_t* mstart, const int32_t* moff, const int32_t* rp, const int32_t* col,
                              const double* w, const int32_t* agg, int32_t* tcol, double* tw, int32_t* rowlen,
                              int32_t* big, unsigned* nbig, hipStream_t s);
+// Up to kPackWordsMax device words (4 or 8 bytes each) gathered into
+// dst[0 ..) as 64-bit values by one launch, for one host read.
+constexpr int kPackWordsMax = 8;
+struct PackWords {
+    const void* src[kPackWordsMax];
+    int32_t bytes[kPackWordsMax];
+    int32_t n;
+};
+hipError_t launch_pack_words(const PackWords& p, unsigned long long* dst, hipStream_t s);
 hipError_t launch_gal_compact(int nc, const int32_t* mstart, const int32_t* moff, const int32_t* crp,
-                              const int32_t* tcol, const double* tw, int32_t* col_out, double* w_out,
-                              hipStream_t s);
+                              const int32_t* tcol, const double* tw, const int32_t* big, const unsigned* nbig,
+                              int32_t* col_out, double* w_out, hipStream_t s);
 // One round of heavy edge matching (two passes; opener[v] = -1 while v is
 // unmatched, else the vertex that opened its aggregate); alive[round] is
 // raised if any vertex was unmatched when the round began.

@@ -726,8 +726,12 @@ __global__ void __launch_bounds__(kBlk) k_gal_wave(int n, int64_t nnz, const int
 }
 
 // pass 2: the rows into the coarse CSR (row pointers from the scan of
-// rowlen), kGalCompactLanes lanes per row
-constexpr int kGalCompactLanes = 16;
+// rowlen).  Rows of at most kGalCompactShort entries (every row the lane
+// pass formed) go kGalCompactLanes lanes to a row; the longer ones, all
+// among the aggregates listed for pass 1b, a wavefront each.
+constexpr int kGalCompactLanes = 4;
+constexpr int kGalCompactShort = 32;
+constexpr int kGalCompactLongBlocks = 256;
 __global__ void k_gal_compact(int nc, const int32_t* __restrict__ mstart, const int32_t* __restrict__ moff,
                               const int32_t* __restrict__ crp, const int32_t* __restrict__ tcol,
                               const double* __restrict__ tw, int32_t* __restrict__ col_out,
@@ -736,12 +740,41 @@ __global__ void k_gal_compact(int nc, const int32_t* __restrict__ mstart, const 
     const int a = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G);
     const int lane = threadIdx.x & (G - 1);
     if (a >= nc) return;
-    const int base = moff[mstart[a]];
     const int o = crp[a], len = crp[a + 1] - o;
+    if (len > kGalCompactShort) return;
+    const int base = moff[mstart[a]];
     for (int t = lane; t < len; t += G) {
         col_out[o + t] = tcol[base + t];
         w_out[o + t] = tw[base + t];
     }
+}
+
+__global__ void k_gal_compact_long(const int32_t* __restrict__ mstart, const int32_t* __restrict__ moff,
+                                   const int32_t* __restrict__ crp, const int32_t* __restrict__ tcol,
+                                   const double* __restrict__ tw, const int32_t* __restrict__ big,
+                                   const unsigned* __restrict__ nbig, int32_t* __restrict__ col_out,
+                                   double* __restrict__ w_out) {
+    const unsigned nb = *nbig;
+    const int lane = threadIdx.x & (kWave - 1);
+    const unsigned nwaves = (gridDim.x * blockDim.x) / kWave;
+    for (unsigned q = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; q < nb; q += nwaves) {
+        const int a = big[q];
+        const int o = crp[a], len = crp[a + 1] - o;
+        if (len <= kGalCompactShort) continue;
+        const int base = moff[mstart[a]];
+        for (int t = lane; t < len; t += kWave) {
+            col_out[o + t] = tcol[base + t];
+            w_out[o + t] = tw[base + t];
+        }
+    }
+}
+
+// values the host reads together: a 4- or 8-byte word from each source,
+// widened to 64 bits in order
+__global__ void k_pack_words(PackWords p, unsigned long long* __restrict__ dst) {
+    const int i = threadIdx.x;
+    if (i < p.n)
+        dst[i] = p.bytes[i] == 4 ? (unsigned long long)*(const unsigned*)p.src[i] : *(const unsigned long long*)p.src[i];
 }
 
 // ------------------------------------------------------------------ scan
@@ -1321,11 +1354,19 @@ hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int slots, int unit, in
     return hipGetLastError();
 }
 
+hipError_t launch_pack_words(const PackWords& p, unsigned long long* dst, hipStream_t s) {
+    if (p.n < 1 || p.n > kPackWordsMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pack_words, dim3(1), dim3(kWave), 0, s, p, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_gal_compact(int nc, const int32_t* mstart, const int32_t* moff, const int32_t* crp,
-                              const int32_t* tcol, const double* tw, int32_t* col_out, double* w_out,
-                              hipStream_t s) {
+                              const int32_t* tcol, const double* tw, const int32_t* big, const unsigned* nbig,
+                              int32_t* col_out, double* w_out, hipStream_t s) {
     hipLaunchKernelGGL(k_gal_compact, dim3(nblocks((int64_t)nc * kGalCompactLanes, kBlk)), dim3(kBlk), 0, s, nc, mstart,
                        moff, crp, tcol, tw, col_out, w_out);
+    hipLaunchKernelGGL(k_gal_compact_long, dim3(kGalCompactLongBlocks), dim3(kBlk), 0, s, mstart, moff, crp, tcol, tw,
+                       big, nbig, col_out, w_out);
     return hipGetLastError();
 }
 

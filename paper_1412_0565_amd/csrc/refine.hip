@@ -1140,9 +1140,10 @@ __device__ __forceinline__ bool job_allreduce(double (&v)[NV], GridCtx& c, doubl
 // ---- per-row operations fed by the two traversal drivers
 //
 // Edge weights are read through WRead<W>: W = double or float (an FP32
-// copy, used only where every weight of the level is exact in FP32), or
+// copy, used only where every weight of the level is exact in FP32),
+// uint8_t (an 8-bit copy where every weight is an integer in 1..255), or
 // WUnit where every weight is 1 and nothing is read.  The value is the
-// same double in all three, so results do not depend on the storage.
+// same double in all of them, so results do not depend on the storage.
 struct WUnit {};
 template <typename W, bool LDS = false>
 struct WRead {
@@ -1170,11 +1171,16 @@ template <typename T>
 struct WStore<T, kWUnit> {
     using type = WUnit;
 };
+template <typename T>
+struct WStore<T, kWU8> {
+    using type = uint8_t;
+};
 // the level's weights of kind WK for iterates of type T
 template <typename T, int WK>
 __device__ __forceinline__ WRead<typename WStore<T, WK>::type> weights_of(const LevelDev& L) {
     WRead<typename WStore<T, WK>::type> r;
     if constexpr (WK == kWUnit) r.p = nullptr;
+    else if constexpr (WK == kWU8) r.p = L.w8;
     else if constexpr (WK == kWF32 || sizeof(T) == 4) r.p = L.w32;
     else r.p = L.w64;
     return r;
@@ -2196,14 +2202,14 @@ hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, int kind, hipStrea
 
 namespace {
 // kind = 16 wk + 2 t + fp32 with t = 0 (merge path) or 1 + log2(G) and wk
-// the weight storage (FP32 iterates have no kWF32 form)
+// the weight storage (FP32 iterates have no kWF32 or kWU8 form)
 template <int TRAV, int WK>
 const void* refine_kernel_w(int fp32) {
     if constexpr (TRAV == 0) {
-        if constexpr (WK == kWF32) return (const void*)k_refine_merge<double, kWF32>;
+        if constexpr (WK == kWF32 || WK == kWU8) return (const void*)k_refine_merge<double, WK>;
         else return fp32 ? (const void*)k_refine_merge<float, WK> : (const void*)k_refine_merge<double, WK>;
-    } else if constexpr (WK == kWF32) {
-        return (const void*)k_refine_rows<TRAV, double, kWF32>;
+    } else if constexpr (WK == kWF32 || WK == kWU8) {
+        return (const void*)k_refine_rows<TRAV, double, WK>;
     } else {
         return fp32 ? (const void*)k_refine_rows<TRAV, float, WK> : (const void*)k_refine_rows<TRAV, double, WK>;
     }
@@ -2212,6 +2218,7 @@ template <int TRAV>
 const void* refine_kernel_t(int fp32, int wk) {
     return wk == kWUnit ? refine_kernel_w<TRAV, kWUnit>(fp32)
            : wk == kWF32 ? refine_kernel_w<TRAV, kWF32>(fp32)
+           : wk == kWU8  ? refine_kernel_w<TRAV, kWU8>(fp32)
                          : refine_kernel_w<TRAV, kWNative>(fp32);
 }
 const void* refine_kernel(int kind) {
@@ -2231,6 +2238,7 @@ template <int TRAV>
 const void* finish_kernel_t(int wk) {
     return wk == kWUnit ? (const void*)k_finish_jobs<TRAV, kWUnit>
            : wk == kWF32 ? (const void*)k_finish_jobs<TRAV, kWF32>
+           : wk == kWU8  ? (const void*)k_finish_jobs<TRAV, kWU8>
                          : (const void*)k_finish_jobs<TRAV, kWNative>;
 }
 const void* finish_kernel(int kind) {
@@ -2317,7 +2325,7 @@ int job_kind(int variant, int lanes, int fp32, int wk) {
         for (int g = lanes; g > 1 && t < 7; g >>= 1) ++t;
     }
     // FP32 iterates read FP32 weights (their native storage)
-    if (fp32 && wk == kWF32) wk = kWNative;
+    if (fp32 && (wk == kWF32 || wk == kWU8)) wk = kWNative;
     return 16 * wk + 2 * t + (fp32 ? 1 : 0);
 }
 
@@ -2382,8 +2390,8 @@ hipError_t launch_step_begin(const StepJob* job, int nblocks, int kind, hipStrea
 namespace {
 template <int G, int WK>
 void step_spmv_w(const StepJob* job, int nblocks, int fp32, hipStream_t s) {
-    if constexpr (WK == kWF32) {
-        hipLaunchKernelGGL((k_step_spmv<G, double, kWF32>), dim3(nblocks), dim3(kStepBlock), 0, s, job);
+    if constexpr (WK == kWF32 || WK == kWU8) {
+        hipLaunchKernelGGL((k_step_spmv<G, double, WK>), dim3(nblocks), dim3(kStepBlock), 0, s, job);
     } else {
         if (fp32) hipLaunchKernelGGL((k_step_spmv<G, float, WK>), dim3(nblocks), dim3(kStepBlock), 0, s, job);
         else hipLaunchKernelGGL((k_step_spmv<G, double, WK>), dim3(nblocks), dim3(kStepBlock), 0, s, job);
@@ -2393,6 +2401,7 @@ template <int G>
 void step_spmv_g(const StepJob* job, int nblocks, int fp32, int wk, hipStream_t s) {
     if (wk == kWUnit) step_spmv_w<G, kWUnit>(job, nblocks, fp32, s);
     else if (wk == kWF32) step_spmv_w<G, kWF32>(job, nblocks, fp32, s);
+    else if (wk == kWU8) step_spmv_w<G, kWU8>(job, nblocks, fp32, s);
     else step_spmv_w<G, kWNative>(job, nblocks, fp32, s);
 }
 }  // namespace

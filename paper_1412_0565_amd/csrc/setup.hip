@@ -99,6 +99,13 @@ __global__ void k_to_f32(int64_t nnz, const double* __restrict__ in, float* __re
     for (; i < nnz; i += st) out[i] = (float)in[i];
 }
 
+// weights known to be integers in 1..255
+__global__ void k_to_u8(int64_t nnz, const double* __restrict__ in, uint8_t* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (; i < nnz; i += st) out[i] = (uint8_t)in[i];
+}
+
 // ------------------------------------------------------- row information
 
 // One G-lane group per row: heaviest neighbour (max weight, lowest column
@@ -1225,6 +1232,13 @@ hipError_t launch_to_f32(int64_t nnz, const double* w64, float* w32, hipStream_t
     unsigned nb = (unsigned)std::min<int64_t>(nblocks(nnz, kBlk), 65536);
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(k_to_f32, dim3(nb), dim3(kBlk), 0, s, nnz, w64, w32);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_u8(int64_t nnz, const double* w64, uint8_t* w8, hipStream_t s) {
+    unsigned nb = (unsigned)std::min<int64_t>(nblocks(nnz, kBlk), 65536);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_u8, dim3(nb), dim3(kBlk), 0, s, nnz, w64, w8);
     return hipGetLastError();
 }
 

@@ -63,6 +63,7 @@ struct HostLevel {
     double* w64 = nullptr;
     float* w32 = nullptr;
     uint8_t* w8 = nullptr;  // 8-bit copy of the weights (kWU8)
+    uint16_t* w16 = nullptr;  // 16-bit copy of the weights (kWU16)
     int32_t* agg = nullptr;
     double g = 0.0, wmax = 0.0;
     int w32exact = 0;
@@ -840,6 +841,7 @@ LevelDev level_dev(const HostLevel& L) {
     d.w64 = L.w64;
     d.w32 = L.w32;
     d.w8 = L.w8;
+    d.w16 = L.w16;
     d.agg = L.agg;
     d.g = L.g;
     d.fp32 = L.fp32;
@@ -1175,14 +1177,15 @@ cmg_status build_refine_plan(cmg_ctx* c) {
             L.fp32 = 1;
         L.variant = choose_variant(L, o.spmv_variant);
         // weights as the grid and step kernels read them: none where all are
-        // 1; beside FP64 iterates an 8-bit copy where every weight is an
-        // integer up to 255 (every input weight an integer: coarse weights
-        // are their sums), else an FP32 copy where every weight is exact in
-        // FP32 (the same values, fewer bytes per entry)
+        // 1; beside FP64 iterates an 8- or 16-bit copy where every weight is
+        // an integer up to 255 or 65535 (every input weight an integer:
+        // coarse weights are their sums), else an FP32 copy where every
+        // weight is exact in FP32 (the same values, fewer bytes per entry)
         L.wk = kWNative;
         if (o.weight_storage == 0 && !L.in_block && j <= top && !(j == J && c->coarse_dense)) {
             if (L.wunit) L.wk = kWUnit;
             else if (!L.fp32 && c->int_weights && L.wmax <= 255.0) L.wk = kWU8;
+            else if (!L.fp32 && c->int_weights && L.wmax <= 65535.0) L.wk = kWU16;
             else if (!L.fp32 && L.w32exact) L.wk = kWF32;
         }
         const size_t vb = L.fp32 ? 4 : 8;
@@ -1198,6 +1201,10 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         if (L.wk == kWU8) {
             ALLOC(L.w8, uint8_t, std::max<int64_t>(L.nnz, 1));
             CK(launch_to_u8(L.nnz, L.w64, L.w8, c->stream));
+        }
+        if (L.wk == kWU16) {
+            ALLOC(L.w16, uint16_t, std::max<int64_t>(L.nnz, 1));
+            CK(launch_to_u16(L.nnz, L.w64, L.w16, c->stream));
         }
         L.grid = default_grid(L, j, ncu);
         const bool auto_step = j >= kStepModeDepth && step_bytes(L) >= kStepModeBytes;
@@ -2396,8 +2403,8 @@ cmg_status cmg_level_info(cmg_handle h, cmg_level_stats* out, int32_t cap, int32
         li.grid = L.grid;
         li.pi_ms = L.pi_ms;
         const double sx = L.fp32 ? 4 : 8;
-        const int wkr = L.wk == kWUnit ? 2 : L.wk == kWU8 ? 3 : (L.fp32 || L.wk == kWF32) ? 1 : 0;
-        const double sw = wkr == 2 ? 0 : wkr == 3 ? 1 : wkr == 1 ? 4 : 8;
+        const int wkr = L.wk == kWUnit ? 2 : L.wk == kWU8 ? 3 : L.wk == kWU16 ? 4 : (L.fp32 || L.wk == kWF32) ? 1 : 0;
+        const double sw = wkr == 2 ? 0 : wkr == 3 ? 1 : wkr == 4 ? 2 : wkr == 1 ? 4 : 8;
         li.bytes_per_iter = 4.0 * (L.n + 1) + (double)L.nnz * (4 + sw) + 2 * sx * L.n;
         li.weights = wkr;
         li.block_waves = L.bwaves;

@@ -185,6 +185,7 @@ constexpr int kWNative = 0;  // the iterates' type (FP64, or FP32 on mixed-preci
 constexpr int kWF32 = 1;     // an FP32 copy beside FP64 iterates (every weight exact in FP32)
 constexpr int kWUnit = 2;    // every weight is 1: none is read
 constexpr int kWU8 = 3;      // an 8-bit copy beside FP64 iterates (every weight an integer in 1..255)
+constexpr int kWU16 = 4;     // a 16-bit copy beside FP64 iterates (every weight an integer in 1..65535)
 
 struct LevelDev {
     int32_t n;
@@ -195,6 +196,7 @@ struct LevelDev {
     const double* w64;
     const float* w32;
     const uint8_t* w8;   // 8-bit copy of the weights (kWU8 levels)
+    const uint16_t* w16; // 16-bit copy of the weights (kWU16 levels)
     const int32_t* agg;  // vertex -> aggregate in level+1 (nullptr on coarsest)
     double g;            // Gershgorin shift
     int32_t fp32;        // 1: FP32 vectors and values
@@ -210,7 +212,7 @@ struct LevelDev {
     int32_t bslots;      // register rows: entry slots per lane and row (E of the layout)
     int32_t stage;       // grid levels: 1 if a workgroup's rows may be staged in LDS
     int32_t kfix;        // > 0: fixed schedule, exactly this many PI steps and no stopping test
-    int32_t wk;          // weight storage of the grid and step kernels (kWNative, kWF32, kWUnit, kWU8)
+    int32_t wk;          // weight storage of the grid and step kernels (kWNative, kWF32, kWUnit, kWU8, kWU16)
     int32_t lmin;        // rows traversal: rows with more entries are long (INT_MAX: none)
     const int32_t* lrows;// ... their count, then the long rows in ascending order (nullptr: none)
     int32_t ileave;      // rows traversal of the persistent grid kernel: 1 if each workgroup's PI

@@ -72,8 +72,9 @@ hipError_t launch_validate(int n, int64_t nnz, const int32_t* rp, const int32_t*
                            int wf32, int full, unsigned* flags, hipStream_t s);
 hipError_t launch_convert_w(int64_t nnz, const void* w, int wf32, double* w64, hipStream_t s);
 hipError_t launch_to_f32(int64_t nnz, const double* w64, float* w32, hipStream_t s);
-// weights known to be integers in 1..255 to an 8-bit copy
+// weights known to be integers in 1..255 (1..65535) to an 8-bit (16-bit) copy
 hipError_t launch_to_u8(int64_t nnz, const double* w64, uint8_t* w8, hipStream_t s);
+hipError_t launch_to_u16(int64_t nnz, const double* w64, uint16_t* w16, hipStream_t s);
 // h[v] = heaviest neighbour (lowest index on ties); out[0] = bits of the
 // Gershgorin shift 2 max_v d_v, out[1] = bits of the largest weight,
 // out[2] = bits of the largest FP32 rounding error of a weight, out[3] =
@@ -215,7 +216,7 @@ hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, int kind, hipStrea
 // Job kernels are specialised by traversal (merge path or G lanes per
 // row) and precision: kind = 2 * t + fp32, t = 0 for the merge path, else
 // 1 + log2(G); finishing kernels depend on the traversal only.
-constexpr int kJobKinds = 64;
+constexpr int kJobKinds = 80;
 // 16 wk + 2 t + fp32: traversal t (0 merge path, else 1 + log2(lanes)),
 // FP32 iterates, weight storage wk
 int job_kind(int variant, int lanes, int fp32, int wk);

@@ -1141,7 +1141,8 @@ __device__ __forceinline__ bool job_allreduce(double (&v)[NV], GridCtx& c, doubl
 //
 // Edge weights are read through WRead<W>: W = double or float (an FP32
 // copy, used only where every weight of the level is exact in FP32),
-// uint8_t (an 8-bit copy where every weight is an integer in 1..255), or
+// uint8_t or uint16_t (a copy where every weight is an integer in 1..255
+// or 1..65535), or
 // WUnit where every weight is 1 and nothing is read.  The value is the
 // same double in all of them, so results do not depend on the storage.
 struct WUnit {};
@@ -1175,12 +1176,17 @@ template <typename T>
 struct WStore<T, kWU8> {
     using type = uint8_t;
 };
+template <typename T>
+struct WStore<T, kWU16> {
+    using type = uint16_t;
+};
 // the level's weights of kind WK for iterates of type T
 template <typename T, int WK>
 __device__ __forceinline__ WRead<typename WStore<T, WK>::type> weights_of(const LevelDev& L) {
     WRead<typename WStore<T, WK>::type> r;
     if constexpr (WK == kWUnit) r.p = nullptr;
     else if constexpr (WK == kWU8) r.p = L.w8;
+    else if constexpr (WK == kWU16) r.p = L.w16;
     else if constexpr (WK == kWF32 || sizeof(T) == 4) r.p = L.w32;
     else r.p = L.w64;
     return r;
@@ -2202,13 +2208,13 @@ hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, int kind, hipStrea
 
 namespace {
 // kind = 16 wk + 2 t + fp32 with t = 0 (merge path) or 1 + log2(G) and wk
-// the weight storage (FP32 iterates have no kWF32 or kWU8 form)
+// the weight storage (FP32 iterates have no kWF32, kWU8 or kWU16 form)
 template <int TRAV, int WK>
 const void* refine_kernel_w(int fp32) {
     if constexpr (TRAV == 0) {
-        if constexpr (WK == kWF32 || WK == kWU8) return (const void*)k_refine_merge<double, WK>;
+        if constexpr (WK == kWF32 || WK == kWU8 || WK == kWU16) return (const void*)k_refine_merge<double, WK>;
         else return fp32 ? (const void*)k_refine_merge<float, WK> : (const void*)k_refine_merge<double, WK>;
-    } else if constexpr (WK == kWF32 || WK == kWU8) {
+    } else if constexpr (WK == kWF32 || WK == kWU8 || WK == kWU16) {
         return (const void*)k_refine_rows<TRAV, double, WK>;
     } else {
         return fp32 ? (const void*)k_refine_rows<TRAV, float, WK> : (const void*)k_refine_rows<TRAV, double, WK>;
@@ -2219,6 +2225,7 @@ const void* refine_kernel_t(int fp32, int wk) {
     return wk == kWUnit ? refine_kernel_w<TRAV, kWUnit>(fp32)
            : wk == kWF32 ? refine_kernel_w<TRAV, kWF32>(fp32)
            : wk == kWU8  ? refine_kernel_w<TRAV, kWU8>(fp32)
+           : wk == kWU16 ? refine_kernel_w<TRAV, kWU16>(fp32)
                          : refine_kernel_w<TRAV, kWNative>(fp32);
 }
 const void* refine_kernel(int kind) {
@@ -2239,6 +2246,7 @@ const void* finish_kernel_t(int wk) {
     return wk == kWUnit ? (const void*)k_finish_jobs<TRAV, kWUnit>
            : wk == kWF32 ? (const void*)k_finish_jobs<TRAV, kWF32>
            : wk == kWU8  ? (const void*)k_finish_jobs<TRAV, kWU8>
+           : wk == kWU16 ? (const void*)k_finish_jobs<TRAV, kWU16>
                          : (const void*)k_finish_jobs<TRAV, kWNative>;
 }
 const void* finish_kernel(int kind) {
@@ -2325,7 +2333,7 @@ int job_kind(int variant, int lanes, int fp32, int wk) {
         for (int g = lanes; g > 1 && t < 7; g >>= 1) ++t;
     }
     // FP32 iterates read FP32 weights (their native storage)
-    if (fp32 && (wk == kWF32 || wk == kWU8)) wk = kWNative;
+    if (fp32 && (wk == kWF32 || wk == kWU8 || wk == kWU16)) wk = kWNative;
     return 16 * wk + 2 * t + (fp32 ? 1 : 0);
 }
 
@@ -2390,7 +2398,7 @@ hipError_t launch_step_begin(const StepJob* job, int nblocks, int kind, hipStrea
 namespace {
 template <int G, int WK>
 void step_spmv_w(const StepJob* job, int nblocks, int fp32, hipStream_t s) {
-    if constexpr (WK == kWF32 || WK == kWU8) {
+    if constexpr (WK == kWF32 || WK == kWU8 || WK == kWU16) {
         hipLaunchKernelGGL((k_step_spmv<G, double, WK>), dim3(nblocks), dim3(kStepBlock), 0, s, job);
     } else {
         if (fp32) hipLaunchKernelGGL((k_step_spmv<G, float, WK>), dim3(nblocks), dim3(kStepBlock), 0, s, job);
@@ -2402,6 +2410,7 @@ void step_spmv_g(const StepJob* job, int nblocks, int fp32, int wk, hipStream_t 
     if (wk == kWUnit) step_spmv_w<G, kWUnit>(job, nblocks, fp32, s);
     else if (wk == kWF32) step_spmv_w<G, kWF32>(job, nblocks, fp32, s);
     else if (wk == kWU8) step_spmv_w<G, kWU8>(job, nblocks, fp32, s);
+    else if (wk == kWU16) step_spmv_w<G, kWU16>(job, nblocks, fp32, s);
     else step_spmv_w<G, kWNative>(job, nblocks, fp32, s);
 }
 }  // namespace

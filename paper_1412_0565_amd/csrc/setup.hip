@@ -99,11 +99,12 @@ __global__ void k_to_f32(int64_t nnz, const double* __restrict__ in, float* __re
     for (; i < nnz; i += st) out[i] = (float)in[i];
 }
 
-// weights known to be integers in 1..255
-__global__ void k_to_u8(int64_t nnz, const double* __restrict__ in, uint8_t* __restrict__ out) {
+// weights known to be integers in 1..255 (U = uint8_t) or 1..65535
+template <typename U>
+__global__ void k_to_uint(int64_t nnz, const double* __restrict__ in, U* __restrict__ out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t st = (int64_t)gridDim.x * blockDim.x;
-    for (; i < nnz; i += st) out[i] = (uint8_t)in[i];
+    for (; i < nnz; i += st) out[i] = (U)in[i];
 }
 
 // ------------------------------------------------------- row information
@@ -1238,7 +1239,14 @@ hipError_t launch_to_f32(int64_t nnz, const double* w64, float* w32, hipStream_t
 hipError_t launch_to_u8(int64_t nnz, const double* w64, uint8_t* w8, hipStream_t s) {
     unsigned nb = (unsigned)std::min<int64_t>(nblocks(nnz, kBlk), 65536);
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_to_u8, dim3(nb), dim3(kBlk), 0, s, nnz, w64, w8);
+    hipLaunchKernelGGL(k_to_uint<uint8_t>, dim3(nb), dim3(kBlk), 0, s, nnz, w64, w8);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_u16(int64_t nnz, const double* w64, uint16_t* w16, hipStream_t s) {
+    unsigned nb = (unsigned)std::min<int64_t>(nblocks(nnz, kBlk), 65536);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_uint<uint16_t>, dim3(nb), dim3(kBlk), 0, s, nnz, w64, w16);
     return hipGetLastError();
 }
 

@@ -627,11 +627,11 @@ def test_barrier_fallback_mixed():
 @pytest.mark.parametrize("name", ["grid128", "grid3d_20", "rgg60k", "grid_aniso", "cl30k"])
 @pytest.mark.parametrize("mode", ["grid", "step", "mixed"])
 def test_narrow_weight_storage_is_bitwise_fp64_storage(name, mode):
-    # the grid and step kernels read no weights where all are 1, an 8-bit
-    # copy where all are integers up to 255 and an FP32 copy where all are
-    # exact in FP32: the values are the same doubles, so step counts,
-    # lambda and the vector equal FP64 storage bit for bit, and both match
-    # the oracle
+    # the grid and step kernels read no weights where all are 1, an 8- or
+    # 16-bit copy where all are integers up to 255 or 65535 and an FP32 copy
+    # where all are exact in FP32: the values are the same doubles, so step
+    # counts, lambda and the vector equal FP64 storage bit for bit, and both
+    # match the oracle
     g = _named(name)
     ref = oracle_of(g)
     kw = {"block_rows": 1}
@@ -654,6 +654,9 @@ def test_narrow_weight_storage_is_bitwise_fp64_storage(name, mode):
         if name in ("rgg60k", "grid_aniso"):
             # integer weights 1..8 and 1..2: the 8-bit copy
             assert runs[0][3][0] == 3, runs[0][3]
+        if name in ("rgg60k", "cl30k"):
+            # coarse integer weights above 255 (at most 65535): the 16-bit copy
+            assert 4 in runs[0][3], runs[0][3]
         assert [l.k for l in ref.levels] == runs[0][2]
     lam_ref = ref.lam
     assert abs(runs[0][0] - lam_ref) <= (1e-5 if mode == "mixed" else 1e-9) * abs(lam_ref)

@@ -649,11 +649,14 @@ cmg_status coarsen_once(cmg_ctx* c, SetupTmp& t, int j, bool* stop) {
             int32_t* tcol = t.idx;
             double* tw = t.v1;
             // a lane per aggregate with 16 register slots where fine rows are
-            // short (coarse rows rarely exceed 16 columns), else 32; on levels
-            // with few aggregates (a lane's walk would be one long chain of
-            // loads on a mostly idle device) every row by the wave sort
+            // short (coarse rows rarely exceed 16 columns), 24 where they
+            // hold up to 16 entries on average, else 32 (a row with more
+            // columns goes to the wave sort); on levels with few aggregates
+            // (a lane's walk would be one long chain of loads on a mostly
+            // idle device) every row by the wave sort
             const int slots = (c->opt.galerkin == 2 || nc < kGalLaneMinRows) ? 0
                               : L.nnz <= 7 * (int64_t)L.n                    ? 16
+                              : L.nnz <= 16 * (int64_t)L.n                   ? 24
                                                                              : 32;
             CK(launch_gal_gather(nc, L.n, L.nnz, slots, L.wunit, c->gal_int32, members, mstart, moff, L.rp, L.col,
                                  L.w64, L.agg,

@@ -1362,6 +1362,11 @@ hipError_t launch_gal_gather(int nc, int n, int64_t nnz, int slots, int unit, in
             else if (int32sum) CMG_GAL_LANE(16, false, true);
             else CMG_GAL_LANE(16, false, false);
             break;
+        case 24:
+            if (unit) CMG_GAL_LANE(24, true, true);
+            else if (int32sum) CMG_GAL_LANE(24, false, true);
+            else CMG_GAL_LANE(24, false, false);
+            break;
         case 32:
             if (unit) CMG_GAL_LANE(32, true, true);
             else if (int32sum) CMG_GAL_LANE(32, false, true);

@@ -264,19 +264,27 @@ __global__ void k_hec_init(int n, const int32_t* __restrict__ h, uint64_t seed, 
     slot[v] = kNoKey;
 }
 
+// The round kernels run a capped grid whose threads stride over the
+// vertices: most vertices of later rounds are settled, and a round launched
+// after the matching finished returns at once, so launching a thread per
+// vertex would cost more than the work.
+constexpr unsigned kHecRoundBlocks = 2048;
+
 // Each live candidate edge {v, h(v)} posts its key at both endpoints.  The
 // round's "any live" flag, raised only by k_hec_kill after this kernel, is
 // cleared here.
 __global__ void k_hec_post(int n, const int32_t* __restrict__ h, uint64_t seed, int level,
                            const uint8_t* __restrict__ live, unsigned long long* slot,
                            unsigned long long* flags, int round) {
-    int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v == 0) flags[round & 1] = 0ull;
+    const int v0 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v0 == 0) flags[round & 1] = 0ull;
     if (flags[(round - 1) & 1] == 0ull) return;
-    if (v >= n || !live[v]) return;
-    unsigned long long k = hec_key(seed, level, v);
-    atomicMin(&slot[v], k);
-    atomicMin(&slot[h[v]], k);
+    for (int v = v0; v < n; v += gridDim.x * blockDim.x) {
+        if (!live[v]) continue;
+        unsigned long long k = hec_key(seed, level, v);
+        atomicMin(&slot[v], k);
+        atomicMin(&slot[h[v]], k);
+    }
 }
 
 // An edge holding the minimum at both endpoints is accepted.  Two accepted
@@ -287,16 +295,17 @@ __global__ void k_hec_accept(int n, const int32_t* __restrict__ h, uint64_t seed
                              const unsigned long long* __restrict__ slot,
                              const unsigned long long* __restrict__ flags, int round) {
     if (flags[(round - 1) & 1] == 0ull) return;
-    int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n || !live[v]) return;
-    unsigned long long k = hec_key(seed, level, v);
-    int m = h[v];
-    if (slot[v] == k && slot[m] == k) {
-        state[v] = kSeed;
-        state[m] = kPartner;
-        pairseed[v] = v;
-        pairseed[m] = v;
-        live[v] = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        if (!live[v]) continue;
+        unsigned long long k = hec_key(seed, level, v);
+        int m = h[v];
+        if (slot[v] == k && slot[m] == k) {
+            state[v] = kSeed;
+            state[m] = kPartner;
+            pairseed[v] = v;
+            pairseed[m] = v;
+            live[v] = 0;
+        }
     }
 }
 
@@ -307,9 +316,9 @@ __global__ void k_hec_kill(int n, const int32_t* __restrict__ h, uint8_t* __rest
                            const uint8_t* __restrict__ state, unsigned long long* slot,
                            unsigned long long* flags, int round) {
     if (flags[(round - 1) & 1] == 0ull) return;
-    int v = blockIdx.x * blockDim.x + threadIdx.x;
     int alive = 0;
-    if (v < n && live[v]) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        if (!live[v]) continue;
         int m = h[v];
         if (state[v] != 0 || state[m] != 0) {
             live[v] = 0;
@@ -1285,7 +1294,7 @@ hipError_t launch_hec_init(int n, const int32_t* h, uint64_t seed, int level, ui
 hipError_t launch_hec_round(int n, const int32_t* h, uint64_t seed, int level, uint8_t* live,
                             uint8_t* state, int32_t* pairseed, unsigned long long* slot,
                             unsigned long long* flags, int round, hipStream_t s) {
-    unsigned nb = nblocks(n, kBlk);
+    const unsigned nb = std::min<unsigned>(nblocks(n, kBlk), kHecRoundBlocks);
     hipLaunchKernelGGL(k_hec_post, dim3(nb), dim3(kBlk), 0, s, n, h, seed, level, live, slot, flags, round);
     hipLaunchKernelGGL(k_hec_accept, dim3(nb), dim3(kBlk), 0, s, n, h, seed, level, live, state,
                        pairseed, slot, flags, round);

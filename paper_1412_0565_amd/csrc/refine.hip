@@ -1389,6 +1389,25 @@ __device__ __forceinline__ int ld_rp(const int32_t* rp, int i) {
     else return gld(rp, i);
 }
 
+// A lane's entries e, e + G, ... of a row up to b, four per trip, while
+// four remain: e is left at the first entry not taken.
+template <int G, typename Op>
+__device__ __forceinline__ void row_rest4(const Op& op, int& e, int b, double x, double& t) {
+    for (; e + 3 * G < b; e += 4 * G) {
+        int c[4];
+        double w[4], v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c[q] = op.colof(e + q * G);
+            w[q] = op.wof(e + q * G);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = op.xk(c[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t += op.term(v[q], w[q], x);
+    }
+}
+
 // the long rows of [r0, r1) (listed in lrows), each summed by the whole
 // workgroup
 template <bool SRP = false, typename Op>
@@ -1408,7 +1427,7 @@ __device__ __forceinline__ void drive_long_rows(const int32_t* __restrict__ rp, 
     }
 }
 
-template <int G, bool SRP = false, class Op>
+template <int G, bool SRP = false, bool REST4 = false, class Op>
 __device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r0, int r1, Op& op,
                                            const int32_t* __restrict__ lrows = nullptr, int lmin = 0x7fffffff,
                                            double* red = nullptr, int loff = 0) {
@@ -1426,6 +1445,15 @@ __device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r
         double t1 = 0.0, t2 = 0.0;
         rows_batch<kRowBatch, G>(op, lane, op.vidx(i), a1, b1, x1, t1, op.vidx(i2), a2, b2, x2, t2);
         int e1 = a1 + lane + kRowBatch * G, e2 = a2 + lane + kRowBatch * G;
+        if constexpr (REST4) {
+            // rows of hundreds of entries: each lane's rest in trips of
+            // four, their columns and weights, then their gathers, in
+            // flight together (the sum keeps the entry order); only where
+            // the registers allow it (the step kernels: the persistent
+            // kernels' cap would spill)
+            row_rest4<G>(op, e1, b1, x1, t1);
+            row_rest4<G>(op, e2, b2, x2, t2);
+        }
         while (e1 < b1 || e2 < b2) {
             if (e1 < b1) {
                 t1 += op.entry(e1, x1);
@@ -2092,7 +2120,7 @@ __global__ void __launch_bounds__(kStepBlock) k_step_spmv(const StepJob* __restr
     op.mu = c.mu;
     op.s = c.s;
     op.acc[0] = op.acc[1] = op.acc[2] = op.acc[3] = 0.0;
-    drive_rows<G>(L.rp, r0, r1, op, L.lrows, L.lmin, red);
+    drive_rows<G, false, (G >= 32)>(L.rp, r0, r1, op, L.lrows, L.lmin, red);
     post_part<4>(op.acc, red, J.part, lb);
 }
 

@@ -1410,7 +1410,7 @@ __device__ __forceinline__ void row_rest4(const Op& op, int& e, int b, double x,
 
 // the long rows of [r0, r1) (listed in lrows), each summed by the whole
 // workgroup
-template <bool SRP = false, typename Op>
+template <bool SRP = false, bool HUB4 = false, typename Op>
 __device__ __forceinline__ void drive_long_rows(const int32_t* __restrict__ rp, int r0, int r1, Op& op,
                                                 const int32_t* __restrict__ lrows, double* red, int loff = 0) {
     const int cnt = gld(lrows, 0);
@@ -1421,7 +1421,24 @@ __device__ __forceinline__ void drive_long_rows(const int32_t* __restrict__ rp, 
         const int a = ld_rp<SRP>(rp, r), b = ld_rp<SRP>(rp, r + 1);
         const double x = op.xi(r);
         double t[1] = {0.0};
-        for (int e = a + (int)threadIdx.x; e < b; e += (int)blockDim.x) t[0] += op.entry(e, x);
+        // HUB4: each thread's entries four per trip, their loads in flight
+        // together (a hub row holds one workgroup while the grid waits)
+        const int bd = (int)blockDim.x;
+        int e = a + (int)threadIdx.x;
+        for (; HUB4 && e + 3 * bd < b; e += 4 * bd) {
+            int c[4];
+            double w[4], v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                c[q] = op.colof(e + q * bd);
+                w[q] = op.wof(e + q * bd);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = op.xk(c[q]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t[0] += op.term(v[q], w[q], x);
+        }
+        for (; e < b; e += bd) t[0] += op.entry(e, x);
         block_sum<1>(t, red);
         if (threadIdx.x == 0) op.row(r, x, t[0]);
     }
@@ -1481,7 +1498,9 @@ __device__ __forceinline__ void drive_rows(const int32_t* __restrict__ rp, int r
             if (lane == 0) op.row(i, x, t);
         }
     }
-    if (lrows != nullptr) drive_long_rows<SRP>(rp, r0, r1, op, lrows, red, loff);
+    // levels of 32 or 64 lanes per row (skewed degrees, hub rows) batch the
+    // hub rows' loads; on the others the extra registers would spill
+    if (lrows != nullptr) drive_long_rows<SRP, (G >= 32)>(rp, r0, r1, op, lrows, red, loff);
 }
 
 // ---- traversal driver 2: merge path
@@ -1759,7 +1778,7 @@ __device__ void refine_level(const GridJob& J, GridCtx& c, double* red, MergeSha
                 const int cw = 4 * ((int)blockDim.x / TRAV);
                 for (int a = x0 + xp * cw; a < x1; a += np * cw)
                     drive_rows<TRAV>(L.rp, a, min(a + cw, x1), op, nullptr, L.lmin, red);
-                if (L.lrows != nullptr) drive_long_rows(L.rp, r0, r1, op, L.lrows, red);
+                if (L.lrows != nullptr) drive_long_rows<false, (TRAV >= 32)>(L.rp, r0, r1, op, L.lrows, red);
             } else {
                 drive_rows<TRAV>(L.rp, r0, r1, op, L.lrows, L.lmin, red);
             }

@@ -157,12 +157,12 @@ typedef struct {
                                     given up; every kernel then exits and the solve is re-run
                                     with the persistent levels one launch per step. */
     int32_t weight_storage;      /* 0 (default): the grid and step kernels read no weights on a
-                                    level whose weights are all 1; on an FP64 level an 8-bit
-                                    (16-bit) copy when every input weight is an integer and the
-                                    level's largest is at most 255 (65535), else an FP32 copy
-                                    when its weights are all exact in FP32 (the same values:
-                                    results are bitwise those of FP64 storage); 1: always the
-                                    iterates' precision. */
+                                    level whose weights are all 1; an 8-bit (16-bit) copy when
+                                    every input weight is an integer and the level's largest is
+                                    at most 255 (65535); else on an FP64 level an FP32 copy when
+                                    its weights are all exact in FP32 (the same values: results
+                                    are bitwise those of FP64 storage); 1: always the iterates'
+                                    precision. */
 } cmg_options;
 
 /* Per-level information (available after cmg_setup; PI fields after
@@ -186,9 +186,9 @@ typedef struct {
     int32_t step;          /* 1 if refined with one launch per PI step (no grid barrier) */
     int32_t weights;       /* edge weights as the level's PI steps read them: 0 FP64, 1 FP32
                               (mixed-precision level, or an exact FP32 copy beside FP64
-                              iterates), 2 none (every weight is 1), 3 an 8-bit copy beside
-                              FP64 iterates (every weight an integer in 1..255), 4 a 16-bit
-                              copy (every weight an integer in 1..65535) */
+                              iterates), 2 none (every weight is 1), 3 an 8-bit copy (every
+                              weight an integer in 1..255), 4 a 16-bit copy (every weight an
+                              integer in 1..65535) */
     int32_t block_slots;   /* in_block with register rows: entry slots per lane and row; the
                               entries of rows longer than lanes x block_slots (at most twice
                               that) are read from a list in LDS */

@@ -915,18 +915,23 @@ int grid_cap(const HostLevel& L, int j, int lanes) {
     return std::max(8, (cap / 8) * 8);
 }
 
+// Bytes of a PI step with FP64 values and vectors: the measure of a level's
+// size for the choice of step mode, the same whatever storage it gets (a
+// mixed-precision level would otherwise fall below the threshold its FP64
+// form passes and run one barrier per step: 4M Chung-Lu level 2, 1940
+// steps, 16.7 MB in FP32, 42.7 ms against 31.1 ms in step mode).
 int64_t step_bytes(const HostLevel& L) {
-    const int64_t sv = L.fp32 ? 4 : 8;
-    return 4 * ((int64_t)L.n + 1) + L.nnz * (4 + sv) + 2 * sv * (int64_t)L.n;
+    return 4 * ((int64_t)L.n + 1) + L.nnz * 12 + 16 * (int64_t)L.n;
 }
 
 // Levels at depth >= kStepModeDepth whose PI step streams at least
-// kStepModeBytes are refined with one launch per step (kernel boundaries
-// and a one-workgroup reduction in place of the grid barrier), with a
-// workgroup of kStepBlock threads per kStepWork rows + entries.  A step
-// there costs less than with the barrier, but the level pays about 70-100
-// us of fixed launches and host checks, which only levels with many steps
-// recover; in a cascadic cycle those are the coarser ones.
+// kStepModeBytes (counted in FP64) are refined with one launch per step
+// (kernel boundaries and a one-workgroup reduction in place of the grid
+// barrier), with a workgroup of kStepBlock threads per kStepWork rows +
+// entries.  A step there costs less than with the barrier, but the level
+// pays about 70-100 us of fixed launches and host checks, which only
+// levels with many steps recover; in a cascadic cycle those are the
+// coarser ones.
 constexpr int64_t kStepModeBytes = (int64_t)16 << 20;
 // rows traversal: rows longer than max(kLongRowMin, 32 lanes) are long
 // (summed by a whole workgroup)
@@ -1180,15 +1185,16 @@ cmg_status build_refine_plan(cmg_ctx* c) {
             L.fp32 = 1;
         L.variant = choose_variant(L, o.spmv_variant);
         // weights as the grid and step kernels read them: none where all are
-        // 1; beside FP64 iterates an 8- or 16-bit copy where every weight is
-        // an integer up to 255 or 65535 (every input weight an integer:
-        // coarse weights are their sums), else an FP32 copy where every
-        // weight is exact in FP32 (the same values, fewer bytes per entry)
+        // 1; an 8- or 16-bit copy where every weight is an integer up to 255
+        // or 65535 (every input weight an integer: coarse weights are their
+        // sums), else beside FP64 iterates an FP32 copy where every weight
+        // is exact in FP32 (the same values, fewer bytes per entry); FP32
+        // iterates otherwise read FP32 weights
         L.wk = kWNative;
         if (o.weight_storage == 0 && !L.in_block && j <= top && !(j == J && c->coarse_dense)) {
             if (L.wunit) L.wk = kWUnit;
-            else if (!L.fp32 && c->int_weights && L.wmax <= 255.0) L.wk = kWU8;
-            else if (!L.fp32 && c->int_weights && L.wmax <= 65535.0) L.wk = kWU16;
+            else if (c->int_weights && L.wmax <= 255.0) L.wk = kWU8;
+            else if (c->int_weights && L.wmax <= 65535.0) L.wk = kWU16;
             else if (!L.fp32 && L.w32exact) L.wk = kWF32;
         }
         const size_t vb = L.fp32 ? 4 : 8;
@@ -1197,7 +1203,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
             L.buf1 = c->dalloc(vb * (size_t)L.n);
             if (!L.buf0 || !L.buf1) return CMG_E_OOM;
         }
-        if (L.fp32 || L.wk == kWF32) {
+        if ((L.fp32 && L.wk == kWNative) || L.wk == kWF32) {
             ALLOC(L.w32, float, std::max<int64_t>(L.nnz, 1));
             CK(launch_to_f32(L.nnz, L.w64, L.w32, c->stream));
         }

@@ -184,8 +184,8 @@ __device__ __forceinline__ void block_sum1(double (&v)[NV], double* red, int& pa
 constexpr int kWNative = 0;  // the iterates' type (FP64, or FP32 on mixed-precision levels)
 constexpr int kWF32 = 1;     // an FP32 copy beside FP64 iterates (every weight exact in FP32)
 constexpr int kWUnit = 2;    // every weight is 1: none is read
-constexpr int kWU8 = 3;      // an 8-bit copy beside FP64 iterates (every weight an integer in 1..255)
-constexpr int kWU16 = 4;     // a 16-bit copy beside FP64 iterates (every weight an integer in 1..65535)
+constexpr int kWU8 = 3;      // an 8-bit copy (every weight an integer in 1..255)
+constexpr int kWU16 = 4;     // a 16-bit copy (every weight an integer in 1..65535)
 
 struct LevelDev {
     int32_t n;

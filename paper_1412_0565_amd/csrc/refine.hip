@@ -2255,14 +2255,14 @@ hipError_t launch_block_jobs(const BlockJob* jobs, int njobs, int kind, hipStrea
 
 namespace {
 // kind = 16 wk + 2 t + fp32 with t = 0 (merge path) or 1 + log2(G) and wk
-// the weight storage (FP32 iterates have no kWF32, kWU8 or kWU16 form)
+// the weight storage (FP32 iterates have no kWF32 form: FP32 is their own)
 template <int TRAV, int WK>
 const void* refine_kernel_w(int fp32) {
     if constexpr (TRAV == 0) {
-        if constexpr (WK == kWF32 || WK == kWU8 || WK == kWU16) return (const void*)k_refine_merge<double, WK>;
+        if constexpr (WK == kWF32) return (const void*)k_refine_merge<double, kWF32>;
         else return fp32 ? (const void*)k_refine_merge<float, WK> : (const void*)k_refine_merge<double, WK>;
-    } else if constexpr (WK == kWF32 || WK == kWU8 || WK == kWU16) {
-        return (const void*)k_refine_rows<TRAV, double, WK>;
+    } else if constexpr (WK == kWF32) {
+        return (const void*)k_refine_rows<TRAV, double, kWF32>;
     } else {
         return fp32 ? (const void*)k_refine_rows<TRAV, float, WK> : (const void*)k_refine_rows<TRAV, double, WK>;
     }
@@ -2380,7 +2380,7 @@ int job_kind(int variant, int lanes, int fp32, int wk) {
         for (int g = lanes; g > 1 && t < 7; g >>= 1) ++t;
     }
     // FP32 iterates read FP32 weights (their native storage)
-    if (fp32 && (wk == kWF32 || wk == kWU8 || wk == kWU16)) wk = kWNative;
+    if (fp32 && wk == kWF32) wk = kWNative;
     return 16 * wk + 2 * t + (fp32 ? 1 : 0);
 }
 
@@ -2445,7 +2445,7 @@ hipError_t launch_step_begin(const StepJob* job, int nblocks, int kind, hipStrea
 namespace {
 template <int G, int WK>
 void step_spmv_w(const StepJob* job, int nblocks, int fp32, hipStream_t s) {
-    if constexpr (WK == kWF32 || WK == kWU8 || WK == kWU16) {
+    if constexpr (WK == kWF32) {
         hipLaunchKernelGGL((k_step_spmv<G, double, WK>), dim3(nblocks), dim3(kStepBlock), 0, s, job);
     } else {
         if (fp32) hipLaunchKernelGGL((k_step_spmv<G, float, WK>), dim3(nblocks), dim3(kStepBlock), 0, s, job);

@@ -122,7 +122,8 @@ typedef struct {
                                     0 always reads them from global memory.  Results are
                                     bitwise equal. */
     int32_t step_mode;           /* grid levels traversed by rows: 0 (default) refines the levels
-                                    at depth >= 2 whose PI step streams >= 16 MB with one launch
+                                    below the finest whose PI step streams >= 16 MB (counted in
+                                    FP64) with one launch
                                     per step (no grid barrier), the others with one persistent
                                     launch; 1 uses one launch per step on every such level; -1 on
                                     none.  The same arithmetic in the same order either way:

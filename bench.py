@@ -92,6 +92,32 @@ def measured_traffic(workload, level0):
     return int(float(kv["HBM bytes per launch"])), os.path.relpath(path, ROOT)
 
 
+def setup_bytes(levels):
+    """Compulsory traffic of cmg_setup: for each level that is coarsened,
+    the row pass (row pointers, columns, FP64 weights unless all are 1),
+    the Galerkin read (row pointers, columns, the aggregate of every column,
+    the weights, the aggregate of every vertex) and the coarse level's CSR
+    written (row pointers, columns, FP64 weights).  HEC rounds, scans and
+    member lists are not counted, so the fraction is an upper bound on how
+    close setup runs to HBM."""
+    b = 0
+    for j in range(len(levels) - 1):
+        L, C = levels[j], levels[j + 1]
+        sw = 0 if L.weights == 2 else 8
+        b += 4 * (L.n + 1) + L.nnz * (4 + sw)
+        b += 4 * (L.n + 1) + L.nnz * (8 + sw) + 4 * L.n
+        b += 4 * (C.n + 1) + 12 * C.nnz
+    return b
+
+
+def setup_roofline(levels, setup_ms):
+    sb = setup_bytes(levels)
+    gbs = sb / (setup_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "bytes": sb, "ms": round(setup_ms, 3), "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "counted": "row pass, Galerkin read and coarse CSR write of every coarsened level"}
+
+
 def launch_bytes(levels, j=0):
     """Algorithmic bytes of the level-j refinement launch: k PI steps of
     4(n+1) + nnz(4+s_v) + 2 s_x n, plus the prolongation (agg read, coarse
@@ -429,6 +455,7 @@ def main():
         "cpu_baseline": cpu,
         "resident_solves_per_s": round(args.steps / el_res, 3),
         "setup_ms": round(statistics.mean(setups), 3),
+        "setup_roofline": setup_roofline(levels, statistics.mean(setups)),
         "lambda": lams[-1],
         "residual": st.residual,
         "footprint_bytes": fp,

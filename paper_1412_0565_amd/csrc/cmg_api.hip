@@ -939,6 +939,18 @@ constexpr int64_t kStepModeBytes = (int64_t)16 << 20;
 constexpr int kLongRowMin = 256;
 constexpr int kStepModeDepth = 1;
 constexpr int64_t kStepWork = 4096;
+// Levels of at least this many rows + entries take twice kStepWork per
+// workgroup (measured on MI355X: 256^3 grid level 1, 58M, 4.19 -> 3.77 ms;
+// 4M Chung-Lu level 1, 29M, 36.5 -> 32.9 ms; but at 2M, grid level 4 and
+// Chung-Lu level 2, fewer workgroups were 15% and 5% slower).
+constexpr int64_t kStepWorkLargeMin = (int64_t)16 << 20;
+
+// Workgroups of a level refined one launch per step.
+int step_grid(const HostLevel& L) {
+    const int64_t work = (int64_t)L.n + L.nnz;
+    const int64_t per = work >= kStepWorkLargeMin ? 2 * kStepWork : kStepWork;
+    return (int)std::min<int64_t>(std::max<int64_t>((work + per - 1) / per, 8), 65535);
+}
 constexpr int kStepChunk = 8;
 constexpr int kChunkEvents = 16;
 
@@ -1249,8 +1261,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
                 ALLOC(L.fpart, int32_t, L.fgrid + 1);
                 CK(launch_partition(L.n, L.nnz, L.rp, L.fgrid, L.fpart, c->stream));
             }
-            const int64_t nb = ((int64_t)L.n + L.nnz + kStepWork - 1) / kStepWork;
-            L.grid = (int)std::min<int64_t>(std::max<int64_t>(nb, 8), 65535);
+            L.grid = step_grid(L);
             max_step_grid = std::max(max_step_grid, L.grid);
         }
         ALLOC(L.part, int32_t, L.grid + 1);
@@ -1259,8 +1270,7 @@ cmg_status build_refine_plan(cmg_ctx* c) {
         // (no inter-workgroup waits) if a barrier wait is given up
         L.fbgrid = 0;
         if (!c->noalloc && !L.in_block && j <= top && L.variant != 2 && !L.step) {
-            const int64_t nb = ((int64_t)L.n + L.nnz + kStepWork - 1) / kStepWork;
-            L.fbgrid = (int)std::min<int64_t>(std::max<int64_t>(nb, 8), 65535);
+            L.fbgrid = step_grid(L);
             ALLOC(L.fbpart, int32_t, L.fbgrid + 1);
             CK(launch_partition(L.n, L.nnz, L.rp, L.fbgrid, L.fbpart, c->stream));
             max_step_grid = std::max(max_step_grid, L.fbgrid);
